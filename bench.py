@@ -1,0 +1,210 @@
+"""Benchmark: JVP+VJP solves per second on one MI355X, FP64, LSQR relative residual 1e-8.
+
+One step (one "solve") = create a handle at the solution (setup: copies, A', Px, cone
+projections and Jacobian factors including the PSD eigendecompositions, Jacobi scales)
++ one JVP + one VJP, on the mixed-cone workload n = 5000, m = 11000 (zero 1000, nonneg 5000,
+500 SOC(4), 10 PSD 20x20, 300 exponential cones), synthetic and seeded. All inputs are
+resident in HBM before the timed region.
+
+Prints ONE JSON line. Also reports the LSQR iteration counts, the setup/JVP/VJP split, the
+roofline position of the dominant kernel (algorithmic bytes per launch / its average launch
+time, measured with HIP events on the library's stream) and the CPU oracle timed on a
+bounded sample on this host.
+
+usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload mixed_qcp]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "JVP+VJP solves/sec at 1e-8 rel. residual; LSQR iters & HBM GB/s vs plain"
+HBM_PEAK_GBS = 8000.0
+
+
+def kernel_bytes(q, which: str) -> float:
+    """Algorithmic bytes of one launch of an LSQR-iteration kernel (JVP configuration):
+    every CSR stream once (8 B value + 4 B column per entry, 4 B per row pointer) and every
+    vector it must read or write once."""
+    n, m = q.n, q.m
+    N = n + m + 1
+    nnzP, nnzA = q.P.nnz, q.A.nnz
+    csr = 12.0 * (nnzP + 2 * nnzA) + 4.0 * (2 * n + m + 3)
+    if which == "rows_F":
+        # in, scale, J-input wy, q, b, out read+write, LSQR x and w read+write
+        vec = 8.0 * (N + N + m + n + m + 2 * N + 4 * N)
+        return csr + vec
+    if which == "rows_FT":
+        # in, c, b, staged output
+        return csr + 8.0 * (N + n + m + N)
+    if which == "cone_FT":
+        c = q.cones
+        fac = 8.0 * (4 * len(c.soc) + sum(c.soc) + 9 * c.n_exp + sum(2 * k * k for k in c.psd))
+        # staged input, in (y + tau), out read+write, scale, jdiag, wy write, c, b
+        return fac + 8.0 * (N + m + 1 + 2 * N + N + c.n_zero + c.n_nonneg + m + n + m)
+    raise ValueError(which)
+
+
+def cpu_baseline(q, iters_jvp, iters_vjp, budget_s=20.0):
+    """The oracle (numpy/scipy, as it stands) on a bounded sample: its setup at the solution
+    plus a fixed number of LSQR iterations of the JVP and of the VJP, single-threaded.
+    Scaled to solves/s with the GPU's iteration counts."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import derivative as D
+    from oracle import embedding as E
+
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        emb = E.Embedding(q)
+        t_setup = time.perf_counter() - t0
+        # per-iteration cost measured on a short run of each direction
+        sample = 400
+        t0 = time.perf_counter()
+        D.jvp(q, q.dP, q.dA, q.dq, q.db, tol=1e-300, max_iter=sample, emb=emb)
+        t_jvp_it = (time.perf_counter() - t0) / sample
+        t0 = time.perf_counter()
+        D.vjp(q, q.gx, q.gy, q.gs, tol=1e-300, max_iter=sample, emb=emb)
+        t_vjp_it = (time.perf_counter() - t0) / sample
+        # a longer sample of the JVP if the budget allows
+        extra = int(max(0, budget_s - 2 * sample * (t_jvp_it + t_vjp_it) - t_setup) / max(t_jvp_it, 1e-9))
+        extra = min(extra, 20000)
+        if extra > 1000:
+            t0 = time.perf_counter()
+            D.jvp(q, q.dP, q.dA, q.dq, q.db, tol=1e-300, max_iter=extra, emb=emb)
+            t_jvp_it = (time.perf_counter() - t0) / extra
+    t_solve = t_setup + t_jvp_it * iters_jvp + t_vjp_it * iters_vjp
+    return {
+        "value": 1.0 / t_solve,
+        "unit": "solves/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"oracle setup at the solution + {sample} LSQR iterations of the VJP and "
+                   f"{max(sample, extra)} of the JVP on the same workload, 1 thread; "
+                   f"per-iteration time x the GPU's iteration counts ({iters_jvp} JVP + "
+                   f"{iters_vjp} VJP)"),
+        "s_per_iter_jvp": t_jvp_it,
+        "s_per_iter_vjp": t_vjp_it,
+        "setup_s": t_setup,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="mixed_qcp")
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precond", default="jacobi", choices=["jacobi", "none"])
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only; the derivative of one QCP is not "
+              "split across GPUs (see DESIGN.md for how it would shard).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2508_17522_amd as Q
+    import qcpgen
+    from qcpgen.torch_io import cones_of, to_device
+
+    q = qcpgen.make(args.workload, 0)
+    dev = "cuda:0"
+    t = to_device(q, dev)
+    cones = cones_of(q)
+    prec = Q.QCPD_PRECOND_JACOBI if args.precond == "jacobi" else Q.QCPD_PRECOND_NONE
+    opts = Q.Opts(tol=args.tol, precond=prec)
+    outs = dict(dx=torch.empty(q.n, dtype=torch.float64, device=dev),
+                dy=torch.empty(q.m, dtype=torch.float64, device=dev),
+                ds=torch.empty(q.m, dtype=torch.float64, device=dev),
+                dP=torch.empty(q.P.nnz, dtype=torch.float64, device=dev),
+                dA=torch.empty(q.A.nnz, dtype=torch.float64, device=dev),
+                dq=torch.empty(q.n, dtype=torch.float64, device=dev),
+                db=torch.empty(q.m, dtype=torch.float64, device=dev))
+    torch.cuda.synchronize()
+
+    def step(record):
+        t0 = time.perf_counter()
+        h = Q.qcpd_create(t["P"], t["A"], t["q"], t["b"], cones, t["x"], t["y"], t["s"], opts=opts)
+        t1 = time.perf_counter()
+        _, _, _, ij, sj = Q.qcpd_jvp(h, t["dP"], t["dA"], t["dq"], t["db"],
+                                    outs["dx"], outs["dy"], outs["ds"])
+        t2 = time.perf_counter()
+        _, _, _, _, iv, sv = Q.qcpd_vjp(h, t["gx"], t["gy"], t["gs"], outs["dP"], outs["dA"],
+                                       outs["dq"], outs["db"])
+        t3 = time.perf_counter()
+        if record is not None:
+            record.append(dict(setup=t1 - t0, jvp=t2 - t1, vjp=t3 - t2, ij=ij, iv=iv, sj=sj, sv=sv))
+        return h
+
+    for _ in range(args.warmup):
+        step(None).close()
+    rec = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        h = step(rec)
+        h.close()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    value = args.steps / elapsed
+
+    # roofline of the dominant kernel: average launch duration measured with HIP events
+    h = step(None)
+    ms = Q.qcpd_profile_kernels(h, reps=200)
+    h.close()
+    names = ["rows_F", "rows_FT", "cone_FT"]
+    iters_total = rec[-1]["ij"].iters + rec[-1]["iv"].iters
+    dom = int(np.argmax(ms))
+    dom_name = names[dom]
+    nbytes = kernel_bytes(q, dom_name)
+    achieved = nbytes / (ms[dom] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                "kernel": dom_name, "avg_launch_us": round(ms[dom] * 1e3, 3),
+                "bytes_per_launch": int(nbytes),
+                "all_kernels_us": {k: round(v * 1e3, 3) for k, v in zip(names, ms)}}
+
+    line = {
+        "metric": METRIC,
+        "value": round(value, 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": q.name, "n": q.n, "m": q.m, "nnz_P": int(q.P.nnz),
+                   "nnz_A": int(q.A.nnz), "tol": args.tol, "precond": args.precond,
+                   "cones": {"zero": q.cones.n_zero, "nonneg": q.cones.n_nonneg,
+                             "soc": len(q.cones.soc), "psd": len(q.cones.psd),
+                             "exp": q.cones.n_exp}},
+        "lsqr_iters": {"jvp": rec[-1]["ij"].iters, "vjp": rec[-1]["iv"].iters},
+        "rel_residual": {"jvp": rec[-1]["ij"].rel_residual, "vjp": rec[-1]["iv"].rel_residual},
+        "split_ms": {k: round(1e3 * float(np.median([r[k] for r in rec])), 3)
+                     for k in ("setup", "jvp", "vjp")},
+        "us_per_lsqr_iter": round(1e6 * float(np.median([r["jvp"] + r["vjp"] for r in rec]))
+                                  / max(iters_total, 1), 3),
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(q, rec[-1]["ij"].iters, rec[-1]["iv"].iters)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

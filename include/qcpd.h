@@ -1,0 +1,164 @@
+/*
+ * qcpd -- derivative and adjoint of a quadratic cone program's solution map on one
+ * MI355X (gfx950), in FP64.
+ *
+ * Problem (Sec. 2.1, eq. conic-pair):
+ *     minimize 1/2 x'Px + q'x  subject to  Ax + s = b, s in K
+ * with dual  Px + A'y = -q, y in K*.  The caller supplies the data theta = (P, A, q, b),
+ * the cone K and a primal-dual solution (x, y, s) from any solver (Sec. 2.2: the derivative
+ * needs the solution at theta, which a numerical solver provides).
+ *
+ * qcpd_jvp evaluates DS(theta)[dtheta] = (dx, dy, ds)          (Sec. 3.1)
+ * qcpd_vjp evaluates DS(theta)'[(gx, gy, gs)] = (dP, dA, dq, db) (Sec. 3.2)
+ * Both form z = (x, y - s, 1), and solve a least-squares problem with the derivative of the
+ * normalised residual map, F = D_z N = D_u Q(Pi z) DPi(z) - DPi(z) + I (Sec. 2.4), by
+ * matrix-free LSQR with a diagonal (Jacobi) right preconditioner. dP and dA live on the
+ * stored patterns of P and A (Sec. 3.2, last paragraph).
+ *
+ * Conventions
+ *   - All floating-point data is FP64; CSR index arrays are int32.
+ *   - P is given in full symmetric CSR (both triangles, pattern and values symmetric).
+ *     A perturbation dP must be symmetric on that pattern; the returned dP is symmetric.
+ *     Inner products over dP, dA are sums over stored entries.
+ *   - Cone rows are ordered: zero, nonnegative, second-order cones (t first), PSD cones
+ *     (svec: lower triangle column-major, off-diagonals times sqrt 2), exponential cones
+ *     (x, y, z) per Appendix A.
+ *   - Pointers marked [device] are device (HBM) pointers on the current HIP device; [host]
+ *     are host pointers. The caller owns every buffer it passes. qcpd_create copies or
+ *     derives everything it needs, so its inputs may be freed once it returns.
+ *   - Work is ordered on the stream given at create time (a hipStream_t passed as void*;
+ *     NULL is the default stream). qcpd_jvp/qcpd_vjp return after the result is complete.
+ *   - A handle is not thread-safe; distinct handles are independent.
+ *   - No function throws; every one returns a status. Negative = error and no output
+ *     written; positive = warning with outputs written.
+ */
+#ifndef QCPD_H
+#define QCPD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t qcpd_status;
+
+#define QCPD_OK                     0
+#define QCPD_WARN_NOT_CONVERGED     1   /* LSQR hit max_iter; outputs at the last iterate  */
+#define QCPD_WARN_NONDIFF           2   /* a cone block lies within 1e-10 (relative) of a
+                                           point where its projection is not differentiable;
+                                           the listed tie-break rules were applied           */
+#define QCPD_ERR_INVALID_ARG       -1   /* null pointer, negative size, bad option           */
+#define QCPD_ERR_DIM               -2   /* inconsistent dimensions                           */
+#define QCPD_ERR_CONE              -3   /* cone rows do not add up to m, or a bad cone size  */
+#define QCPD_ERR_PATTERN           -4   /* P is not symmetric (pattern or values)            */
+#define QCPD_ERR_NAN               -5   /* NaN or Inf in an input                            */
+#define QCPD_ERR_HIP               -6   /* a HIP runtime call failed                         */
+#define QCPD_ERR_OOM               -7   /* device allocation failed                          */
+
+/* preconditioners for LSQR (right preconditioning; the residual is unchanged) */
+#define QCPD_PRECOND_NONE    0
+#define QCPD_PRECOND_JACOBI  1   /* 1 / column norms of the operator with each cone block's
+                                    Jacobian replaced by its diagonal                        */
+#define QCPD_PRECOND_CUSTOM  2   /* caller-supplied diagonal (qcpd_set_precond), e.g. the
+                                    output of a learned model                               */
+
+/* Compressed sparse rows. [device] arrays: rowptr (nrows+1), colind (nnz), val (nnz). */
+typedef struct {
+    int32_t nrows, ncols, nnz;
+    const int32_t *rowptr;
+    const int32_t *colind;
+    const double  *val;
+} qcpd_csr;
+
+/* Cone K as a Cartesian product, in row order (see Conventions). [host] arrays. */
+typedef struct {
+    int32_t n_zero;              /* zero cone rows ({0}; its dual is R)                     */
+    int32_t n_nonneg;            /* nonnegative orthant rows                                */
+    int32_t n_soc;               /* number of second-order cones                            */
+    const int32_t *soc_dims;     /* n_soc dimensions, each >= 1                             */
+    int32_t n_psd;               /* number of PSD cones                                     */
+    const int32_t *psd_orders;   /* n_psd matrix orders k (1 <= k <= 64); k(k+1)/2 rows each */
+    int32_t n_exp;               /* number of exponential cones, 3 rows each                */
+} qcpd_cones;
+
+typedef struct {
+    double  tol;          /* stop when the LSQR residual estimate <= tol * ||rhs||  (1e-8)   */
+    int32_t max_iter;     /* iteration cap; 0 = 20 * (n + m + 1)                              */
+    int32_t precond;      /* QCPD_PRECOND_*                                   (JACOBI)         */
+    int32_t graph_chunk;  /* LSQR iterations per captured HIP graph launch     (32)            */
+    int32_t check_symmetry; /* verify that P is symmetric at create              (1)           */
+} qcpd_opts;
+
+typedef struct {
+    int32_t  iters;          /* LSQR iterations                                              */
+    double   est_residual;   /* LSQR estimate ||residual|| / ||rhs|| at exit                 */
+    double   rel_residual;   /* explicit ||F dz + d|| / ||d|| (JVP) or ||F'w + dz|| / ||dz||
+                                (VJP), recomputed from the returned iterate                  */
+    uint32_t flags;          /* bit 0: not converged; bit 1: non-differentiable warning      */
+    float    ms_total;       /* wall time of the call on its stream (HIP events)             */
+} qcpd_info;
+
+typedef struct qcpd_handle qcpd_handle;
+
+/* Default options. */
+void qcpd_opts_default(qcpd_opts *opts);
+
+/* Build a handle at a solution (Sec. 3.1, "First, we compute Pi z"): copies P, A, q, b, x,
+ * y, s; builds A' (for the products with A'); computes Px, x'Px and c = -2Px - q; projects
+ * z_y = y - s onto K* block by block and stores each block's Jacobian factors (Appendix A:
+ * nonnegative mask, SOC scalars, exponential 3x3 matrices, PSD eigenvectors and the B
+ * matrix); computes the Jacobi scales. P: n x n, A: m x n, q: n, b, y, s: m, x: n, all
+ * [device]. K: [host]. opts may be NULL (defaults). stream: hipStream_t or NULL.
+ * Returns QCPD_OK or QCPD_WARN_NONDIFF with *h set; on error *h is NULL. */
+qcpd_status qcpd_create(qcpd_handle **h, const qcpd_csr *P, const qcpd_csr *A,
+                        const double *q, const double *b, const qcpd_cones *K,
+                        const double *x, const double *y, const double *s,
+                        const qcpd_opts *opts, void *stream);
+
+/* JVP (Sec. 3.1): (dx, dy, ds) = DS(theta)[(dP, dA, dq, db)].
+ * Inputs [device]: dP_val (nnz P, symmetric on P's pattern), dA_val (nnz A), dq (n), db (m).
+ * Outputs [device], caller-allocated: dx (n), dy (m), ds (m). info: [host], may be NULL. */
+qcpd_status qcpd_jvp(qcpd_handle *h, const double *dP_val, const double *dA_val,
+                     const double *dq, const double *db,
+                     double *dx, double *dy, double *ds, qcpd_info *info);
+
+/* VJP (Sec. 3.2): (dP, dA, dq, db) = DS(theta)'[(gx, gy, gs)].
+ * Inputs [device]: gx (n), gy (m), gs (m). Outputs [device], caller-allocated:
+ * dP_val (nnz P), dA_val (nnz A), dq (n), db (m). info: [host], may be NULL. */
+qcpd_status qcpd_vjp(qcpd_handle *h, const double *gx, const double *gy, const double *gs,
+                     double *dP_val, double *dA_val, double *dq, double *db,
+                     qcpd_info *info);
+
+/* Replace the handle's LSQR options (tolerance, iteration cap, chunk); precond is applied
+ * from the next call. Returns QCPD_ERR_INVALID_ARG for bad values. */
+qcpd_status qcpd_set_opts(qcpd_handle *h, const qcpd_opts *opts);
+
+/* Supply a custom diagonal right preconditioner for QCPD_PRECOND_CUSTOM: d_jvp scales the
+ * columns of F (JVP), d_vjp the columns of F' (VJP); each (n + m + 1) [device], entries > 0.
+ * The values are copied. */
+qcpd_status qcpd_set_precond(qcpd_handle *h, const double *d_jvp, const double *d_vjp);
+
+/* Copy the handle's Jacobi scales and the diagonal of DPi_{K*}(z_y) out [device]:
+ * d_jvp, d_vjp (n + m + 1 each), jdiag (m). Any pointer may be NULL. */
+qcpd_status qcpd_get_diagnostics(qcpd_handle *h, double *d_jvp, double *d_vjp, double *jdiag);
+
+/* Measurement support: time the three kernels of one LSQR iteration of the JVP (the
+ * product with F over CSR rows; the CSR-row part of the product with F'; the per-cone part
+ * of the product with F') by launching each `reps` times back to back on the handle's
+ * stream between HIP events, on the handle's current vectors. Writes the average duration
+ * of one launch in milliseconds to ms_out[0..2] [host]. Leaves the LSQR state undefined:
+ * call it between, not during, derivative evaluations. */
+qcpd_status qcpd_profile_kernels(qcpd_handle *h, int32_t reps, float *ms_out);
+
+/* Free a handle (NULL is allowed). */
+void qcpd_destroy(qcpd_handle *h);
+
+/* Static string for a status code. */
+const char *qcpd_status_str(qcpd_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QCPD_H */

@@ -1,0 +1,18 @@
+"""qcpd: derivative and adjoint of a quadratic cone program's solution map on MI355X.
+
+The computation lives in the HIP library libqcpd.so (C-ABI in include/qcpd.h); this package
+is its Python binding plus a torch.autograd.Function whose backward is the adjoint.
+"""
+from ._capi import (QCPD_OK, QCPD_WARN_NOT_CONVERGED, QCPD_WARN_NONDIFF, QCPD_ERR_INVALID_ARG,
+                    QCPD_ERR_DIM, QCPD_ERR_CONE, QCPD_ERR_PATTERN, QCPD_ERR_NAN, QCPD_ERR_HIP,
+                    QCPD_ERR_OOM, QCPD_PRECOND_NONE, QCPD_PRECOND_JACOBI, QCPD_PRECOND_CUSTOM,
+                    LIB_PATH, EXPORTS)
+from .api import (Cones, Opts, Info, Handle, QCPDError, qcpd_create, qcpd_jvp, qcpd_vjp,
+                  qcpd_destroy, qcpd_status_str, qcpd_opts_default, qcpd_set_opts,
+                  qcpd_set_precond, qcpd_get_diagnostics, qcpd_profile_kernels)
+
+__all__ = [
+    "Cones", "Opts", "Info", "Handle", "QCPDError", "qcpd_create", "qcpd_jvp", "qcpd_vjp",
+    "qcpd_destroy", "qcpd_status_str", "qcpd_opts_default", "qcpd_set_opts",
+    "qcpd_set_precond", "qcpd_get_diagnostics", "qcpd_profile_kernels", "LIB_PATH", "EXPORTS",
+]

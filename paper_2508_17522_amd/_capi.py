@@ -1,0 +1,93 @@
+"""ctypes declarations of the C-ABI in include/qcpd.h. Loading fails loudly when the HIP
+library has not been built: there is no fallback path."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqcpd.so")
+
+c_int32 = ctypes.c_int32
+c_double = ctypes.c_double
+c_void_p = ctypes.c_void_p
+
+
+class qcpd_csr(ctypes.Structure):
+    _fields_ = [("nrows", c_int32), ("ncols", c_int32), ("nnz", c_int32),
+                ("rowptr", c_void_p), ("colind", c_void_p), ("val", c_void_p)]
+
+
+class qcpd_cones(ctypes.Structure):
+    _fields_ = [("n_zero", c_int32), ("n_nonneg", c_int32), ("n_soc", c_int32),
+                ("soc_dims", ctypes.POINTER(c_int32)), ("n_psd", c_int32),
+                ("psd_orders", ctypes.POINTER(c_int32)), ("n_exp", c_int32)]
+
+
+class qcpd_opts(ctypes.Structure):
+    _fields_ = [("tol", c_double), ("max_iter", c_int32), ("precond", c_int32),
+                ("graph_chunk", c_int32), ("check_symmetry", c_int32)]
+
+
+class qcpd_info(ctypes.Structure):
+    _fields_ = [("iters", c_int32), ("est_residual", c_double), ("rel_residual", c_double),
+                ("flags", ctypes.c_uint32), ("ms_total", ctypes.c_float)]
+
+
+QCPD_OK = 0
+QCPD_WARN_NOT_CONVERGED = 1
+QCPD_WARN_NONDIFF = 2
+QCPD_ERR_INVALID_ARG = -1
+QCPD_ERR_DIM = -2
+QCPD_ERR_CONE = -3
+QCPD_ERR_PATTERN = -4
+QCPD_ERR_NAN = -5
+QCPD_ERR_HIP = -6
+QCPD_ERR_OOM = -7
+
+QCPD_PRECOND_NONE = 0
+QCPD_PRECOND_JACOBI = 1
+QCPD_PRECOND_CUSTOM = 2
+
+EXPORTS = ["qcpd_opts_default", "qcpd_create", "qcpd_jvp", "qcpd_vjp", "qcpd_set_opts",
+           "qcpd_set_precond", "qcpd_get_diagnostics", "qcpd_profile_kernels", "qcpd_destroy",
+           "qcpd_status_str"]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libqcpd.so and declare the signatures. Raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"{path} is missing: build the HIP library first "
+            "(python -m paper_2508_17522_amd.build)")
+    lib = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    lib.qcpd_opts_default.argtypes = [P(qcpd_opts)]
+    lib.qcpd_opts_default.restype = None
+    lib.qcpd_create.argtypes = [P(c_void_p), P(qcpd_csr), P(qcpd_csr), c_void_p, c_void_p,
+                                P(qcpd_cones), c_void_p, c_void_p, c_void_p, P(qcpd_opts),
+                                c_void_p]
+    lib.qcpd_create.restype = c_int32
+    lib.qcpd_jvp.argtypes = [c_void_p] + [c_void_p] * 7 + [P(qcpd_info)]
+    lib.qcpd_jvp.restype = c_int32
+    lib.qcpd_vjp.argtypes = [c_void_p] + [c_void_p] * 7 + [P(qcpd_info)]
+    lib.qcpd_vjp.restype = c_int32
+    lib.qcpd_set_opts.argtypes = [c_void_p, P(qcpd_opts)]
+    lib.qcpd_set_opts.restype = c_int32
+    lib.qcpd_set_precond.argtypes = [c_void_p, c_void_p, c_void_p]
+    lib.qcpd_set_precond.restype = c_int32
+    lib.qcpd_get_diagnostics.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]
+    lib.qcpd_get_diagnostics.restype = c_int32
+    lib.qcpd_profile_kernels.argtypes = [c_void_p, c_int32, P(ctypes.c_float)]
+    lib.qcpd_profile_kernels.restype = c_int32
+    lib.qcpd_destroy.argtypes = [c_void_p]
+    lib.qcpd_destroy.restype = None
+    lib.qcpd_status_str.argtypes = [c_int32]
+    lib.qcpd_status_str.restype = ctypes.c_char_p
+    _lib = lib
+    return lib

@@ -1,0 +1,626 @@
+// C-ABI entry points: handle creation at a solution, JVP, VJP (Sec. 3.1, 3.2).
+// Device-resident throughout: the inputs are device pointers and only status scalars come
+// back to the host. The LSQR iterations run as captured HIP graphs of `graph_chunk`
+// iterations each; the host reads the device stop flag once per graph launch.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "qcpd_internal.h"
+#include "setup.h"
+
+using namespace qcpd;
+
+struct qcpd_handle {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t cap = nullptr;   // private stream used only for graph capture
+    qcpd_opts opts{};
+    Problem p{};
+    ConeGrid cg{};
+    RowGrid rg{};
+    int lds = 0;
+    int nblk_max = 0;
+    std::vector<void *> allocs;
+    double *u = nullptr, *v = nullptr, *xk = nullptr, *wk = nullptr, *tmp = nullptr,
+           *rhs = nullptr, *sol = nullptr, *wy = nullptr, *scratch = nullptr;
+    double *scale[2] = {nullptr, nullptr};   // Jacobi: [0] columns of F, [1] columns of F'
+    double *custom[2] = {nullptr, nullptr};  // caller-supplied diagonal
+    double *jdiag = nullptr;
+    double *partials = nullptr;
+    int *counter = nullptr;
+    int *flag = nullptr;
+    LsqrState *st = nullptr;
+    LsqrState *host_st = nullptr;            // pinned
+    int *host_flag = nullptr;                // pinned
+    void *seg = nullptr;                     // device segment table for the NaN scan
+    void *host_seg = nullptr;                // pinned staging for it
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    int graph_chunk[2] = {0, 0};
+    const double *graph_sc[2] = {nullptr, nullptr};
+    uint32_t create_flags = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+namespace {
+
+constexpr int kMaxSeg = 8;
+
+#define HIPCHK(expr)                              \
+    do {                                          \
+        hipError_t e_ = (expr);                   \
+        if (e_ != hipSuccess) return QCPD_ERR_HIP; \
+    } while (0)
+
+template <class T>
+qcpd_status dalloc(qcpd_handle *h, T **ptr, size_t count) {
+    *ptr = nullptr;
+    if (count == 0) count = 1;
+    void *p = nullptr;
+    if (hipMalloc(&p, sizeof(T) * count) != hipSuccess) return QCPD_ERR_OOM;
+    h->allocs.push_back(p);
+    *ptr = static_cast<T *>(p);
+    return QCPD_OK;
+}
+
+#define ALLOC(ptr, count)                                   \
+    do {                                                    \
+        qcpd_status s_ = dalloc(h, &(ptr), (size_t)(count)); \
+        if (s_ != QCPD_OK) return s_;                       \
+    } while (0)
+
+int lanes_for(double avg) {
+    int L = 1;
+    while (L < 64 && 2 * L <= avg) L *= 2;
+    return L;
+}
+
+void free_handle(qcpd_handle *h) {
+    if (!h) return;
+    for (int d = 0; d < 2; ++d)
+        if (h->graph[d]) hipGraphExecDestroy(h->graph[d]);
+    for (void *p : h->allocs) hipFree(p);
+    if (h->host_st) hipHostFree(h->host_st);
+    if (h->host_flag) hipHostFree(h->host_flag);
+    if (h->host_seg) hipHostFree(h->host_seg);
+    if (h->cap) hipStreamDestroy(h->cap);
+    if (h->ev0) hipEventDestroy(h->ev0);
+    if (h->ev1) hipEventDestroy(h->ev1);
+    delete h;
+}
+
+qcpd_status check_opts(const qcpd_opts *o) {
+    if (!(o->tol >= 0.0) || o->max_iter < 0 || o->graph_chunk < 1 || o->graph_chunk > 4096 ||
+        o->precond < QCPD_PRECOND_NONE || o->precond > QCPD_PRECOND_CUSTOM)
+        return QCPD_ERR_INVALID_ARG;
+    return QCPD_OK;
+}
+
+int max_iter_of(const qcpd_handle *h) {
+    return h->opts.max_iter > 0 ? h->opts.max_iter : 20 * h->p.N;
+}
+
+// NaN / Inf scan over device arrays; returns QCPD_ERR_NAN, QCPD_ERR_HIP or QCPD_OK.
+qcpd_status scan_finite(qcpd_handle *h, std::vector<const double *> ptrs, std::vector<long long> lens) {
+    const double *P2[kMaxSeg];
+    long long L2[kMaxSeg];
+    int nseg = 0;
+    for (size_t i = 0; i < ptrs.size() && nseg < kMaxSeg; ++i)
+        if (lens[i] > 0) { P2[nseg] = ptrs[i]; L2[nseg] = lens[i]; ++nseg; }
+    if (nseg == 0) return QCPD_OK;
+    hipStream_t s = h->stream;
+    memcpy(h->host_seg, P2, nseg * sizeof(double *));
+    memcpy(reinterpret_cast<char *>(h->host_seg) + kMaxSeg * sizeof(double *), L2, nseg * sizeof(long long));
+    HIPCHK(hipMemcpyAsync(h->seg, h->host_seg, kMaxSeg * (sizeof(double *) + sizeof(long long)),
+                          hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemsetAsync(h->flag, 0, sizeof(int), s));
+    const double *const *dptr = reinterpret_cast<const double *const *>(h->seg);
+    const long long *dlen = reinterpret_cast<const long long *>(
+        reinterpret_cast<char *>(h->seg) + kMaxSeg * sizeof(double *));
+    launch_nan_scan(dptr, dlen, nseg, h->flag, s);
+    HIPCHK(hipMemcpyAsync(h->host_flag, h->flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return *h->host_flag ? QCPD_ERR_NAN : QCPD_OK;
+}
+
+const double *active_scale(const qcpd_handle *h, int dir) {
+    switch (h->opts.precond) {
+    case QCPD_PRECOND_JACOBI: return h->scale[dir];
+    case QCPD_PRECOND_CUSTOM: return h->custom[dir] ? h->custom[dir] : h->scale[dir];
+    default: return nullptr;
+    }
+}
+
+StepArgs base_args(const qcpd_handle *h, const double *sc) {
+    StepArgs a{};
+    a.sc = sc;
+    a.wy = h->wy;
+    a.xk = h->xk;
+    a.wk = h->wk;
+    a.tmp = h->tmp;
+    a.rhs = h->rhs;
+    a.partials = h->partials;
+    a.counter = h->counter;
+    a.st = h->st;
+    a.in_nrm = NRM_ONE;
+    a.role = ROLE_PLAIN;
+    return a;
+}
+
+// One LSQR iteration. JVP: the LSQR matrix is F diag(sc); VJP: it is F' diag(sc).
+void enqueue_iteration(const qcpd_handle *h, int dir, const double *sc, hipStream_t s) {
+    StepArgs a = base_args(h, sc);
+    a.check_done = 1;
+    if (dir == 0) {
+        StepArgs f = a;  // u~ <- F(sc o v) - alpha u~
+        f.in = h->v; f.in_nrm = NRM_ALPHA; f.in_is_v = 1;
+        f.out = h->u; f.role = ROLE_U; f.do_update = 1;
+        launch_rows_F(h->p, f, h->rg, s);
+        StepArgs t1 = a;  // F'u, rows
+        t1.in = h->u; t1.in_nrm = NRM_BETA;
+        launch_rows_FT(h->p, t1, h->rg, s);
+        StepArgs t2 = t1;  // v~ <- sc o F'u - beta v~, J(sc o v~) for the next product
+        t2.out = h->v; t2.role = ROLE_V; t2.out_is_v = 1; t2.do_pre = 1;
+        launch_cone_FT(h->p, t2, h->cg, h->lds, s);
+    } else {
+        StepArgs t1 = a;  // F'(sc o v), rows
+        t1.in = h->v; t1.in_nrm = NRM_ALPHA; t1.in_is_v = 1; t1.do_update = 1;
+        launch_rows_FT(h->p, t1, h->rg, s);
+        StepArgs t2 = t1;  // u~ <- F'(sc o v) - alpha u~, J(u~) for the next product
+        t2.do_update = 0;
+        t2.out = h->u; t2.role = ROLE_U; t2.do_pre = 1;
+        launch_cone_FT(h->p, t2, h->cg, h->lds, s);
+        StepArgs f = a;  // v~ <- sc o F u - beta v~
+        f.in = h->u; f.in_nrm = NRM_BETA;
+        f.out = h->v; f.role = ROLE_V; f.out_is_v = 1;
+        launch_rows_F(h->p, f, h->rg, s);
+    }
+}
+
+qcpd_status ensure_graph(qcpd_handle *h, int dir, const double *sc) {
+    const int chunk = h->opts.graph_chunk;
+    if (h->graph[dir] && h->graph_chunk[dir] == chunk && h->graph_sc[dir] == sc) return QCPD_OK;
+    if (h->graph[dir]) {
+        hipGraphExecDestroy(h->graph[dir]);
+        h->graph[dir] = nullptr;
+    }
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+    for (int i = 0; i < chunk; ++i) enqueue_iteration(h, dir, sc, h->cap);
+    HIPCHK(hipStreamEndCapture(h->cap, &g));
+    hipError_t e = hipGraphInstantiate(&h->graph[dir], g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        h->graph[dir] = nullptr;
+        return QCPD_ERR_HIP;
+    }
+    h->graph_chunk[dir] = chunk;
+    h->graph_sc[dir] = sc;
+    return QCPD_OK;
+}
+
+// Runs LSQR from the right-hand side already placed in u (with beta set), leaves the
+// solution (mapped back through the scale) in h->sol.
+qcpd_status run_lsqr(qcpd_handle *h, int dir, const double *sc) {
+    hipStream_t s = h->stream;
+    StepArgs a = base_args(h, sc);
+    a.check_done = 1;
+    if (dir == 0) {
+        StepArgs t1 = a;
+        t1.in = h->u; t1.in_nrm = NRM_BETA;
+        launch_rows_FT(h->p, t1, h->rg, s);
+        StepArgs t2 = t1;
+        t2.out = h->v; t2.role = ROLE_V0; t2.out_is_v = 1; t2.do_pre = 1;
+        launch_cone_FT(h->p, t2, h->cg, h->lds, s);
+    } else {
+        StepArgs pre = a;
+        pre.in = h->u;
+        launch_cone_pre(h->p, pre, h->cg, h->lds, s);
+        StepArgs f = a;
+        f.in = h->u; f.in_nrm = NRM_BETA;
+        f.out = h->v; f.role = ROLE_V0; f.out_is_v = 1;
+        launch_rows_F(h->p, f, h->rg, s);
+    }
+    qcpd_status rc = ensure_graph(h, dir, sc);
+    if (rc != QCPD_OK) return rc;
+    const long long max_launch = (long long)max_iter_of(h) / h->opts.graph_chunk + 4;
+    for (long long l = 0;; ++l) {
+        HIPCHK(hipMemcpyAsync(h->host_st, h->st, sizeof(LsqrState), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (h->host_st->done || l >= max_launch) break;
+        HIPCHK(hipGraphLaunch(h->graph[dir], s));
+    }
+    StepArgs fl = base_args(h, sc);
+    launch_flush(h->p, fl, h->sol, div_up(h->p.N, kBlock), s);
+    return QCPD_OK;
+}
+
+void fill_info(qcpd_handle *h, qcpd_info *info) {
+    if (!info) return;
+    const LsqrState &st = *h->host_st;
+    info->iters = st.iters;
+    info->est_residual = st.beta1 > 0.0 ? st.phibar / st.beta1 : 0.0;
+    info->rel_residual = st.beta1 > 0.0 ? st.resid / st.beta1 : 0.0;
+    info->flags = (st.conv ? 0u : 1u) | h->create_flags;
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, h->ev0, h->ev1);
+    info->ms_total = ms;
+}
+
+qcpd_status create_impl(qcpd_handle *h, const qcpd_csr *P, const qcpd_csr *A, const double *q,
+                        const double *b, const qcpd_cones *K, const double *x, const double *y,
+                        const double *s) {
+    const int n = P->nrows, m = A->nrows, N = n + m + 1;
+    hipStream_t st = h->stream;
+    Problem &p = h->p;
+    p.n = n; p.m = m; p.N = N;
+    p.nnzP = P->nnz; p.nnzA = A->nnz;
+    // --- copies of the data -----------------------------------------------------------
+    int *Prp, *Pci, *Arp, *Aci, *Trp, *Tci, *Tperm;
+    double *Pv, *Av, *Tv, *dq_, *db_, *dx_, *dy_, *ds_, *c, *zy, *xpx;
+    ALLOC(Prp, n + 1); ALLOC(Pci, P->nnz); ALLOC(Pv, P->nnz);
+    ALLOC(Arp, m + 1); ALLOC(Aci, A->nnz); ALLOC(Av, A->nnz);
+    ALLOC(Trp, n + 1); ALLOC(Tci, A->nnz); ALLOC(Tv, A->nnz); ALLOC(Tperm, A->nnz);
+    ALLOC(dq_, n); ALLOC(db_, m); ALLOC(dx_, n); ALLOC(dy_, m); ALLOC(ds_, m);
+    ALLOC(c, n); ALLOC(zy, m); ALLOC(xpx, 1);
+    HIPCHK(hipMemcpyAsync(Prp, P->rowptr, sizeof(int) * (n + 1), hipMemcpyDeviceToDevice, st));
+    if (P->nnz) {
+        HIPCHK(hipMemcpyAsync(Pci, P->colind, sizeof(int) * P->nnz, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(Pv, P->val, sizeof(double) * P->nnz, hipMemcpyDeviceToDevice, st));
+    }
+    HIPCHK(hipMemcpyAsync(Arp, A->rowptr, sizeof(int) * (m + 1), hipMemcpyDeviceToDevice, st));
+    if (A->nnz) {
+        HIPCHK(hipMemcpyAsync(Aci, A->colind, sizeof(int) * A->nnz, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(Av, A->val, sizeof(double) * A->nnz, hipMemcpyDeviceToDevice, st));
+    }
+    if (n) {
+        HIPCHK(hipMemcpyAsync(dq_, q, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(dx_, x, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    }
+    if (m) {
+        HIPCHK(hipMemcpyAsync(db_, b, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(dy_, y, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(ds_, s, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
+    }
+    p.Prp = Prp; p.Pci = Pci; p.Pv = Pv; p.Arp = Arp; p.Aci = Aci; p.Av = Av;
+    p.q = dq_; p.b = db_; p.x = dx_; p.y = dy_; p.s = ds_; p.c = c; p.zy = zy;
+    // --- workspace ------------------------------------------------------------------------
+    ALLOC(h->u, N); ALLOC(h->v, N); ALLOC(h->xk, N); ALLOC(h->wk, N); ALLOC(h->tmp, N);
+    ALLOC(h->rhs, N); ALLOC(h->sol, N); ALLOC(h->wy, m); ALLOC(h->scratch, N);
+    ALLOC(h->scale[0], N); ALLOC(h->scale[1], N); ALLOC(h->jdiag, m);
+    ALLOC(h->counter, 1); ALLOC(h->flag, 4); ALLOC(h->st, 1);
+    {
+        char *segp = nullptr;
+        ALLOC(segp, kMaxSeg * 16);
+        h->seg = segp;
+    }
+    HIPCHK(hipMemsetAsync(h->counter, 0, sizeof(int), st));
+    HIPCHK(hipMemsetAsync(h->flag, 0, 4 * sizeof(int), st));
+    HIPCHK(hipMemsetAsync(h->wy, 0, sizeof(double) * std::max(m, 1), st));
+    // --- grids ----------------------------------------------------------------------------
+    RowGrid &rg = h->rg;
+    rg.lx = lanes_for(n ? (double)(P->nnz + A->nnz) / n : 1.0);
+    rg.ly = lanes_for(m ? (double)A->nnz / m : 1.0);
+    rg.bx = div_up((long long)n * rg.lx, kBlock);
+    rg.by = div_up((long long)(m + 1) * rg.ly, kBlock);
+    // cone tables
+    std::vector<int> soc_row, soc_dim, psd_row, psd_k;
+    std::vector<long long> psd_off;
+    int row = K->n_zero + K->n_nonneg;
+    for (int i = 0; i < K->n_soc; ++i) { soc_row.push_back(row); soc_dim.push_back(K->soc_dims[i]); row += K->soc_dims[i]; }
+    long long off = 0;
+    int kmax = 0;
+    for (int i = 0; i < K->n_psd; ++i) {
+        const int k = K->psd_orders[i];
+        psd_row.push_back(row); psd_k.push_back(k); psd_off.push_back(off);
+        row += k * (k + 1) / 2; off += 2LL * k * k; kmax = std::max(kmax, k);
+    }
+    p.exp_row0 = row;
+    p.n_diag = K->n_zero + K->n_nonneg;
+    p.n_soc = K->n_soc; p.n_psd = K->n_psd; p.n_exp = K->n_exp;
+    int *d_soc_row, *d_soc_dim, *d_psd_row, *d_psd_k;
+    long long *d_psd_off;
+    double *soc_par, *exp_J, *pool;
+    ALLOC(d_soc_row, K->n_soc); ALLOC(d_soc_dim, K->n_soc); ALLOC(soc_par, 4LL * K->n_soc);
+    ALLOC(d_psd_row, K->n_psd); ALLOC(d_psd_k, K->n_psd); ALLOC(d_psd_off, K->n_psd); ALLOC(pool, off);
+    ALLOC(exp_J, 9LL * K->n_exp);
+    if (K->n_soc) {
+        HIPCHK(hipMemcpy(d_soc_row, soc_row.data(), sizeof(int) * K->n_soc, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(d_soc_dim, soc_dim.data(), sizeof(int) * K->n_soc, hipMemcpyHostToDevice));
+    }
+    if (K->n_psd) {
+        HIPCHK(hipMemcpy(d_psd_row, psd_row.data(), sizeof(int) * K->n_psd, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(d_psd_k, psd_k.data(), sizeof(int) * K->n_psd, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(d_psd_off, psd_off.data(), sizeof(long long) * K->n_psd, hipMemcpyHostToDevice));
+    }
+    p.soc_row = d_soc_row; p.soc_dim = d_soc_dim; p.soc_par = soc_par;
+    p.psd_row = d_psd_row; p.psd_k = d_psd_k; p.psd_off = d_psd_off; p.psd_pool = pool;
+    p.exp_J = exp_J; p.jdiag = h->jdiag;
+    ConeGrid &cg = h->cg;
+    cg.nE = n + p.n_diag + 1;
+    cg.bE = div_up(cg.nE, kBlock);
+    cg.bS = div_up(K->n_soc, kBlock);
+    cg.bX = div_up(K->n_exp, kBlock);
+    cg.bP = K->n_psd;
+    h->lds = kmax ? (3 * kmax * (kmax | 1) + kmax * (kmax + 1) / 2) * (int)sizeof(double) : 0;
+    h->nblk_max = std::max({cg.total(), rg.total(), div_up(N, kBlock), 1});
+    ALLOC(h->partials, 3LL * h->nblk_max);
+    // --- validation on the device -----------------------------------------------------------
+    qcpd_status rc = scan_finite(h, {Pv, Av, dq_, db_, dx_, dy_, ds_},
+                                 {P->nnz, A->nnz, n, m, n, m, m});
+    if (rc != QCPD_OK) return rc;
+    HIPCHK(hipMemsetAsync(h->flag, 0, sizeof(int), st));
+    launch_check_csr(Prp, Pci, n, n, P->nnz, h->flag, st);
+    launch_check_csr(Arp, Aci, m, n, A->nnz, h->flag, st);
+    HIPCHK(hipMemcpyAsync(h->host_flag, h->flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (*h->host_flag) return QCPD_ERR_INVALID_ARG;
+    // A' with its slot map
+    HIPCHK(csr_transpose(m, n, A->nnz, Arp, Aci, Av, Trp, Tci, Tv, Tperm, st));
+    p.Trp = Trp; p.Tci = Tci; p.Tv = Tv; p.Tperm = Tperm;
+    if (h->opts.check_symmetry) {
+        int *Srp, *Sci, *Sperm;
+        double *Sv;
+        ALLOC(Srp, n + 1); ALLOC(Sci, P->nnz); ALLOC(Sv, P->nnz); ALLOC(Sperm, P->nnz);
+        HIPCHK(hipMemsetAsync(h->flag, 0, sizeof(int), st));
+        launch_check_sorted(Prp, Pci, n, n, h->flag, st);
+        HIPCHK(hipMemcpyAsync(h->host_flag, h->flag, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (*h->host_flag) return QCPD_ERR_PATTERN;
+        HIPCHK(csr_transpose(n, n, P->nnz, Prp, Pci, Pv, Srp, Sci, Sv, Sperm, st));
+        launch_check_symmetric(Prp, Pci, Pv, Srp, Sci, Sv, n, P->nnz, h->flag, st);
+        HIPCHK(hipMemcpyAsync(h->host_flag, h->flag, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (*h->host_flag) return QCPD_ERR_PATTERN;
+    }
+    // --- Px, c, x'Px, z_y -------------------------------------------------------------------
+    RowGrid pg = rg;
+    pg.by = 0;
+    launch_px(p, pg, c, xpx, h->partials, h->counter, st);
+    launch_sub(dy_, ds_, zy, m, st);
+    double host_xpx = 0.0;
+    HIPCHK(hipMemcpyAsync(&h->host_st->tau_rhs, xpx, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    host_xpx = h->host_st->tau_rhs;
+    p.xPx = host_xpx;
+    // --- cone factors -------------------------------------------------------------------------
+    HIPCHK(hipMemsetAsync(h->flag, 0, 4 * sizeof(int), st));
+    ConeHost ch{K->n_zero};
+    launch_cone_factors(p, ch, h->jdiag, soc_par, exp_J, pool, h->flag + 1, h->flag + 2,
+                        psd_factor_lds_bytes(kmax), st);
+    launch_scales(p, rg, h->scale[0], h->scale[1], h->partials, h->counter, st);
+    HIPCHK(hipMemcpyAsync(h->host_flag, h->flag, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipGetLastError());
+    if (h->host_flag[2]) return QCPD_ERR_CONE;  // projection root-find or eigensolver failed
+    if (h->lds > 0) set_cone_kernel_lds(h->lds);
+    h->create_flags = h->host_flag[1] ? 2u : 0u;
+    return h->host_flag[1] ? QCPD_WARN_NONDIFF : QCPD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void qcpd_opts_default(qcpd_opts *o) {
+    if (!o) return;
+    o->tol = 1e-8;
+    o->max_iter = 0;
+    o->precond = QCPD_PRECOND_JACOBI;
+    o->graph_chunk = 32;
+    o->check_symmetry = 1;
+}
+
+const char *qcpd_status_str(qcpd_status s) {
+    switch (s) {
+    case QCPD_OK: return "ok";
+    case QCPD_WARN_NOT_CONVERGED: return "warning: LSQR did not reach the tolerance";
+    case QCPD_WARN_NONDIFF: return "warning: a cone block is within 1e-10 of a non-differentiable point";
+    case QCPD_ERR_INVALID_ARG: return "error: invalid argument";
+    case QCPD_ERR_DIM: return "error: inconsistent dimensions";
+    case QCPD_ERR_CONE: return "error: bad cone specification or cone factorisation failed";
+    case QCPD_ERR_PATTERN: return "error: P is not symmetric or its column indices are not sorted";
+    case QCPD_ERR_NAN: return "error: NaN or Inf in an input";
+    case QCPD_ERR_HIP: return "error: HIP runtime failure";
+    case QCPD_ERR_OOM: return "error: device allocation failed";
+    default: return "unknown status";
+    }
+}
+
+qcpd_status qcpd_create(qcpd_handle **out, const qcpd_csr *P, const qcpd_csr *A, const double *q,
+                        const double *b, const qcpd_cones *K, const double *x, const double *y,
+                        const double *s, const qcpd_opts *opts, void *stream) {
+    if (!out) return QCPD_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!P || !A || !K || !P->rowptr || !A->rowptr) return QCPD_ERR_INVALID_ARG;
+    const int n = P->nrows, m = A->nrows;
+    if (n < 1 || m < 0 || P->nnz < 0 || A->nnz < 0) return QCPD_ERR_INVALID_ARG;
+    if (P->ncols != n || A->ncols != n) return QCPD_ERR_DIM;
+    if ((P->nnz > 0 && (!P->colind || !P->val)) || (A->nnz > 0 && (!A->colind || !A->val)))
+        return QCPD_ERR_INVALID_ARG;
+    if (!q || !x || (m > 0 && (!b || !y || !s))) return QCPD_ERR_INVALID_ARG;
+    if (K->n_zero < 0 || K->n_nonneg < 0 || K->n_soc < 0 || K->n_psd < 0 || K->n_exp < 0)
+        return QCPD_ERR_CONE;
+    if ((K->n_soc > 0 && !K->soc_dims) || (K->n_psd > 0 && !K->psd_orders)) return QCPD_ERR_CONE;
+    long long rows = (long long)K->n_zero + K->n_nonneg + 3LL * K->n_exp;
+    for (int i = 0; i < K->n_soc; ++i) {
+        if (K->soc_dims[i] < 1) return QCPD_ERR_CONE;
+        rows += K->soc_dims[i];
+    }
+    for (int i = 0; i < K->n_psd; ++i) {
+        const int k = K->psd_orders[i];
+        if (k < 1 || k > kMaxPsd) return QCPD_ERR_CONE;
+        rows += (long long)k * (k + 1) / 2;
+    }
+    if (rows != m) return QCPD_ERR_CONE;
+    qcpd_opts o;
+    qcpd_opts_default(&o);
+    if (opts) o = *opts;
+    if (check_opts(&o) != QCPD_OK) return QCPD_ERR_INVALID_ARG;
+
+    qcpd_handle *h = new (std::nothrow) qcpd_handle();
+    if (!h) return QCPD_ERR_OOM;
+    h->opts = o;
+    h->stream = static_cast<hipStream_t>(stream);
+    if (hipGetDevice(&h->device) != hipSuccess ||
+        hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking) != hipSuccess ||
+        hipHostMalloc((void **)&h->host_st, sizeof(LsqrState), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&h->host_flag, 4 * sizeof(int), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(&h->host_seg, kMaxSeg * 16, hipHostMallocDefault) != hipSuccess ||
+        hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess) {
+        free_handle(h);
+        return QCPD_ERR_HIP;
+    }
+    memset(h->host_st, 0, sizeof(LsqrState));
+    qcpd_status rc = create_impl(h, P, A, q, b, K, x, y, s);
+    if (rc < 0) {
+        hipStreamSynchronize(h->stream);
+        free_handle(h);
+        return rc;
+    }
+    *out = h;
+    return rc;
+}
+
+qcpd_status qcpd_set_opts(qcpd_handle *h, const qcpd_opts *opts) {
+    if (!h || !opts || check_opts(opts) != QCPD_OK) return QCPD_ERR_INVALID_ARG;
+    h->opts = *opts;
+    return QCPD_OK;
+}
+
+qcpd_status qcpd_set_precond(qcpd_handle *h, const double *d_jvp, const double *d_vjp) {
+    if (!h || !d_jvp || !d_vjp) return QCPD_ERR_INVALID_ARG;
+    for (int d = 0; d < 2; ++d) {
+        if (!h->custom[d]) {
+            qcpd_status rc = dalloc(h, &h->custom[d], (size_t)h->p.N);
+            if (rc != QCPD_OK) return rc;
+        }
+        HIPCHK(hipMemcpyAsync(h->custom[d], d == 0 ? d_jvp : d_vjp, sizeof(double) * h->p.N,
+                              hipMemcpyDeviceToDevice, h->stream));
+    }
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return QCPD_OK;
+}
+
+qcpd_status qcpd_get_diagnostics(qcpd_handle *h, double *d_jvp, double *d_vjp, double *jdiag) {
+    if (!h) return QCPD_ERR_INVALID_ARG;
+    const size_t N = h->p.N, m = h->p.m;
+    if (d_jvp) HIPCHK(hipMemcpyAsync(d_jvp, h->scale[0], N * 8, hipMemcpyDeviceToDevice, h->stream));
+    if (d_vjp) HIPCHK(hipMemcpyAsync(d_vjp, h->scale[1], N * 8, hipMemcpyDeviceToDevice, h->stream));
+    if (jdiag && m) HIPCHK(hipMemcpyAsync(jdiag, h->jdiag, m * 8, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return QCPD_OK;
+}
+
+qcpd_status qcpd_jvp(qcpd_handle *h, const double *dP, const double *dA, const double *dq,
+                     const double *db, double *dx, double *dy, double *ds, qcpd_info *info) {
+    if (!h) return QCPD_ERR_INVALID_ARG;
+    const Problem &p = h->p;
+    if ((p.nnzP && !dP) || (p.nnzA && !dA) || !dq || !dx || (p.m && (!db || !dy || !ds)))
+        return QCPD_ERR_INVALID_ARG;
+    hipStream_t s = h->stream;
+    HIPCHK(hipEventRecord(h->ev0, s));
+    qcpd_status rc = scan_finite(h, {dP, dA, dq, db}, {p.nnzP, p.nnzA, p.n, p.m});
+    if (rc != QCPD_OK) return rc;
+    const double *sc = active_scale(h, 0);
+    launch_state_init(h->st, h->opts.tol, max_iter_of(h), s);
+    launch_fill(h->xk, p.N, 0.0, s);
+    launch_fill(h->wk, p.N, 0.0, s);
+    StepArgs r = base_args(h, sc);
+    r.out = h->u;
+    launch_jvp_rhs(p, r, h->rg, dP, dA, dq, db, s);
+    rc = run_lsqr(h, 0, sc);
+    if (rc != QCPD_OK) return rc;
+    // explicit residual ||F dz + d|| with dz = sol, then (dx, dy, ds) = D phi dz
+    StepArgs pre = base_args(h, sc);
+    pre.in = h->sol;
+    launch_cone_pre(p, pre, h->cg, h->lds, s);
+    StepArgs res = base_args(h, sc);
+    res.in = h->sol; res.in_nrm = NRM_ONE; res.out = h->scratch; res.role = ROLE_RESID;
+    launch_rows_F(p, res, h->rg, s);
+    launch_jvp_out(p, h->sol, h->wy, dx, dy, ds, s);
+    HIPCHK(hipEventRecord(h->ev1, s));
+    HIPCHK(hipMemcpyAsync(h->host_st, h->st, sizeof(LsqrState), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipGetLastError());
+    fill_info(h, info);
+    return h->host_st->conv ? QCPD_OK : QCPD_WARN_NOT_CONVERGED;
+}
+
+qcpd_status qcpd_vjp(qcpd_handle *h, const double *gx, const double *gy, const double *gs,
+                     double *dP, double *dA, double *dq, double *db, qcpd_info *info) {
+    if (!h) return QCPD_ERR_INVALID_ARG;
+    const Problem &p = h->p;
+    if (!gx || !dq || (p.m && (!gy || !gs || !db)) || (p.nnzP && !dP) || (p.nnzA && !dA))
+        return QCPD_ERR_INVALID_ARG;
+    hipStream_t s = h->stream;
+    HIPCHK(hipEventRecord(h->ev0, s));
+    qcpd_status rc = scan_finite(h, {gx, gy, gs}, {p.n, p.m, p.m});
+    if (rc != QCPD_OK) return rc;
+    const double *sc = active_scale(h, 1);
+    launch_state_init(h->st, h->opts.tol, max_iter_of(h), s);
+    launch_fill(h->xk, p.N, 0.0, s);
+    launch_fill(h->wk, p.N, 0.0, s);
+    StepArgs r = base_args(h, sc);
+    r.out = h->u;
+    launch_vjp_rhs(p, r, h->cg, h->lds, gx, gy, gs, s);
+    rc = run_lsqr(h, 1, sc);
+    if (rc != QCPD_OK) return rc;
+    // explicit residual ||F'w + dz|| with w = sol, then dtheta = D_theta N'[w]
+    StepArgs t1 = base_args(h, sc);
+    t1.in = h->sol; t1.in_nrm = NRM_ONE;
+    launch_rows_FT(p, t1, h->rg, s);
+    StepArgs t2 = t1;
+    t2.out = h->scratch; t2.role = ROLE_RESID;
+    launch_cone_FT(p, t2, h->cg, h->lds, s);
+    launch_vjp_out(p, h->rg, h->sol, dP, dA, dq, db, s);
+    HIPCHK(hipEventRecord(h->ev1, s));
+    HIPCHK(hipMemcpyAsync(h->host_st, h->st, sizeof(LsqrState), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipGetLastError());
+    fill_info(h, info);
+    return h->host_st->conv ? QCPD_OK : QCPD_WARN_NOT_CONVERGED;
+}
+
+qcpd_status qcpd_profile_kernels(qcpd_handle *h, int32_t reps, float *ms_out) {
+    if (!h || reps < 1 || !ms_out) return QCPD_ERR_INVALID_ARG;
+    hipStream_t s = h->stream;
+    const double *sc = active_scale(h, 0);
+    // plain products on the current vectors; the state keeps finite normalisers
+    launch_state_init(h->st, h->opts.tol, max_iter_of(h), s);
+    StepArgs a = base_args(h, sc);
+    StepArgs f = a;
+    f.in = h->v; f.in_is_v = 1; f.out = h->scratch;
+    StepArgs t1 = a;
+    t1.in = h->u;
+    StepArgs t2 = t1;
+    t2.out = h->scratch; t2.do_pre = 1; t2.out_is_v = 1;
+    for (int kid = 0; kid < 3; ++kid) {
+        auto launch = [&]() {
+            if (kid == 0) launch_rows_F(h->p, f, h->rg, s);
+            else if (kid == 1) launch_rows_FT(h->p, t1, h->rg, s);
+            else launch_cone_FT(h->p, t2, h->cg, h->lds, s);
+        };
+        launch();  // warm
+        HIPCHK(hipEventRecord(h->ev0, s));
+        for (int r = 0; r < reps; ++r) launch();
+        HIPCHK(hipEventRecord(h->ev1, s));
+        HIPCHK(hipEventSynchronize(h->ev1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+        ms_out[kid] = ms / reps;
+    }
+    HIPCHK(hipGetLastError());
+    return QCPD_OK;
+}
+
+void qcpd_destroy(qcpd_handle *h) {
+    if (!h) return;
+    hipStreamSynchronize(h->stream);
+    free_handle(h);
+}
+
+}  // extern "C"

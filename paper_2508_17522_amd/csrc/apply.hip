@@ -1,0 +1,747 @@
+// Hot-path kernels of the derivative evaluation: the products with F and F' that LSQR
+// needs (Sec. 3.1 / 3.2), the cone Jacobian-vector products (Appendix A), and the maps
+// into and out of the least-squares problems.
+//
+// F = D_u Q(Pi z) DPi(z) - DPi(z) + I at z_N = 1 (Sec. 2.4), with
+//   D_u Q w = (P w_x + A' w_y + q w_N,  -A w_x + b w_N,  c'w_x - b'w_y + x'Px w_N),
+//   c = -2Px - q,  DPi = blockdiag(I_n, J, 1),  J = DPi_{K*}(z_y).
+// So F v = (P v_x + A'(J v_y) + q v_N,
+//           -A v_x + b v_N - J v_y + v_y,
+//           c'v_x - b'(J v_y) + x'Px v_N)
+// and  F'r = (P r_x - A'r_y + c r_N,
+//             J(A r_x - b r_N - r_y) + r_y,
+//             q'r_x + b'r_y + x'Px r_N).
+//
+// One LSQR iteration is three launches:
+//   rows_F  : CSR rows of P and A' (x rows), A (y rows), the tau row   -> product with F
+//   rows_FT : CSR rows of P and A' (x rows), A (y rows)                -> staged in tmp
+//   cone_FT : per cone block J(tmp_y) + r_y, the tau entry             -> product with F'
+// The J needed by the next product with F is applied inside cone_FT (block-local), and the
+// tau-row dot products of each product are accumulated by the kernel that produces its
+// input, so no launch waits on a reduction of its own.
+#include <algorithm>
+
+#include "qcpd_internal.h"
+
+namespace qcpd {
+
+constexpr double kSqrt2 = 1.41421356237309504880;
+constexpr double kRsqrt2 = 0.70710678118654752440;
+
+// ---------------------------------------------------------------------------------------
+// cone Jacobian-vector products, J = DPi_{K*}(z_y) per block
+// ---------------------------------------------------------------------------------------
+
+// Second-order cone (self-dual), one thread per cone. par = (mode, 1/||u||, c1, c2):
+// mode 0: J = 0; mode 1: J = I; mode 2 (||u|| > |t|):
+//   J(dt, du) = (1/2 (dt + uh'du),  1/2 uh dt + c1 du - c2 (uh'du) uh),
+//   uh = u/||u||, c1 = (t + ||u||)/(2||u||), c2 = t/(2||u||).
+template <class IN, class OUT>
+__device__ inline void soc_jv(const Problem &p, int cone, IN in, OUT out) {
+    const int r0 = p.soc_row[cone], k = p.soc_dim[cone];
+    const double *par = p.soc_par + 4 * cone;
+    const int mode = (int)par[0];
+    if (mode == 0) {
+        for (int i = 0; i < k; ++i) out(r0 + i, 0.0);
+        return;
+    }
+    if (mode == 1) {
+        for (int i = 0; i < k; ++i) out(r0 + i, in(r0 + i));
+        return;
+    }
+    const double inv_nu = par[1], c1 = par[2], c2 = par[3];
+    const double *u = p.zy + r0 + 1;
+    const double dt = in(r0);
+    double a = 0.0;
+    for (int i = 1; i < k; ++i) a += u[i - 1] * inv_nu * in(r0 + i);
+    out(r0, 0.5 * (dt + a));
+    for (int i = 1; i < k; ++i) {
+        const double uh = u[i - 1] * inv_nu;
+        out(r0 + i, 0.5 * uh * dt + c1 * in(r0 + i) - c2 * a * uh);
+    }
+}
+
+// Dual exponential cone, one thread per cone: a stored 3x3 matrix (I - DPi_exp(-z)).
+template <class IN, class OUT>
+__device__ inline void exp_jv(const Problem &p, int cone, IN in, OUT out) {
+    const int r0 = p.exp_row0 + 3 * cone;
+    const double *J = p.exp_J + 9 * cone;
+    const double a = in(r0), b = in(r0 + 1), c = in(r0 + 2);
+    out(r0, J[0] * a + J[1] * b + J[2] * c);
+    out(r0 + 1, J[3] * a + J[4] * b + J[5] * c);
+    out(r0 + 2, J[6] * a + J[7] * b + J[8] * c);
+}
+
+__device__ inline int svec_index(int i, int j, int k) {  // i >= j
+    return j * k - (j * (j - 1)) / 2 + (i - j);
+}
+
+// PSD cone on svec coordinates, one workgroup per cone:
+//   J[dZ] = V (B o (V' dZ V)) V'.
+// LDS: X, T, V as k x ld matrices (ld = k | 1, odd, to spread LDS banks).
+template <class IN, class OUT>
+__device__ inline void psd_jv(const Problem &p, int cone, double *sm, IN in, OUT out) {
+    const int k = p.psd_k[cone], r0 = p.psd_row[cone];
+    const int ld = k | 1, kk = k * k;
+    const double *Vg = p.psd_pool + p.psd_off[cone];
+    const double *Bg = Vg + kk;
+    double *X = sm, *T = sm + k * ld, *V = sm + 2 * k * ld;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < kk; e += kBlock) {
+        const int i = e / k, j = e - (e / k) * k;
+        V[i * ld + j] = Vg[e];
+        if (i >= j) {
+            double v = in(r0 + svec_index(i, j, k));
+            if (i == j) {
+                X[i * ld + i] = v;
+            } else {
+                v *= kRsqrt2;
+                X[i * ld + j] = v;
+                X[j * ld + i] = v;
+            }
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < kk; e += kBlock) {  // T = X V
+        const int i = e / k, j = e - (e / k) * k;
+        double acc = 0.0;
+        for (int l = 0; l < k; ++l) acc += X[i * ld + l] * V[l * ld + j];
+        T[i * ld + j] = acc;
+    }
+    __syncthreads();
+    for (int e = tid; e < kk; e += kBlock) {  // X = B o (V' T)
+        const int i = e / k, j = e - (e / k) * k;
+        double acc = 0.0;
+        for (int l = 0; l < k; ++l) acc += V[l * ld + i] * T[l * ld + j];
+        X[i * ld + j] = Bg[e] * acc;
+    }
+    __syncthreads();
+    for (int e = tid; e < kk; e += kBlock) {  // T = V X
+        const int i = e / k, j = e - (e / k) * k;
+        double acc = 0.0;
+        for (int l = 0; l < k; ++l) acc += V[i * ld + l] * X[l * ld + j];
+        T[i * ld + j] = acc;
+    }
+    __syncthreads();
+    for (int e = tid; e < kk; e += kBlock) {  // Y = T V', lower triangle into svec
+        const int i = e / k, j = e - (e / k) * k;
+        if (i >= j) {
+            double acc = 0.0;
+            for (int l = 0; l < k; ++l) acc += T[i * ld + l] * V[j * ld + l];
+            out(r0 + svec_index(i, j, k), i == j ? acc : acc * kSqrt2);
+        }
+    }
+    __syncthreads();
+}
+
+__device__ inline int psd_stage_offset(int k) { return 3 * k * (k | 1); }
+
+// ---------------------------------------------------------------------------------------
+// LSQR bookkeeping
+// ---------------------------------------------------------------------------------------
+
+__device__ inline void finalize(LsqrState *st, int role, const double tot[3], bool dot_is_fwd) {
+    switch (role) {
+    case ROLE_U: {
+        const double beta = sqrt(tot[0]);
+        st->beta = beta;
+        st->pending = 0;
+        if (dot_is_fwd) st->dot_fwd = tot[1]; else st->dot_adj = tot[1];
+        if (!(beta > 0.0)) { st->done = 1; st->conv = 1; }
+        break;
+    }
+    case ROLE_V0: {
+        const double alpha = sqrt(tot[0]);
+        st->alpha = alpha;
+        st->rhobar = alpha;
+        st->phibar = st->beta1;
+        st->phr = 0.0;
+        st->thr = 0.0;
+        st->pending = 0;
+        if (dot_is_fwd) st->dot_fwd = tot[1]; else st->dot_adj = tot[1];
+        if (!(alpha > 0.0)) { st->done = 1; st->conv = 1; }
+        break;
+    }
+    case ROLE_V: {
+        // plane rotation that eliminates beta (Paige & Saunders), then the x/w update is
+        // owed to the next iteration's first kernel (or the final flush)
+        const double alpha = sqrt(tot[0]);
+        const double beta = st->beta, rhobar = st->rhobar;
+        const double rho = hypot(rhobar, beta);
+        if (!(rho > 0.0)) { st->done = 1; st->conv = 1; st->pending = 0; break; }
+        const double c = rhobar / rho, s = beta / rho;
+        const double theta = s * alpha;
+        const double phi = c * st->phibar;
+        st->rhobar = -c * alpha;
+        st->phibar = s * st->phibar;
+        st->phr = phi / rho;
+        st->thr = theta / rho;
+        st->pending = 1;
+        st->iters += 1;
+        st->alpha = alpha;
+        if (dot_is_fwd) st->dot_fwd = tot[1]; else st->dot_adj = tot[1];
+        if (st->phibar <= st->tol * st->beta1 || !(alpha > 0.0)) {
+            st->done = 1;
+            st->conv = 1;
+        } else if (st->iters >= st->max_iter) {
+            st->done = 1;
+        }
+        break;
+    }
+    case ROLE_RESID:
+        st->resid = sqrt(tot[0]);
+        break;
+    default:
+        if (dot_is_fwd) st->dot_fwd = tot[1]; else st->dot_adj = tot[1];
+        break;
+    }
+}
+
+struct Ctx {  // per-launch scalars every thread derives from the state block
+    double inv, cU, cV, inv_alpha_up, phr, thr, in_N;
+    bool in_sc, out_sc;
+};
+
+__device__ inline Ctx make_ctx(const Problem &p, const StepArgs &a) {
+    const LsqrState *st = a.st;
+    const double *sv = reinterpret_cast<const double *>(st);
+    Ctx c;
+    c.inv = 1.0 / sv[a.in_nrm];
+    c.cU = (a.role == ROLE_U) ? st->alpha / st->beta : 0.0;
+    c.cV = (a.role == ROLE_V) ? st->beta / st->alpha : 0.0;
+    c.inv_alpha_up = a.do_update ? 1.0 / st->alpha : 0.0;
+    c.phr = st->phr;
+    c.thr = st->thr;
+    c.in_sc = a.in_is_v && a.sc != nullptr;
+    c.out_sc = a.out_is_v && a.sc != nullptr;
+    const int N1 = p.N - 1;
+    c.in_N = a.in[N1] * c.inv * (c.in_sc ? a.sc[N1] : 1.0);
+    return c;
+}
+
+__device__ inline double ldin(const StepArgs &a, const Ctx &c, int i) {
+    const double v = a.in[i] * c.inv;
+    return c.in_sc ? v * a.sc[i] : v;
+}
+
+__device__ inline double role_value(const StepArgs &a, const Ctx &c, int idx, double val) {
+    switch (a.role) {
+    case ROLE_U: return val - c.cU * a.out[idx];
+    case ROLE_V: return (c.out_sc ? a.sc[idx] : 1.0) * val - c.cV * a.out[idx];
+    case ROLE_V0: return (c.out_sc ? a.sc[idx] : 1.0) * val;
+    case ROLE_RESID: return val - a.rhs[idx];
+    default: return val;
+    }
+}
+
+__device__ inline void lsqr_update(const StepArgs &a, const Ctx &c, int idx) {
+    const double w = a.wk[idx];
+    a.xk[idx] += c.phr * w;
+    a.wk[idx] = a.in[idx] * c.inv_alpha_up - c.thr * w;
+}
+
+__device__ inline double group_sum(double v, int L) {
+    for (int off = L >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// ---------------------------------------------------------------------------------------
+// product with F: CSR rows
+// ---------------------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_rows_F(Problem p, StepArgs a, RowGrid g) {
+    LsqrState *st = a.st;
+    if (a.check_done && st->done) return;
+    const Ctx c = make_ctx(p, a);
+    const int n = p.n, m = p.m, N = p.N;
+    const int tid = threadIdx.x;
+    const bool xr = blockIdx.x < (unsigned)g.bx;
+    const int L = xr ? g.lx : g.ly;
+    const long long gt = (long long)(xr ? blockIdx.x : blockIdx.x - g.bx) * kBlock + tid;
+    const int row = (int)(gt / L), lane = (int)(gt & (L - 1));
+    double acc = 0.0, accT = 0.0;
+    int idx = -1;
+    if (xr) {
+        if (row < n) {
+            for (int k = p.Prp[row] + lane; k < p.Prp[row + 1]; k += L)
+                acc += p.Pv[k] * ldin(a, c, p.Pci[k]);
+            for (int t = p.Trp[row] + lane; t < p.Trp[row + 1]; t += L)
+                accT += p.Tv[t] * a.wy[p.Tci[t]];
+            idx = row;
+        }
+    } else {
+        if (row < m) {
+            for (int k = p.Arp[row] + lane; k < p.Arp[row + 1]; k += L)
+                acc += p.Av[k] * ldin(a, c, p.Aci[k]);
+            idx = n + row;
+        } else if (row == m) {
+            idx = N - 1;
+        }
+    }
+    acc = group_sum(acc, L);
+    accT = group_sum(accT, L);
+    double s0 = 0.0, s1 = 0.0;
+    if (lane == 0 && idx >= 0) {
+        double val;
+        if (idx < n) {
+            val = acc + accT * c.inv + p.q[idx] * c.in_N;
+        } else if (idx < N - 1) {
+            const int r = idx - n;
+            val = -acc + p.b[r] * c.in_N - a.wy[r] * c.inv + ldin(a, c, idx);
+        } else {
+            val = st->dot_fwd * c.inv + p.xPx * c.in_N;
+        }
+        const double o = role_value(a, c, idx, val);
+        a.out[idx] = o;
+        s0 = o * o;
+        const double nsc = c.out_sc ? a.sc[idx] : 1.0;
+        if (idx < n) s1 = p.q[idx] * nsc * o;
+        else if (idx < N - 1) s1 = p.b[idx - n] * nsc * o;
+        if (a.do_update) lsqr_update(a, c, idx);
+    }
+    double tot[3];
+    if (last_block_sum3(s0, s1, 0.0, a.partials, a.counter, gridDim.x, tot) && tid == 0)
+        finalize(st, a.role, tot, false);
+}
+
+// ---------------------------------------------------------------------------------------
+// product with F': CSR rows, staged in tmp (x rows final, y rows before J)
+// ---------------------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_rows_FT(Problem p, StepArgs a, RowGrid g) {
+    LsqrState *st = a.st;
+    if (a.check_done && st->done) return;
+    const Ctx c = make_ctx(p, a);
+    const int n = p.n, m = p.m, N = p.N;
+    const int tid = threadIdx.x;
+    const bool xr = blockIdx.x < (unsigned)g.bx;
+    const int L = xr ? g.lx : g.ly;
+    const long long gt = (long long)(xr ? blockIdx.x : blockIdx.x - g.bx) * kBlock + tid;
+    const int row = (int)(gt / L), lane = (int)(gt & (L - 1));
+    double acc = 0.0, accT = 0.0;
+    int idx = -1;
+    if (xr) {
+        if (row < n) {
+            for (int k = p.Prp[row] + lane; k < p.Prp[row + 1]; k += L)
+                acc += p.Pv[k] * ldin(a, c, p.Pci[k]);
+            for (int t = p.Trp[row] + lane; t < p.Trp[row + 1]; t += L)
+                accT += p.Tv[t] * ldin(a, c, n + p.Tci[t]);
+            idx = row;
+        }
+    } else {
+        if (row < m) {
+            for (int k = p.Arp[row] + lane; k < p.Arp[row + 1]; k += L)
+                acc += p.Av[k] * ldin(a, c, p.Aci[k]);
+            idx = n + row;
+        } else if (row == m) {
+            idx = N - 1;
+        }
+    }
+    acc = group_sum(acc, L);
+    accT = group_sum(accT, L);
+    if (lane == 0 && idx >= 0) {
+        if (idx < n) a.tmp[idx] = acc - accT + p.c[idx] * c.in_N;
+        else if (idx < N - 1) a.tmp[idx] = acc - p.b[idx - n] * c.in_N - ldin(a, c, idx);
+        if (a.do_update) lsqr_update(a, c, idx);
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// product with F': per cone block, plus the J the next product with F needs
+// ---------------------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_cone_FT(Problem p, StepArgs a, ConeGrid g) {
+    extern __shared__ double sm[];
+    LsqrState *st = a.st;
+    if (a.check_done && st->done) return;
+    const Ctx c = make_ctx(p, a);
+    const int n = p.n, N = p.N;
+    const int tid = threadIdx.x;
+    double s0 = 0.0, s1 = 0.0;
+    auto nsc = [&](int idx) { return c.out_sc ? a.sc[idx] : 1.0; };
+    auto finish = [&](int idx, double val) {
+        const double o = role_value(a, c, idx, val);
+        a.out[idx] = o;
+        s0 += o * o;
+        return o;
+    };
+    const int bid = blockIdx.x;
+    if (bid < g.bE) {
+        const int e = bid * kBlock + tid;
+        if (e < g.nE) {
+            const int idx = (e < g.nE - 1) ? e : N - 1;
+            if (idx < n) {
+                const double o = finish(idx, a.tmp[idx]);
+                if (a.do_pre) s1 += p.c[idx] * nsc(idx) * o;
+            } else if (idx < N - 1) {
+                const int r = idx - n;
+                const double o = finish(idx, p.jdiag[r] * a.tmp[idx] + ldin(a, c, idx));
+                if (a.do_pre) {
+                    const double w = p.jdiag[r] * nsc(idx) * o;
+                    a.wy[r] = w;
+                    s1 -= p.b[r] * w;
+                }
+            } else {
+                finish(idx, st->dot_adj * c.inv + p.xPx * c.in_N);
+            }
+        }
+    } else if (bid < g.bE + g.bS) {
+        const int cone = (bid - g.bE) * kBlock + tid;
+        if (cone < p.n_soc) {
+            soc_jv(p, cone, [&](int r) { return a.tmp[n + r]; },
+                   [&](int r, double jt) { finish(n + r, jt + ldin(a, c, n + r)); });
+            if (a.do_pre)
+                soc_jv(p, cone, [&](int r) { return nsc(n + r) * a.out[n + r]; },
+                       [&](int r, double w) { a.wy[r] = w; s1 -= p.b[r] * w; });
+        }
+    } else if (bid < g.bE + g.bS + g.bX) {
+        const int cone = (bid - g.bE - g.bS) * kBlock + tid;
+        if (cone < p.n_exp) {
+            exp_jv(p, cone, [&](int r) { return a.tmp[n + r]; },
+                   [&](int r, double jt) { finish(n + r, jt + ldin(a, c, n + r)); });
+            if (a.do_pre)
+                exp_jv(p, cone, [&](int r) { return nsc(n + r) * a.out[n + r]; },
+                       [&](int r, double w) { a.wy[r] = w; s1 -= p.b[r] * w; });
+        }
+    } else {
+        const int cone = bid - g.bE - g.bS - g.bX;
+        const int r0 = p.psd_row[cone];
+        double *stage = sm + psd_stage_offset(p.psd_k[cone]);
+        psd_jv(p, cone, sm, [&](int r) { return a.tmp[n + r]; },
+               [&](int r, double jt) {
+                   const double o = finish(n + r, jt + ldin(a, c, n + r));
+                   stage[r - r0] = nsc(n + r) * o;
+               });
+        if (a.do_pre)
+            psd_jv(p, cone, sm, [&](int r) { return stage[r - r0]; },
+                   [&](int r, double w) { a.wy[r] = w; s1 -= p.b[r] * w; });
+    }
+    double tot[3];
+    if (last_block_sum3(s0, s1, 0.0, a.partials, a.counter, gridDim.x, tot) && tid == 0)
+        finalize(st, a.role, tot, true);
+}
+
+// wy = J(s o in_y) (raw, no normaliser) and dot_fwd = c'(s o in)_x - b'wy, for a product
+// with F whose input was not produced by cone_FT.
+__global__ __launch_bounds__(kBlock) void k_cone_pre(Problem p, StepArgs a, ConeGrid g) {
+    extern __shared__ double sm[];
+    LsqrState *st = a.st;
+    if (a.check_done && st->done) return;
+    const int n = p.n, N = p.N;
+    const int tid = threadIdx.x;
+    const bool isc = a.in_is_v && a.sc != nullptr;
+    auto ld = [&](int idx) { return isc ? a.sc[idx] * a.in[idx] : a.in[idx]; };
+    double s1 = 0.0;
+    const int bid = blockIdx.x;
+    if (bid < g.bE) {
+        const int e = bid * kBlock + tid;
+        if (e < g.nE - 1) {
+            if (e < n) {
+                s1 += p.c[e] * ld(e);
+            } else {
+                const int r = e - n;
+                const double w = p.jdiag[r] * ld(e);
+                a.wy[r] = w;
+                s1 -= p.b[r] * w;
+            }
+        }
+    } else if (bid < g.bE + g.bS) {
+        const int cone = (bid - g.bE) * kBlock + tid;
+        if (cone < p.n_soc)
+            soc_jv(p, cone, [&](int r) { return ld(n + r); },
+                   [&](int r, double w) { a.wy[r] = w; s1 -= p.b[r] * w; });
+    } else if (bid < g.bE + g.bS + g.bX) {
+        const int cone = (bid - g.bE - g.bS) * kBlock + tid;
+        if (cone < p.n_exp)
+            exp_jv(p, cone, [&](int r) { return ld(n + r); },
+                   [&](int r, double w) { a.wy[r] = w; s1 -= p.b[r] * w; });
+    } else {
+        const int cone = bid - g.bE - g.bS - g.bX;
+        psd_jv(p, cone, sm, [&](int r) { return ld(n + r); },
+               [&](int r, double w) { a.wy[r] = w; s1 -= p.b[r] * w; });
+    }
+    (void)N;
+    double tot[3];
+    if (last_block_sum3(0.0, s1, 0.0, a.partials, a.counter, gridDim.x, tot) && tid == 0)
+        st->dot_fwd = tot[1];
+}
+
+// ---------------------------------------------------------------------------------------
+// LSQR start / finish
+// ---------------------------------------------------------------------------------------
+
+__global__ void k_state_init(LsqrState *st, double tol, int max_iter) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        LsqrState s = {};
+        s.one = 1.0;
+        s.tol = tol;
+        s.max_iter = max_iter;
+        *st = s;
+    }
+}
+
+__global__ void k_fill(double *p, long long n, double v) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// Apply the owed x update, map the LSQR iterate back through the diagonal scale
+// (sol = sc o x), and accumulate q'sol_x + b'sol_y for a following product with F'.
+__global__ __launch_bounds__(kBlock) void k_flush(Problem p, StepArgs a, double *sol) {
+    LsqrState *st = a.st;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const bool pend = st->pending != 0;
+    const double phr = st->phr;
+    double s1 = 0.0;
+    if (i < p.N) {
+        double x = a.xk[i];
+        if (pend) x += phr * a.wk[i];
+        a.xk[i] = x;
+        const double v = a.sc ? a.sc[i] * x : x;
+        sol[i] = v;
+        if (i < p.n) s1 = p.q[i] * v;
+        else if (i < p.N - 1) s1 = p.b[i - p.n] * v;
+    }
+    double tot[3];
+    if (last_block_sum3(0.0, s1, 0.0, a.partials, a.counter, gridDim.x, tot) && threadIdx.x == 0) {
+        st->pending = 0;
+        st->dot_adj = tot[1];
+    }
+}
+
+// JVP right-hand side (Sec. 2.4, D_theta N at z_N = 1, Pi z = (x, y, 1)):
+//   d = (dP x + dA'y + dq,  -dA x + db,  -x'dP x - dq'x - db'y);
+// LSQR starts from u~ = -d (also kept in rhs for the explicit residual).
+__global__ __launch_bounds__(kBlock) void k_jvp_rhs(Problem p, StepArgs a, RowGrid g,
+                                                    const double *dP, const double *dA,
+                                                    const double *dq, const double *db) {
+    LsqrState *st = a.st;
+    const int n = p.n, m = p.m, N = p.N;
+    const int tid = threadIdx.x;
+    const bool xr = blockIdx.x < (unsigned)g.bx;
+    const int L = xr ? g.lx : g.ly;
+    const long long gt = (long long)(xr ? blockIdx.x : blockIdx.x - g.bx) * kBlock + tid;
+    const int row = (int)(gt / L), lane = (int)(gt & (L - 1));
+    double acc = 0.0, accT = 0.0;
+    int idx = -1;
+    if (xr) {
+        if (row < n) {
+            for (int k = p.Prp[row] + lane; k < p.Prp[row + 1]; k += L) acc += dP[k] * p.x[p.Pci[k]];
+            for (int t = p.Trp[row] + lane; t < p.Trp[row + 1]; t += L)
+                accT += dA[p.Tperm[t]] * p.y[p.Tci[t]];
+            idx = row;
+        }
+    } else if (row < m) {
+        for (int k = p.Arp[row] + lane; k < p.Arp[row + 1]; k += L) acc += dA[k] * p.x[p.Aci[k]];
+        idx = n + row;
+    }
+    acc = group_sum(acc, L);
+    accT = group_sum(accT, L);
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    if (lane == 0 && idx >= 0) {
+        double o;
+        if (idx < n) {
+            o = -(acc + accT + dq[idx]);
+            s1 = p.q[idx] * o;
+            s2 = p.x[idx] * acc + dq[idx] * p.x[idx];
+        } else {
+            const int r = idx - n;
+            o = -(-acc + db[r]);
+            s1 = p.b[r] * o;
+            s2 = db[r] * p.y[r];
+        }
+        a.out[idx] = o;
+        const_cast<double *>(a.rhs)[idx] = o;
+        s0 = o * o;
+    }
+    double tot[3];
+    if (last_block_sum3(s0, s1, s2, a.partials, a.counter, gridDim.x, tot) && tid == 0) {
+        const double oN = tot[2];  // -d_N = x'dP x + dq'x + db'y
+        a.out[N - 1] = oN;
+        const_cast<double *>(a.rhs)[N - 1] = oN;
+        const double beta = sqrt(tot[0] + oN * oN);
+        st->beta = beta;
+        st->beta1 = beta;
+        st->phibar = beta;
+        st->dot_adj = tot[1];
+        if (!(beta > 0.0)) { st->done = 1; st->conv = 1; }
+    }
+}
+
+// VJP right-hand side (Sec. 3.2): dz = D phi'(gx, gy, gs)
+//   = (gx, J(gy + gs) - gs, -x'gx - y'gy - s'gs); LSQR starts from u~ = -dz.
+__global__ __launch_bounds__(kBlock) void k_vjp_rhs(Problem p, StepArgs a, ConeGrid g,
+                                                    const double *gx, const double *gy,
+                                                    const double *gs) {
+    extern __shared__ double sm[];
+    LsqrState *st = a.st;
+    const int n = p.n, N = p.N;
+    const int tid = threadIdx.x;
+    double *rhs = const_cast<double *>(a.rhs);
+    double s0 = 0.0, s2 = 0.0;
+    auto put = [&](int idx, double o) {
+        a.out[idx] = o;
+        rhs[idx] = o;
+        s0 += o * o;
+    };
+    auto gsum = [&](int r) { return gy[r] + gs[r]; };
+    auto yout = [&](int r, double jt) {
+        put(n + r, -(jt - gs[r]));
+        s2 += p.y[r] * gy[r] + p.s[r] * gs[r];
+    };
+    const int bid = blockIdx.x;
+    if (bid < g.bE) {
+        const int e = bid * kBlock + tid;
+        if (e < g.nE - 1) {
+            if (e < n) {
+                put(e, -gx[e]);
+                s2 += p.x[e] * gx[e];
+            } else {
+                const int r = e - n;
+                yout(r, p.jdiag[r] * gsum(r));
+            }
+        }
+    } else if (bid < g.bE + g.bS) {
+        const int cone = (bid - g.bE) * kBlock + tid;
+        if (cone < p.n_soc) soc_jv(p, cone, gsum, yout);
+    } else if (bid < g.bE + g.bS + g.bX) {
+        const int cone = (bid - g.bE - g.bS) * kBlock + tid;
+        if (cone < p.n_exp) exp_jv(p, cone, gsum, yout);
+    } else {
+        const int cone = bid - g.bE - g.bS - g.bX;
+        psd_jv(p, cone, sm, gsum, yout);
+    }
+    double tot[3];
+    if (last_block_sum3(s0, 0.0, s2, a.partials, a.counter, gridDim.x, tot) && tid == 0) {
+        const double oN = tot[2];  // -dz_N
+        a.out[N - 1] = oN;
+        rhs[N - 1] = oN;
+        const double beta = sqrt(tot[0] + oN * oN);
+        st->beta = beta;
+        st->beta1 = beta;
+        st->phibar = beta;
+        if (!(beta > 0.0)) { st->done = 1; st->conv = 1; }
+    }
+}
+
+// JVP output (Sec. 3.1): dx = dz_x - dz_N x, dy = J dz_y - dz_N y,
+// ds = J dz_y - dz_y - dz_N s; jdz = J dz_y precomputed.
+__global__ __launch_bounds__(kBlock) void k_jvp_out(Problem p, const double *sol,
+                                                    const double *jdz, double *dx, double *dy,
+                                                    double *ds) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const int n = p.n, m = p.m;
+    const double dzN = sol[p.N - 1];
+    if (i < n) {
+        dx[i] = sol[i] - dzN * p.x[i];
+    } else if (i < n + m) {
+        const int r = i - n;
+        dy[r] = jdz[r] - dzN * p.y[r];
+        ds[r] = jdz[r] - sol[i] - dzN * p.s[r];
+    }
+}
+
+// VJP output (Sec. 3.2, tau = 1), on the stored patterns of P and A:
+//   dP_ij = 1/2 (w_i x_j + x_i w_j) - w_N x_i x_j,  dA_ij = y_i w_j - w_{n+i} x_j,
+//   dq = w_x - w_N x,  db = w_y - w_N y.
+__global__ __launch_bounds__(kBlock) void k_vjp_out(Problem p, RowGrid g, const double *w,
+                                                    double *dP, double *dA, double *dq,
+                                                    double *db) {
+    const int n = p.n, m = p.m;
+    const int tid = threadIdx.x;
+    const bool xr = blockIdx.x < (unsigned)g.bx;
+    const int L = xr ? g.lx : g.ly;
+    const long long gt = (long long)(xr ? blockIdx.x : blockIdx.x - g.bx) * kBlock + tid;
+    const int row = (int)(gt / L), lane = (int)(gt & (L - 1));
+    const double wN = w[p.N - 1];
+    if (xr) {
+        if (row < n) {
+            const double wi = w[row], xi = p.x[row];
+            for (int k = p.Prp[row] + lane; k < p.Prp[row + 1]; k += L) {
+                const int j = p.Pci[k];
+                const double xj = p.x[j];
+                dP[k] = 0.5 * (wi * xj + xi * w[j]) - wN * xi * xj;
+            }
+            if (lane == 0) dq[row] = wi - wN * xi;
+        }
+    } else if (row < m) {
+        const double yi = p.y[row], wyi = w[n + row];
+        for (int k = p.Arp[row] + lane; k < p.Arp[row + 1]; k += L) {
+            const int j = p.Aci[k];
+            dA[k] = yi * w[j] - wyi * p.x[j];
+        }
+        if (lane == 0) db[row] = wyi - wN * yi;
+    }
+}
+
+__global__ void k_nan_scan(const double *const *ptrs, const long long *lens, int nseg,
+                           int *flag) {
+    for (int sgi = 0; sgi < nseg; ++sgi) {
+        const double *ptr = ptrs[sgi];
+        const long long len = lens[sgi];
+        bool bad = false;
+        for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < len;
+             i += (long long)gridDim.x * blockDim.x)
+            if (!isfinite(ptr[i])) bad = true;
+        if (bad) atomicOr(flag, 1);
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------------------
+
+void launch_rows_F(const Problem &p, const StepArgs &a, const RowGrid &g, hipStream_t s) {
+    hipLaunchKernelGGL(k_rows_F, dim3(g.total()), dim3(kBlock), 0, s, p, a, g);
+}
+void launch_rows_FT(const Problem &p, const StepArgs &a, const RowGrid &g, hipStream_t s) {
+    hipLaunchKernelGGL(k_rows_FT, dim3(g.total()), dim3(kBlock), 0, s, p, a, g);
+}
+void launch_cone_FT(const Problem &p, const StepArgs &a, const ConeGrid &g, int lds, hipStream_t s) {
+    hipLaunchKernelGGL(k_cone_FT, dim3(g.total()), dim3(kBlock), lds, s, p, a, g);
+}
+void launch_cone_pre(const Problem &p, const StepArgs &a, const ConeGrid &g, int lds, hipStream_t s) {
+    hipLaunchKernelGGL(k_cone_pre, dim3(g.total()), dim3(kBlock), lds, s, p, a, g);
+}
+void launch_state_init(LsqrState *st, double tol, int max_iter, hipStream_t s) {
+    hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, s, st, tol, max_iter);
+}
+void launch_fill(double *ptr, long long n, double v, hipStream_t s) {
+    if (n <= 0) return;
+    int blocks = (int)std::min<long long>((n + kBlock - 1) / kBlock, 4096);
+    hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(kBlock), 0, s, ptr, n, v);
+}
+void launch_flush(const Problem &p, const StepArgs &a, double *sol, int nblk, hipStream_t s) {
+    hipLaunchKernelGGL(k_flush, dim3(nblk), dim3(kBlock), 0, s, p, a, sol);
+}
+void launch_jvp_rhs(const Problem &p, const StepArgs &a, const RowGrid &g, const double *dP,
+                    const double *dA, const double *dq, const double *db, hipStream_t s) {
+    hipLaunchKernelGGL(k_jvp_rhs, dim3(g.total()), dim3(kBlock), 0, s, p, a, g, dP, dA, dq, db);
+}
+void launch_vjp_rhs(const Problem &p, const StepArgs &a, const ConeGrid &g, int lds,
+                    const double *gx, const double *gy, const double *gs, hipStream_t s) {
+    hipLaunchKernelGGL(k_vjp_rhs, dim3(g.total()), dim3(kBlock), lds, s, p, a, g, gx, gy, gs);
+}
+void launch_jvp_out(const Problem &p, const double *sol, const double *wy, double *dx,
+                    double *dy, double *ds, hipStream_t s) {
+    const int nb = div_up((long long)p.n + p.m, kBlock);
+    if (nb > 0) hipLaunchKernelGGL(k_jvp_out, dim3(nb), dim3(kBlock), 0, s, p, sol, wy, dx, dy, ds);
+}
+void launch_vjp_out(const Problem &p, const RowGrid &g, const double *w, double *dP,
+                    double *dA, double *dq, double *db, hipStream_t s) {
+    hipLaunchKernelGGL(k_vjp_out, dim3(g.total()), dim3(kBlock), 0, s, p, g, w, dP, dA, dq, db);
+}
+void launch_nan_scan(const double *const *ptrs, const long long *lens, int nseg, int *flag,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(k_nan_scan, dim3(256), dim3(kBlock), 0, s, ptrs, lens, nseg, flag);
+}
+
+// the cone kernels may need more than the default 64 KB of dynamic LDS for PSD blocks
+void set_cone_kernel_lds(int bytes) {
+    hipFuncSetAttribute((const void *)k_cone_FT, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    hipFuncSetAttribute((const void *)k_cone_pre, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    hipFuncSetAttribute((const void *)k_vjp_rhs, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+}  // namespace qcpd

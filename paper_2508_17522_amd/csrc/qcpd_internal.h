@@ -1,0 +1,207 @@
+// Internal device data layout and helpers shared by the library's HIP sources.
+// gfx950 only: 64-lane wavefronts, 256-thread workgroups, FP64 arithmetic throughout.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/qcpd.h"
+
+namespace qcpd {
+
+constexpr int kBlock = 256;      // threads per workgroup (4 wavefronts)
+constexpr int kWave = 64;
+constexpr int kMaxPsd = 64;      // largest PSD order kept in LDS
+
+// LSQR scalars live in device memory so that a captured graph of many iterations runs
+// without host round trips; the host only reads `done` once per graph launch.
+struct LsqrState {
+    double alpha;     // ||v~||  (v = v~ / alpha)
+    double beta;      // ||u~||  (u = u~ / beta)
+    double rhobar, phibar, beta1;
+    double phr, thr;  // phi/rho and theta/rho of the last rotation (pending x, w update)
+    double dot_fwd;   // c'(s o in)_x - b'(J s o in)_y for the next product with F
+    double dot_adj;   // q'(s o in)_x + b'(s o in)_y for the next product with F'
+    double one;       // 1.0: normaliser for plain (non-LSQR) products
+    double tol;
+    double resid;     // explicit residual norm (absolute)
+    double tau_rhs;   // scratch
+    int32_t pending;  // an x/w update is owed (set by the v-step, cleared by the u-step)
+    int32_t done;     // stop flag read by every kernel on entry
+    int32_t iters;
+    int32_t max_iter;
+    int32_t conv;     // 1 when the stopping test passed
+    int32_t pad[3];
+};
+
+// Offsets of doubles inside LsqrState, used to select a normaliser by index.
+enum NrmSel { NRM_ALPHA = 0, NRM_BETA = 1, NRM_ONE = 9 };
+
+// Read-only view of one problem on the device (passed by value to kernels).
+struct Problem {
+    int n, m, N;
+    int nnzP, nnzA;
+    const int *Prp, *Pci;
+    const double *Pv;
+    const int *Arp, *Aci;
+    const double *Av;
+    const int *Trp, *Tci, *Tperm;   // A' in CSR and, per A' slot, the A slot it came from
+    const double *Tv;
+    const double *q, *b, *x, *y, *s;
+    const double *c;                // c = -2Px - q (the tau-row of D_u Q at tau = 1)
+    const double *zy;               // z_y = y - s
+    double xPx;
+    // cones
+    int n_diag;                     // zero + nonnegative rows (leading rows of y)
+    const double *jdiag;            // diag of J for every y row
+    int n_soc;
+    const int *soc_row, *soc_dim;   // first y-row and dimension of each SOC
+    const double *soc_par;          // 4 per cone: mode, 1/||u||, c1, c2
+    int n_exp;
+    int exp_row0;                   // first y-row of the exponential cones (3 rows each)
+    const double *exp_J;            // 9 per cone, row-major, J of the dual exponential cone
+    int n_psd;
+    const int *psd_row, *psd_k;
+    const long long *psd_off;       // offset of (V, B) in psd_pool, 2 k^2 doubles per cone
+    const double *psd_pool;
+};
+
+// Cone-kernel grid: [elementwise | SOC | exp | PSD] block ranges.
+struct ConeGrid {
+    int nE;         // elementwise items: x-part (n) + diagonal y rows (n_diag) + tau (1)
+    int bE, bS, bX, bP;
+    int total() const { return bE + bS + bX + bP; }
+};
+
+// Rows-kernel grid: x rows with lx lanes each, then y rows (+ tau) with ly lanes each.
+struct RowGrid {
+    int lx, ly;
+    int bx, by;
+    int total() const { return bx + by; }
+};
+
+// ---------------------------------------------------------------------------------------
+// reductions
+// ---------------------------------------------------------------------------------------
+
+__device__ inline double wave_sum(double v) {
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// Sum of three values over the workgroup; result valid in thread 0.
+__device__ inline void block_sum3(double &a, double &b, double &c) {
+    __shared__ double sh[3][kBlock / kWave];
+    a = wave_sum(a);
+    b = wave_sum(b);
+    c = wave_sum(c);
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    if (lane == 0) { sh[0][w] = a; sh[1][w] = b; sh[2][w] = c; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a = sh[0][0]; b = sh[1][0]; c = sh[2][0];
+        for (int i = 1; i < kBlock / kWave; ++i) { a += sh[0][i]; b += sh[1][i]; c += sh[2][i]; }
+    }
+    __syncthreads();
+}
+
+__device__ inline void store_coherent(double *p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline double load_coherent(const double *p) {
+    return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Publish this block's three partial sums (3 doubles per block in `partials`). Returns true
+// in every thread of the last block to arrive; that block then holds the totals, summed in
+// a fixed order so the result does not depend on which block arrived last. The last block
+// also rearms the counter for the next launch.
+__device__ inline bool last_block_sum3(double a, double b, double c, double *partials,
+                                       int *counter, int nblocks, double tot[3]) {
+    __shared__ int is_last;
+    __shared__ double tsh[3];
+    block_sum3(a, b, c);
+    if (threadIdx.x == 0) {
+        store_coherent(&partials[3 * blockIdx.x], a);
+        store_coherent(&partials[3 * blockIdx.x + 1], b);
+        store_coherent(&partials[3 * blockIdx.x + 2], c);
+        __threadfence();
+        int t = atomicAdd(counter, 1);
+        is_last = (t == nblocks - 1);
+    }
+    __syncthreads();
+    if (!is_last) return false;
+    __threadfence();
+    double sa = 0.0, sb = 0.0, sc = 0.0;
+    for (int i = threadIdx.x; i < nblocks; i += kBlock) {
+        sa += load_coherent(&partials[3 * i]);
+        sb += load_coherent(&partials[3 * i + 1]);
+        sc += load_coherent(&partials[3 * i + 2]);
+    }
+    block_sum3(sa, sb, sc);
+    if (threadIdx.x == 0) {
+        tsh[0] = sa; tsh[1] = sb; tsh[2] = sc;
+        __hip_atomic_store(counter, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    tot[0] = tsh[0]; tot[1] = tsh[1]; tot[2] = tsh[2];
+    return true;
+}
+
+inline int div_up(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+}  // namespace qcpd
+
+namespace qcpd {
+
+// Roles of an operator product inside LSQR (Paige & Saunders bidiagonalisation):
+//   U:     u~ <- op(in) - (alpha/beta) u~        (product with the LSQR matrix)
+//   V:     v~ <- sc o op(in) - (beta/alpha) v~   (product with its transpose), then the
+//          plane rotation and the convergence test
+//   V0:    v~ <- sc o op(in)                     (first v of the bidiagonalisation)
+//   RESID: out <- op(in) - rhs                   (explicit residual)
+//   PLAIN: out <- op(in)
+enum Role { ROLE_U = 0, ROLE_V = 1, ROLE_V0 = 2, ROLE_RESID = 3, ROLE_PLAIN = 4 };
+
+struct StepArgs {
+    const double *in;   // operator input buffer (N)
+    int in_nrm;         // NrmSel: input is in / state[in_nrm]
+    int in_is_v;        // the input is the v-side vector: read it through sc
+    double *out;        // output buffer (N), updated in place
+    int role;
+    int out_is_v;       // the output is the v-side vector (scaled by sc)
+    const double *sc;   // v-side diagonal scale (Jacobi / custom), or null
+    const double *rhs;  // ROLE_RESID right-hand side
+    double *wy;         // J applied to the next product's y-input (unnormalised), m
+    int do_pre;         // compute wy and the F tau-row dot for the next product
+    int do_update;      // apply the owed LSQR x/w update (first kernel of an iteration)
+    double *xk, *wk;    // LSQR iterate and direction (N)
+    double *tmp;        // staging between the two kernels of a product with F' (N)
+    double *partials;   // 3 doubles per block
+    int *counter;
+    LsqrState *st;
+    int check_done;     // return at once when st->done is set (kernels inside the loop)
+};
+
+// host launchers (apply.hip)
+void launch_rows_F(const Problem &p, const StepArgs &a, const RowGrid &g, hipStream_t s);
+void launch_rows_FT(const Problem &p, const StepArgs &a, const RowGrid &g, hipStream_t s);
+void launch_cone_FT(const Problem &p, const StepArgs &a, const ConeGrid &g, int lds_bytes,
+                    hipStream_t s);
+void launch_cone_pre(const Problem &p, const StepArgs &a, const ConeGrid &g, int lds_bytes,
+                     hipStream_t s);
+void launch_state_init(LsqrState *st, double tol, int max_iter, hipStream_t s);
+void launch_fill(double *p, long long n, double v, hipStream_t s);
+void launch_flush(const Problem &p, const StepArgs &a, double *sol, int nblk, hipStream_t s);
+void launch_jvp_rhs(const Problem &p, const StepArgs &a, const RowGrid &g, const double *dP,
+                    const double *dA, const double *dq, const double *db, hipStream_t s);
+void launch_vjp_rhs(const Problem &p, const StepArgs &a, const ConeGrid &g, int lds_bytes,
+                    const double *gx, const double *gy, const double *gs, hipStream_t s);
+void launch_jvp_out(const Problem &p, const double *sol, const double *wy, double *dx,
+                    double *dy, double *ds, hipStream_t s);
+void launch_vjp_out(const Problem &p, const RowGrid &g, const double *w, double *dP,
+                    double *dA, double *dq, double *db, hipStream_t s);
+void launch_nan_scan(const double *const *ptrs, const long long *lens, int nseg, int *flag,
+                     hipStream_t s);
+
+}  // namespace qcpd

@@ -1,0 +1,32 @@
+// Host-side declarations of the create-time kernels.
+#pragma once
+
+#include "qcpd_internal.h"
+
+namespace qcpd {
+
+struct ConeHost {
+    int n_zero;
+};
+
+hipError_t csr_transpose(int nrows, int ncols, int nnz, const int *rp, const int *ci,
+                         const double *val, int *trp, int *tci, double *tv, int *perm,
+                         hipStream_t s);
+void launch_check_csr(const int *rp, const int *ci, int nrows, int ncols, int nnz, int *flag,
+                      hipStream_t s);
+void launch_check_sorted(const int *rp, const int *ci, int nrows, int ncols, int *flag, hipStream_t s);
+void launch_check_symmetric(const int *rp, const int *ci, const double *v, const int *trp,
+                            const int *tci, const double *tv, int n, int nnz, int *flag,
+                            hipStream_t s);
+void launch_px(const Problem &p, const RowGrid &g, double *c, double *xpx, double *partials,
+               int *counter, hipStream_t s);
+void launch_sub(const double *a, const double *b, double *out, int n, hipStream_t s);
+void launch_cone_factors(const Problem &p, const ConeHost &ch, double *jdiag, double *soc_par,
+                         double *exp_J, double *pool, int *nondiff, int *fail, int psd_lds,
+                         hipStream_t s);
+void launch_scales(const Problem &p, const RowGrid &g, double *dj, double *dv, double *partials,
+                   int *counter, hipStream_t s);
+int psd_factor_lds_bytes(int kmax);
+void set_cone_kernel_lds(int bytes);
+
+}  // namespace qcpd

@@ -459,7 +459,8 @@ def large_psd_soc(idx=0) -> QCP:
 
 
 def small_mixed(idx=0, n=40, n_zero=6, n_nonneg=30, soc=(3, 4, 5), psd=(2, 3, 4), n_exp=3,
-                A_density=0.15, P_rank=None, P_eps=0.0, nonneg_active=None) -> QCP:
+                A_density=0.15, P_rank=None, P_eps=0.0, nonneg_active=None,
+                psd_ranks=None) -> QCP:
     """A small mixed-cone instance (every cone type) for pins and parity tests."""
     rng = np.random.default_rng([10, idx, n])
     cones = Cones(n_zero=n_zero, n_nonneg=n_nonneg, soc=list(soc), psd=list(psd),
@@ -470,7 +471,8 @@ def small_mixed(idx=0, n=40, n_zero=6, n_nonneg=30, soc=(3, 4, 5), psd=(2, 3, 4)
     Pd = 0.5 * (Pd + Pd.T)
     P = _csr(sp.csr_matrix(np.ones((n, n))))
     P.data = Pd.reshape(-1).copy()
-    psd_ranks = [max(1, k // 2) for k in psd]
+    if psd_ranks is None:
+        psd_ranks = [max(1, k // 2) for k in psd]
     if nonneg_active is None:
         nonneg_active = n_nonneg // 3
     qcp = build(rng, f"small_mixed_{n}", n, cones, A_density=A_density, P=P,

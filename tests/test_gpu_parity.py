@@ -1,0 +1,225 @@
+"""GPU parity: the HIP library (through its C-ABI) against the CPU oracle.
+
+Bar (FP64): relative 2-norm error <= 1e-7 on dx, dy, ds and on dP, dA, dq, db. The least
+squares problems are solved to a relative residual of 1e-12 here so that the forward error,
+which can reach cond(K_red) x tol, stays well below the bar; the oracle reference is the
+dense implicit-function solve (exact up to rounding) where it is affordable.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import qcpgen
+from oracle import derivative as D
+from oracle import embedding as E
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # collected on CPU machines, skipped there
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2508_17522_amd as Q  # noqa: E402
+from qcpgen.torch_io import cones_of, to_device  # noqa: E402
+
+BAR = 1e-7
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def make_handle(qcp, tol=1e-12, precond=Q.QCPD_PRECOND_JACOBI, max_iter=0, chunk=32):
+    t = to_device(qcp)
+    o = Q.Opts(tol=tol, max_iter=max_iter, precond=precond, graph_chunk=chunk)
+    h = Q.qcpd_create(t["P"], t["A"], t["q"], t["b"], cones_of(qcp), t["x"], t["y"], t["s"], opts=o)
+    return h, t
+
+
+def gpu_jvp(h, t):
+    dx, dy, ds, info, st = Q.qcpd_jvp(h, t["dP"], t["dA"], t["dq"], t["db"])
+    return dx.cpu().numpy(), dy.cpu().numpy(), ds.cpu().numpy(), info, st
+
+
+def gpu_vjp(h, t):
+    dP, dA, dq, db, info, st = Q.qcpd_vjp(h, t["gx"], t["gy"], t["gs"])
+    return dP.cpu().numpy(), dA.cpu().numpy(), dq.cpu().numpy(), db.cpu().numpy(), info, st
+
+
+def check_jvp_vjp_dense(qcp, tol=1e-12, **kw):
+    h, t = make_handle(qcp, tol=tol, **kw)
+    dx, dy, ds, info, st = gpu_jvp(h, t)
+    print(f"[{qcp.name}] jvp iters={info.iters} rel_res={info.rel_residual:.2e} st={st}", flush=True)
+    assert st == Q.QCPD_OK
+    assert info.rel_residual <= 10 * tol
+    ref = D.jvp_dense(qcp, qcp.dP, qcp.dA, qcp.dq, qcp.db)
+    errs = [rel(a, b) for a, b in zip((dx, dy, ds), ref)]
+    print(f"[{qcp.name}] jvp errors {errs}", flush=True)
+    assert max(errs) <= BAR
+    dP, dA, dq, db, info2, st2 = gpu_vjp(h, t)
+    print(f"[{qcp.name}] vjp iters={info2.iters} rel_res={info2.rel_residual:.2e} st={st2}", flush=True)
+    assert st2 == Q.QCPD_OK
+    refv = D.vjp_dense(qcp, qcp.gx, qcp.gy, qcp.gs)
+    errs2 = [rel(a, b) for a, b in zip((dP, dA, dq, db), refv)]
+    print(f"[{qcp.name}] vjp errors {errs2}", flush=True)
+    assert max(errs2) <= BAR
+    h.close()
+
+
+# ---- small instances, dense oracle ----------------------------------------------------
+
+@pytest.mark.parametrize("idx", [0, 1])
+def test_tiny_qp(idx):
+    check_jvp_vjp_dense(qcpgen.tiny_qp(idx))
+
+
+def test_small_mixed_all_cones():
+    check_jvp_vjp_dense(qcpgen.small_mixed(0))
+
+
+def test_medium_mixed_several_tiles():
+    """Every cone type, several workgroups per region and ragged tails (n, m not multiples
+    of the tile), PSD orders up to 12."""
+    q = qcpgen.small_mixed(1, n=301, n_zero=37, n_nonneg=260, soc=(3, 4, 5, 6, 7, 8) * 5,
+                           psd=(4, 7, 12, 9), n_exp=23, A_density=0.04, P_rank=150,
+                           nonneg_active=100)
+    check_jvp_vjp_dense(q)
+
+
+def test_unpreconditioned_matches():
+    q = qcpgen.small_mixed(0)
+    check_jvp_vjp_dense(q, precond=Q.QCPD_PRECOND_NONE)
+
+
+def test_psd_max_order():
+    """A 64 x 64 PSD block (the largest order held in LDS) next to a 1 x 1 block."""
+    q = qcpgen.small_mixed(2, n=200, n_zero=10, n_nonneg=40, soc=(1, 2), psd=(64, 1), n_exp=2,
+                           A_density=0.02, P_rank=150, P_eps=1e-2, nonneg_active=15,
+                           psd_ranks=(12, 1))
+    check_jvp_vjp_dense(q)
+
+
+def test_only_zero_cone_and_graph_chunk_one():
+    q = qcpgen.small_mixed(3, n=30, n_zero=12, n_nonneg=0, soc=(), psd=(), n_exp=0,
+                           A_density=0.3, P_rank=25, P_eps=0.1)
+    check_jvp_vjp_dense(q, chunk=1)
+
+
+# ---- the 5000 x 11000 mixed-cone workload at full size ----------------------------------
+
+def kkt_linearised_residual(qcp, dx, dy, ds):
+    """Residuals of the linearised optimality conditions that (dx, dy, ds) must satisfy:
+    P dx + dP x + A'dy + dA'y + dq = 0,  A dx + dA x + ds - db = 0,  dy = J (dy - ds)."""
+    from oracle import cones as C
+    dPm = qcp.P.copy(); dPm.data = qcp.dP.copy()
+    dAm = qcp.A.copy(); dAm.data = qcp.dA.copy()
+    r1 = qcp.P @ dx + dPm @ qcp.x + qcp.A.T @ dy + dAm.T @ qcp.y + qcp.dq
+    r2 = qcp.A @ dx + dAm @ qcp.x + ds - qcp.db
+    J = C.DualJacobian(qcp.y - qcp.s, qcp.cones)
+    r3 = dy - J.apply(dy - ds)
+    scale = (np.linalg.norm(dPm @ qcp.x) + np.linalg.norm(dAm.T @ qcp.y) + np.linalg.norm(qcp.dq)
+             + np.linalg.norm(dAm @ qcp.x) + np.linalg.norm(qcp.db))
+    return (np.linalg.norm(r1) + np.linalg.norm(r2) + np.linalg.norm(r3)) / scale
+
+
+@pytest.fixture(scope="module")
+def mixed_full():
+    return qcpgen.mixed_qcp(0)
+
+
+def test_mixed_full_size_properties(mixed_full):
+    """At the benchmark size and tolerance: the JVP satisfies the linearised KKT system
+    (oracle J and data, any size) and JVP/VJP satisfy the adjoint identity."""
+    q = mixed_full
+    h, t = make_handle(q, tol=1e-8)
+    dx, dy, ds, info, st = gpu_jvp(h, t)
+    print(f"[mixed full] jvp iters={info.iters} rel_res={info.rel_residual:.2e} "
+          f"ms={info.ms_total:.1f} st={st}", flush=True)
+    assert st == Q.QCPD_OK and info.rel_residual <= 1e-7
+    res = kkt_linearised_residual(q, dx, dy, ds)
+    print(f"[mixed full] linearised KKT residual {res:.2e}", flush=True)
+    assert res <= 1e-6
+    dP, dA, dq, db, info2, st2 = gpu_vjp(h, t)
+    print(f"[mixed full] vjp iters={info2.iters} rel_res={info2.rel_residual:.2e} "
+          f"ms={info2.ms_total:.1f} st={st2}", flush=True)
+    assert st2 == Q.QCPD_OK
+    lhs = q.gx @ dx + q.gy @ dy + q.gs @ ds
+    rhs = dP @ q.dP + dA @ q.dA + dq @ q.dq + db @ q.db
+    print(f"[mixed full] adjoint identity {lhs:.10e} {rhs:.10e}", flush=True)
+    assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+    h.close()
+
+
+# ---- edge cases and errors ----------------------------------------------------------------
+
+def test_zero_perturbation_and_zero_cotangent():
+    q = qcpgen.small_mixed(0)
+    h, t = make_handle(q)
+    for k in ("dP", "dA", "dq", "db", "gx", "gy", "gs"):
+        t[k] = torch.zeros_like(t[k])
+    dx, dy, ds, info, st = gpu_jvp(h, t)
+    assert st == Q.QCPD_OK and info.iters == 0
+    assert not np.any(dx) and not np.any(dy) and not np.any(ds)
+    dP, dA, dq, db, info, st = gpu_vjp(h, t)
+    assert st == Q.QCPD_OK and not np.any(dP) and not np.any(dq)
+
+
+def test_not_converged_warning():
+    q = qcpgen.small_mixed(0)
+    h, t = make_handle(q, max_iter=3, chunk=2)
+    dx, dy, ds, info, st = gpu_jvp(h, t)
+    assert st == Q.QCPD_WARN_NOT_CONVERGED and info.iters == 3 and (info.flags & 1)
+
+
+def test_deterministic():
+    q = qcpgen.small_mixed(1, n=120, A_density=0.08)
+    h, t = make_handle(q, tol=1e-10)
+    a = gpu_jvp(h, t)
+    b = gpu_jvp(h, t)
+    for u, v in zip(a[:3], b[:3]):
+        assert np.array_equal(u, v)
+    c = gpu_vjp(h, t)
+    d = gpu_vjp(h, t)
+    for u, v in zip(c[:4], d[:4]):
+        assert np.array_equal(u, v)
+
+
+def test_errors_are_reported():
+    q = qcpgen.small_mixed(0)
+    t = to_device(q)
+    cones = cones_of(q)
+    # NaN in the data
+    bad = t["q"].clone()
+    bad[3] = float("nan")
+    with pytest.raises(Q.QCPDError) as e:
+        Q.qcpd_create(t["P"], t["A"], bad, t["b"], cones, t["x"], t["y"], t["s"])
+    assert e.value.status == Q.QCPD_ERR_NAN
+    # cone rows do not add up to m
+    c2 = Q.Cones(n_zero=cones.n_zero + 1, n_nonneg=cones.n_nonneg, soc=cones.soc,
+                 psd=cones.psd, n_exp=cones.n_exp)
+    with pytest.raises(Q.QCPDError) as e:
+        Q.qcpd_create(t["P"], t["A"], t["q"], t["b"], c2, t["x"], t["y"], t["s"])
+    assert e.value.status == Q.QCPD_ERR_CONE
+    # asymmetric P
+    Pv = t["P"][2].clone()
+    Pv[1] += 1.0
+    with pytest.raises(Q.QCPDError) as e:
+        Q.qcpd_create((t["P"][0], t["P"][1], Pv), t["A"], t["q"], t["b"], cones, t["x"], t["y"], t["s"])
+    assert e.value.status == Q.QCPD_ERR_PATTERN
+    # column index out of range in A
+    Aci = t["A"][1].clone()
+    Aci[0] = q.n + 5
+    with pytest.raises(Q.QCPDError) as e:
+        Q.qcpd_create(t["P"], (t["A"][0], Aci, t["A"][2]), t["q"], t["b"], cones, t["x"], t["y"], t["s"])
+    assert e.value.status == Q.QCPD_ERR_INVALID_ARG
+    # NaN in a perturbation
+    h, _ = make_handle(q)
+    dq = t["dq"].clone()
+    dq[0] = float("inf")
+    with pytest.raises(Q.QCPDError) as e:
+        Q.qcpd_jvp(h, t["dP"], t["dA"], dq, t["db"])
+    assert e.value.status == Q.QCPD_ERR_NAN
