@@ -76,7 +76,7 @@ typedef struct {
     int32_t n_zero;              /* zero cone rows ({0}; its dual is R)                     */
     int32_t n_nonneg;            /* nonnegative orthant rows                                */
     int32_t n_soc;               /* number of second-order cones                            */
-    const int32_t *soc_dims;     /* n_soc dimensions, each >= 1                             */
+    const int32_t *soc_dims;     /* n_soc dimensions, each in [1, 1024]                     */
     int32_t n_psd;               /* number of PSD cones                                     */
     const int32_t *psd_orders;   /* n_psd matrix orders k (1 <= k <= 64); k(k+1)/2 rows each */
     int32_t n_exp;               /* number of exponential cones, 3 rows each                */
@@ -143,13 +143,62 @@ qcpd_status qcpd_set_precond(qcpd_handle *h, const double *d_jvp, const double *
  * d_jvp, d_vjp (n + m + 1 each), jdiag (m). Any pointer may be NULL. */
 qcpd_status qcpd_get_diagnostics(qcpd_handle *h, double *d_jvp, double *d_vjp, double *jdiag);
 
-/* Measurement support: time the three kernels of one LSQR iteration of the JVP (the
- * product with F over CSR rows; the CSR-row part of the product with F'; the per-cone part
- * of the product with F') by launching each `reps` times back to back on the handle's
- * stream between HIP events, on the handle's current vectors. Writes the average duration
- * of one launch in milliseconds to ms_out[0..2] [host]. Leaves the LSQR state undefined:
- * call it between, not during, derivative evaluations. */
+/* Measurement support: time the two kernels of one LSQR iteration of the JVP (the product
+ * with F over CSR rows; the fused product with F': CSR rows of each cone block followed by
+ * its Jacobian block) by launching each `reps` times back to back on the handle's stream
+ * between HIP events, on the handle's current vectors. Writes the average duration of one
+ * launch in milliseconds to ms_out[0..1] [host]. Leaves the LSQR state undefined: call it
+ * between, not during, derivative evaluations. */
 qcpd_status qcpd_profile_kernels(qcpd_handle *h, int32_t reps, float *ms_out);
+
+/* ---------------------------------------------------------------------------------------
+ * Batched form: many QCPs of uneven sizes evaluated in one launch (a persistent kernel in
+ * which each workgroup takes whole problems from a work queue, longest first). Each problem
+ * keeps its own LSQR iteration count and stopping test, so the results equal those of
+ * qcpd_jvp / qcpd_vjp on each problem up to rounding. The vjp of the batch is the per-problem
+ * adjoint of Sec. 3.2, the jvp the per-problem derivative of Sec. 3.1.
+ * ------------------------------------------------------------------------------------- */
+typedef struct qcpd_batch qcpd_batch;
+
+/* Sizes of the problems of a batch; all arrays [host], nprob entries each. */
+typedef struct {
+    int32_t nprob;
+    const int32_t *n;            /* variables of each problem (>= 1)               */
+    const int32_t *m;            /* constraint rows of each problem (>= 0)         */
+    const int32_t *nnz_P;        /* stored entries of each P                      */
+    const int32_t *nnz_A;        /* stored entries of each A                      */
+    const qcpd_cones *cones;     /* cone of each problem (same rules as above)     */
+} qcpd_batch_layout;
+
+/* Build a batch at the problems' solutions. All data arrays are [device] concatenations,
+ * problem after problem: P_rowptr has sum(n_i + 1) entries (each problem's local row
+ * pointers, starting at 0), P_colind / P_val sum(nnz_P) entries with local column indices;
+ * A likewise with sum(m_i + 1) row pointers; q, x: sum(n_i); b, y, s: sum(m_i).
+ * opts->precond may be NONE or JACOBI; graph_chunk is ignored. */
+qcpd_status qcpd_batch_create(qcpd_batch **hb, const qcpd_batch_layout *layout,
+                              const int32_t *P_rowptr, const int32_t *P_colind, const double *P_val,
+                              const int32_t *A_rowptr, const int32_t *A_colind, const double *A_val,
+                              const double *q, const double *b, const double *x, const double *y,
+                              const double *s, const qcpd_opts *opts, void *stream);
+
+/* Per-problem JVPs in one launch. [device] concatenations as in qcpd_batch_create:
+ * dP_val sum(nnz_P), dA_val sum(nnz_A), dq sum(n), db sum(m); outputs dx sum(n), dy and ds
+ * sum(m). info: [host] array of nprob entries or NULL. Returns QCPD_WARN_NOT_CONVERGED when
+ * any problem did not reach the tolerance. */
+qcpd_status qcpd_batch_jvp(qcpd_batch *hb, const double *dP_val, const double *dA_val,
+                           const double *dq, const double *db, double *dx, double *dy,
+                           double *ds, qcpd_info *info);
+
+/* Per-problem VJPs in one launch; layouts as above. */
+qcpd_status qcpd_batch_vjp(qcpd_batch *hb, const double *gx, const double *gy, const double *gs,
+                           double *dP_val, double *dA_val, double *dq, double *db,
+                           qcpd_info *info);
+
+/* Replace the batch's LSQR options (tolerance, iteration cap, NONE or JACOBI). */
+qcpd_status qcpd_batch_set_opts(qcpd_batch *hb, const qcpd_opts *opts);
+
+/* Free a batch (NULL is allowed). */
+void qcpd_batch_destroy(qcpd_batch *hb);
 
 /* Free a handle (NULL is allowed). */
 void qcpd_destroy(qcpd_handle *h);

@@ -10,8 +10,14 @@ from ._capi import (QCPD_OK, QCPD_WARN_NOT_CONVERGED, QCPD_WARN_NONDIFF, QCPD_ER
 from .api import (Cones, Opts, Info, Handle, QCPDError, qcpd_create, qcpd_jvp, qcpd_vjp,
                   qcpd_destroy, qcpd_status_str, qcpd_opts_default, qcpd_set_opts,
                   qcpd_set_precond, qcpd_get_diagnostics, qcpd_profile_kernels)
+from .autograd import QCPStructure, qcp_solution_map
+from .batch import (BatchHandle, qcpd_batch_create, qcpd_batch_jvp, qcpd_batch_vjp,
+                    qcpd_batch_set_opts, qcpd_batch_destroy)
 
 __all__ = [
+    "BatchHandle", "qcpd_batch_create", "qcpd_batch_jvp", "qcpd_batch_vjp", "qcpd_batch_set_opts",
+    "qcpd_batch_destroy",
+    "QCPStructure", "qcp_solution_map",
     "Cones", "Opts", "Info", "Handle", "QCPDError", "qcpd_create", "qcpd_jvp", "qcpd_vjp",
     "qcpd_destroy", "qcpd_status_str", "qcpd_opts_default", "qcpd_set_opts",
     "qcpd_set_precond", "qcpd_get_diagnostics", "qcpd_profile_kernels", "LIB_PATH", "EXPORTS",

@@ -49,9 +49,16 @@ QCPD_PRECOND_NONE = 0
 QCPD_PRECOND_JACOBI = 1
 QCPD_PRECOND_CUSTOM = 2
 
+class qcpd_batch_layout(ctypes.Structure):
+    _fields_ = [("nprob", c_int32), ("n", ctypes.POINTER(c_int32)), ("m", ctypes.POINTER(c_int32)),
+                ("nnz_P", ctypes.POINTER(c_int32)), ("nnz_A", ctypes.POINTER(c_int32)),
+                ("cones", ctypes.POINTER(qcpd_cones))]
+
+
 EXPORTS = ["qcpd_opts_default", "qcpd_create", "qcpd_jvp", "qcpd_vjp", "qcpd_set_opts",
            "qcpd_set_precond", "qcpd_get_diagnostics", "qcpd_profile_kernels", "qcpd_destroy",
-           "qcpd_status_str"]
+           "qcpd_status_str", "qcpd_batch_create", "qcpd_batch_jvp", "qcpd_batch_vjp",
+           "qcpd_batch_set_opts", "qcpd_batch_destroy"]
 
 _lib = None
 
@@ -87,6 +94,17 @@ def load(path: str = LIB_PATH):
     lib.qcpd_profile_kernels.restype = c_int32
     lib.qcpd_destroy.argtypes = [c_void_p]
     lib.qcpd_destroy.restype = None
+    lib.qcpd_batch_create.argtypes = [P(c_void_p), P(qcpd_batch_layout)] + [c_void_p] * 11 + \
+        [P(qcpd_opts), c_void_p]
+    lib.qcpd_batch_create.restype = c_int32
+    lib.qcpd_batch_jvp.argtypes = [c_void_p] + [c_void_p] * 7 + [P(qcpd_info)]
+    lib.qcpd_batch_jvp.restype = c_int32
+    lib.qcpd_batch_vjp.argtypes = [c_void_p] + [c_void_p] * 7 + [P(qcpd_info)]
+    lib.qcpd_batch_vjp.restype = c_int32
+    lib.qcpd_batch_set_opts.argtypes = [c_void_p, P(qcpd_opts)]
+    lib.qcpd_batch_set_opts.restype = c_int32
+    lib.qcpd_batch_destroy.argtypes = [c_void_p]
+    lib.qcpd_batch_destroy.restype = None
     lib.qcpd_status_str.argtypes = [c_int32]
     lib.qcpd_status_str.restype = ctypes.c_char_p
     _lib = lib

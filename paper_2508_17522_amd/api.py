@@ -225,9 +225,9 @@ def qcpd_get_diagnostics(h: Handle):
 
 
 def qcpd_profile_kernels(h: Handle, reps: int = 50):
-    """Average launch duration (ms) of the three LSQR-iteration kernels of the JVP:
-    (rows_F, rows_FT, cone_FT)."""
-    out = (ctypes.c_float * 3)()
+    """Average launch duration (ms) of the two LSQR-iteration kernels of the JVP:
+    (rows_F, fused_FT)."""
+    out = (ctypes.c_float * 2)()
     with torch.cuda.device(h.device):
         st = _lib().qcpd_profile_kernels(h.ptr, int(reps), out)
     if st < 0:

@@ -1,0 +1,77 @@
+"""torch.autograd integration: the solution map S(theta) = (x, y, s) of a QCP as a
+differentiable function of the data theta = (P values, A values, q, b).
+
+The forward pass does not solve the QCP: as in the paper (Sec. 2.2), the solution comes from
+an upstream solver and is passed in. It returns that solution and keeps a library handle
+built at it. The backward pass is the adjoint of the derivative (Sec. 3.2) evaluated by the
+HIP library (qcpd_vjp); forward-mode AD (torch.func.jvp / autograd.forward_ad) uses the
+derivative itself (Sec. 3.1, qcpd_jvp). Gradients for P and A are on their stored patterns;
+the gradient for P is symmetric on the pattern.
+"""
+from __future__ import annotations
+
+import dataclasses
+import warnings
+from typing import Optional, Sequence
+
+import torch
+
+from . import api
+
+
+@dataclasses.dataclass
+class QCPStructure:
+    """Everything about the problem that is not differentiated: the sparsity patterns (int32
+    GPU tensors, P in full symmetric CSR), the cone and the LSQR options."""
+    P_rowptr: torch.Tensor
+    P_colind: torch.Tensor
+    A_rowptr: torch.Tensor
+    A_colind: torch.Tensor
+    cones: api.Cones
+    opts: Optional[api.Opts] = None
+
+
+class _SolutionMap(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, P_val, A_val, q, b, x, y, s, structure: QCPStructure):
+        st = structure
+        h = api.qcpd_create((st.P_rowptr, st.P_colind, P_val.detach()),
+                            (st.A_rowptr, st.A_colind, A_val.detach()),
+                            q.detach(), b.detach(), st.cones, x.detach(), y.detach(), s.detach(),
+                            opts=st.opts)
+        ctx.handle = h
+        return x.detach().clone(), y.detach().clone(), s.detach().clone()
+
+    @staticmethod
+    def backward(ctx, gx, gy, gs):
+        h = ctx.handle
+        f64 = dict(dtype=torch.float64, device=h.device)
+        gx = torch.zeros(h.n, **f64) if gx is None else gx.contiguous()
+        gy = torch.zeros(h.m, **f64) if gy is None else gy.contiguous()
+        gs = torch.zeros(h.m, **f64) if gs is None else gs.contiguous()
+        dP, dA, dq, db, info, status = api.qcpd_vjp(h, gx, gy, gs)
+        ctx.vjp_info = info
+        if status != 0:
+            warnings.warn(f"qcpd_vjp: {api.qcpd_status_str(status)} "
+                          f"(iters {info.iters}, residual {info.rel_residual:.2e})")
+        return dP, dA, dq, db, None, None, None, None
+
+    @staticmethod
+    def jvp(ctx, dP, dA, dq, db, dx_in, dy_in, ds_in, _structure):
+        h = ctx.handle
+        f64 = dict(dtype=torch.float64, device=h.device)
+        z = lambda k: torch.zeros(k, **f64)
+        dP = z(h.nnzP) if dP is None else dP.contiguous()
+        dA = z(h.nnzA) if dA is None else dA.contiguous()
+        dq = z(h.n) if dq is None else dq.contiguous()
+        db = z(h.m) if db is None else db.contiguous()
+        dx, dy, ds, info, status = api.qcpd_jvp(h, dP, dA, dq, db)
+        if status != 0:
+            warnings.warn(f"qcpd_jvp: {api.qcpd_status_str(status)} "
+                          f"(iters {info.iters}, residual {info.rel_residual:.2e})")
+        return dx, dy, ds
+
+
+def qcp_solution_map(P_val, A_val, q, b, x, y, s, structure: QCPStructure):
+    """(x, y, s) as a differentiable function of (P_val, A_val, q, b) at a given solution."""
+    return _SolutionMap.apply(P_val, A_val, q, b, x, y, s, structure)

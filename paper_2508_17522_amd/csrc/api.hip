@@ -22,7 +22,9 @@ struct qcpd_handle {
     Problem p{};
     ConeGrid cg{};
     RowGrid rg{};
+    FusedGrid fg{};
     int lds = 0;
+    int lds_fused = 0;
     int nblk_max = 0;
     std::vector<void *> allocs;
     double *u = nullptr, *v = nullptr, *xk = nullptr, *wk = nullptr, *tmp = nullptr,
@@ -155,24 +157,19 @@ void enqueue_iteration(const qcpd_handle *h, int dir, const double *sc, hipStrea
     StepArgs a = base_args(h, sc);
     a.check_done = 1;
     if (dir == 0) {
-        StepArgs f = a;  // u~ <- F(sc o v) - alpha u~
+        StepArgs f = a;  // u~ <- F(sc o v) - alpha u~   (and the owed x, w update)
         f.in = h->v; f.in_nrm = NRM_ALPHA; f.in_is_v = 1;
         f.out = h->u; f.role = ROLE_U; f.do_update = 1;
         launch_rows_F(h->p, f, h->rg, s);
-        StepArgs t1 = a;  // F'u, rows
-        t1.in = h->u; t1.in_nrm = NRM_BETA;
-        launch_rows_FT(h->p, t1, h->rg, s);
-        StepArgs t2 = t1;  // v~ <- sc o F'u - beta v~, J(sc o v~) for the next product
-        t2.out = h->v; t2.role = ROLE_V; t2.out_is_v = 1; t2.do_pre = 1;
-        launch_cone_FT(h->p, t2, h->cg, h->lds, s);
+        StepArgs t = a;  // v~ <- sc o F'u - beta v~, then J(sc o v~) for the next product
+        t.in = h->u; t.in_nrm = NRM_BETA;
+        t.out = h->v; t.role = ROLE_V; t.out_is_v = 1; t.do_pre = 1;
+        launch_fused_FT(h->p, t, h->fg, h->lds_fused, s);
     } else {
-        StepArgs t1 = a;  // F'(sc o v), rows
-        t1.in = h->v; t1.in_nrm = NRM_ALPHA; t1.in_is_v = 1; t1.do_update = 1;
-        launch_rows_FT(h->p, t1, h->rg, s);
-        StepArgs t2 = t1;  // u~ <- F'(sc o v) - alpha u~, J(u~) for the next product
-        t2.do_update = 0;
-        t2.out = h->u; t2.role = ROLE_U; t2.do_pre = 1;
-        launch_cone_FT(h->p, t2, h->cg, h->lds, s);
+        StepArgs t = a;  // u~ <- F'(sc o v) - alpha u~ (and the owed update), J(u~)
+        t.in = h->v; t.in_nrm = NRM_ALPHA; t.in_is_v = 1; t.do_update = 1;
+        t.out = h->u; t.role = ROLE_U; t.do_pre = 1;
+        launch_fused_FT(h->p, t, h->fg, h->lds_fused, s);
         StepArgs f = a;  // v~ <- sc o F u - beta v~
         f.in = h->u; f.in_nrm = NRM_BETA;
         f.out = h->v; f.role = ROLE_V; f.out_is_v = 1;
@@ -209,12 +206,10 @@ qcpd_status run_lsqr(qcpd_handle *h, int dir, const double *sc) {
     StepArgs a = base_args(h, sc);
     a.check_done = 1;
     if (dir == 0) {
-        StepArgs t1 = a;
-        t1.in = h->u; t1.in_nrm = NRM_BETA;
-        launch_rows_FT(h->p, t1, h->rg, s);
-        StepArgs t2 = t1;
-        t2.out = h->v; t2.role = ROLE_V0; t2.out_is_v = 1; t2.do_pre = 1;
-        launch_cone_FT(h->p, t2, h->cg, h->lds, s);
+        StepArgs t = a;
+        t.in = h->u; t.in_nrm = NRM_BETA;
+        t.out = h->v; t.role = ROLE_V0; t.out_is_v = 1; t.do_pre = 1;
+        launch_fused_FT(h->p, t, h->fg, h->lds_fused, s);
     } else {
         StepArgs pre = a;
         pre.in = h->u;
@@ -346,7 +341,38 @@ qcpd_status create_impl(qcpd_handle *h, const qcpd_csr *P, const qcpd_csr *A, co
     cg.bX = div_up(K->n_exp, kBlock);
     cg.bP = K->n_psd;
     h->lds = kmax ? (3 * kmax * (kmax | 1) + kmax * (kmax + 1) / 2) * (int)sizeof(double) : 0;
-    h->nblk_max = std::max({cg.total(), rg.total(), div_up(N, kBlock), 1});
+    // work units of the fused product with F'
+    {
+        std::vector<Unit> units;
+        const int rpx = kBlock / rg.lx, rpy = kBlock / rg.ly;
+        for (int r = 0; r < n; r += rpx) units.push_back({U_XROWS, r, std::min(n, r + rpx), 0});
+        for (int r = 0; r < p.n_diag; r += rpy)
+            units.push_back({U_DIAG, r, std::min(p.n_diag, r + rpy), 0});
+        const int target = 256;  // y rows per SOC / exponential unit
+        for (int i = 0; i < K->n_soc;) {
+            int j = i, rws = 0;
+            while (j < K->n_soc && j - i < kBlock &&
+                   (j == i || rws + K->soc_dims[j] <= target) && rws + K->soc_dims[j] <= kUnitRows) {
+                rws += K->soc_dims[j];
+                ++j;
+            }
+            if (j == i) return QCPD_ERR_CONE;  // a single cone larger than kUnitRows rows
+            units.push_back({U_SOC, i, j, soc_row[i]});
+            i = j;
+        }
+        for (int i = 0; i < K->n_exp; i += target / 3)
+            units.push_back({U_EXP, i, std::min(K->n_exp, i + target / 3), p.exp_row0 + 3 * i});
+        for (int i = 0; i < K->n_psd; ++i) units.push_back({U_PSD, i, i + 1, psd_row[i]});
+        Unit *du;
+        ALLOC(du, units.size());
+        HIPCHK(hipMemcpy(du, units.data(), sizeof(Unit) * units.size(), hipMemcpyHostToDevice));
+        h->fg.nunits = (int)units.size();
+        h->fg.units = du;
+        h->fg.lx = rg.lx;
+        h->fg.ly = rg.ly;
+        h->lds_fused = fused_lds_bytes(kmax);
+    }
+    h->nblk_max = std::max({cg.total(), rg.total(), h->fg.nunits, div_up(N, kBlock), 1});
     ALLOC(h->partials, 3LL * h->nblk_max);
     // --- validation on the device -----------------------------------------------------------
     qcpd_status rc = scan_finite(h, {Pv, Av, dq_, db_, dx_, dy_, ds_},
@@ -397,6 +423,7 @@ qcpd_status create_impl(qcpd_handle *h, const qcpd_csr *P, const qcpd_csr *A, co
     HIPCHK(hipGetLastError());
     if (h->host_flag[2]) return QCPD_ERR_CONE;  // projection root-find or eigensolver failed
     if (h->lds > 0) set_cone_kernel_lds(h->lds);
+    set_fused_kernel_lds(h->lds_fused);
     h->create_flags = h->host_flag[1] ? 2u : 0u;
     return h->host_flag[1] ? QCPD_WARN_NONDIFF : QCPD_OK;
 }
@@ -447,7 +474,7 @@ qcpd_status qcpd_create(qcpd_handle **out, const qcpd_csr *P, const qcpd_csr *A,
     if ((K->n_soc > 0 && !K->soc_dims) || (K->n_psd > 0 && !K->psd_orders)) return QCPD_ERR_CONE;
     long long rows = (long long)K->n_zero + K->n_nonneg + 3LL * K->n_exp;
     for (int i = 0; i < K->n_soc; ++i) {
-        if (K->soc_dims[i] < 1) return QCPD_ERR_CONE;
+        if (K->soc_dims[i] < 1 || K->soc_dims[i] > kUnitRows) return QCPD_ERR_CONE;
         rows += K->soc_dims[i];
     }
     for (int i = 0; i < K->n_psd; ++i) {
@@ -570,12 +597,10 @@ qcpd_status qcpd_vjp(qcpd_handle *h, const double *gx, const double *gy, const d
     rc = run_lsqr(h, 1, sc);
     if (rc != QCPD_OK) return rc;
     // explicit residual ||F'w + dz|| with w = sol, then dtheta = D_theta N'[w]
-    StepArgs t1 = base_args(h, sc);
-    t1.in = h->sol; t1.in_nrm = NRM_ONE;
-    launch_rows_FT(p, t1, h->rg, s);
-    StepArgs t2 = t1;
-    t2.out = h->scratch; t2.role = ROLE_RESID;
-    launch_cone_FT(p, t2, h->cg, h->lds, s);
+    StepArgs t = base_args(h, sc);
+    t.in = h->sol; t.in_nrm = NRM_ONE;
+    t.out = h->scratch; t.role = ROLE_RESID;
+    launch_fused_FT(p, t, h->fg, h->lds_fused, s);
     launch_vjp_out(p, h->rg, h->sol, dP, dA, dq, db, s);
     HIPCHK(hipEventRecord(h->ev1, s));
     HIPCHK(hipMemcpyAsync(h->host_st, h->st, sizeof(LsqrState), hipMemcpyDeviceToHost, s));
@@ -594,15 +619,12 @@ qcpd_status qcpd_profile_kernels(qcpd_handle *h, int32_t reps, float *ms_out) {
     StepArgs a = base_args(h, sc);
     StepArgs f = a;
     f.in = h->v; f.in_is_v = 1; f.out = h->scratch;
-    StepArgs t1 = a;
-    t1.in = h->u;
-    StepArgs t2 = t1;
-    t2.out = h->scratch; t2.do_pre = 1; t2.out_is_v = 1;
-    for (int kid = 0; kid < 3; ++kid) {
+    StepArgs t = a;
+    t.in = h->u; t.out = h->scratch; t.do_pre = 1; t.out_is_v = 1;
+    for (int kid = 0; kid < 2; ++kid) {
         auto launch = [&]() {
             if (kid == 0) launch_rows_F(h->p, f, h->rg, s);
-            else if (kid == 1) launch_rows_FT(h->p, t1, h->rg, s);
-            else launch_cone_FT(h->p, t2, h->cg, h->lds, s);
+            else launch_fused_FT(h->p, t, h->fg, h->lds_fused, s);
         };
         launch();  // warm
         HIPCHK(hipEventRecord(h->ev0, s));

@@ -21,229 +21,11 @@
 // input, so no launch waits on a reduction of its own.
 #include <algorithm>
 
+#include "cone_jv.h"
+#include "lsqr_dev.h"
 #include "qcpd_internal.h"
 
 namespace qcpd {
-
-constexpr double kSqrt2 = 1.41421356237309504880;
-constexpr double kRsqrt2 = 0.70710678118654752440;
-
-// ---------------------------------------------------------------------------------------
-// cone Jacobian-vector products, J = DPi_{K*}(z_y) per block
-// ---------------------------------------------------------------------------------------
-
-// Second-order cone (self-dual), one thread per cone. par = (mode, 1/||u||, c1, c2):
-// mode 0: J = 0; mode 1: J = I; mode 2 (||u|| > |t|):
-//   J(dt, du) = (1/2 (dt + uh'du),  1/2 uh dt + c1 du - c2 (uh'du) uh),
-//   uh = u/||u||, c1 = (t + ||u||)/(2||u||), c2 = t/(2||u||).
-template <class IN, class OUT>
-__device__ inline void soc_jv(const Problem &p, int cone, IN in, OUT out) {
-    const int r0 = p.soc_row[cone], k = p.soc_dim[cone];
-    const double *par = p.soc_par + 4 * cone;
-    const int mode = (int)par[0];
-    if (mode == 0) {
-        for (int i = 0; i < k; ++i) out(r0 + i, 0.0);
-        return;
-    }
-    if (mode == 1) {
-        for (int i = 0; i < k; ++i) out(r0 + i, in(r0 + i));
-        return;
-    }
-    const double inv_nu = par[1], c1 = par[2], c2 = par[3];
-    const double *u = p.zy + r0 + 1;
-    const double dt = in(r0);
-    double a = 0.0;
-    for (int i = 1; i < k; ++i) a += u[i - 1] * inv_nu * in(r0 + i);
-    out(r0, 0.5 * (dt + a));
-    for (int i = 1; i < k; ++i) {
-        const double uh = u[i - 1] * inv_nu;
-        out(r0 + i, 0.5 * uh * dt + c1 * in(r0 + i) - c2 * a * uh);
-    }
-}
-
-// Dual exponential cone, one thread per cone: a stored 3x3 matrix (I - DPi_exp(-z)).
-template <class IN, class OUT>
-__device__ inline void exp_jv(const Problem &p, int cone, IN in, OUT out) {
-    const int r0 = p.exp_row0 + 3 * cone;
-    const double *J = p.exp_J + 9 * cone;
-    const double a = in(r0), b = in(r0 + 1), c = in(r0 + 2);
-    out(r0, J[0] * a + J[1] * b + J[2] * c);
-    out(r0 + 1, J[3] * a + J[4] * b + J[5] * c);
-    out(r0 + 2, J[6] * a + J[7] * b + J[8] * c);
-}
-
-__device__ inline int svec_index(int i, int j, int k) {  // i >= j
-    return j * k - (j * (j - 1)) / 2 + (i - j);
-}
-
-// PSD cone on svec coordinates, one workgroup per cone:
-//   J[dZ] = V (B o (V' dZ V)) V'.
-// LDS: X, T, V as k x ld matrices (ld = k | 1, odd, to spread LDS banks).
-template <class IN, class OUT>
-__device__ inline void psd_jv(const Problem &p, int cone, double *sm, IN in, OUT out) {
-    const int k = p.psd_k[cone], r0 = p.psd_row[cone];
-    const int ld = k | 1, kk = k * k;
-    const double *Vg = p.psd_pool + p.psd_off[cone];
-    const double *Bg = Vg + kk;
-    double *X = sm, *T = sm + k * ld, *V = sm + 2 * k * ld;
-    const int tid = threadIdx.x;
-    for (int e = tid; e < kk; e += kBlock) {
-        const int i = e / k, j = e - (e / k) * k;
-        V[i * ld + j] = Vg[e];
-        if (i >= j) {
-            double v = in(r0 + svec_index(i, j, k));
-            if (i == j) {
-                X[i * ld + i] = v;
-            } else {
-                v *= kRsqrt2;
-                X[i * ld + j] = v;
-                X[j * ld + i] = v;
-            }
-        }
-    }
-    __syncthreads();
-    for (int e = tid; e < kk; e += kBlock) {  // T = X V
-        const int i = e / k, j = e - (e / k) * k;
-        double acc = 0.0;
-        for (int l = 0; l < k; ++l) acc += X[i * ld + l] * V[l * ld + j];
-        T[i * ld + j] = acc;
-    }
-    __syncthreads();
-    for (int e = tid; e < kk; e += kBlock) {  // X = B o (V' T)
-        const int i = e / k, j = e - (e / k) * k;
-        double acc = 0.0;
-        for (int l = 0; l < k; ++l) acc += V[l * ld + i] * T[l * ld + j];
-        X[i * ld + j] = Bg[e] * acc;
-    }
-    __syncthreads();
-    for (int e = tid; e < kk; e += kBlock) {  // T = V X
-        const int i = e / k, j = e - (e / k) * k;
-        double acc = 0.0;
-        for (int l = 0; l < k; ++l) acc += V[i * ld + l] * X[l * ld + j];
-        T[i * ld + j] = acc;
-    }
-    __syncthreads();
-    for (int e = tid; e < kk; e += kBlock) {  // Y = T V', lower triangle into svec
-        const int i = e / k, j = e - (e / k) * k;
-        if (i >= j) {
-            double acc = 0.0;
-            for (int l = 0; l < k; ++l) acc += T[i * ld + l] * V[j * ld + l];
-            out(r0 + svec_index(i, j, k), i == j ? acc : acc * kSqrt2);
-        }
-    }
-    __syncthreads();
-}
-
-__device__ inline int psd_stage_offset(int k) { return 3 * k * (k | 1); }
-
-// ---------------------------------------------------------------------------------------
-// LSQR bookkeeping
-// ---------------------------------------------------------------------------------------
-
-__device__ inline void finalize(LsqrState *st, int role, const double tot[3], bool dot_is_fwd) {
-    switch (role) {
-    case ROLE_U: {
-        const double beta = sqrt(tot[0]);
-        st->beta = beta;
-        st->pending = 0;
-        if (dot_is_fwd) st->dot_fwd = tot[1]; else st->dot_adj = tot[1];
-        if (!(beta > 0.0)) { st->done = 1; st->conv = 1; }
-        break;
-    }
-    case ROLE_V0: {
-        const double alpha = sqrt(tot[0]);
-        st->alpha = alpha;
-        st->rhobar = alpha;
-        st->phibar = st->beta1;
-        st->phr = 0.0;
-        st->thr = 0.0;
-        st->pending = 0;
-        if (dot_is_fwd) st->dot_fwd = tot[1]; else st->dot_adj = tot[1];
-        if (!(alpha > 0.0)) { st->done = 1; st->conv = 1; }
-        break;
-    }
-    case ROLE_V: {
-        // plane rotation that eliminates beta (Paige & Saunders), then the x/w update is
-        // owed to the next iteration's first kernel (or the final flush)
-        const double alpha = sqrt(tot[0]);
-        const double beta = st->beta, rhobar = st->rhobar;
-        const double rho = hypot(rhobar, beta);
-        if (!(rho > 0.0)) { st->done = 1; st->conv = 1; st->pending = 0; break; }
-        const double c = rhobar / rho, s = beta / rho;
-        const double theta = s * alpha;
-        const double phi = c * st->phibar;
-        st->rhobar = -c * alpha;
-        st->phibar = s * st->phibar;
-        st->phr = phi / rho;
-        st->thr = theta / rho;
-        st->pending = 1;
-        st->iters += 1;
-        st->alpha = alpha;
-        if (dot_is_fwd) st->dot_fwd = tot[1]; else st->dot_adj = tot[1];
-        if (st->phibar <= st->tol * st->beta1 || !(alpha > 0.0)) {
-            st->done = 1;
-            st->conv = 1;
-        } else if (st->iters >= st->max_iter) {
-            st->done = 1;
-        }
-        break;
-    }
-    case ROLE_RESID:
-        st->resid = sqrt(tot[0]);
-        break;
-    default:
-        if (dot_is_fwd) st->dot_fwd = tot[1]; else st->dot_adj = tot[1];
-        break;
-    }
-}
-
-struct Ctx {  // per-launch scalars every thread derives from the state block
-    double inv, cU, cV, inv_alpha_up, phr, thr, in_N;
-    bool in_sc, out_sc;
-};
-
-__device__ inline Ctx make_ctx(const Problem &p, const StepArgs &a) {
-    const LsqrState *st = a.st;
-    const double *sv = reinterpret_cast<const double *>(st);
-    Ctx c;
-    c.inv = 1.0 / sv[a.in_nrm];
-    c.cU = (a.role == ROLE_U) ? st->alpha / st->beta : 0.0;
-    c.cV = (a.role == ROLE_V) ? st->beta / st->alpha : 0.0;
-    c.inv_alpha_up = a.do_update ? 1.0 / st->alpha : 0.0;
-    c.phr = st->phr;
-    c.thr = st->thr;
-    c.in_sc = a.in_is_v && a.sc != nullptr;
-    c.out_sc = a.out_is_v && a.sc != nullptr;
-    const int N1 = p.N - 1;
-    c.in_N = a.in[N1] * c.inv * (c.in_sc ? a.sc[N1] : 1.0);
-    return c;
-}
-
-__device__ inline double ldin(const StepArgs &a, const Ctx &c, int i) {
-    const double v = a.in[i] * c.inv;
-    return c.in_sc ? v * a.sc[i] : v;
-}
-
-__device__ inline double role_value(const StepArgs &a, const Ctx &c, int idx, double val) {
-    switch (a.role) {
-    case ROLE_U: return val - c.cU * a.out[idx];
-    case ROLE_V: return (c.out_sc ? a.sc[idx] : 1.0) * val - c.cV * a.out[idx];
-    case ROLE_V0: return (c.out_sc ? a.sc[idx] : 1.0) * val;
-    case ROLE_RESID: return val - a.rhs[idx];
-    default: return val;
-    }
-}
-
-__device__ inline void lsqr_update(const StepArgs &a, const Ctx &c, int idx) {
-    const double w = a.wk[idx];
-    a.xk[idx] += c.phr * w;
-    a.wk[idx] = a.in[idx] * c.inv_alpha_up - c.thr * w;
-}
-
-__device__ inline double group_sum(double v, int L) {
-    for (int off = L >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    return v;
-}
 
 // ---------------------------------------------------------------------------------------
 // product with F: CSR rows
@@ -252,7 +34,7 @@ __device__ inline double group_sum(double v, int L) {
 __global__ __launch_bounds__(kBlock) void k_rows_F(Problem p, StepArgs a, RowGrid g) {
     LsqrState *st = a.st;
     if (a.check_done && st->done) return;
-    const Ctx c = make_ctx(p, a);
+    const Ctx c = make_ctx(a, p.N - 1);
     const int n = p.n, m = p.m, N = p.N;
     const int tid = threadIdx.x;
     const bool xr = blockIdx.x < (unsigned)g.bx;
@@ -311,7 +93,7 @@ __global__ __launch_bounds__(kBlock) void k_rows_F(Problem p, StepArgs a, RowGri
 __global__ __launch_bounds__(kBlock) void k_rows_FT(Problem p, StepArgs a, RowGrid g) {
     LsqrState *st = a.st;
     if (a.check_done && st->done) return;
-    const Ctx c = make_ctx(p, a);
+    const Ctx c = make_ctx(a, p.N - 1);
     const int n = p.n, m = p.m, N = p.N;
     const int tid = threadIdx.x;
     const bool xr = blockIdx.x < (unsigned)g.bx;
@@ -354,7 +136,7 @@ __global__ __launch_bounds__(kBlock) void k_cone_FT(Problem p, StepArgs a, ConeG
     extern __shared__ double sm[];
     LsqrState *st = a.st;
     if (a.check_done && st->done) return;
-    const Ctx c = make_ctx(p, a);
+    const Ctx c = make_ctx(a, p.N - 1);
     const int n = p.n, N = p.N;
     const int tid = threadIdx.x;
     double s0 = 0.0, s1 = 0.0;
@@ -419,6 +201,44 @@ __global__ __launch_bounds__(kBlock) void k_cone_FT(Problem p, StepArgs a, ConeG
     double tot[3];
     if (last_block_sum3(s0, s1, 0.0, a.partials, a.counter, gridDim.x, tot) && tid == 0)
         finalize(st, a.role, tot, true);
+}
+
+// ---------------------------------------------------------------------------------------
+// product with F', fused: each workgroup forms the rows of D_u Q'r for one work unit and
+// applies that unit's block of J in LDS, so no launch boundary separates the two halves:
+//   x rows:  (F'r)_x = P r_x - A'r_y + c r_N
+//   y rows:  t = A r_x - b r_N - r_y,  (F'r)_y = J t + r_y      (per cone block)
+//   tau:     (F'r)_N = q'r_x + b'r_y + x'Px r_N                  (dot accumulated earlier)
+// then the LSQR role update and, when asked, the J of the next product with F.
+// ---------------------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_fused_FT(Problem p, StepArgs a, FusedGrid g) {
+    extern __shared__ double sm[];
+    LsqrState *st = a.st;
+    if (a.check_done && st->done) return;
+    const int N = p.N;
+    const Ctx c = make_ctx(a, N - 1);
+    const int tid = threadIdx.x;
+    double s0 = 0.0, s1 = 0.0;
+    fused_unit(p, a, c, g.lx, g.ly, g.units[blockIdx.x], sm, s0, s1);
+    if (blockIdx.x == 0 && tid == 0) {  // the tau entry
+        const double o = role_value(a, c, N - 1, st->dot_adj * c.inv + p.xPx * c.in_N);
+        a.out[N - 1] = o;
+        s0 += o * o;
+        if (a.do_update) lsqr_update(a, c, N - 1);
+    }
+    double tot[3];
+    if (last_block_sum3(s0, s1, 0.0, a.partials, a.counter, gridDim.x, tot) && tid == 0)
+        finalize(st, a.role, tot, true);
+}
+
+void set_fused_kernel_lds(int bytes) {
+    hipFuncSetAttribute((const void *)k_fused_FT, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+int fused_lds_bytes(int kmax) {
+    const int psd = kmax > 0 ? (3 * kmax * (kmax | 1) + kmax * (kmax + 1)) : 0;
+    return (int)sizeof(double) * std::max(2 * kUnitRows, psd);
 }
 
 // wy = J(s o in_y) (raw, no normaliser) and dot_fwd = c'(s o in)_x - b'wy, for a product
@@ -701,6 +521,9 @@ void launch_rows_FT(const Problem &p, const StepArgs &a, const RowGrid &g, hipSt
 void launch_cone_FT(const Problem &p, const StepArgs &a, const ConeGrid &g, int lds, hipStream_t s) {
     hipLaunchKernelGGL(k_cone_FT, dim3(g.total()), dim3(kBlock), lds, s, p, a, g);
 }
+void launch_fused_FT(const Problem &p, const StepArgs &a, const FusedGrid &g, int lds, hipStream_t s) {
+    hipLaunchKernelGGL(k_fused_FT, dim3(g.nunits), dim3(kBlock), lds, s, p, a, g);
+}
 void launch_cone_pre(const Problem &p, const StepArgs &a, const ConeGrid &g, int lds, hipStream_t s) {
     hipLaunchKernelGGL(k_cone_pre, dim3(g.total()), dim3(kBlock), lds, s, p, a, g);
 }
@@ -742,6 +565,7 @@ void set_cone_kernel_lds(int bytes) {
     hipFuncSetAttribute((const void *)k_cone_FT, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     hipFuncSetAttribute((const void *)k_cone_pre, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     hipFuncSetAttribute((const void *)k_vjp_rhs, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+
 }
 
 }  // namespace qcpd

@@ -59,6 +59,7 @@ struct Problem {
     const double *soc_par;          // 4 per cone: mode, 1/||u||, c1, c2
     int n_exp;
     int exp_row0;                   // first y-row of the exponential cones (3 rows each)
+    const int *exp_rows;            // or, when not null, the first y-row of each cone
     const double *exp_J;            // 9 per cone, row-major, J of the dual exponential cone
     int n_psd;
     const int *psd_row, *psd_k;
@@ -183,7 +184,26 @@ struct StepArgs {
     int check_done;     // return at once when st->done is set (kernels inside the loop)
 };
 
+// Work units of the fused product with F' (one workgroup each): x rows, diagonal y rows,
+// runs of whole SOC or exponential cones, or one PSD cone. Rows of D_u Q' r for the unit
+// are formed in LDS and the unit's block of J is applied to them in the same workgroup.
+enum UnitType { U_XROWS = 0, U_DIAG = 1, U_SOC = 2, U_EXP = 3, U_PSD = 4 };
+struct Unit {
+    int type, begin, end, row0;  // row0: first y row of a cone run (SOC / exp / PSD)
+};
+constexpr int kUnitRows = 1024;   // most y rows staged by one SOC / exp unit
+
+struct FusedGrid {
+    int nunits;
+    const Unit *units;   // device table
+    int lx, ly;
+};
+
 // host launchers (apply.hip)
+void launch_fused_FT(const Problem &p, const StepArgs &a, const FusedGrid &g, int lds_bytes,
+                     hipStream_t s);
+int fused_lds_bytes(int kmax);
+void set_fused_kernel_lds(int bytes);
 void launch_rows_F(const Problem &p, const StepArgs &a, const RowGrid &g, hipStream_t s);
 void launch_rows_FT(const Problem &p, const StepArgs &a, const RowGrid &g, hipStream_t s);
 void launch_cone_FT(const Problem &p, const StepArgs &a, const ConeGrid &g, int lds_bytes,

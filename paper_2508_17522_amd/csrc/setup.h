@@ -25,7 +25,7 @@ void launch_cone_factors(const Problem &p, const ConeHost &ch, double *jdiag, do
                          double *exp_J, double *pool, int *nondiff, int *fail, int psd_lds,
                          hipStream_t s);
 void launch_scales(const Problem &p, const RowGrid &g, double *dj, double *dv, double *partials,
-                   int *counter, hipStream_t s);
+                   int *counter, hipStream_t s, int do_tau = 1);
 int psd_factor_lds_bytes(int kmax);
 void set_cone_kernel_lds(int bytes);
 

@@ -280,11 +280,11 @@ __device__ bool exp_root(double x0, double y0, double z0, double &r_out) {
 // In the smooth case DPi_exp is the leading 3x3 block of the inverse of the bordered
 // matrix [[H, g], [g', 0]] with H = I + mu Hess(y e^{x/y}) and g = grad(y e^{x/y} - z),
 // evaluated as H^-1 - (H^-1 g)(H^-1 g)'/(g' H^-1 g).
-__global__ void k_exp_factors(const double *zy, int row0, int n_exp, double *Jout, double *jdiag,
-                              int *nondiff, int *fail) {
+__global__ void k_exp_factors(const double *zy, int row0, const int *rows, int n_exp, double *Jout,
+                              double *jdiag, int *nondiff, int *fail) {
     const int cone = blockIdx.x * blockDim.x + threadIdx.x;
     if (cone >= n_exp) return;
-    const int r0 = row0 + 3 * cone;
+    const int r0 = rows ? rows[cone] : row0 + 3 * cone;
     const double x0 = -zy[r0], y0 = -zy[r0 + 1], z0 = -zy[r0 + 2];  // p = -z
     const double scale = fmax(1.0, fmax(fabs(x0), fmax(fabs(y0), fabs(z0))));
     const double tol = kKinkTol * scale;
@@ -497,7 +497,7 @@ __global__ __launch_bounds__(kBlock) void k_psd_factors(const double *zy, const 
 __device__ inline double inv_norm(double s2) { return s2 > 0.0 ? 1.0 / sqrt(s2) : 1.0; }
 
 __global__ __launch_bounds__(kBlock) void k_scales(Problem p, RowGrid g, double *dj, double *dv,
-                                                   double *partials, int *counter) {
+                                                   double *partials, int *counter, int do_tau) {
     const int tid = threadIdx.x;
     const bool xr = blockIdx.x < (unsigned)g.bx;
     const int L = xr ? g.lx : g.ly;
@@ -536,7 +536,7 @@ __global__ __launch_bounds__(kBlock) void k_scales(Problem p, RowGrid g, double 
         }
     }
     double tot[3];
-    if (last_block_sum3(s0, s1, 0.0, partials, counter, gridDim.x, tot) && tid == 0) {
+    if (last_block_sum3(s0, s1, 0.0, partials, counter, gridDim.x, tot) && tid == 0 && do_tau) {
         const double x2 = p.xPx * p.xPx;
         dj[p.N - 1] = inv_norm(tot[0] + x2);
         dv[p.N - 1] = inv_norm(tot[1] + x2);
@@ -579,7 +579,7 @@ void launch_cone_factors(const Problem &p, const ConeHost &ch, double *jdiag, do
                            p.soc_row, p.soc_dim, p.n_soc, soc_par, jdiag, nondiff);
     if (p.n_exp > 0)
         hipLaunchKernelGGL(k_exp_factors, dim3(div_up(p.n_exp, 64)), dim3(64), 0, s, p.zy,
-                           p.exp_row0, p.n_exp, exp_J, jdiag, nondiff, fail);
+                           p.exp_row0, p.exp_rows, p.n_exp, exp_J, jdiag, nondiff, fail);
     if (p.n_psd > 0) {
         hipFuncSetAttribute((const void *)k_psd_factors, hipFuncAttributeMaxDynamicSharedMemorySize, psd_lds);
         hipLaunchKernelGGL(k_psd_factors, dim3(p.n_psd), dim3(kBlock), psd_lds, s, p.zy, p.psd_row,
@@ -587,8 +587,9 @@ void launch_cone_factors(const Problem &p, const ConeHost &ch, double *jdiag, do
     }
 }
 void launch_scales(const Problem &p, const RowGrid &g, double *dj, double *dv, double *partials,
-                   int *counter, hipStream_t s) {
-    hipLaunchKernelGGL(k_scales, dim3(g.total()), dim3(kBlock), 0, s, p, g, dj, dv, partials, counter);
+                   int *counter, hipStream_t s, int do_tau) {
+    hipLaunchKernelGGL(k_scales, dim3(g.total()), dim3(kBlock), 0, s, p, g, dj, dv, partials, counter,
+                       do_tau);
 }
 
 int psd_factor_lds_bytes(int kmax) {

@@ -176,7 +176,7 @@ def test_not_converged_warning():
 
 
 def test_deterministic():
-    q = qcpgen.small_mixed(1, n=120, A_density=0.08)
+    q = qcpgen.small_mixed(1, n=120, A_density=0.08, P_rank=100, P_eps=0.1)
     h, t = make_handle(q, tol=1e-10)
     a = gpu_jvp(h, t)
     b = gpu_jvp(h, t)
