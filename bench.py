@@ -41,14 +41,11 @@ def kernel_bytes(q, which: str) -> float:
         # in, scale, J-input wy, q, b, out read+write, LSQR x and w read+write
         vec = 8.0 * (N + N + m + n + m + 2 * N + 4 * N)
         return csr + vec
-    if which == "rows_FT":
-        # in, c, b, staged output
-        return csr + 8.0 * (N + n + m + N)
-    if which == "cone_FT":
+    if which == "fused_FT":
         c = q.cones
         fac = 8.0 * (4 * len(c.soc) + sum(c.soc) + 9 * c.n_exp + sum(2 * k * k for k in c.psd))
-        # staged input, in (y + tau), out read+write, scale, jdiag, wy write, c, b
-        return fac + 8.0 * (N + m + 1 + 2 * N + N + c.n_zero + c.n_nonneg + m + n + m)
+        # in, c, b, out read+write, scale, jdiag of diagonal rows, wy write
+        return csr + fac + 8.0 * (N + n + m + 2 * N + N + c.n_zero + c.n_nonneg + m)
     raise ValueError(which)
 
 
@@ -105,6 +102,7 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precond", default="jacobi", choices=["jacobi", "none"])
+    ap.add_argument("--engine", default="auto", choices=["auto", "graph", "persistent"])
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; the derivative of one QCP is not "
@@ -123,7 +121,9 @@ def main():
     t = to_device(q, dev)
     cones = cones_of(q)
     prec = Q.QCPD_PRECOND_JACOBI if args.precond == "jacobi" else Q.QCPD_PRECOND_NONE
-    opts = Q.Opts(tol=args.tol, precond=prec)
+    eng = {"auto": Q.QCPD_ENGINE_AUTO, "graph": Q.QCPD_ENGINE_GRAPH,
+           "persistent": Q.QCPD_ENGINE_PERSISTENT}[args.engine]
+    opts = Q.Opts(tol=args.tol, precond=prec, engine=eng)
     outs = dict(dx=torch.empty(q.n, dtype=torch.float64, device=dev),
                 dy=torch.empty(q.m, dtype=torch.float64, device=dev),
                 ds=torch.empty(q.m, dtype=torch.float64, device=dev),
@@ -163,7 +163,7 @@ def main():
     h = step(None)
     ms = Q.qcpd_profile_kernels(h, reps=200)
     h.close()
-    names = ["rows_F", "rows_FT", "cone_FT"]
+    names = ["rows_F", "fused_FT"]
     iters_total = rec[-1]["ij"].iters + rec[-1]["iv"].iters
     dom = int(np.argmax(ms))
     dom_name = names[dom]
@@ -190,6 +190,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": q.name, "n": q.n, "m": q.m, "nnz_P": int(q.P.nnz),
                    "nnz_A": int(q.A.nnz), "tol": args.tol, "precond": args.precond,
+                   "engine": args.engine,
                    "cones": {"zero": q.cones.n_zero, "nonneg": q.cones.n_nonneg,
                              "soc": len(q.cones.soc), "psd": len(q.cones.psd),
                              "exp": q.cones.n_exp}},

@@ -88,7 +88,17 @@ typedef struct {
     int32_t precond;      /* QCPD_PRECOND_*                                   (JACOBI)         */
     int32_t graph_chunk;  /* LSQR iterations per captured HIP graph launch     (32)            */
     int32_t check_symmetry; /* verify that P is symmetric at create              (1)           */
+    int32_t engine;       /* LSQR driver: QCPD_ENGINE_AUTO, _GRAPH, _PERSISTENT (AUTO)         */
 } qcpd_opts;
+
+/* LSQR drivers of the single-problem path. GRAPH: two launches per iteration, captured in
+ * HIP graphs of graph_chunk iterations, the host polling a device stop flag per graph.
+ * PERSISTENT: the whole loop in one cooperative launch with two grid barriers per iteration.
+ * AUTO picks PERSISTENT when the device supports cooperative launches. Both give the same
+ * results up to the order of floating-point sums. */
+#define QCPD_ENGINE_AUTO        0
+#define QCPD_ENGINE_GRAPH       1
+#define QCPD_ENGINE_PERSISTENT  2
 
 typedef struct {
     int32_t  iters;          /* LSQR iterations                                              */

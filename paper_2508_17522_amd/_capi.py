@@ -26,7 +26,7 @@ class qcpd_cones(ctypes.Structure):
 
 class qcpd_opts(ctypes.Structure):
     _fields_ = [("tol", c_double), ("max_iter", c_int32), ("precond", c_int32),
-                ("graph_chunk", c_int32), ("check_symmetry", c_int32)]
+                ("graph_chunk", c_int32), ("check_symmetry", c_int32), ("engine", c_int32)]
 
 
 class qcpd_info(ctypes.Structure):
@@ -44,6 +44,10 @@ QCPD_ERR_PATTERN = -4
 QCPD_ERR_NAN = -5
 QCPD_ERR_HIP = -6
 QCPD_ERR_OOM = -7
+
+QCPD_ENGINE_AUTO = 0
+QCPD_ENGINE_GRAPH = 1
+QCPD_ENGINE_PERSISTENT = 2
 
 QCPD_PRECOND_NONE = 0
 QCPD_PRECOND_JACOBI = 1

@@ -64,10 +64,11 @@ class Opts:
     precond: int = C.QCPD_PRECOND_JACOBI
     graph_chunk: int = 32
     check_symmetry: int = 1
+    engine: int = C.QCPD_ENGINE_AUTO
 
     def to_c(self) -> C.qcpd_opts:
         return C.qcpd_opts(self.tol, self.max_iter, self.precond, self.graph_chunk,
-                           self.check_symmetry)
+                           self.check_symmetry, self.engine)
 
 
 @dataclasses.dataclass
@@ -116,7 +117,7 @@ def qcpd_status_str(status: int) -> str:
 def qcpd_opts_default() -> Opts:
     o = C.qcpd_opts()
     _lib().qcpd_opts_default(ctypes.byref(o))
-    return Opts(o.tol, o.max_iter, o.precond, o.graph_chunk, o.check_symmetry)
+    return Opts(o.tol, o.max_iter, o.precond, o.graph_chunk, o.check_symmetry, o.engine)
 
 
 def _csr(rowptr, colind, val, nrows, ncols, name):

@@ -3,6 +3,7 @@
 // back to the host. The LSQR iterations run as captured HIP graphs of `graph_chunk`
 // iterations each; the host reads the device stop flag once per graph launch.
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -25,6 +26,8 @@ struct qcpd_handle {
     FusedGrid fg{};
     int lds = 0;
     int lds_fused = 0;
+    int persist_grid = 0;              // 0: cooperative launch unavailable
+    double *persist_partials = nullptr;
     int nblk_max = 0;
     std::vector<void *> allocs;
     double *u = nullptr, *v = nullptr, *xk = nullptr, *wk = nullptr, *tmp = nullptr,
@@ -96,7 +99,8 @@ void free_handle(qcpd_handle *h) {
 
 qcpd_status check_opts(const qcpd_opts *o) {
     if (!(o->tol >= 0.0) || o->max_iter < 0 || o->graph_chunk < 1 || o->graph_chunk > 4096 ||
-        o->precond < QCPD_PRECOND_NONE || o->precond > QCPD_PRECOND_CUSTOM)
+        o->precond < QCPD_PRECOND_NONE || o->precond > QCPD_PRECOND_CUSTOM ||
+        o->engine < QCPD_ENGINE_AUTO || o->engine > QCPD_ENGINE_PERSISTENT)
         return QCPD_ERR_INVALID_ARG;
     return QCPD_OK;
 }
@@ -218,6 +222,26 @@ qcpd_status run_lsqr(qcpd_handle *h, int dir, const double *sc) {
         f.in = h->u; f.in_nrm = NRM_BETA;
         f.out = h->v; f.role = ROLE_V0; f.out_is_v = 1;
         launch_rows_F(h->p, f, h->rg, s);
+    }
+    const bool persistent = h->persist_grid > 0 && (h->opts.engine == QCPD_ENGINE_PERSISTENT ||
+                                                     h->opts.engine == QCPD_ENGINE_AUTO);
+    if (persistent) {
+        StepArgs f = a, t = a;
+        if (dir == 0) {
+            f.in = h->v; f.in_nrm = NRM_ALPHA; f.in_is_v = 1; f.out = h->u; f.role = ROLE_U; f.do_update = 1;
+            t.in = h->u; t.in_nrm = NRM_BETA; t.out = h->v; t.role = ROLE_V; t.out_is_v = 1; t.do_pre = 1;
+        } else {
+            t.in = h->v; t.in_nrm = NRM_ALPHA; t.in_is_v = 1; t.do_update = 1;
+            t.out = h->u; t.role = ROLE_U; t.do_pre = 1;
+            f.in = h->u; f.in_nrm = NRM_BETA; f.out = h->v; f.role = ROLE_V; f.out_is_v = 1;
+        }
+        HIPCHK(launch_lsqr_persistent(h->p, f, t, h->rg, h->fg, dir, h->st, h->persist_partials,
+                                      h->persist_grid, h->lds_fused, s));
+        HIPCHK(hipMemcpyAsync(h->host_st, h->st, sizeof(LsqrState), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        StepArgs fl = base_args(h, sc);
+        launch_flush(h->p, fl, h->sol, div_up(h->p.N, kBlock), s);
+        return QCPD_OK;
     }
     qcpd_status rc = ensure_graph(h, dir, sc);
     if (rc != QCPD_OK) return rc;
@@ -424,6 +448,23 @@ qcpd_status create_impl(qcpd_handle *h, const qcpd_csr *P, const qcpd_csr *A, co
     if (h->host_flag[2]) return QCPD_ERR_CONE;  // projection root-find or eigensolver failed
     if (h->lds > 0) set_cone_kernel_lds(h->lds);
     set_fused_kernel_lds(h->lds_fused);
+    // persistent LSQR: as many co-resident workgroups as the work needs, at most one wave of
+    // the whole device (QCPD_PERSIST_GRID overrides the count, for tuning)
+    {
+        int coop = 0, ncu = 0;
+        hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, h->device);
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device);
+        const int per_cu = coop ? persistent_blocks_per_cu(h->lds_fused) : 0;
+        if (per_cu > 0) {
+            int g = std::min(per_cu * ncu, std::max(rg.total(), h->fg.nunits));
+            if (const char *env = getenv("QCPD_PERSIST_GRID")) {
+                const int e = atoi(env);
+                if (e > 0) g = std::min(e, per_cu * ncu);
+            }
+            h->persist_grid = std::max(g, 1);
+            ALLOC(h->persist_partials, 6LL * h->persist_grid);
+        }
+    }
     h->create_flags = h->host_flag[1] ? 2u : 0u;
     return h->host_flag[1] ? QCPD_WARN_NONDIFF : QCPD_OK;
 }
@@ -439,6 +480,7 @@ void qcpd_opts_default(qcpd_opts *o) {
     o->precond = QCPD_PRECOND_JACOBI;
     o->graph_chunk = 32;
     o->check_symmetry = 1;
+    o->engine = QCPD_ENGINE_AUTO;
 }
 
 const char *qcpd_status_str(qcpd_status s) {

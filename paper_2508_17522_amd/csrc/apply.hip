@@ -19,6 +19,8 @@
 // The J needed by the next product with F is applied inside cone_FT (block-local), and the
 // tau-row dot products of each product are accumulated by the kernel that produces its
 // input, so no launch waits on a reduction of its own.
+#include <hip/hip_cooperative_groups.h>
+
 #include <algorithm>
 
 #include "cone_jv.h"
@@ -27,19 +29,21 @@
 
 namespace qcpd {
 
+namespace cg = cooperative_groups;
+
 // ---------------------------------------------------------------------------------------
 // product with F: CSR rows
 // ---------------------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kBlock) void k_rows_F(Problem p, StepArgs a, RowGrid g) {
-    LsqrState *st = a.st;
-    if (a.check_done && st->done) return;
-    const Ctx c = make_ctx(a, p.N - 1);
+// The rows of one virtual workgroup `vb` of the product with F: x rows (P and A'), then y
+// rows and the tau row (A). Accumulates ||out||^2 (s0) and the F' tau-row dot (s1).
+__device__ inline void rows_F_vblock(const Problem &p, const StepArgs &a, const Ctx &c,
+                                     const RowGrid &g, int vb, double &s0, double &s1) {
     const int n = p.n, m = p.m, N = p.N;
     const int tid = threadIdx.x;
-    const bool xr = blockIdx.x < (unsigned)g.bx;
+    const bool xr = vb < g.bx;
     const int L = xr ? g.lx : g.ly;
-    const long long gt = (long long)(xr ? blockIdx.x : blockIdx.x - g.bx) * kBlock + tid;
+    const long long gt = (long long)(xr ? vb : vb - g.bx) * kBlock + tid;
     const int row = (int)(gt / L), lane = (int)(gt & (L - 1));
     double acc = 0.0, accT = 0.0;
     int idx = -1;
@@ -62,7 +66,6 @@ __global__ __launch_bounds__(kBlock) void k_rows_F(Problem p, StepArgs a, RowGri
     }
     acc = group_sum(acc, L);
     accT = group_sum(accT, L);
-    double s0 = 0.0, s1 = 0.0;
     if (lane == 0 && idx >= 0) {
         double val;
         if (idx < n) {
@@ -71,18 +74,26 @@ __global__ __launch_bounds__(kBlock) void k_rows_F(Problem p, StepArgs a, RowGri
             const int r = idx - n;
             val = -acc + p.b[r] * c.in_N - a.wy[r] * c.inv + ldin(a, c, idx);
         } else {
-            val = st->dot_fwd * c.inv + p.xPx * c.in_N;
+            val = a.st->dot_fwd * c.inv + p.xPx * c.in_N;
         }
         const double o = role_value(a, c, idx, val);
         a.out[idx] = o;
-        s0 = o * o;
+        s0 += o * o;
         const double nsc = c.out_sc ? a.sc[idx] : 1.0;
-        if (idx < n) s1 = p.q[idx] * nsc * o;
-        else if (idx < N - 1) s1 = p.b[idx - n] * nsc * o;
+        if (idx < n) s1 += p.q[idx] * nsc * o;
+        else if (idx < N - 1) s1 += p.b[idx - n] * nsc * o;
         if (a.do_update) lsqr_update(a, c, idx);
     }
+}
+
+__global__ __launch_bounds__(kBlock) void k_rows_F(Problem p, StepArgs a, RowGrid g) {
+    LsqrState *st = a.st;
+    if (a.check_done && st->done) return;
+    const Ctx c = make_ctx(a, p.N - 1);
+    double s0 = 0.0, s1 = 0.0;
+    rows_F_vblock(p, a, c, g, blockIdx.x, s0, s1);
     double tot[3];
-    if (last_block_sum3(s0, s1, 0.0, a.partials, a.counter, gridDim.x, tot) && tid == 0)
+    if (last_block_sum3(s0, s1, 0.0, a.partials, a.counter, gridDim.x, tot) && threadIdx.x == 0)
         finalize(st, a.role, tot, false);
 }
 
@@ -239,6 +250,91 @@ void set_fused_kernel_lds(int bytes) {
 int fused_lds_bytes(int kmax) {
     const int psd = kmax > 0 ? (3 * kmax * (kmax | 1) + kmax * (kmax + 1)) : 0;
     return (int)sizeof(double) * std::max(2 * kUnitRows, psd);
+}
+
+// ---------------------------------------------------------------------------------------
+// The whole LSQR loop in one cooperative launch. Each iteration is two phases (the product
+// with F over CSR rows, the fused product with F'), each ending in one grid barrier. After a
+// barrier every workgroup reduces the per-block partial sums in the same fixed order and runs
+// the same LSQR scalar update into its own LDS copy of the state, so the copies stay
+// identical without a second barrier. Partials are double-buffered by phase: a block can only
+// overwrite a buffer after the next barrier, by which time every block has read it.
+// ---------------------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_lsqr_persistent(Problem p, StepArgs fa, StepArgs ta,
+                                                            RowGrid rg, FusedGrid fg, int dir,
+                                                            LsqrState *gst, double *partials) {
+    extern __shared__ double sm[];
+    __shared__ LsqrState S;
+    cg::grid_group grid = cg::this_grid();
+    const int tid = threadIdx.x, G = gridDim.x, N = p.N;
+    if (tid == 0) S = *gst;
+    __syncthreads();
+    fa.st = &S;
+    ta.st = &S;
+    while (!S.done) {
+        for (int phase = 0; phase < 2; ++phase) {
+            const bool isF = (dir == 0) ? (phase == 0) : (phase == 1);
+            const StepArgs &a = isF ? fa : ta;
+            const Ctx c = make_ctx(a, N - 1);
+            double s0 = 0.0, s1 = 0.0, z = 0.0;
+            if (isF) {
+                for (int vb = blockIdx.x; vb < rg.bx + rg.by; vb += G) rows_F_vblock(p, a, c, rg, vb, s0, s1);
+            } else {
+                for (int ui = blockIdx.x; ui < fg.nunits; ui += G) {
+                    fused_unit(p, a, c, fg.lx, fg.ly, fg.units[ui], sm, s0, s1);
+                    __syncthreads();
+                }
+                if (blockIdx.x == 0 && tid == 0) {
+                    const double o = role_value(a, c, N - 1, S.dot_adj * c.inv + p.xPx * c.in_N);
+                    a.out[N - 1] = o;
+                    s0 += o * o;
+                    if (a.do_update) lsqr_update(a, c, N - 1);
+                }
+            }
+            block_sum3(s0, s1, z);
+            double *buf = partials + (size_t)phase * 3 * G;
+            if (tid == 0) {
+                store_coherent(&buf[3 * blockIdx.x], s0);
+                store_coherent(&buf[3 * blockIdx.x + 1], s1);
+            }
+            grid.sync();
+            double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+            for (int i = tid; i < G; i += kBlock) {
+                t0 += load_coherent(&buf[3 * i]);
+                t1 += load_coherent(&buf[3 * i + 1]);
+            }
+            block_sum3(t0, t1, t2);
+            if (tid == 0) {
+                const double tot[3] = {t0, t1, 0.0};
+                finalize(&S, a.role, tot, !isF);
+            }
+            __syncthreads();
+            if (S.done) break;
+        }
+    }
+    if (blockIdx.x == 0 && tid == 0) *gst = S;
+}
+
+int persistent_blocks_per_cu(int lds_bytes) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)k_lsqr_persistent, kBlock,
+                                                     lds_bytes) != hipSuccess)
+        return 0;
+    return nb;
+}
+
+hipError_t launch_lsqr_persistent(const Problem &p, const StepArgs &fa, const StepArgs &ta,
+                                  const RowGrid &rg, const FusedGrid &fg, int dir, LsqrState *st,
+                                  double *partials, int grid, int lds, hipStream_t s) {
+    Problem pp = p;
+    StepArgs f = fa, t = ta;
+    RowGrid r = rg;
+    FusedGrid u = fg;
+    void *args[] = {&pp, &f, &t, &r, &u, &dir, &st, &partials};
+    hipFuncSetAttribute((const void *)k_lsqr_persistent, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    return hipLaunchCooperativeKernel((const void *)k_lsqr_persistent, dim3(grid), dim3(kBlock), args,
+                                      (unsigned)lds, s);
 }
 
 // wy = J(s o in_y) (raw, no normaliser) and dot_fwd = c'(s o in)_x - b'wy, for a product

@@ -203,6 +203,10 @@ struct FusedGrid {
 void launch_fused_FT(const Problem &p, const StepArgs &a, const FusedGrid &g, int lds_bytes,
                      hipStream_t s);
 int fused_lds_bytes(int kmax);
+int persistent_blocks_per_cu(int lds_bytes);
+hipError_t launch_lsqr_persistent(const Problem &p, const StepArgs &fa, const StepArgs &ta,
+                                  const RowGrid &rg, const FusedGrid &fg, int dir, LsqrState *st,
+                                  double *partials, int grid, int lds, hipStream_t s);
 void set_fused_kernel_lds(int bytes);
 void launch_rows_F(const Problem &p, const StepArgs &a, const RowGrid &g, hipStream_t s);
 void launch_rows_FT(const Problem &p, const StepArgs &a, const RowGrid &g, hipStream_t s);

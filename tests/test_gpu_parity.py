@@ -33,9 +33,10 @@ def rel(a, b):
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
-def make_handle(qcp, tol=1e-12, precond=Q.QCPD_PRECOND_JACOBI, max_iter=0, chunk=32):
+def make_handle(qcp, tol=1e-12, precond=Q.QCPD_PRECOND_JACOBI, max_iter=0, chunk=32,
+                engine=Q.QCPD_ENGINE_AUTO):
     t = to_device(qcp)
-    o = Q.Opts(tol=tol, max_iter=max_iter, precond=precond, graph_chunk=chunk)
+    o = Q.Opts(tol=tol, max_iter=max_iter, precond=precond, graph_chunk=chunk, engine=engine)
     h = Q.qcpd_create(t["P"], t["A"], t["q"], t["b"], cones_of(qcp), t["x"], t["y"], t["s"], opts=o)
     return h, t
 
@@ -81,13 +82,14 @@ def test_small_mixed_all_cones():
     check_jvp_vjp_dense(qcpgen.small_mixed(0))
 
 
-def test_medium_mixed_several_tiles():
+@pytest.mark.parametrize("engine", [Q.QCPD_ENGINE_GRAPH, Q.QCPD_ENGINE_PERSISTENT])
+def test_medium_mixed_several_tiles(engine):
     """Every cone type, several workgroups per region and ragged tails (n, m not multiples
-    of the tile), PSD orders up to 12."""
+    of the tile), PSD orders up to 12; both LSQR drivers."""
     q = qcpgen.small_mixed(1, n=301, n_zero=37, n_nonneg=260, soc=(3, 4, 5, 6, 7, 8) * 5,
                            psd=(4, 7, 12, 9), n_exp=23, A_density=0.04, P_rank=150,
                            nonneg_active=100)
-    check_jvp_vjp_dense(q)
+    check_jvp_vjp_dense(q, engine=engine)
 
 
 def test_unpreconditioned_matches():
@@ -131,11 +133,12 @@ def mixed_full():
     return qcpgen.mixed_qcp(0)
 
 
-def test_mixed_full_size_properties(mixed_full):
+@pytest.mark.parametrize("engine", [Q.QCPD_ENGINE_GRAPH, Q.QCPD_ENGINE_PERSISTENT])
+def test_mixed_full_size_properties(mixed_full, engine):
     """At the benchmark size and tolerance: the JVP satisfies the linearised KKT system
     (oracle J and data, any size) and JVP/VJP satisfy the adjoint identity."""
     q = mixed_full
-    h, t = make_handle(q, tol=1e-8)
+    h, t = make_handle(q, tol=1e-8, engine=engine)
     dx, dy, ds, info, st = gpu_jvp(h, t)
     print(f"[mixed full] jvp iters={info.iters} rel_res={info.rel_residual:.2e} "
           f"ms={info.ms_total:.1f} st={st}", flush=True)
@@ -168,16 +171,18 @@ def test_zero_perturbation_and_zero_cotangent():
     assert st == Q.QCPD_OK and not np.any(dP) and not np.any(dq)
 
 
-def test_not_converged_warning():
+@pytest.mark.parametrize("engine", [Q.QCPD_ENGINE_GRAPH, Q.QCPD_ENGINE_PERSISTENT])
+def test_not_converged_warning(engine):
     q = qcpgen.small_mixed(0)
-    h, t = make_handle(q, max_iter=3, chunk=2)
+    h, t = make_handle(q, max_iter=3, chunk=2, engine=engine)
     dx, dy, ds, info, st = gpu_jvp(h, t)
     assert st == Q.QCPD_WARN_NOT_CONVERGED and info.iters == 3 and (info.flags & 1)
 
 
-def test_deterministic():
+@pytest.mark.parametrize("engine", [Q.QCPD_ENGINE_GRAPH, Q.QCPD_ENGINE_PERSISTENT])
+def test_deterministic(engine):
     q = qcpgen.small_mixed(1, n=120, A_density=0.08, P_rank=100, P_eps=0.1)
-    h, t = make_handle(q, tol=1e-10)
+    h, t = make_handle(q, tol=1e-10, engine=engine)
     a = gpu_jvp(h, t)
     b = gpu_jvp(h, t)
     for u, v in zip(a[:3], b[:3]):
