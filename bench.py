@@ -101,7 +101,9 @@ def main():
     ap.add_argument("--workload", default="mixed_qcp")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--precond", default="jacobi", choices=["jacobi", "none"])
+    ap.add_argument("--precond", default="equil", choices=["equil", "jacobi", "none"])
+    ap.add_argument("--no-plain", action="store_true",
+                    help="skip the plain Jacobi-preconditioned LSQR comparison")
     ap.add_argument("--engine", default="auto", choices=["auto", "graph", "persistent"])
     args = ap.parse_args()
     if args.gpus != 1:
@@ -120,7 +122,9 @@ def main():
     dev = "cuda:0"
     t = to_device(q, dev)
     cones = cones_of(q)
-    prec = Q.QCPD_PRECOND_JACOBI if args.precond == "jacobi" else Q.QCPD_PRECOND_NONE
+    PREC = {"equil": Q.QCPD_PRECOND_EQUIL, "jacobi": Q.QCPD_PRECOND_JACOBI,
+            "none": Q.QCPD_PRECOND_NONE}
+    prec = PREC[args.precond]
     eng = {"auto": Q.QCPD_ENGINE_AUTO, "graph": Q.QCPD_ENGINE_GRAPH,
            "persistent": Q.QCPD_ENGINE_PERSISTENT}[args.engine]
     opts = Q.Opts(tol=args.tol, precond=prec, engine=eng)
@@ -133,9 +137,10 @@ def main():
                 db=torch.empty(q.m, dtype=torch.float64, device=dev))
     torch.cuda.synchronize()
 
-    def step(record):
+    def step(record, o=None):
         t0 = time.perf_counter()
-        h = Q.qcpd_create(t["P"], t["A"], t["q"], t["b"], cones, t["x"], t["y"], t["s"], opts=opts)
+        h = Q.qcpd_create(t["P"], t["A"], t["q"], t["b"], cones, t["x"], t["y"], t["s"],
+                          opts=o or opts)
         t1 = time.perf_counter()
         _, _, _, ij, sj = Q.qcpd_jvp(h, t["dP"], t["dA"], t["dq"], t["db"],
                                     outs["dx"], outs["dy"], outs["ds"])
@@ -147,14 +152,18 @@ def main():
             record.append(dict(setup=t1 - t0, jvp=t2 - t1, vjp=t3 - t2, ij=ij, iv=iv, sj=sj, sv=sv))
         return h
 
-    for _ in range(args.warmup):
+    for i in range(args.warmup):
         step(None).close()
+        print(f"[bench] warmup step {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
     rec = []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
-    for _ in range(args.steps):
+    for i in range(args.steps):
         h = step(rec)
         h.close()
+        print(f"[bench] step {i + 1}/{args.steps}: jvp {rec[-1]['ij'].iters} it "
+              f"{rec[-1]['jvp']:.2f}s, vjp {rec[-1]['iv'].iters} it {rec[-1]['vjp']:.2f}s",
+              file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     value = args.steps / elapsed
@@ -202,7 +211,23 @@ def main():
                                   / max(iters_total, 1), 3),
         "roofline": roofline,
     }
+    if not args.no_plain and args.precond != "jacobi":
+        # plain Jacobi-preconditioned LSQR on the same GPU, same stopping tolerance
+        print("[bench] plain Jacobi LSQR for comparison", file=sys.stderr, flush=True)
+        plain = []
+        o2 = Q.Opts(tol=args.tol, precond=Q.QCPD_PRECOND_JACOBI, engine=eng)
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        step(plain, o2).close()
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - tp
+        line["vs_plain"] = {"precond": "jacobi", "value": round(1.0 / tp, 4),
+                            "unit": "solves/s", "speedup": round(value * tp, 3),
+                            "lsqr_iters": {"jvp": plain[0]["ij"].iters, "vjp": plain[0]["iv"].iters},
+                            "rel_residual": {"jvp": plain[0]["ij"].rel_residual,
+                                             "vjp": plain[0]["iv"].rel_residual}}
     if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(q, rec[-1]["ij"].iters, rec[-1]["iv"].iters)
     print(json.dumps(line), flush=True)
 

@@ -60,8 +60,13 @@ typedef int32_t qcpd_status;
 #define QCPD_PRECOND_NONE    0
 #define QCPD_PRECOND_JACOBI  1   /* 1 / column norms of the operator with each cone block's
                                     Jacobian replaced by its diagonal                        */
-#define QCPD_PRECOND_CUSTOM  2   /* caller-supplied diagonal (qcpd_set_precond), e.g. the
-                                    output of a learned model                               */
+#define QCPD_PRECOND_CUSTOM  2   /* caller-supplied two-sided scaling (qcpd_set_precond), e.g.
+                                    the output of a learned model                           */
+#define QCPD_PRECOND_EQUIL   3   /* two-sided: rows and columns of F balanced in 2-norm by
+                                    repeated square-root scaling sweeps (each cone block's
+                                    Jacobian replaced by its diagonal); the systems are
+                                    consistent, so a row scaling leaves the solution unchanged.
+                                    The stop is decided on the unscaled residual.           */
 
 /* Compressed sparse rows. [device] arrays: rowptr (nrows+1), colind (nnz), val (nnz). */
 typedef struct {
@@ -84,7 +89,7 @@ typedef struct {
 
 typedef struct {
     double  tol;          /* stop when the LSQR residual estimate <= tol * ||rhs||  (1e-8)   */
-    int32_t max_iter;     /* iteration cap; 0 = 20 * (n + m + 1)                              */
+    int32_t max_iter;     /* iteration cap; 0 = 100 * (n + m + 1)                             */
     int32_t precond;      /* QCPD_PRECOND_*                                   (JACOBI)         */
     int32_t graph_chunk;  /* LSQR iterations per captured HIP graph launch     (32)            */
     int32_t check_symmetry; /* verify that P is symmetric at create              (1)           */
@@ -92,10 +97,11 @@ typedef struct {
 } qcpd_opts;
 
 /* LSQR drivers of the single-problem path. GRAPH: two launches per iteration, captured in
- * HIP graphs of graph_chunk iterations, the host polling a device stop flag per graph.
- * PERSISTENT: the whole loop in one cooperative launch with two grid barriers per iteration.
- * AUTO picks PERSISTENT when the device supports cooperative launches. Both give the same
- * results up to the order of floating-point sums. */
+ * HIP graphs of graph_chunk iterations, the host polling a device stop flag per graph; each
+ * launch finalises the previous launch's reductions at entry, so the loop needs no fences.
+ * PERSISTENT: the whole loop in one cooperative launch with two grid barriers per iteration
+ * (each barrier writes back and invalidates L2, which costs more than a launch on MI355X).
+ * AUTO picks GRAPH. Both give the same results up to the order of floating-point sums. */
 #define QCPD_ENGINE_AUTO        0
 #define QCPD_ENGINE_GRAPH       1
 #define QCPD_ENGINE_PERSISTENT  2
@@ -144,14 +150,16 @@ qcpd_status qcpd_vjp(qcpd_handle *h, const double *gx, const double *gy, const d
  * from the next call. Returns QCPD_ERR_INVALID_ARG for bad values. */
 qcpd_status qcpd_set_opts(qcpd_handle *h, const qcpd_opts *opts);
 
-/* Supply a custom diagonal right preconditioner for QCPD_PRECOND_CUSTOM: d_jvp scales the
- * columns of F (JVP), d_vjp the columns of F' (VJP); each (n + m + 1) [device], entries > 0.
- * The values are copied. */
-qcpd_status qcpd_set_precond(qcpd_handle *h, const double *d_jvp, const double *d_vjp);
+/* Supply the two-sided scaling used by QCPD_PRECOND_CUSTOM: LSQR then solves the JVP with
+ * diag(d_row) F diag(d_col) and the VJP with diag(d_col) F' diag(d_row). d_col, d_row:
+ * (n + m + 1) [device], entries > 0; the values are copied. */
+qcpd_status qcpd_set_precond(qcpd_handle *h, const double *d_col, const double *d_row);
 
-/* Copy the handle's Jacobi scales and the diagonal of DPi_{K*}(z_y) out [device]:
- * d_jvp, d_vjp (n + m + 1 each), jdiag (m). Any pointer may be NULL. */
-qcpd_status qcpd_get_diagnostics(qcpd_handle *h, double *d_jvp, double *d_vjp, double *jdiag);
+/* Copy out [device]: the Jacobi scales (d_jvp: columns of F, d_vjp: columns of F'), the
+ * equilibration scales (eq_col, eq_row), each n + m + 1, and the diagonal of DPi_{K*}(z_y)
+ * (jdiag, m). Any pointer may be NULL. */
+qcpd_status qcpd_get_diagnostics(qcpd_handle *h, double *d_jvp, double *d_vjp, double *eq_col,
+                                 double *eq_row, double *jdiag);
 
 /* Measurement support: time the two kernels of one LSQR iteration of the JVP (the product
  * with F over CSR rows; the fused product with F': CSR rows of each cone block followed by

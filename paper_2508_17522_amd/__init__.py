@@ -6,6 +6,7 @@ is its Python binding plus a torch.autograd.Function whose backward is the adjoi
 from ._capi import (QCPD_OK, QCPD_WARN_NOT_CONVERGED, QCPD_WARN_NONDIFF, QCPD_ERR_INVALID_ARG,
                     QCPD_ERR_DIM, QCPD_ERR_CONE, QCPD_ERR_PATTERN, QCPD_ERR_NAN, QCPD_ERR_HIP,
                     QCPD_ERR_OOM, QCPD_PRECOND_NONE, QCPD_PRECOND_JACOBI, QCPD_PRECOND_CUSTOM,
+                    QCPD_PRECOND_EQUIL,
                     QCPD_ENGINE_AUTO, QCPD_ENGINE_GRAPH, QCPD_ENGINE_PERSISTENT,
                     LIB_PATH, EXPORTS)
 from .api import (Cones, Opts, Info, Handle, QCPDError, qcpd_create, qcpd_jvp, qcpd_vjp,

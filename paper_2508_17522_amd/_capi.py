@@ -52,6 +52,7 @@ QCPD_ENGINE_PERSISTENT = 2
 QCPD_PRECOND_NONE = 0
 QCPD_PRECOND_JACOBI = 1
 QCPD_PRECOND_CUSTOM = 2
+QCPD_PRECOND_EQUIL = 3
 
 class qcpd_batch_layout(ctypes.Structure):
     _fields_ = [("nprob", c_int32), ("n", ctypes.POINTER(c_int32)), ("m", ctypes.POINTER(c_int32)),
@@ -92,7 +93,7 @@ def load(path: str = LIB_PATH):
     lib.qcpd_set_opts.restype = c_int32
     lib.qcpd_set_precond.argtypes = [c_void_p, c_void_p, c_void_p]
     lib.qcpd_set_precond.restype = c_int32
-    lib.qcpd_get_diagnostics.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p]
+    lib.qcpd_get_diagnostics.argtypes = [c_void_p] + [c_void_p] * 5
     lib.qcpd_get_diagnostics.restype = c_int32
     lib.qcpd_profile_kernels.argtypes = [c_void_p, c_int32, P(ctypes.c_float)]
     lib.qcpd_profile_kernels.restype = c_int32

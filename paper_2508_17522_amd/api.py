@@ -202,27 +202,29 @@ def qcpd_set_opts(h: Handle, opts: Opts):
         raise QCPDError(st, "qcpd_set_opts")
 
 
-def qcpd_set_precond(h: Handle, d_jvp, d_vjp):
+def qcpd_set_precond(h: Handle, d_col, d_row):
+    """Two-sided scaling for QCPD_PRECOND_CUSTOM: the JVP solves with diag(d_row) F
+    diag(d_col), the VJP with the transposed pair."""
     with torch.cuda.device(h.device):
-        st = _lib().qcpd_set_precond(h.ptr, _ptr(d_jvp, torch.float64, "d_jvp", h.N),
-                                     _ptr(d_vjp, torch.float64, "d_vjp", h.N))
+        st = _lib().qcpd_set_precond(h.ptr, _ptr(d_col, torch.float64, "d_col", h.N),
+                                     _ptr(d_row, torch.float64, "d_row", h.N))
     if st < 0:
         raise QCPDError(st, "qcpd_set_precond")
 
 
 def qcpd_get_diagnostics(h: Handle):
-    """Returns (d_jvp, d_vjp, jdiag) as new GPU tensors."""
+    """Returns dict of new GPU tensors: jacobi_jvp, jacobi_vjp, equil_col, equil_row, jdiag."""
     f64 = dict(dtype=torch.float64, device=h.device)
-    a = torch.empty(h.N, **f64)
-    b = torch.empty(h.N, **f64)
+    out = {k: torch.empty(h.N, **f64) for k in ("jacobi_jvp", "jacobi_vjp", "equil_col", "equil_row")}
     j = torch.empty(max(h.m, 1), **f64)
     with torch.cuda.device(h.device):
-        st = _lib().qcpd_get_diagnostics(h.ptr, _ptr(a, torch.float64, "d_jvp"),
-                                         _ptr(b, torch.float64, "d_vjp"),
+        st = _lib().qcpd_get_diagnostics(h.ptr, *[_ptr(out[k], torch.float64, k) for k in
+                                                  ("jacobi_jvp", "jacobi_vjp", "equil_col", "equil_row")],
                                          _ptr(j, torch.float64, "jdiag"))
     if st < 0:
         raise QCPDError(st, "qcpd_get_diagnostics")
-    return a, b, j[:h.m]
+    out["jdiag"] = j[:h.m]
+    return out
 
 
 def qcpd_profile_kernels(h: Handle, reps: int = 50):

@@ -33,12 +33,18 @@ struct qcpd_handle {
     double *u = nullptr, *v = nullptr, *xk = nullptr, *wk = nullptr, *tmp = nullptr,
            *rhs = nullptr, *sol = nullptr, *wy = nullptr, *scratch = nullptr;
     double *scale[2] = {nullptr, nullptr};   // Jacobi: [0] columns of F, [1] columns of F'
-    double *custom[2] = {nullptr, nullptr};  // caller-supplied diagonal
+    double *equil[2] = {nullptr, nullptr};   // two-sided equilibration: [0] columns, [1] rows of F
+    double *custom[2] = {nullptr, nullptr};  // caller-supplied: [0] columns, [1] rows of F
+    LsqrState *st_res = nullptr;             // state of the explicit-residual launches
+    double *wy_res = nullptr;                // J(sol_y) of the explicit residual / JVP output
     double *jdiag = nullptr;
     double *partials = nullptr;
     int *counter = nullptr;
     int *flag = nullptr;
     LsqrState *st = nullptr;
+    LsqrState *st2 = nullptr;                // second state buffer of the deferred loop
+    double *lpart[2] = {nullptr, nullptr};   // per-block partials of the deferred loop
+    int loop_grid_F = 0, loop_grid_T = 0;    // workgroups of the two loop launches
     LsqrState *host_st = nullptr;            // pinned
     int *host_flag = nullptr;                // pinned
     void *seg = nullptr;                     // device segment table for the NaN scan
@@ -46,6 +52,7 @@ struct qcpd_handle {
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     int graph_chunk[2] = {0, 0};
     const double *graph_sc[2] = {nullptr, nullptr};
+    const double *graph_scl[2] = {nullptr, nullptr};
     uint32_t create_flags = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
@@ -53,6 +60,7 @@ struct qcpd_handle {
 namespace {
 
 constexpr int kMaxSeg = 8;
+constexpr int kEquilSweeps = 20;  // even: the result ends in the destination buffers
 
 #define HIPCHK(expr)                              \
     do {                                          \
@@ -99,14 +107,14 @@ void free_handle(qcpd_handle *h) {
 
 qcpd_status check_opts(const qcpd_opts *o) {
     if (!(o->tol >= 0.0) || o->max_iter < 0 || o->graph_chunk < 1 || o->graph_chunk > 4096 ||
-        o->precond < QCPD_PRECOND_NONE || o->precond > QCPD_PRECOND_CUSTOM ||
+        o->precond < QCPD_PRECOND_NONE || o->precond > QCPD_PRECOND_EQUIL ||
         o->engine < QCPD_ENGINE_AUTO || o->engine > QCPD_ENGINE_PERSISTENT)
         return QCPD_ERR_INVALID_ARG;
     return QCPD_OK;
 }
 
 int max_iter_of(const qcpd_handle *h) {
-    return h->opts.max_iter > 0 ? h->opts.max_iter : 20 * h->p.N;
+    return h->opts.max_iter > 0 ? h->opts.max_iter : 100 * h->p.N;
 }
 
 // NaN / Inf scan over device arrays; returns QCPD_ERR_NAN, QCPD_ERR_HIP or QCPD_OK.
@@ -132,17 +140,27 @@ qcpd_status scan_finite(qcpd_handle *h, std::vector<const double *> ptrs, std::v
     return *h->host_flag ? QCPD_ERR_NAN : QCPD_OK;
 }
 
-const double *active_scale(const qcpd_handle *h, int dir) {
+// Diagonal scales of the LSQR matrix for a direction: sc (columns) and scl (rows). The JVP
+// solves with L F R, the VJP with the transpose pair R' F' L', so a two-sided (column,
+// row) scaling of F serves the VJP with its roles exchanged.
+void active_scales(const qcpd_handle *h, int dir, const double **sc, const double **scl) {
+    *sc = nullptr;
+    *scl = nullptr;
     switch (h->opts.precond) {
-    case QCPD_PRECOND_JACOBI: return h->scale[dir];
-    case QCPD_PRECOND_CUSTOM: return h->custom[dir] ? h->custom[dir] : h->scale[dir];
-    default: return nullptr;
+    case QCPD_PRECOND_JACOBI: *sc = h->scale[dir]; break;
+    case QCPD_PRECOND_EQUIL: *sc = h->equil[dir]; *scl = h->equil[1 - dir]; break;
+    case QCPD_PRECOND_CUSTOM:
+        if (h->custom[0]) { *sc = h->custom[dir]; *scl = h->custom[1 - dir]; }
+        else { *sc = h->scale[dir]; }
+        break;
+    default: break;
     }
 }
 
-StepArgs base_args(const qcpd_handle *h, const double *sc) {
+StepArgs base_args(const qcpd_handle *h, const double *sc, const double *scl = nullptr) {
     StepArgs a{};
     a.sc = sc;
+    a.scl = scl;
     a.wy = h->wy;
     a.xk = h->xk;
     a.wk = h->wk;
@@ -157,40 +175,49 @@ StepArgs base_args(const qcpd_handle *h, const double *sc) {
 }
 
 // One LSQR iteration. JVP: the LSQR matrix is F diag(sc); VJP: it is F' diag(sc).
-void enqueue_iteration(const qcpd_handle *h, int dir, const double *sc, hipStream_t s) {
-    StepArgs a = base_args(h, sc);
-    a.check_done = 1;
+// One LSQR iteration (two launches, deferred protocol). JVP: the LSQR matrix is F diag(sc),
+// VJP: F' diag(sc). The first launch of an iteration reads state buffer 0 and the second
+// launch's partials, the second reads buffer 1 and the first's partials.
+void enqueue_iteration(const qcpd_handle *h, int dir, const double *sc, const double *scl,
+                       hipStream_t s) {
+    StepArgs a = base_args(h, sc, scl);
+    a.deferred = 1;
+    StepArgs first = a, second = a;
+    first.st = h->st;    first.part_prev = h->lpart[0]; first.st_next = h->st2; first.part_next = h->lpart[1];
+    second.st = h->st2;  second.part_prev = h->lpart[1]; second.st_next = h->st; second.part_next = h->lpart[0];
     if (dir == 0) {
-        StepArgs f = a;  // u~ <- F(sc o v) - alpha u~   (and the owed x, w update)
+        StepArgs &f = first;  // u~ <- F(sc o v) - alpha u~   (and the owed x, w update)
         f.in = h->v; f.in_nrm = NRM_ALPHA; f.in_is_v = 1;
         f.out = h->u; f.role = ROLE_U; f.do_update = 1;
-        launch_rows_F(h->p, f, h->rg, s);
-        StepArgs t = a;  // v~ <- sc o F'u - beta v~, then J(sc o v~) for the next product
+        launch_rows_F(h->p, f, h->rg, s, h->loop_grid_F);
+        StepArgs &t = second;  // v~ <- sc o F'u - beta v~, then J(sc o v~) for the next product
         t.in = h->u; t.in_nrm = NRM_BETA;
         t.out = h->v; t.role = ROLE_V; t.out_is_v = 1; t.do_pre = 1;
-        launch_fused_FT(h->p, t, h->fg, h->lds_fused, s);
+        launch_fused_FT(h->p, t, h->fg, h->lds_fused, s, h->loop_grid_T);
     } else {
-        StepArgs t = a;  // u~ <- F'(sc o v) - alpha u~ (and the owed update), J(u~)
+        StepArgs &t = first;  // u~ <- F'(sc o v) - alpha u~ (and the owed update), J(u~)
         t.in = h->v; t.in_nrm = NRM_ALPHA; t.in_is_v = 1; t.do_update = 1;
         t.out = h->u; t.role = ROLE_U; t.do_pre = 1;
-        launch_fused_FT(h->p, t, h->fg, h->lds_fused, s);
-        StepArgs f = a;  // v~ <- sc o F u - beta v~
+        launch_fused_FT(h->p, t, h->fg, h->lds_fused, s, h->loop_grid_T);
+        StepArgs &f = second;  // v~ <- sc o F u - beta v~
         f.in = h->u; f.in_nrm = NRM_BETA;
         f.out = h->v; f.role = ROLE_V; f.out_is_v = 1;
-        launch_rows_F(h->p, f, h->rg, s);
+        launch_rows_F(h->p, f, h->rg, s, h->loop_grid_F);
     }
 }
 
-qcpd_status ensure_graph(qcpd_handle *h, int dir, const double *sc) {
+qcpd_status ensure_graph(qcpd_handle *h, int dir, const double *sc, const double *scl) {
     const int chunk = h->opts.graph_chunk;
-    if (h->graph[dir] && h->graph_chunk[dir] == chunk && h->graph_sc[dir] == sc) return QCPD_OK;
+    if (h->graph[dir] && h->graph_chunk[dir] == chunk && h->graph_sc[dir] == sc &&
+        h->graph_scl[dir] == scl)
+        return QCPD_OK;
     if (h->graph[dir]) {
         hipGraphExecDestroy(h->graph[dir]);
         h->graph[dir] = nullptr;
     }
     hipGraph_t g = nullptr;
     HIPCHK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
-    for (int i = 0; i < chunk; ++i) enqueue_iteration(h, dir, sc, h->cap);
+    for (int i = 0; i < chunk; ++i) enqueue_iteration(h, dir, sc, scl, h->cap);
     HIPCHK(hipStreamEndCapture(h->cap, &g));
     hipError_t e = hipGraphInstantiate(&h->graph[dir], g, nullptr, nullptr, 0);
     hipGraphDestroy(g);
@@ -200,14 +227,14 @@ qcpd_status ensure_graph(qcpd_handle *h, int dir, const double *sc) {
     }
     h->graph_chunk[dir] = chunk;
     h->graph_sc[dir] = sc;
+    h->graph_scl[dir] = scl;
     return QCPD_OK;
 }
 
-// Runs LSQR from the right-hand side already placed in u (with beta set), leaves the
-// solution (mapped back through the scale) in h->sol.
-qcpd_status run_lsqr(qcpd_handle *h, int dir, const double *sc) {
+// The first product of the bidiagonalisation (u~ is in place with beta set).
+void lsqr_start(qcpd_handle *h, int dir, const double *sc, const double *scl) {
     hipStream_t s = h->stream;
-    StepArgs a = base_args(h, sc);
+    StepArgs a = base_args(h, sc, scl);
     a.check_done = 1;
     if (dir == 0) {
         StepArgs t = a;
@@ -223,8 +250,14 @@ qcpd_status run_lsqr(qcpd_handle *h, int dir, const double *sc) {
         f.out = h->v; f.role = ROLE_V0; f.out_is_v = 1;
         launch_rows_F(h->p, f, h->rg, s);
     }
-    const bool persistent = h->persist_grid > 0 && (h->opts.engine == QCPD_ENGINE_PERSISTENT ||
-                                                     h->opts.engine == QCPD_ENGINE_AUTO);
+}
+
+// Iterates until the device stop flag is set, then maps the iterate back through the
+// column scale into h->sol (x update owed by the last rotation applied).
+qcpd_status lsqr_iterate(qcpd_handle *h, int dir, const double *sc, const double *scl) {
+    hipStream_t s = h->stream;
+    StepArgs a = base_args(h, sc, scl);
+    const bool persistent = h->persist_grid > 0 && h->opts.engine == QCPD_ENGINE_PERSISTENT;
     if (persistent) {
         StepArgs f = a, t = a;
         if (dir == 0) {
@@ -237,32 +270,88 @@ qcpd_status run_lsqr(qcpd_handle *h, int dir, const double *sc) {
         }
         HIPCHK(launch_lsqr_persistent(h->p, f, t, h->rg, h->fg, dir, h->st, h->persist_partials,
                                       h->persist_grid, h->lds_fused, s));
-        HIPCHK(hipMemcpyAsync(h->host_st, h->st, sizeof(LsqrState), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        StepArgs fl = base_args(h, sc);
-        launch_flush(h->p, fl, h->sol, div_up(h->p.N, kBlock), s);
-        return QCPD_OK;
+    } else {
+        qcpd_status rc = ensure_graph(h, dir, sc, scl);
+        if (rc != QCPD_OK) return rc;
+        const long long max_launch = (long long)max_iter_of(h) / h->opts.graph_chunk + 4;
+        for (long long l = 0;; ++l) {
+            HIPCHK(hipMemcpyAsync(h->host_st, h->st, sizeof(LsqrState), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            if (h->host_st->done || l >= max_launch) break;
+            HIPCHK(hipGraphLaunch(h->graph[dir], s));
+        }
     }
-    qcpd_status rc = ensure_graph(h, dir, sc);
-    if (rc != QCPD_OK) return rc;
-    const long long max_launch = (long long)max_iter_of(h) / h->opts.graph_chunk + 4;
-    for (long long l = 0;; ++l) {
-        HIPCHK(hipMemcpyAsync(h->host_st, h->st, sizeof(LsqrState), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        if (h->host_st->done || l >= max_launch) break;
-        HIPCHK(hipGraphLaunch(h->graph[dir], s));
-    }
-    StepArgs fl = base_args(h, sc);
+    StepArgs fl = base_args(h, sc, scl);
+    fl.st_next = h->st_res;
+    launch_state_init(h->st_res, 0.0, 1, s);
     launch_flush(h->p, fl, h->sol, div_up(h->p.N, kBlock), s);
     return QCPD_OK;
 }
 
-void fill_info(qcpd_handle *h, qcpd_info *info) {
+// Explicit residual of the unscaled system at h->sol: JVP ||F sol + d|| (also leaves
+// J sol_y in wy_res for the outputs), VJP ||F'sol + dz||. Reads the LSQR state back and
+// returns the relative residual.
+qcpd_status explicit_residual(qcpd_handle *h, int dir, double *rel) {
+    hipStream_t s = h->stream;
+    StepArgs r = base_args(h, nullptr, nullptr);
+    r.st = h->st_res;
+    r.wy = h->wy_res;
+    r.in = h->sol;
+    r.in_nrm = NRM_ONE;
+    if (dir == 0) {
+        launch_cone_pre(h->p, r, h->cg, h->lds, s);
+        StepArgs f = r;
+        f.out = h->scratch; f.role = ROLE_RESID;
+        launch_rows_F(h->p, f, h->rg, s);
+    } else {
+        StepArgs t = r;
+        t.out = h->scratch; t.role = ROLE_RESID;
+        launch_fused_FT(h->p, t, h->fg, h->lds_fused, s);
+    }
+    HIPCHK(hipMemcpyAsync(h->host_st, h->st, sizeof(LsqrState), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(h->host_st + 1, h->st_res, sizeof(LsqrState), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const LsqrState &rs = h->host_st[1];
+    *rel = rs.tau_rhs > 0.0 ? rs.resid / rs.tau_rhs : 0.0;
+    return QCPD_OK;
+}
+
+// LSQR from the right-hand side in place, to the caller's tolerance on the UNSCALED
+// relative residual: with a row scaling the stopping test sees the scaled residual, so after
+// each stop the explicit residual is checked and, if it is too large, LSQR resumes from its
+// state with a tighter internal tolerance.
+qcpd_status solve(qcpd_handle *h, int dir, const double *sc, const double *scl, double *rel) {
+    lsqr_start(h, dir, sc, scl);
+    qcpd_status rc = lsqr_iterate(h, dir, sc, scl);
+    if (rc != QCPD_OK) return rc;
+    rc = explicit_residual(h, dir, rel);
+    if (rc != QCPD_OK) return rc;
+    const double tol = h->opts.tol;
+    for (int attempt = 0; attempt < 8; ++attempt) {
+        LsqrState st = h->host_st[0];
+        if (*rel <= tol || !st.conv || st.iters >= st.max_iter || !(st.tol > 0.0)) break;
+        st.tol *= std::max(0.02, 0.5 * tol / *rel);
+        st.done = 0;
+        st.conv = 0;
+        st.phr = 0.0;  // the flush already applied the owed x update
+        st.pend_role = -1;
+        h->host_st[0] = st;
+        HIPCHK(hipMemcpyAsync(h->st, h->host_st, sizeof(LsqrState), hipMemcpyHostToDevice, h->stream));
+        HIPCHK(hipMemcpyAsync(h->st2, h->host_st, sizeof(LsqrState), hipMemcpyHostToDevice, h->stream));
+        rc = lsqr_iterate(h, dir, sc, scl);
+        if (rc != QCPD_OK) return rc;
+        rc = explicit_residual(h, dir, rel);
+        if (rc != QCPD_OK) return rc;
+    }
+    return QCPD_OK;
+}
+
+void fill_info(qcpd_handle *h, qcpd_info *info, double rel) {
     if (!info) return;
-    const LsqrState &st = *h->host_st;
+    const LsqrState &st = h->host_st[0];
     info->iters = st.iters;
     info->est_residual = st.beta1 > 0.0 ? st.phibar / st.beta1 : 0.0;
-    info->rel_residual = st.beta1 > 0.0 ? st.resid / st.beta1 : 0.0;
+    info->rel_residual = rel;
     info->flags = (st.conv ? 0u : 1u) | h->create_flags;
     float ms = 0.f;
     hipEventElapsedTime(&ms, h->ev0, h->ev1);
@@ -310,6 +399,7 @@ qcpd_status create_impl(qcpd_handle *h, const qcpd_csr *P, const qcpd_csr *A, co
     ALLOC(h->u, N); ALLOC(h->v, N); ALLOC(h->xk, N); ALLOC(h->wk, N); ALLOC(h->tmp, N);
     ALLOC(h->rhs, N); ALLOC(h->sol, N); ALLOC(h->wy, m); ALLOC(h->scratch, N);
     ALLOC(h->scale[0], N); ALLOC(h->scale[1], N); ALLOC(h->jdiag, m);
+    ALLOC(h->equil[0], N); ALLOC(h->equil[1], N); ALLOC(h->st_res, 1); ALLOC(h->wy_res, m);
     ALLOC(h->counter, 1); ALLOC(h->flag, 4); ALLOC(h->st, 1);
     {
         char *segp = nullptr;
@@ -397,6 +487,22 @@ qcpd_status create_impl(qcpd_handle *h, const qcpd_csr *P, const qcpd_csr *A, co
         h->lds_fused = fused_lds_bytes(kmax);
     }
     h->nblk_max = std::max({cg.total(), rg.total(), h->fg.nunits, div_up(N, kBlock), 1});
+    // the two launches of the deferred LSQR loop: at most `cap` workgroups each, so the next
+    // launch's fixed-order reduction of their partial sums stays short (QCPD_LOOP_GRID
+    // overrides the cap, for tuning)
+    {
+        int cap = 512;
+        if (const char *env = getenv("QCPD_LOOP_GRID")) {
+            const int e = atoi(env);
+            if (e > 0) cap = e;
+        }
+        h->loop_grid_F = std::max(1, std::min(rg.total(), cap));
+        h->loop_grid_T = std::max(1, std::min(h->fg.nunits, cap));
+        const int lp = std::max(h->loop_grid_F, h->loop_grid_T);
+        ALLOC(h->lpart[0], 3LL * lp);
+        ALLOC(h->lpart[1], 3LL * lp);
+        ALLOC(h->st2, 1);
+    }
     ALLOC(h->partials, 3LL * h->nblk_max);
     // --- validation on the device -----------------------------------------------------------
     qcpd_status rc = scan_finite(h, {Pv, Av, dq_, db_, dx_, dy_, ds_},
@@ -442,6 +548,11 @@ qcpd_status create_impl(qcpd_handle *h, const qcpd_csr *P, const qcpd_csr *A, co
     launch_cone_factors(p, ch, h->jdiag, soc_par, exp_J, pool, h->flag + 1, h->flag + 2,
                         psd_factor_lds_bytes(kmax), st);
     launch_scales(p, rg, h->scale[0], h->scale[1], h->partials, h->counter, st);
+    // two-sided equilibration of F (column scale in equil[0], row scale in equil[1])
+    launch_fill(h->equil[0], N, 1.0, st);
+    launch_fill(h->equil[1], N, 1.0, st);
+    launch_equilibrate(p, rg, h->equil[1], h->equil[0], h->tmp, h->scratch, kEquilSweeps,
+                       h->partials, h->counter, st);
     HIPCHK(hipMemcpyAsync(h->host_flag, h->flag, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     HIPCHK(hipGetLastError());
@@ -536,14 +647,14 @@ qcpd_status qcpd_create(qcpd_handle **out, const qcpd_csr *P, const qcpd_csr *A,
     h->stream = static_cast<hipStream_t>(stream);
     if (hipGetDevice(&h->device) != hipSuccess ||
         hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking) != hipSuccess ||
-        hipHostMalloc((void **)&h->host_st, sizeof(LsqrState), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&h->host_st, 2 * sizeof(LsqrState), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&h->host_flag, 4 * sizeof(int), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(&h->host_seg, kMaxSeg * 16, hipHostMallocDefault) != hipSuccess ||
         hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess) {
         free_handle(h);
         return QCPD_ERR_HIP;
     }
-    memset(h->host_st, 0, sizeof(LsqrState));
+    memset(h->host_st, 0, 2 * sizeof(LsqrState));
     qcpd_status rc = create_impl(h, P, A, q, b, K, x, y, s);
     if (rc < 0) {
         hipStreamSynchronize(h->stream);
@@ -560,25 +671,28 @@ qcpd_status qcpd_set_opts(qcpd_handle *h, const qcpd_opts *opts) {
     return QCPD_OK;
 }
 
-qcpd_status qcpd_set_precond(qcpd_handle *h, const double *d_jvp, const double *d_vjp) {
-    if (!h || !d_jvp || !d_vjp) return QCPD_ERR_INVALID_ARG;
+qcpd_status qcpd_set_precond(qcpd_handle *h, const double *d_col, const double *d_row) {
+    if (!h || !d_col || !d_row) return QCPD_ERR_INVALID_ARG;
     for (int d = 0; d < 2; ++d) {
         if (!h->custom[d]) {
             qcpd_status rc = dalloc(h, &h->custom[d], (size_t)h->p.N);
             if (rc != QCPD_OK) return rc;
         }
-        HIPCHK(hipMemcpyAsync(h->custom[d], d == 0 ? d_jvp : d_vjp, sizeof(double) * h->p.N,
+        HIPCHK(hipMemcpyAsync(h->custom[d], d == 0 ? d_col : d_row, sizeof(double) * h->p.N,
                               hipMemcpyDeviceToDevice, h->stream));
     }
     HIPCHK(hipStreamSynchronize(h->stream));
     return QCPD_OK;
 }
 
-qcpd_status qcpd_get_diagnostics(qcpd_handle *h, double *d_jvp, double *d_vjp, double *jdiag) {
+qcpd_status qcpd_get_diagnostics(qcpd_handle *h, double *d_jvp, double *d_vjp, double *eq_col,
+                                 double *eq_row, double *jdiag) {
     if (!h) return QCPD_ERR_INVALID_ARG;
     const size_t N = h->p.N, m = h->p.m;
     if (d_jvp) HIPCHK(hipMemcpyAsync(d_jvp, h->scale[0], N * 8, hipMemcpyDeviceToDevice, h->stream));
     if (d_vjp) HIPCHK(hipMemcpyAsync(d_vjp, h->scale[1], N * 8, hipMemcpyDeviceToDevice, h->stream));
+    if (eq_col) HIPCHK(hipMemcpyAsync(eq_col, h->equil[0], N * 8, hipMemcpyDeviceToDevice, h->stream));
+    if (eq_row) HIPCHK(hipMemcpyAsync(eq_row, h->equil[1], N * 8, hipMemcpyDeviceToDevice, h->stream));
     if (jdiag && m) HIPCHK(hipMemcpyAsync(jdiag, h->jdiag, m * 8, hipMemcpyDeviceToDevice, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     return QCPD_OK;
@@ -594,29 +708,24 @@ qcpd_status qcpd_jvp(qcpd_handle *h, const double *dP, const double *dA, const d
     HIPCHK(hipEventRecord(h->ev0, s));
     qcpd_status rc = scan_finite(h, {dP, dA, dq, db}, {p.nnzP, p.nnzA, p.n, p.m});
     if (rc != QCPD_OK) return rc;
-    const double *sc = active_scale(h, 0);
+    const double *sc, *scl;
+    active_scales(h, 0, &sc, &scl);
     launch_state_init(h->st, h->opts.tol, max_iter_of(h), s);
     launch_fill(h->xk, p.N, 0.0, s);
     launch_fill(h->wk, p.N, 0.0, s);
-    StepArgs r = base_args(h, sc);
+    StepArgs r = base_args(h, sc, scl);
     r.out = h->u;
     launch_jvp_rhs(p, r, h->rg, dP, dA, dq, db, s);
-    rc = run_lsqr(h, 0, sc);
+    double rel = 0.0;
+    rc = solve(h, 0, sc, scl, &rel);
     if (rc != QCPD_OK) return rc;
-    // explicit residual ||F dz + d|| with dz = sol, then (dx, dy, ds) = D phi dz
-    StepArgs pre = base_args(h, sc);
-    pre.in = h->sol;
-    launch_cone_pre(p, pre, h->cg, h->lds, s);
-    StepArgs res = base_args(h, sc);
-    res.in = h->sol; res.in_nrm = NRM_ONE; res.out = h->scratch; res.role = ROLE_RESID;
-    launch_rows_F(p, res, h->rg, s);
-    launch_jvp_out(p, h->sol, h->wy, dx, dy, ds, s);
+    // (dx, dy, ds) = D phi dz with dz = sol and J dz_y left in wy_res by the residual check
+    launch_jvp_out(p, h->sol, h->wy_res, dx, dy, ds, s);
     HIPCHK(hipEventRecord(h->ev1, s));
-    HIPCHK(hipMemcpyAsync(h->host_st, h->st, sizeof(LsqrState), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     HIPCHK(hipGetLastError());
-    fill_info(h, info);
-    return h->host_st->conv ? QCPD_OK : QCPD_WARN_NOT_CONVERGED;
+    fill_info(h, info, rel);
+    return h->host_st[0].conv ? QCPD_OK : QCPD_WARN_NOT_CONVERGED;
 }
 
 qcpd_status qcpd_vjp(qcpd_handle *h, const double *gx, const double *gy, const double *gs,
@@ -629,44 +738,54 @@ qcpd_status qcpd_vjp(qcpd_handle *h, const double *gx, const double *gy, const d
     HIPCHK(hipEventRecord(h->ev0, s));
     qcpd_status rc = scan_finite(h, {gx, gy, gs}, {p.n, p.m, p.m});
     if (rc != QCPD_OK) return rc;
-    const double *sc = active_scale(h, 1);
+    const double *sc, *scl;
+    active_scales(h, 1, &sc, &scl);
     launch_state_init(h->st, h->opts.tol, max_iter_of(h), s);
     launch_fill(h->xk, p.N, 0.0, s);
     launch_fill(h->wk, p.N, 0.0, s);
-    StepArgs r = base_args(h, sc);
+    StepArgs r = base_args(h, sc, scl);
     r.out = h->u;
     launch_vjp_rhs(p, r, h->cg, h->lds, gx, gy, gs, s);
-    rc = run_lsqr(h, 1, sc);
+    double rel = 0.0;
+    rc = solve(h, 1, sc, scl, &rel);
     if (rc != QCPD_OK) return rc;
-    // explicit residual ||F'w + dz|| with w = sol, then dtheta = D_theta N'[w]
-    StepArgs t = base_args(h, sc);
-    t.in = h->sol; t.in_nrm = NRM_ONE;
-    t.out = h->scratch; t.role = ROLE_RESID;
-    launch_fused_FT(p, t, h->fg, h->lds_fused, s);
+    // dtheta = D_theta N'[w] with w = sol
     launch_vjp_out(p, h->rg, h->sol, dP, dA, dq, db, s);
     HIPCHK(hipEventRecord(h->ev1, s));
-    HIPCHK(hipMemcpyAsync(h->host_st, h->st, sizeof(LsqrState), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     HIPCHK(hipGetLastError());
-    fill_info(h, info);
-    return h->host_st->conv ? QCPD_OK : QCPD_WARN_NOT_CONVERGED;
+    fill_info(h, info, rel);
+    return h->host_st[0].conv ? QCPD_OK : QCPD_WARN_NOT_CONVERGED;
 }
 
 qcpd_status qcpd_profile_kernels(qcpd_handle *h, int32_t reps, float *ms_out) {
     if (!h || reps < 1 || !ms_out) return QCPD_ERR_INVALID_ARG;
     hipStream_t s = h->stream;
-    const double *sc = active_scale(h, 0);
-    // plain products on the current vectors; the state keeps finite normalisers
-    launch_state_init(h->st, h->opts.tol, max_iter_of(h), s);
-    StepArgs a = base_args(h, sc);
+    const double *sc, *scl;
+    active_scales(h, 0, &sc, &scl);
+    // The two loop launches as the JVP's LSQR runs them (deferred protocol, entry reduction
+    // of the previous launch's partials included), on the handle's current vectors. The state
+    // is set so that nothing ever stops: plain products, finite normalisers.
+    LsqrState img{};
+    img.alpha = 1.0; img.beta = 1.0; img.one = 1.0; img.tol = 0.0; img.max_iter = 1 << 30;
+    img.pend_role = ROLE_PLAIN;
+    img.pend_blocks = std::max(h->loop_grid_F, h->loop_grid_T);
+    img.pend_fwd = 0;
+    *h->host_st = img;
+    HIPCHK(hipMemcpyAsync(h->st, h->host_st, sizeof(LsqrState), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemsetAsync(h->lpart[0], 0, 3 * sizeof(double) * img.pend_blocks, s));
+    HIPCHK(hipMemsetAsync(h->lpart[1], 0, 3 * sizeof(double) * img.pend_blocks, s));
+    StepArgs a = base_args(h, sc, scl);
+    a.deferred = 1;
+    a.st = h->st; a.part_prev = h->lpart[0]; a.st_next = h->st2; a.part_next = h->lpart[1];
     StepArgs f = a;
     f.in = h->v; f.in_is_v = 1; f.out = h->scratch;
     StepArgs t = a;
     t.in = h->u; t.out = h->scratch; t.do_pre = 1; t.out_is_v = 1;
     for (int kid = 0; kid < 2; ++kid) {
         auto launch = [&]() {
-            if (kid == 0) launch_rows_F(h->p, f, h->rg, s);
-            else launch_fused_FT(h->p, t, h->fg, h->lds_fused, s);
+            if (kid == 0) launch_rows_F(h->p, f, h->rg, s, h->loop_grid_F);
+            else launch_fused_FT(h->p, t, h->fg, h->lds_fused, s, h->loop_grid_T);
         };
         launch();  // warm
         HIPCHK(hipEventRecord(h->ev0, s));

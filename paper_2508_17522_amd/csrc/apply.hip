@@ -79,14 +79,29 @@ __device__ inline void rows_F_vblock(const Problem &p, const StepArgs &a, const 
         const double o = role_value(a, c, idx, val);
         a.out[idx] = o;
         s0 += o * o;
-        const double nsc = c.out_sc ? a.sc[idx] : 1.0;
-        if (idx < n) s1 += p.q[idx] * nsc * o;
-        else if (idx < N - 1) s1 += p.b[idx - n] * nsc * o;
+        if (a.role == ROLE_RESID) {
+            s1 += a.rhs[idx] * a.rhs[idx];  // for the unscaled relative residual
+        } else {
+            const double nsc = nscale(c, idx);
+            if (idx < n) s1 += p.q[idx] * nsc * o;
+            else if (idx < N - 1) s1 += p.b[idx - n] * nsc * o;
+        }
         if (a.do_update) lsqr_update(a, c, idx);
     }
 }
 
 __global__ __launch_bounds__(kBlock) void k_rows_F(Problem p, StepArgs a, RowGrid g) {
+    if (a.deferred) {
+        __shared__ LsqrState S;
+        if (!deferred_enter(a, &S, 0)) return;
+        StepArgs b = a;
+        b.st = &S;
+        const Ctx c = make_ctx(b, p.N - 1);
+        double s0 = 0.0, s1 = 0.0;
+        for (int vb = blockIdx.x; vb < g.bx + g.by; vb += gridDim.x) rows_F_vblock(p, b, c, g, vb, s0, s1);
+        deferred_leave(a, s0, s1);
+        return;
+    }
     LsqrState *st = a.st;
     if (a.check_done && st->done) return;
     const Ctx c = make_ctx(a, p.N - 1);
@@ -95,123 +110,6 @@ __global__ __launch_bounds__(kBlock) void k_rows_F(Problem p, StepArgs a, RowGri
     double tot[3];
     if (last_block_sum3(s0, s1, 0.0, a.partials, a.counter, gridDim.x, tot) && threadIdx.x == 0)
         finalize(st, a.role, tot, false);
-}
-
-// ---------------------------------------------------------------------------------------
-// product with F': CSR rows, staged in tmp (x rows final, y rows before J)
-// ---------------------------------------------------------------------------------------
-
-__global__ __launch_bounds__(kBlock) void k_rows_FT(Problem p, StepArgs a, RowGrid g) {
-    LsqrState *st = a.st;
-    if (a.check_done && st->done) return;
-    const Ctx c = make_ctx(a, p.N - 1);
-    const int n = p.n, m = p.m, N = p.N;
-    const int tid = threadIdx.x;
-    const bool xr = blockIdx.x < (unsigned)g.bx;
-    const int L = xr ? g.lx : g.ly;
-    const long long gt = (long long)(xr ? blockIdx.x : blockIdx.x - g.bx) * kBlock + tid;
-    const int row = (int)(gt / L), lane = (int)(gt & (L - 1));
-    double acc = 0.0, accT = 0.0;
-    int idx = -1;
-    if (xr) {
-        if (row < n) {
-            for (int k = p.Prp[row] + lane; k < p.Prp[row + 1]; k += L)
-                acc += p.Pv[k] * ldin(a, c, p.Pci[k]);
-            for (int t = p.Trp[row] + lane; t < p.Trp[row + 1]; t += L)
-                accT += p.Tv[t] * ldin(a, c, n + p.Tci[t]);
-            idx = row;
-        }
-    } else {
-        if (row < m) {
-            for (int k = p.Arp[row] + lane; k < p.Arp[row + 1]; k += L)
-                acc += p.Av[k] * ldin(a, c, p.Aci[k]);
-            idx = n + row;
-        } else if (row == m) {
-            idx = N - 1;
-        }
-    }
-    acc = group_sum(acc, L);
-    accT = group_sum(accT, L);
-    if (lane == 0 && idx >= 0) {
-        if (idx < n) a.tmp[idx] = acc - accT + p.c[idx] * c.in_N;
-        else if (idx < N - 1) a.tmp[idx] = acc - p.b[idx - n] * c.in_N - ldin(a, c, idx);
-        if (a.do_update) lsqr_update(a, c, idx);
-    }
-}
-
-// ---------------------------------------------------------------------------------------
-// product with F': per cone block, plus the J the next product with F needs
-// ---------------------------------------------------------------------------------------
-
-__global__ __launch_bounds__(kBlock) void k_cone_FT(Problem p, StepArgs a, ConeGrid g) {
-    extern __shared__ double sm[];
-    LsqrState *st = a.st;
-    if (a.check_done && st->done) return;
-    const Ctx c = make_ctx(a, p.N - 1);
-    const int n = p.n, N = p.N;
-    const int tid = threadIdx.x;
-    double s0 = 0.0, s1 = 0.0;
-    auto nsc = [&](int idx) { return c.out_sc ? a.sc[idx] : 1.0; };
-    auto finish = [&](int idx, double val) {
-        const double o = role_value(a, c, idx, val);
-        a.out[idx] = o;
-        s0 += o * o;
-        return o;
-    };
-    const int bid = blockIdx.x;
-    if (bid < g.bE) {
-        const int e = bid * kBlock + tid;
-        if (e < g.nE) {
-            const int idx = (e < g.nE - 1) ? e : N - 1;
-            if (idx < n) {
-                const double o = finish(idx, a.tmp[idx]);
-                if (a.do_pre) s1 += p.c[idx] * nsc(idx) * o;
-            } else if (idx < N - 1) {
-                const int r = idx - n;
-                const double o = finish(idx, p.jdiag[r] * a.tmp[idx] + ldin(a, c, idx));
-                if (a.do_pre) {
-                    const double w = p.jdiag[r] * nsc(idx) * o;
-                    a.wy[r] = w;
-                    s1 -= p.b[r] * w;
-                }
-            } else {
-                finish(idx, st->dot_adj * c.inv + p.xPx * c.in_N);
-            }
-        }
-    } else if (bid < g.bE + g.bS) {
-        const int cone = (bid - g.bE) * kBlock + tid;
-        if (cone < p.n_soc) {
-            soc_jv(p, cone, [&](int r) { return a.tmp[n + r]; },
-                   [&](int r, double jt) { finish(n + r, jt + ldin(a, c, n + r)); });
-            if (a.do_pre)
-                soc_jv(p, cone, [&](int r) { return nsc(n + r) * a.out[n + r]; },
-                       [&](int r, double w) { a.wy[r] = w; s1 -= p.b[r] * w; });
-        }
-    } else if (bid < g.bE + g.bS + g.bX) {
-        const int cone = (bid - g.bE - g.bS) * kBlock + tid;
-        if (cone < p.n_exp) {
-            exp_jv(p, cone, [&](int r) { return a.tmp[n + r]; },
-                   [&](int r, double jt) { finish(n + r, jt + ldin(a, c, n + r)); });
-            if (a.do_pre)
-                exp_jv(p, cone, [&](int r) { return nsc(n + r) * a.out[n + r]; },
-                       [&](int r, double w) { a.wy[r] = w; s1 -= p.b[r] * w; });
-        }
-    } else {
-        const int cone = bid - g.bE - g.bS - g.bX;
-        const int r0 = p.psd_row[cone];
-        double *stage = sm + psd_stage_offset(p.psd_k[cone]);
-        psd_jv(p, cone, sm, [&](int r) { return a.tmp[n + r]; },
-               [&](int r, double jt) {
-                   const double o = finish(n + r, jt + ldin(a, c, n + r));
-                   stage[r - r0] = nsc(n + r) * o;
-               });
-        if (a.do_pre)
-            psd_jv(p, cone, sm, [&](int r) { return stage[r - r0]; },
-                   [&](int r, double w) { a.wy[r] = w; s1 -= p.b[r] * w; });
-    }
-    double tot[3];
-    if (last_block_sum3(s0, s1, 0.0, a.partials, a.counter, gridDim.x, tot) && tid == 0)
-        finalize(st, a.role, tot, true);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -225,6 +123,27 @@ __global__ __launch_bounds__(kBlock) void k_cone_FT(Problem p, StepArgs a, ConeG
 
 __global__ __launch_bounds__(kBlock) void k_fused_FT(Problem p, StepArgs a, FusedGrid g) {
     extern __shared__ double sm[];
+    if (a.deferred) {
+        __shared__ LsqrState S;
+        if (!deferred_enter(a, &S, 1)) return;
+        StepArgs b = a;
+        b.st = &S;
+        const Ctx c = make_ctx(b, p.N - 1);
+        double s0 = 0.0, s1 = 0.0;
+        for (int ui = blockIdx.x; ui < g.nunits; ui += gridDim.x) {
+            fused_unit(p, b, c, g.lx, g.ly, g.units[ui], sm, s0, s1);
+            __syncthreads();
+        }
+        if (blockIdx.x == 0 && threadIdx.x == 0) {  // the tau entry
+            const int N = p.N;
+            const double o = role_value(b, c, N - 1, S.dot_adj * c.inv + p.xPx * c.in_N);
+            b.out[N - 1] = o;
+            s0 += o * o;
+            if (b.do_update) lsqr_update(b, c, N - 1);
+        }
+        deferred_leave(a, s0, s1);
+        return;
+    }
     LsqrState *st = a.st;
     if (a.check_done && st->done) return;
     const int N = p.N;
@@ -236,6 +155,7 @@ __global__ __launch_bounds__(kBlock) void k_fused_FT(Problem p, StepArgs a, Fuse
         const double o = role_value(a, c, N - 1, st->dot_adj * c.inv + p.xPx * c.in_N);
         a.out[N - 1] = o;
         s0 += o * o;
+        if (a.role == ROLE_RESID) s1 += a.rhs[N - 1] * a.rhs[N - 1];
         if (a.do_update) lsqr_update(a, c, N - 1);
     }
     double tot[3];
@@ -345,8 +265,8 @@ __global__ __launch_bounds__(kBlock) void k_cone_pre(Problem p, StepArgs a, Cone
     if (a.check_done && st->done) return;
     const int n = p.n, N = p.N;
     const int tid = threadIdx.x;
-    const bool isc = a.in_is_v && a.sc != nullptr;
-    auto ld = [&](int idx) { return isc ? a.sc[idx] * a.in[idx] : a.in[idx]; };
+    const double *isc = a.in_is_v ? a.sc : a.scl;
+    auto ld = [&](int idx) { return isc ? isc[idx] * a.in[idx] : a.in[idx]; };
     double s1 = 0.0;
     const int bid = blockIdx.x;
     if (bid < g.bE) {
@@ -392,6 +312,7 @@ __global__ void k_state_init(LsqrState *st, double tol, int max_iter) {
         s.one = 1.0;
         s.tol = tol;
         s.max_iter = max_iter;
+        s.pend_role = -1;
         *st = s;
     }
 }
@@ -422,7 +343,7 @@ __global__ __launch_bounds__(kBlock) void k_flush(Problem p, StepArgs a, double 
     double tot[3];
     if (last_block_sum3(0.0, s1, 0.0, a.partials, a.counter, gridDim.x, tot) && threadIdx.x == 0) {
         st->pending = 0;
-        st->dot_adj = tot[1];
+        (a.st_next ? a.st_next : st)->dot_adj = tot[1];  // for a product with F' at sol
     }
 }
 
@@ -467,16 +388,21 @@ __global__ __launch_bounds__(kBlock) void k_jvp_rhs(Problem p, StepArgs a, RowGr
             s1 = p.b[r] * o;
             s2 = db[r] * p.y[r];
         }
-        a.out[idx] = o;
+        // LSQR starts from u~ = L(-d) (L = scl, the row scale); the unscaled -d is kept for
+        // the explicit residual
+        const double l = a.scl ? a.scl[idx] : 1.0;
+        a.out[idx] = l * o;
         const_cast<double *>(a.rhs)[idx] = o;
-        s0 = o * o;
+        s0 = l * o * l * o;
+        s1 *= l * l;
     }
     double tot[3];
     if (last_block_sum3(s0, s1, s2, a.partials, a.counter, gridDim.x, tot) && tid == 0) {
         const double oN = tot[2];  // -d_N = x'dP x + dq'x + db'y
-        a.out[N - 1] = oN;
+        const double lN = a.scl ? a.scl[N - 1] : 1.0;
+        a.out[N - 1] = lN * oN;
         const_cast<double *>(a.rhs)[N - 1] = oN;
-        const double beta = sqrt(tot[0] + oN * oN);
+        const double beta = sqrt(tot[0] + lN * oN * lN * oN);
         st->beta = beta;
         st->beta1 = beta;
         st->phibar = beta;
@@ -497,9 +423,10 @@ __global__ __launch_bounds__(kBlock) void k_vjp_rhs(Problem p, StepArgs a, ConeG
     double *rhs = const_cast<double *>(a.rhs);
     double s0 = 0.0, s2 = 0.0;
     auto put = [&](int idx, double o) {
-        a.out[idx] = o;
+        const double l = a.scl ? a.scl[idx] : 1.0;  // scaled LSQR start, unscaled copy
+        a.out[idx] = l * o;
         rhs[idx] = o;
-        s0 += o * o;
+        s0 += l * o * l * o;
     };
     auto gsum = [&](int r) { return gy[r] + gs[r]; };
     auto yout = [&](int r, double jt) {
@@ -531,9 +458,10 @@ __global__ __launch_bounds__(kBlock) void k_vjp_rhs(Problem p, StepArgs a, ConeG
     double tot[3];
     if (last_block_sum3(s0, 0.0, s2, a.partials, a.counter, gridDim.x, tot) && tid == 0) {
         const double oN = tot[2];  // -dz_N
-        a.out[N - 1] = oN;
+        const double lN = a.scl ? a.scl[N - 1] : 1.0;
+        a.out[N - 1] = lN * oN;
         rhs[N - 1] = oN;
-        const double beta = sqrt(tot[0] + oN * oN);
+        const double beta = sqrt(tot[0] + lN * oN * lN * oN);
         st->beta = beta;
         st->beta1 = beta;
         st->phibar = beta;
@@ -608,17 +536,12 @@ __global__ void k_nan_scan(const double *const *ptrs, const long long *lens, int
 // host launchers
 // ---------------------------------------------------------------------------------------
 
-void launch_rows_F(const Problem &p, const StepArgs &a, const RowGrid &g, hipStream_t s) {
-    hipLaunchKernelGGL(k_rows_F, dim3(g.total()), dim3(kBlock), 0, s, p, a, g);
+void launch_rows_F(const Problem &p, const StepArgs &a, const RowGrid &g, hipStream_t s, int grid) {
+    hipLaunchKernelGGL(k_rows_F, dim3(grid > 0 ? grid : g.total()), dim3(kBlock), 0, s, p, a, g);
 }
-void launch_rows_FT(const Problem &p, const StepArgs &a, const RowGrid &g, hipStream_t s) {
-    hipLaunchKernelGGL(k_rows_FT, dim3(g.total()), dim3(kBlock), 0, s, p, a, g);
-}
-void launch_cone_FT(const Problem &p, const StepArgs &a, const ConeGrid &g, int lds, hipStream_t s) {
-    hipLaunchKernelGGL(k_cone_FT, dim3(g.total()), dim3(kBlock), lds, s, p, a, g);
-}
-void launch_fused_FT(const Problem &p, const StepArgs &a, const FusedGrid &g, int lds, hipStream_t s) {
-    hipLaunchKernelGGL(k_fused_FT, dim3(g.nunits), dim3(kBlock), lds, s, p, a, g);
+void launch_fused_FT(const Problem &p, const StepArgs &a, const FusedGrid &g, int lds, hipStream_t s,
+                     int grid) {
+    hipLaunchKernelGGL(k_fused_FT, dim3(grid > 0 ? grid : g.nunits), dim3(kBlock), lds, s, p, a, g);
 }
 void launch_cone_pre(const Problem &p, const StepArgs &a, const ConeGrid &g, int lds, hipStream_t s) {
     hipLaunchKernelGGL(k_cone_pre, dim3(g.total()), dim3(kBlock), lds, s, p, a, g);
@@ -658,7 +581,6 @@ void launch_nan_scan(const double *const *ptrs, const long long *lens, int nseg,
 
 // the cone kernels may need more than the default 64 KB of dynamic LDS for PSD blocks
 void set_cone_kernel_lds(int bytes) {
-    hipFuncSetAttribute((const void *)k_cone_FT, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     hipFuncSetAttribute((const void *)k_cone_pre, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     hipFuncSetAttribute((const void *)k_vjp_rhs, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 

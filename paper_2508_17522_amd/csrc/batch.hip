@@ -80,7 +80,7 @@ __device__ void blk_rows_F(const Problem &p, const StepArgs &a, const Ctx &c, co
                 const double o = role_value(a, c, row, acc + accT * c.inv + p.q[row] * c.in_N);
                 a.out[row] = o;
                 s0 += o * o;
-                s1 += p.q[row] * (c.out_sc ? a.sc[row] : 1.0) * o;
+                s1 += (a.role == ROLE_RESID) ? a.rhs[row] * a.rhs[row] : p.q[row] * nscale(c, row) * o;
                 if (a.do_update) lsqr_update(a, c, row);
             }
         }
@@ -100,7 +100,7 @@ __device__ void blk_rows_F(const Problem &p, const StepArgs &a, const Ctx &c, co
                 const double o = role_value(a, c, idx, val);
                 a.out[idx] = o;
                 s0 += o * o;
-                s1 += p.b[r] * (c.out_sc ? a.sc[idx] : 1.0) * o;
+                s1 += (a.role == ROLE_RESID) ? a.rhs[idx] * a.rhs[idx] : p.b[r] * nscale(c, idx) * o;
                 if (a.do_update) lsqr_update(a, c, idx);
             }
         }
@@ -109,6 +109,7 @@ __device__ void blk_rows_F(const Problem &p, const StepArgs &a, const Ctx &c, co
         const double o = role_value(a, c, bc.tix, a.st->dot_fwd * c.inv + bc.xPx * c.in_N);
         a.out[bc.tix] = o;
         s0 += o * o;
+        if (a.role == ROLE_RESID) s1 += a.rhs[bc.tix] * a.rhs[bc.tix];
         if (a.do_update) lsqr_update(a, c, bc.tix);
     }
 }
@@ -124,6 +125,7 @@ __device__ void blk_fused_FT(const Problem &p, const BatchDev &d, const StepArgs
         const double o = role_value(a, c, bc.tix, a.st->dot_adj * c.inv + bc.xPx * c.in_N);
         a.out[bc.tix] = o;
         s0 += o * o;
+        if (a.role == ROLE_RESID) s1 += a.rhs[bc.tix] * a.rhs[bc.tix];
         if (a.do_update) lsqr_update(a, c, bc.tix);
     }
 }
@@ -251,7 +253,7 @@ __device__ void solve_one(const BatchDev &d, int dir, int b, LsqrState *S, doubl
         LsqrState z = {};
         z.one = 1.0;
         z.tol = d.tol;
-        z.max_iter = d.max_iter > 0 ? d.max_iter : 20 * Nb;
+        z.max_iter = d.max_iter > 0 ? d.max_iter : 100 * Nb;
         *S = z;
     }
     auto each_index = [&](auto f) {

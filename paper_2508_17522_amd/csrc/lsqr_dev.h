@@ -61,6 +61,7 @@ __device__ inline void finalize(LsqrState *st, int role, const double tot[3], bo
     }
     case ROLE_RESID:
         st->resid = sqrt(tot[0]);
+        st->tau_rhs = sqrt(tot[1]);  // ||rhs|| of the unscaled system
         break;
     default:
         if (dot_is_fwd) st->dot_fwd = tot[1]; else st->dot_adj = tot[1];
@@ -68,11 +69,68 @@ __device__ inline void finalize(LsqrState *st, int role, const double tot[3], bo
     }
 }
 
+// Entry of a deferred-protocol launch (see StepArgs): all threads call it; returns false in
+// every thread when the loop has finished. S is the workgroup's LDS copy of the state.
+__device__ inline bool deferred_enter(const StepArgs &a, LsqrState *S, int my_fwd) {
+    const int tid = threadIdx.x;
+    if (tid == 0) *S = *a.st;
+    __syncthreads();
+    if (S->done) {
+        if (blockIdx.x == 0 && tid == 0) *a.st_next = *S;
+        return false;
+    }
+    if (S->pend_role >= 0) {
+        double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+        for (int i = tid; i < S->pend_blocks; i += kBlock) {
+            t0 += a.part_prev[3 * i];
+            t1 += a.part_prev[3 * i + 1];
+        }
+        block_sum3(t0, t1, t2);
+        if (tid == 0) {
+            const double tot[3] = {t0, t1, 0.0};
+            finalize(S, S->pend_role, tot, S->pend_fwd != 0);
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        if (S->done) {
+            S->pend_role = -1;
+        } else {
+            S->pend_role = a.role;
+            S->pend_blocks = gridDim.x;
+            S->pend_fwd = my_fwd;
+        }
+        if (blockIdx.x == 0) {
+            *a.st_next = *S;
+            // on the stop decision both buffers get the final state (any block still reading
+            // the input buffer then also sees `done` and exits without working)
+            if (S->done) *a.st = *S;
+        }
+    }
+    __syncthreads();
+    return !S->done;
+}
+
+// Exit of a deferred-protocol launch: this workgroup's partial sums, plain stores.
+__device__ inline void deferred_leave(const StepArgs &a, double s0, double s1) {
+    double z = 0.0;
+    block_sum3(s0, s1, z);
+    if (threadIdx.x == 0) {
+        a.part_next[3 * blockIdx.x] = s0;
+        a.part_next[3 * blockIdx.x + 1] = s1;
+    }
+}
+
 struct Ctx {  // per-launch scalars every thread derives from the state block
     double inv, cU, cV, inv_alpha_up, phr, thr, in_N;
-    bool in_sc, out_sc;
+    const double *isc;  // scale applied when reading the input (sc for v, scl for u)
+    const double *osc;  // scale applied to the operator's output in the role update
+    const double *nxs;  // scale the next product applies when it reads this output
 };
 
+// The LSQR matrix is M = L F R (JVP) or L F' R (VJP) with diagonal L = scl, R = sc. The
+// v-side vectors are read through sc, the u-side vectors through scl; M v = L op(R v) and
+// M'u = R op'(L u), so a u-step output is scaled by scl and a v-step output by sc.
 __device__ inline Ctx make_ctx(const StepArgs &a, int tau_idx) {
     const LsqrState *st = a.st;
     const double *sv = reinterpret_cast<const double *>(st);
@@ -83,22 +141,26 @@ __device__ inline Ctx make_ctx(const StepArgs &a, int tau_idx) {
     c.inv_alpha_up = a.do_update ? 1.0 / st->alpha : 0.0;
     c.phr = st->phr;
     c.thr = st->thr;
-    c.in_sc = a.in_is_v && a.sc != nullptr;
-    c.out_sc = a.out_is_v && a.sc != nullptr;
-    c.in_N = a.in[tau_idx] * c.inv * (c.in_sc ? a.sc[tau_idx] : 1.0);
+    c.isc = a.in_is_v ? a.sc : a.scl;
+    c.osc = (a.role == ROLE_U) ? a.scl : (a.role == ROLE_V || a.role == ROLE_V0) ? a.sc : nullptr;
+    c.nxs = a.out_is_v ? a.sc : a.scl;
+    c.in_N = a.in[tau_idx] * c.inv * (c.isc ? c.isc[tau_idx] : 1.0);
     return c;
 }
 
 __device__ inline double ldin(const StepArgs &a, const Ctx &c, int i) {
     const double v = a.in[i] * c.inv;
-    return c.in_sc ? v * a.sc[i] : v;
+    return c.isc ? v * c.isc[i] : v;
 }
 
+__device__ inline double nscale(const Ctx &c, int idx) { return c.nxs ? c.nxs[idx] : 1.0; }
+
 __device__ inline double role_value(const StepArgs &a, const Ctx &c, int idx, double val) {
+    const double sv = c.osc ? c.osc[idx] * val : val;
     switch (a.role) {
-    case ROLE_U: return val - c.cU * a.out[idx];
-    case ROLE_V: return (c.out_sc ? a.sc[idx] : 1.0) * val - c.cV * a.out[idx];
-    case ROLE_V0: return (c.out_sc ? a.sc[idx] : 1.0) * val;
+    case ROLE_U: return sv - c.cU * a.out[idx];
+    case ROLE_V: return sv - c.cV * a.out[idx];
+    case ROLE_V0: return sv;
     case ROLE_RESID: return val - a.rhs[idx];
     default: return val;
     }
@@ -124,11 +186,12 @@ __device__ inline void fused_unit(const Problem &p, const StepArgs &a, const Ctx
                                   int ly, const Unit &u, double *sm, double &s0, double &s1) {
     const int n = p.n;
     const int tid = threadIdx.x;
-    auto nsc = [&](int idx) { return c.out_sc ? a.sc[idx] : 1.0; };
+    auto nsc = [&](int idx) { return nscale(c, idx); };
     auto finish = [&](int idx, double val) {
         const double o = role_value(a, c, idx, val);
         a.out[idx] = o;
         s0 += o * o;
+        if (a.role == ROLE_RESID) s1 += a.rhs[idx] * a.rhs[idx];
         return o;
     };
     // t_r = A_r. r_x - b_r r_N - r_y for y rows [r0, r1), L lanes per row, into buf

@@ -31,7 +31,9 @@ struct LsqrState {
     int32_t iters;
     int32_t max_iter;
     int32_t conv;     // 1 when the stopping test passed
-    int32_t pad[3];
+    // deferred protocol of the LSQR loop kernels: the role, block count and dot kind of the
+    // partial sums the previous launch left for the next launch to finalise (-1: none)
+    int32_t pend_role, pend_blocks, pend_fwd;
 };
 
 // Offsets of doubles inside LsqrState, used to select a normaliser by index.
@@ -171,7 +173,8 @@ struct StepArgs {
     double *out;        // output buffer (N), updated in place
     int role;
     int out_is_v;       // the output is the v-side vector (scaled by sc)
-    const double *sc;   // v-side diagonal scale (Jacobi / custom), or null
+    const double *sc;   // v-side (column) diagonal scale of the LSQR matrix, or null
+    const double *scl;  // u-side (row) diagonal scale of the LSQR matrix, or null
     const double *rhs;  // ROLE_RESID right-hand side
     double *wy;         // J applied to the next product's y-input (unnormalised), m
     int do_pre;         // compute wy and the F tau-row dot for the next product
@@ -182,6 +185,13 @@ struct StepArgs {
     int *counter;
     LsqrState *st;
     int check_done;     // return at once when st->done is set (kernels inside the loop)
+    // deferred protocol (LSQR loop): read the state from st and the previous launch's
+    // partials from part_prev, finalise them at entry, write the state to st_next and this
+    // launch's partials to part_next. No fences or atomics: launch order gives visibility.
+    int deferred;
+    LsqrState *st_next;
+    const double *part_prev;
+    double *part_next;
 };
 
 // Work units of the fused product with F' (one workgroup each): x rows, diagonal y rows,
@@ -201,17 +211,14 @@ struct FusedGrid {
 
 // host launchers (apply.hip)
 void launch_fused_FT(const Problem &p, const StepArgs &a, const FusedGrid &g, int lds_bytes,
-                     hipStream_t s);
+                     hipStream_t s, int grid = 0);
 int fused_lds_bytes(int kmax);
 int persistent_blocks_per_cu(int lds_bytes);
 hipError_t launch_lsqr_persistent(const Problem &p, const StepArgs &fa, const StepArgs &ta,
                                   const RowGrid &rg, const FusedGrid &fg, int dir, LsqrState *st,
                                   double *partials, int grid, int lds, hipStream_t s);
 void set_fused_kernel_lds(int bytes);
-void launch_rows_F(const Problem &p, const StepArgs &a, const RowGrid &g, hipStream_t s);
-void launch_rows_FT(const Problem &p, const StepArgs &a, const RowGrid &g, hipStream_t s);
-void launch_cone_FT(const Problem &p, const StepArgs &a, const ConeGrid &g, int lds_bytes,
-                    hipStream_t s);
+void launch_rows_F(const Problem &p, const StepArgs &a, const RowGrid &g, hipStream_t s, int grid = 0);
 void launch_cone_pre(const Problem &p, const StepArgs &a, const ConeGrid &g, int lds_bytes,
                      hipStream_t s);
 void launch_state_init(LsqrState *st, double tol, int max_iter, hipStream_t s);

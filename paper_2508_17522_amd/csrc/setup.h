@@ -27,6 +27,8 @@ void launch_cone_factors(const Problem &p, const ConeHost &ch, double *jdiag, do
 void launch_scales(const Problem &p, const RowGrid &g, double *dj, double *dv, double *partials,
                    int *counter, hipStream_t s, int do_tau = 1);
 int psd_factor_lds_bytes(int kmax);
+void launch_equilibrate(const Problem &p, const RowGrid &g, double *DL, double *DR, double *tmpL,
+                        double *tmpR, int sweeps, double *partials, int *counter, hipStream_t s);
 void set_cone_kernel_lds(int bytes);
 
 }  // namespace qcpd

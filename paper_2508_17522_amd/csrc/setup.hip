@@ -544,6 +544,90 @@ __global__ __launch_bounds__(kBlock) void k_scales(Problem p, RowGrid g, double 
 }
 
 // ---------------------------------------------------------------------------------------
+// Two-sided equilibration of F-hat (F with each cone block's J replaced by its diagonal):
+// one sweep divides every row and every column of M = DL F-hat DR by the square root of its
+// 2-norm, DL_i /= sqrt(||M_i.||), DR_j /= sqrt(||M_.j||), both from the same M. Entries:
+//   x row i:  P_i., (A'_i. J), q_i      y row r:  -A_r., (1 - J_rr) at (r, r), b_r
+//   tau row:  c', -(b o J)', x'Px
+// Repeated sweeps balance row and column norms (the LSQR systems are consistent, so a row
+// scaling leaves their solutions unchanged).
+// ---------------------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_equil_sweep(Problem p, RowGrid g, const double *DL,
+                                                        const double *DR, double *DLo, double *DRo,
+                                                        double *partials, int *counter) {
+    const int tid = threadIdx.x, n = p.n, N = p.N;
+    const bool xr = blockIdx.x < (unsigned)g.bx;
+    const int L = xr ? g.lx : g.ly;
+    const long long gt = (long long)(xr ? blockIdx.x : blockIdx.x - g.bx) * kBlock + tid;
+    const int row = (int)(gt / L), lane = (int)(gt & (L - 1));
+    const double dlN = DL[N - 1], drN = DR[N - 1];
+    double rs = 0.0, cs = 0.0;
+    if (xr && row < n) {
+        for (int k = p.Prp[row] + lane; k < p.Prp[row + 1]; k += L) {
+            const double v2 = p.Pv[k] * p.Pv[k];
+            const int j = p.Pci[k];
+            rs += v2 * DR[j] * DR[j];
+            cs += v2 * DL[j] * DL[j];  // P symmetric: column i = row i
+        }
+        for (int t = p.Trp[row] + lane; t < p.Trp[row + 1]; t += L) {
+            const int r = p.Tci[t];
+            const double v2 = p.Tv[t] * p.Tv[t], jd = p.jdiag[r];
+            rs += v2 * jd * jd * DR[n + r] * DR[n + r];
+            cs += v2 * DL[n + r] * DL[n + r];
+        }
+    } else if (!xr && row < p.m) {
+        for (int k = p.Arp[row] + lane; k < p.Arp[row + 1]; k += L) {
+            const double v2 = p.Av[k] * p.Av[k];
+            const int j = p.Aci[k];
+            rs += v2 * DR[j] * DR[j];
+            cs += v2 * DL[j] * DL[j];
+        }
+    }
+    for (int off = L >> 1; off > 0; off >>= 1) {
+        rs += __shfl_xor(rs, off);
+        cs += __shfl_xor(cs, off);
+    }
+    double s0 = 0.0, s1 = 0.0;
+    auto upd = [&](int i, double rsum, double csum) {
+        const double rn = DL[i] * sqrt(rsum), cn = DR[i] * sqrt(csum);
+        DLo[i] = rn > 0.0 ? DL[i] / sqrt(rn) : DL[i];
+        DRo[i] = cn > 0.0 ? DR[i] / sqrt(cn) : DR[i];
+    };
+    if (lane == 0) {
+        if (xr && row < n) {
+            const double q = p.q[row], c = p.c[row];
+            upd(row, rs + q * q * drN * drN, cs + c * c * dlN * dlN);
+            s0 = c * c * DR[row] * DR[row];  // tau row
+            s1 = q * q * DL[row] * DL[row];  // tau column
+        } else if (!xr && row < p.m) {
+            const int i = n + row;
+            const double jd = p.jdiag[row], b = p.b[row], o = 1.0 - jd;
+            upd(i, rs + o * o * DR[i] * DR[i] + b * b * drN * drN,
+                jd * jd * cs + o * o * DL[i] * DL[i] + b * b * jd * jd * dlN * dlN);
+            s0 = b * b * jd * jd * DR[i] * DR[i];
+            s1 = b * b * DL[i] * DL[i];
+        }
+    }
+    double tot[3];
+    if (last_block_sum3(s0, s1, 0.0, partials, counter, gridDim.x, tot) && tid == 0) {
+        const double x2 = p.xPx * p.xPx;
+        upd(N - 1, tot[0] + x2 * drN * drN, tot[1] + x2 * dlN * dlN);
+    }
+}
+
+void launch_equilibrate(const Problem &p, const RowGrid &g, double *DL, double *DR, double *tmpL,
+                        double *tmpR, int sweeps, double *partials, int *counter, hipStream_t s) {
+    // starts from DL = DR = 1 (filled by the caller); an even number of sweeps ends in DL, DR
+    for (int k = 0; k < sweeps; ++k) {
+        const bool even = (k % 2) == 0;
+        hipLaunchKernelGGL(k_equil_sweep, dim3(g.total()), dim3(kBlock), 0, s, p, g,
+                           even ? DL : tmpL, even ? DR : tmpR, even ? tmpL : DL, even ? tmpR : DR,
+                           partials, counter);
+    }
+}
+
+// ---------------------------------------------------------------------------------------
 // host wrappers
 // ---------------------------------------------------------------------------------------
 

@@ -92,9 +92,26 @@ def test_medium_mixed_several_tiles(engine):
     check_jvp_vjp_dense(q, engine=engine)
 
 
-def test_unpreconditioned_matches():
+@pytest.mark.parametrize("precond", [Q.QCPD_PRECOND_NONE, Q.QCPD_PRECOND_EQUIL])
+def test_other_preconditioners_match(precond):
     q = qcpgen.small_mixed(0)
-    check_jvp_vjp_dense(q, precond=Q.QCPD_PRECOND_NONE)
+    check_jvp_vjp_dense(q, precond=precond)
+
+
+def test_equilibrated_medium_and_custom_scaling():
+    """Two-sided equilibration on every cone type, then the same scales passed back in as a
+    custom two-sided preconditioner."""
+    q = qcpgen.small_mixed(1, n=301, n_zero=37, n_nonneg=260, soc=(3, 4, 5, 6, 7, 8) * 5,
+                           psd=(4, 7, 12, 9), n_exp=23, A_density=0.04, P_rank=150,
+                           nonneg_active=100)
+    check_jvp_vjp_dense(q, precond=Q.QCPD_PRECOND_EQUIL)
+    h, t = make_handle(q, precond=Q.QCPD_PRECOND_CUSTOM)
+    dg = Q.qcpd_get_diagnostics(h)
+    assert torch.all(dg["equil_col"] > 0) and torch.all(dg["equil_row"] > 0)
+    Q.qcpd_set_precond(h, dg["equil_col"], dg["equil_row"])
+    dx, dy, ds, info, st = gpu_jvp(h, t)
+    ref = D.jvp_dense(q, q.dP, q.dA, q.dq, q.db)
+    assert st == Q.QCPD_OK and max(rel(a, b) for a, b in zip((dx, dy, ds), ref)) <= BAR
 
 
 def test_psd_max_order():
@@ -133,23 +150,25 @@ def mixed_full():
     return qcpgen.mixed_qcp(0)
 
 
-@pytest.mark.parametrize("engine", [Q.QCPD_ENGINE_GRAPH, Q.QCPD_ENGINE_PERSISTENT])
-def test_mixed_full_size_properties(mixed_full, engine):
+@pytest.mark.parametrize("engine,precond", [(Q.QCPD_ENGINE_GRAPH, Q.QCPD_PRECOND_EQUIL),
+                                            (Q.QCPD_ENGINE_GRAPH, Q.QCPD_PRECOND_JACOBI),
+                                            (Q.QCPD_ENGINE_PERSISTENT, Q.QCPD_PRECOND_EQUIL)])
+def test_mixed_full_size_properties(mixed_full, engine, precond):
     """At the benchmark size and tolerance: the JVP satisfies the linearised KKT system
     (oracle J and data, any size) and JVP/VJP satisfy the adjoint identity."""
     q = mixed_full
-    h, t = make_handle(q, tol=1e-8, engine=engine)
+    h, t = make_handle(q, tol=1e-8, engine=engine, precond=precond)
     dx, dy, ds, info, st = gpu_jvp(h, t)
     print(f"[mixed full] jvp iters={info.iters} rel_res={info.rel_residual:.2e} "
           f"ms={info.ms_total:.1f} st={st}", flush=True)
-    assert st == Q.QCPD_OK and info.rel_residual <= 1e-7
+    assert st == Q.QCPD_OK and info.rel_residual <= 1e-8
     res = kkt_linearised_residual(q, dx, dy, ds)
     print(f"[mixed full] linearised KKT residual {res:.2e}", flush=True)
     assert res <= 1e-6
     dP, dA, dq, db, info2, st2 = gpu_vjp(h, t)
     print(f"[mixed full] vjp iters={info2.iters} rel_res={info2.rel_residual:.2e} "
           f"ms={info2.ms_total:.1f} st={st2}", flush=True)
-    assert st2 == Q.QCPD_OK
+    assert st2 == Q.QCPD_OK and info2.rel_residual <= 1e-8
     lhs = q.gx @ dx + q.gy @ dy + q.gs @ ds
     rhs = dP @ q.dP + dA @ q.dA + dq @ q.dq + db @ q.db
     print(f"[mixed full] adjoint identity {lhs:.10e} {rhs:.10e}", flush=True)
