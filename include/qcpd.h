@@ -67,6 +67,11 @@ typedef int32_t qcpd_status;
                                     Jacobian replaced by its diagonal); the systems are
                                     consistent, so a row scaling leaves the solution unchanged.
                                     The stop is decided on the unscaled residual.           */
+#define QCPD_PRECOND_LEARNED 4   /* two-sided scaling predicted from per-index features of F
+                                    by the model installed with qcpd_set_learned. When LSQR
+                                    does not reach tol with it, the call is repeated with
+                                    JACOBI, which also serves as the reference (info flags
+                                    bit 2).                                                  */
 
 /* Compressed sparse rows. [device] arrays: rowptr (nrows+1), colind (nnz), val (nnz). */
 typedef struct {
@@ -111,7 +116,8 @@ typedef struct {
     double   est_residual;   /* LSQR estimate ||residual|| / ||rhs|| at exit                 */
     double   rel_residual;   /* explicit ||F dz + d|| / ||d|| (JVP) or ||F'w + dz|| / ||dz||
                                 (VJP), recomputed from the returned iterate                  */
-    uint32_t flags;          /* bit 0: not converged; bit 1: non-differentiable warning      */
+    uint32_t flags;          /* bit 0: not converged; bit 1: non-differentiable warning;
+                                bit 2: LEARNED fell back to JACOBI                            */
     float    ms_total;       /* wall time of the call on its stream (HIP events)             */
 } qcpd_info;
 
@@ -168,6 +174,66 @@ qcpd_status qcpd_get_diagnostics(qcpd_handle *h, double *d_jvp, double *d_vjp, d
  * launch in milliseconds to ms_out[0..1] [host]. Leaves the LSQR state undefined: call it
  * between, not during, derivative evaluations. */
 qcpd_status qcpd_profile_kernels(qcpd_handle *h, int32_t reps, float *ms_out);
+
+/* ---------------------------------------------------------------------------------------
+ * Learned preconditioner (an addition to the method: the iterative solves of Sec. 3.1-3.2
+ * name no preconditioner). For each index i of z = (x, y, tau) a feature row of
+ * QCPD_NFEAT floats is read off F; a 3-layer FP32 MLP (QCPD_NFEAT -> 64 -> 64 -> 2, tanh
+ * hidden layers) maps it to log corrections (c_col, c_row) of the Jacobi column and row
+ * scales: d_col = jacobi_col * exp(c_col), d_row = jacobi_row * exp(c_row).
+ *
+ * Feature row: 0 log column norm and 1 log row norm of F with each cone block's Jacobian
+ * replaced by its diagonal; 2..8 one-hot kind (x, zero, nonneg, SOC, PSD, exp, tau);
+ * 9 diagonal of DPi (1 for x and tau); 10 log(1 + |P_ii|) (x only); 11 log(1 + stored
+ * entries in row i of [P A'] (x) or of A (y)).
+ *
+ * Parameter blob, QCPD_MLP_PARAMS floats: mu[F] sd[F] (feature standardisation, fixed at
+ * init from data), W1[64][F] b1[64] W2[64][64] b2[64] W3[2][64] b3[2], W[out][in] row-major.
+ * Training minimises the mean over rows of the squared error against target rows
+ * (c_col, c_row); qcpd_learned_targets gives the corrections that reproduce the handle's
+ * equilibration scales.
+ * ------------------------------------------------------------------------------------- */
+#define QCPD_NFEAT        12
+#define QCPD_MLP_HIDDEN   64
+#define QCPD_MLP_PARAMS   (2 * QCPD_NFEAT + QCPD_MLP_HIDDEN * QCPD_NFEAT + QCPD_MLP_HIDDEN + \
+                           QCPD_MLP_HIDDEN * QCPD_MLP_HIDDEN + QCPD_MLP_HIDDEN +             \
+                           2 * QCPD_MLP_HIDDEN + 2)
+
+/* Feature rows of the handle's operator: feat [device] (n + m + 1) x QCPD_NFEAT, row-major. */
+qcpd_status qcpd_features(qcpd_handle *h, float *feat);
+
+/* Training targets of the handle: target [device] (n + m + 1) x 2, row-major, the log ratios
+ * of the equilibration scales to the Jacobi scales (columns, rows). */
+qcpd_status qcpd_learned_targets(qcpd_handle *h, float *target);
+
+/* Install the scales predicted by a model (weights [device], QCPD_MLP_PARAMS floats) on the
+ * handle, for QCPD_PRECOND_LEARNED. Features and inference run on the handle's stream; the
+ * weights are not kept. Replaces earlier learned scales. */
+qcpd_status qcpd_set_learned(qcpd_handle *h, const float *weights);
+
+/* Initialise a model [device]: mu and sd from the first nrows feature rows (sd below 1e-3
+ * becomes 1), Glorot-uniform weights from a SplitMix64 hash of (seed, index), zero biases. */
+qcpd_status qcpd_mlp_init(const float *feat, int32_t nrows, uint64_t seed, float *weights,
+                          void *stream);
+
+/* Raw model outputs: out [device] nrows x 2 from feat [device] nrows x QCPD_NFEAT. */
+qcpd_status qcpd_mlp_predict(const float *feat, int32_t nrows, const float *weights, float *out,
+                             void *stream);
+
+/* Floats of workspace qcpd_mlp_grad needs for nrows rows. */
+int64_t qcpd_mlp_workspace_floats(int32_t nrows);
+
+/* Gradient of the loss (1/nrows) sum_r ||MLP(feat_r) - target_r||^2 with respect to the
+ * parameters: grad [device] QCPD_MLP_PARAMS + 1 floats, the last one the loss itself
+ * (mu, sd entries are 0). workspace [device]: qcpd_mlp_workspace_floats(nrows) floats.
+ * Asynchronous on the stream. Sums run in a fixed order (deterministic). */
+qcpd_status qcpd_mlp_grad(const float *feat, const float *target, int32_t nrows,
+                          const float *weights, float *workspace, float *grad, void *stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8; step counts from 1) on the trained
+ * parameters; adam_m, adam_v [device] QCPD_MLP_PARAMS floats, zero before step 1. */
+qcpd_status qcpd_mlp_adam(const float *grad, float *weights, float *adam_m, float *adam_v,
+                          int32_t step, float lr, void *stream);
 
 /* ---------------------------------------------------------------------------------------
  * Batched form: many QCPs of uneven sizes evaluated in one launch (a persistent kernel in

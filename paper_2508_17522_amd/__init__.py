@@ -6,13 +6,15 @@ is its Python binding plus a torch.autograd.Function whose backward is the adjoi
 from ._capi import (QCPD_OK, QCPD_WARN_NOT_CONVERGED, QCPD_WARN_NONDIFF, QCPD_ERR_INVALID_ARG,
                     QCPD_ERR_DIM, QCPD_ERR_CONE, QCPD_ERR_PATTERN, QCPD_ERR_NAN, QCPD_ERR_HIP,
                     QCPD_ERR_OOM, QCPD_PRECOND_NONE, QCPD_PRECOND_JACOBI, QCPD_PRECOND_CUSTOM,
-                    QCPD_PRECOND_EQUIL,
+                    QCPD_PRECOND_EQUIL, QCPD_PRECOND_LEARNED, QCPD_FLAG_FALLBACK,
                     QCPD_ENGINE_AUTO, QCPD_ENGINE_GRAPH, QCPD_ENGINE_PERSISTENT,
                     LIB_PATH, EXPORTS)
 from .api import (Cones, Opts, Info, Handle, QCPDError, qcpd_create, qcpd_jvp, qcpd_vjp,
                   qcpd_destroy, qcpd_status_str, qcpd_opts_default, qcpd_set_opts,
                   qcpd_set_precond, qcpd_get_diagnostics, qcpd_profile_kernels)
 from .autograd import QCPStructure, qcp_solution_map
+from .learned import (LearnedModel, qcpd_features, qcpd_learned_targets, qcpd_set_learned,
+                      qcpd_mlp_init, qcpd_mlp_predict, qcpd_mlp_grad, qcpd_mlp_adam)
 from .batch import (BatchHandle, qcpd_batch_create, qcpd_batch_jvp, qcpd_batch_vjp,
                     qcpd_batch_set_opts, qcpd_batch_destroy)
 
@@ -20,6 +22,8 @@ __all__ = [
     "BatchHandle", "qcpd_batch_create", "qcpd_batch_jvp", "qcpd_batch_vjp", "qcpd_batch_set_opts",
     "qcpd_batch_destroy",
     "QCPStructure", "qcp_solution_map",
+    "LearnedModel", "qcpd_features", "qcpd_learned_targets", "qcpd_set_learned", "qcpd_mlp_init",
+    "qcpd_mlp_predict", "qcpd_mlp_grad", "qcpd_mlp_adam",
     "Cones", "Opts", "Info", "Handle", "QCPDError", "qcpd_create", "qcpd_jvp", "qcpd_vjp",
     "qcpd_destroy", "qcpd_status_str", "qcpd_opts_default", "qcpd_set_opts",
     "qcpd_set_precond", "qcpd_get_diagnostics", "qcpd_profile_kernels", "LIB_PATH", "EXPORTS",

@@ -53,6 +53,17 @@ QCPD_PRECOND_NONE = 0
 QCPD_PRECOND_JACOBI = 1
 QCPD_PRECOND_CUSTOM = 2
 QCPD_PRECOND_EQUIL = 3
+QCPD_PRECOND_LEARNED = 4
+
+QCPD_FLAG_NOT_CONVERGED = 1
+QCPD_FLAG_NONDIFF = 2
+QCPD_FLAG_FALLBACK = 4
+
+# learned preconditioner model
+QCPD_NFEAT = 12
+QCPD_MLP_HIDDEN = 64
+QCPD_MLP_PARAMS = (2 * QCPD_NFEAT + QCPD_MLP_HIDDEN * QCPD_NFEAT + QCPD_MLP_HIDDEN
+                   + QCPD_MLP_HIDDEN * QCPD_MLP_HIDDEN + QCPD_MLP_HIDDEN + 2 * QCPD_MLP_HIDDEN + 2)
 
 class qcpd_batch_layout(ctypes.Structure):
     _fields_ = [("nprob", c_int32), ("n", ctypes.POINTER(c_int32)), ("m", ctypes.POINTER(c_int32)),
@@ -63,7 +74,9 @@ class qcpd_batch_layout(ctypes.Structure):
 EXPORTS = ["qcpd_opts_default", "qcpd_create", "qcpd_jvp", "qcpd_vjp", "qcpd_set_opts",
            "qcpd_set_precond", "qcpd_get_diagnostics", "qcpd_profile_kernels", "qcpd_destroy",
            "qcpd_status_str", "qcpd_batch_create", "qcpd_batch_jvp", "qcpd_batch_vjp",
-           "qcpd_batch_set_opts", "qcpd_batch_destroy"]
+           "qcpd_batch_set_opts", "qcpd_batch_destroy", "qcpd_features", "qcpd_learned_targets",
+           "qcpd_set_learned", "qcpd_mlp_init", "qcpd_mlp_predict", "qcpd_mlp_workspace_floats",
+           "qcpd_mlp_grad", "qcpd_mlp_adam"]
 
 _lib = None
 
@@ -110,6 +123,24 @@ def load(path: str = LIB_PATH):
     lib.qcpd_batch_set_opts.restype = c_int32
     lib.qcpd_batch_destroy.argtypes = [c_void_p]
     lib.qcpd_batch_destroy.restype = None
+    lib.qcpd_features.argtypes = [c_void_p, c_void_p]
+    lib.qcpd_features.restype = c_int32
+    lib.qcpd_learned_targets.argtypes = [c_void_p, c_void_p]
+    lib.qcpd_learned_targets.restype = c_int32
+    lib.qcpd_set_learned.argtypes = [c_void_p, c_void_p]
+    lib.qcpd_set_learned.restype = c_int32
+    lib.qcpd_mlp_init.argtypes = [c_void_p, c_int32, ctypes.c_uint64, c_void_p, c_void_p]
+    lib.qcpd_mlp_init.restype = c_int32
+    lib.qcpd_mlp_predict.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_void_p]
+    lib.qcpd_mlp_predict.restype = c_int32
+    lib.qcpd_mlp_workspace_floats.argtypes = [c_int32]
+    lib.qcpd_mlp_workspace_floats.restype = ctypes.c_int64
+    lib.qcpd_mlp_grad.argtypes = [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p,
+                                  c_void_p]
+    lib.qcpd_mlp_grad.restype = c_int32
+    lib.qcpd_mlp_adam.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_int32,
+                                  ctypes.c_float, c_void_p]
+    lib.qcpd_mlp_adam.restype = c_int32
     lib.qcpd_status_str.argtypes = [c_int32]
     lib.qcpd_status_str.restype = ctypes.c_char_p
     _lib = lib

@@ -35,6 +35,9 @@ struct qcpd_handle {
     double *scale[2] = {nullptr, nullptr};   // Jacobi: [0] columns of F, [1] columns of F'
     double *equil[2] = {nullptr, nullptr};   // two-sided equilibration: [0] columns, [1] rows of F
     double *custom[2] = {nullptr, nullptr};  // caller-supplied: [0] columns, [1] rows of F
+    double *learned[2] = {nullptr, nullptr}; // predicted by a learned model: columns, rows
+    float *feat = nullptr;                   // feature rows of the learned model (N x NFEAT)
+    FeatMeta fmeta{};                        // y-row boundaries of the cone kinds
     LsqrState *st_res = nullptr;             // state of the explicit-residual launches
     double *wy_res = nullptr;                // J(sol_y) of the explicit residual / JVP output
     double *jdiag = nullptr;
@@ -107,7 +110,7 @@ void free_handle(qcpd_handle *h) {
 
 qcpd_status check_opts(const qcpd_opts *o) {
     if (!(o->tol >= 0.0) || o->max_iter < 0 || o->graph_chunk < 1 || o->graph_chunk > 4096 ||
-        o->precond < QCPD_PRECOND_NONE || o->precond > QCPD_PRECOND_EQUIL ||
+        o->precond < QCPD_PRECOND_NONE || o->precond > QCPD_PRECOND_LEARNED ||
         o->engine < QCPD_ENGINE_AUTO || o->engine > QCPD_ENGINE_PERSISTENT)
         return QCPD_ERR_INVALID_ARG;
     return QCPD_OK;
@@ -149,6 +152,7 @@ void active_scales(const qcpd_handle *h, int dir, const double **sc, const doubl
     switch (h->opts.precond) {
     case QCPD_PRECOND_JACOBI: *sc = h->scale[dir]; break;
     case QCPD_PRECOND_EQUIL: *sc = h->equil[dir]; *scl = h->equil[1 - dir]; break;
+    case QCPD_PRECOND_LEARNED: *sc = h->learned[dir]; *scl = h->learned[1 - dir]; break;
     case QCPD_PRECOND_CUSTOM:
         if (h->custom[0]) { *sc = h->custom[dir]; *scl = h->custom[1 - dir]; }
         else { *sc = h->scale[dir]; }
@@ -346,13 +350,14 @@ qcpd_status solve(qcpd_handle *h, int dir, const double *sc, const double *scl, 
     return QCPD_OK;
 }
 
-void fill_info(qcpd_handle *h, qcpd_info *info, double rel) {
+void fill_info(qcpd_handle *h, qcpd_info *info, double rel, int extra_iters = 0,
+               uint32_t extra_flags = 0) {
     if (!info) return;
     const LsqrState &st = h->host_st[0];
-    info->iters = st.iters;
+    info->iters = st.iters + extra_iters;
     info->est_residual = st.beta1 > 0.0 ? st.phibar / st.beta1 : 0.0;
     info->rel_residual = rel;
-    info->flags = (st.conv ? 0u : 1u) | h->create_flags;
+    info->flags = (st.conv ? 0u : 1u) | h->create_flags | extra_flags;
     float ms = 0.f;
     hipEventElapsedTime(&ms, h->ev0, h->ev1);
     info->ms_total = ms;
@@ -429,6 +434,10 @@ qcpd_status create_impl(qcpd_handle *h, const qcpd_csr *P, const qcpd_csr *A, co
     }
     p.exp_row0 = row;
     p.n_diag = K->n_zero + K->n_nonneg;
+    h->fmeta.n_zero = K->n_zero;
+    h->fmeta.n_diag = p.n_diag;
+    h->fmeta.psd_end = row;
+    h->fmeta.soc_end = K->n_psd ? psd_row[0] : row;
     p.n_soc = K->n_soc; p.n_psd = K->n_psd; p.n_exp = K->n_exp;
     int *d_soc_row, *d_soc_dim, *d_psd_row, *d_psd_k;
     long long *d_psd_off;
@@ -580,6 +589,39 @@ qcpd_status create_impl(qcpd_handle *h, const qcpd_csr *P, const qcpd_csr *A, co
     return h->host_flag[1] ? QCPD_WARN_NONDIFF : QCPD_OK;
 }
 
+// A learned scaling is replaced by Jacobi when LSQR stopped at the iteration cap or the
+// explicit residual stayed above the tolerance.
+bool needs_fallback(const qcpd_handle *h, double rel) {
+    return !h->host_st[0].conv || (h->opts.tol > 0.0 && !(rel <= h->opts.tol));
+}
+
+// One derivative solve with the given scales: state, right-hand side, LSQR.
+qcpd_status jvp_solve(qcpd_handle *h, const double *dP, const double *dA, const double *dq,
+                      const double *db, const double *sc, const double *scl, double *rel) {
+    const Problem &p = h->p;
+    hipStream_t s = h->stream;
+    launch_state_init(h->st, h->opts.tol, max_iter_of(h), s);
+    launch_fill(h->xk, p.N, 0.0, s);
+    launch_fill(h->wk, p.N, 0.0, s);
+    StepArgs r = base_args(h, sc, scl);
+    r.out = h->u;
+    launch_jvp_rhs(p, r, h->rg, dP, dA, dq, db, s);
+    return solve(h, 0, sc, scl, rel);
+}
+
+qcpd_status vjp_solve(qcpd_handle *h, const double *gx, const double *gy, const double *gs,
+                      const double *sc, const double *scl, double *rel) {
+    const Problem &p = h->p;
+    hipStream_t s = h->stream;
+    launch_state_init(h->st, h->opts.tol, max_iter_of(h), s);
+    launch_fill(h->xk, p.N, 0.0, s);
+    launch_fill(h->wk, p.N, 0.0, s);
+    StepArgs r = base_args(h, sc, scl);
+    r.out = h->u;
+    launch_vjp_rhs(p, r, h->cg, h->lds, gx, gy, gs, s);
+    return solve(h, 1, sc, scl, rel);
+}
+
 }  // namespace
 
 extern "C" {
@@ -704,27 +746,31 @@ qcpd_status qcpd_jvp(qcpd_handle *h, const double *dP, const double *dA, const d
     const Problem &p = h->p;
     if ((p.nnzP && !dP) || (p.nnzA && !dA) || !dq || !dx || (p.m && (!db || !dy || !ds)))
         return QCPD_ERR_INVALID_ARG;
+    const bool learned = h->opts.precond == QCPD_PRECOND_LEARNED;
+    if (learned && !h->learned[0]) return QCPD_ERR_INVALID_ARG;
     hipStream_t s = h->stream;
     HIPCHK(hipEventRecord(h->ev0, s));
     qcpd_status rc = scan_finite(h, {dP, dA, dq, db}, {p.nnzP, p.nnzA, p.n, p.m});
     if (rc != QCPD_OK) return rc;
     const double *sc, *scl;
     active_scales(h, 0, &sc, &scl);
-    launch_state_init(h->st, h->opts.tol, max_iter_of(h), s);
-    launch_fill(h->xk, p.N, 0.0, s);
-    launch_fill(h->wk, p.N, 0.0, s);
-    StepArgs r = base_args(h, sc, scl);
-    r.out = h->u;
-    launch_jvp_rhs(p, r, h->rg, dP, dA, dq, db, s);
     double rel = 0.0;
-    rc = solve(h, 0, sc, scl, &rel);
+    rc = jvp_solve(h, dP, dA, dq, db, sc, scl, &rel);
     if (rc != QCPD_OK) return rc;
+    int extra_iters = 0;
+    uint32_t extra_flags = 0;
+    if (learned && needs_fallback(h, rel)) {  // fall back to Jacobi
+        extra_iters = h->host_st[0].iters;
+        extra_flags = 4u;
+        rc = jvp_solve(h, dP, dA, dq, db, h->scale[0], nullptr, &rel);
+        if (rc != QCPD_OK) return rc;
+    }
     // (dx, dy, ds) = D phi dz with dz = sol and J dz_y left in wy_res by the residual check
     launch_jvp_out(p, h->sol, h->wy_res, dx, dy, ds, s);
     HIPCHK(hipEventRecord(h->ev1, s));
     HIPCHK(hipStreamSynchronize(s));
     HIPCHK(hipGetLastError());
-    fill_info(h, info, rel);
+    fill_info(h, info, rel, extra_iters, extra_flags);
     return h->host_st[0].conv ? QCPD_OK : QCPD_WARN_NOT_CONVERGED;
 }
 
@@ -734,28 +780,66 @@ qcpd_status qcpd_vjp(qcpd_handle *h, const double *gx, const double *gy, const d
     const Problem &p = h->p;
     if (!gx || !dq || (p.m && (!gy || !gs || !db)) || (p.nnzP && !dP) || (p.nnzA && !dA))
         return QCPD_ERR_INVALID_ARG;
+    const bool learned = h->opts.precond == QCPD_PRECOND_LEARNED;
+    if (learned && !h->learned[0]) return QCPD_ERR_INVALID_ARG;
     hipStream_t s = h->stream;
     HIPCHK(hipEventRecord(h->ev0, s));
     qcpd_status rc = scan_finite(h, {gx, gy, gs}, {p.n, p.m, p.m});
     if (rc != QCPD_OK) return rc;
     const double *sc, *scl;
     active_scales(h, 1, &sc, &scl);
-    launch_state_init(h->st, h->opts.tol, max_iter_of(h), s);
-    launch_fill(h->xk, p.N, 0.0, s);
-    launch_fill(h->wk, p.N, 0.0, s);
-    StepArgs r = base_args(h, sc, scl);
-    r.out = h->u;
-    launch_vjp_rhs(p, r, h->cg, h->lds, gx, gy, gs, s);
     double rel = 0.0;
-    rc = solve(h, 1, sc, scl, &rel);
+    rc = vjp_solve(h, gx, gy, gs, sc, scl, &rel);
     if (rc != QCPD_OK) return rc;
+    int extra_iters = 0;
+    uint32_t extra_flags = 0;
+    if (learned && needs_fallback(h, rel)) {  // fall back to Jacobi
+        extra_iters = h->host_st[0].iters;
+        extra_flags = 4u;
+        rc = vjp_solve(h, gx, gy, gs, h->scale[1], nullptr, &rel);
+        if (rc != QCPD_OK) return rc;
+    }
     // dtheta = D_theta N'[w] with w = sol
     launch_vjp_out(p, h->rg, h->sol, dP, dA, dq, db, s);
     HIPCHK(hipEventRecord(h->ev1, s));
     HIPCHK(hipStreamSynchronize(s));
     HIPCHK(hipGetLastError());
-    fill_info(h, info, rel);
+    fill_info(h, info, rel, extra_iters, extra_flags);
     return h->host_st[0].conv ? QCPD_OK : QCPD_WARN_NOT_CONVERGED;
+}
+
+qcpd_status qcpd_features(qcpd_handle *h, float *feat) {
+    if (!h || !feat) return QCPD_ERR_INVALID_ARG;
+    HIPCHK(launch_features(h->p, h->fmeta, h->scale[0], h->scale[1], feat, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return QCPD_OK;
+}
+
+qcpd_status qcpd_learned_targets(qcpd_handle *h, float *target) {
+    if (!h || !target) return QCPD_ERR_INVALID_ARG;
+    HIPCHK(launch_targets(h->p.N, h->scale[0], h->scale[1], h->equil[0], h->equil[1], target,
+                          h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return QCPD_OK;
+}
+
+qcpd_status qcpd_set_learned(qcpd_handle *h, const float *weights) {
+    if (!h || !weights) return QCPD_ERR_INVALID_ARG;
+    const size_t N = h->p.N;
+    for (int d = 0; d < 2; ++d)
+        if (!h->learned[d]) {
+            qcpd_status rc = dalloc(h, &h->learned[d], N);
+            if (rc != QCPD_OK) return rc;
+        }
+    if (!h->feat) {
+        qcpd_status rc = dalloc(h, &h->feat, N * QCPD_NFEAT);
+        if (rc != QCPD_OK) return rc;
+    }
+    HIPCHK(launch_features(h->p, h->fmeta, h->scale[0], h->scale[1], h->feat, h->stream));
+    HIPCHK(launch_mlp_scales(h->feat, h->p.N, weights, h->scale[0], h->scale[1], h->learned[0],
+                             h->learned[1], h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return QCPD_OK;
 }
 
 qcpd_status qcpd_profile_kernels(qcpd_handle *h, int32_t reps, float *ms_out) {

@@ -235,4 +235,15 @@ void launch_vjp_out(const Problem &p, const RowGrid &g, const double *w, double 
 void launch_nan_scan(const double *const *ptrs, const long long *lens, int nseg, int *flag,
                      hipStream_t s);
 
+// learned preconditioner (learned.hip)
+struct FeatMeta {
+    int n_zero, n_diag, soc_end, psd_end;  // y-row boundaries of the cone kinds
+};
+hipError_t launch_features(const Problem &p, const FeatMeta &fm, const double *jcol,
+                           const double *jrow, float *feat, hipStream_t s);
+hipError_t launch_targets(int N, const double *jcol, const double *jrow, const double *ecol,
+                          const double *erow, float *target, hipStream_t s);
+hipError_t launch_mlp_scales(const float *feat, int N, const float *w, const double *jcol,
+                             const double *jrow, double *col, double *row, hipStream_t s);
+
 }  // namespace qcpd
