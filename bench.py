@@ -12,6 +12,7 @@ time, measured with HIP events on the library's stream) and the CPU oracle timed
 bounded sample on this host.
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload mixed_qcp]
+       python bench.py --workload batch [--batch-count 512]   (batched form, one launch)
 """
 from __future__ import annotations
 
@@ -93,6 +94,103 @@ def cpu_baseline(q, iters_jvp, iters_vjp, budget_s=20.0):
     }
 
 
+def run_batch(args):
+    """Batched form: `count` uneven problems (n ~ U{20..400}, m ~ U{1.5n..3n}) per launch.
+    One step = batch create + batch JVP + batch VJP over all of them; the value counts every
+    problem's JVP+VJP as one solve. vs_plain times the single-problem Jacobi path over the
+    first `plain` problems."""
+    import numpy as np
+    import torch
+
+    import paper_2508_17522_amd as Q
+    import qcpgen
+    from qcpgen.torch_io import batch_create_args, batch_to_device, cones_of, to_device
+
+    count = args.batch_count
+    print(f"[bench] generating {count} batch problems", file=sys.stderr, flush=True)
+    qs = [qcpgen.batch_member(i) for i in range(count)]
+    bt = batch_to_device(qs)
+    opts = Q.Opts(tol=args.tol, precond=Q.QCPD_PRECOND_JACOBI)
+    torch.cuda.synchronize()
+
+    def step(record):
+        t0 = time.perf_counter()
+        hb = Q.qcpd_batch_create(*batch_create_args(bt), opts=opts)
+        t1 = time.perf_counter()
+        _, _, _, ij, sj = Q.qcpd_batch_jvp(hb, bt["dP"], bt["dA"], bt["dq"], bt["db"])
+        t2 = time.perf_counter()
+        _, _, _, _, iv, sv = Q.qcpd_batch_vjp(hb, bt["gx"], bt["gy"], bt["gs"])
+        t3 = time.perf_counter()
+        hb.close()
+        if record is not None:
+            record.append(dict(setup=t1 - t0, jvp=t2 - t1, vjp=t3 - t2, ij=ij, iv=iv, sj=sj, sv=sv))
+
+    for i in range(args.warmup):
+        step(None)
+        print(f"[bench] warmup step {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    rec = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        step(rec)
+        print(f"[bench] step {i + 1}/{args.steps}: jvp {rec[-1]['jvp']:.3f}s vjp "
+              f"{rec[-1]['vjp']:.3f}s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    value = count * args.steps / elapsed
+    last = rec[-1]
+    it_j = [i.iters for i in last["ij"]]
+    it_v = [i.iters for i in last["iv"]]
+    # roofline of the persistent batch kernel over the JVP launch: algorithmic bytes of every
+    # problem's LSQR iterations / the launch's duration (HIP events on the library's stream)
+    per_iter = [kernel_bytes(q, "rows_F") + kernel_bytes(q, "fused_FT") for q in qs]
+    t_launch = last["ij"][0].ms_total * 1e-3
+    nbytes = float(sum(b * k for b, k in zip(per_iter, it_j)))
+    achieved = nbytes / t_launch / 1e9
+    line = {
+        "metric": METRIC, "value": round(value, 3), "unit": "solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"batch_member x{count} (uneven, one launch)",
+                   "sum_N": int(sum(q.n + q.m + 1 for q in qs)),
+                   "sum_nnz_P": int(sum(q.P.nnz for q in qs)),
+                   "sum_nnz_A": int(sum(q.A.nnz for q in qs)), "tol": args.tol,
+                   "precond": "jacobi"},
+        "lsqr_iters": {"jvp_median": float(np.median(it_j)), "jvp_max": int(max(it_j)),
+                       "vjp_median": float(np.median(it_v)), "vjp_max": int(max(it_v))},
+        "max_rel_residual": {"jvp": max(i.rel_residual for i in last["ij"]),
+                             "vjp": max(i.rel_residual for i in last["iv"])},
+        "status": {"jvp": last["sj"], "vjp": last["sv"]},
+        "split_ms": {k: round(1e3 * float(np.median([r[k] for r in rec])), 3)
+                     for k in ("setup", "jvp", "vjp")},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                     "kernel": "batch_solve (JVP launch)",
+                     "avg_launch_us": round(t_launch * 1e6, 3), "bytes_per_launch": int(nbytes)},
+    }
+    if args.batch_plain > 0:
+        k = min(args.batch_plain, count)
+        print(f"[bench] plain single-problem Jacobi LSQR over {k} problems", file=sys.stderr,
+              flush=True)
+        o2 = Q.Opts(tol=args.tol, precond=Q.QCPD_PRECOND_JACOBI)
+        tens = [to_device(q) for q in qs[:k]]
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        for q, t in zip(qs[:k], tens):
+            h = Q.qcpd_create(t["P"], t["A"], t["q"], t["b"], cones_of(q), t["x"], t["y"],
+                              t["s"], opts=o2)
+            Q.qcpd_jvp(h, t["dP"], t["dA"], t["dq"], t["db"])
+            Q.qcpd_vjp(h, t["gx"], t["gy"], t["gs"])
+            h.close()
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - tp
+        line["vs_plain"] = {"precond": "jacobi", "path": "one problem per call",
+                            "problems": k, "value": round(k / tp, 3), "unit": "solves/s",
+                            "speedup": round(value / (k / tp), 3)}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -105,11 +203,19 @@ def main():
     ap.add_argument("--no-plain", action="store_true",
                     help="skip the plain Jacobi-preconditioned LSQR comparison")
     ap.add_argument("--engine", default="auto", choices=["auto", "graph", "persistent"])
+    ap.add_argument("--batch-count", type=int, default=512,
+                    help="problems per launch for --workload batch")
+    ap.add_argument("--batch-plain", type=int, default=64,
+                    help="problems timed on the single-problem path for --workload batch")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; the derivative of one QCP is not "
               "split across GPUs (see DESIGN.md for how it would shard).", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "batch":
+        run_batch(args)
+        return
 
     import numpy as np
     import torch

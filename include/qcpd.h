@@ -175,6 +175,17 @@ qcpd_status qcpd_get_diagnostics(qcpd_handle *h, double *d_jvp, double *d_vjp, d
  * between, not during, derivative evaluations. */
 qcpd_status qcpd_profile_kernels(qcpd_handle *h, int32_t reps, float *ms_out);
 
+/* Launch shape of the LSQR loop, for tuning (an autotuner's choice): the product with F
+ * over CSR rows runs on at most grid_F workgroups and the fused product with F' on at most
+ * grid_FT (each loops over its work with a grid stride; 0 = the default cap, 512). Results
+ * are unchanged up to the order of floating-point sums. Graphs captured earlier are
+ * discarded. Synchronises the handle's stream. */
+qcpd_status qcpd_set_launch(qcpd_handle *h, int32_t grid_F, int32_t grid_FT);
+
+/* out [host] 4 entries: the current grid_F, grid_FT, and the largest useful values (the
+ * work items of each launch). */
+qcpd_status qcpd_get_launch(qcpd_handle *h, int32_t *out);
+
 /* ---------------------------------------------------------------------------------------
  * Learned preconditioner (an addition to the method: the iterative solves of Sec. 3.1-3.2
  * name no preconditioner). For each index i of z = (x, y, tau) a feature row of
@@ -280,6 +291,14 @@ qcpd_status qcpd_batch_vjp(qcpd_batch *hb, const double *gx, const double *gy, c
 
 /* Replace the batch's LSQR options (tolerance, iteration cap, NONE or JACOBI). */
 qcpd_status qcpd_batch_set_opts(qcpd_batch *hb, const qcpd_opts *opts);
+
+/* Persistent workgroups of the batch kernel (each takes whole problems from the queue until
+ * it is empty): grid >= 1, capped at the number of problems; 0 restores the default (all
+ * workgroups that fit on the device at once). For tuning. */
+qcpd_status qcpd_batch_set_launch(qcpd_batch *hb, int32_t grid);
+
+/* out [host] 2 entries: the current grid and the default. */
+qcpd_status qcpd_batch_get_launch(qcpd_batch *hb, int32_t *out);
 
 /* Free a batch (NULL is allowed). */
 void qcpd_batch_destroy(qcpd_batch *hb);

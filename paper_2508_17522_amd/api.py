@@ -238,5 +238,22 @@ def qcpd_profile_kernels(h: Handle, reps: int = 50):
     return list(out)
 
 
+def qcpd_set_launch(h: Handle, grid_F: int = 0, grid_FT: int = 0):
+    """Workgroup caps of the two LSQR-loop launches (0 = library default)."""
+    with torch.cuda.device(h.device):
+        st = _lib().qcpd_set_launch(h.ptr, int(grid_F), int(grid_FT))
+    if st < 0:
+        raise QCPDError(st, "qcpd_set_launch")
+
+
+def qcpd_get_launch(h: Handle):
+    """(grid_F, grid_FT, max_F, max_FT)."""
+    out = (C.c_int32 * 4)()
+    st = _lib().qcpd_get_launch(h.ptr, out)
+    if st < 0:
+        raise QCPDError(st, "qcpd_get_launch")
+    return tuple(out)
+
+
 def qcpd_destroy(h: Handle):
     h.close()

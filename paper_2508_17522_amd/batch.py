@@ -128,5 +128,21 @@ def qcpd_batch_set_opts(h: BatchHandle, opts: Opts):
         raise QCPDError(st, "qcpd_batch_set_opts")
 
 
+def qcpd_batch_set_launch(h: BatchHandle, grid: int = 0):
+    """Persistent workgroups of the batch kernel (0 = default: all that fit)."""
+    st = _lib().qcpd_batch_set_launch(h.ptr, int(grid))
+    if st < 0:
+        raise QCPDError(st, "qcpd_batch_set_launch")
+
+
+def qcpd_batch_get_launch(h: BatchHandle):
+    """(grid, default grid)."""
+    out = (C.c_int32 * 2)()
+    st = _lib().qcpd_batch_get_launch(h.ptr, out)
+    if st < 0:
+        raise QCPDError(st, "qcpd_batch_get_launch")
+    return tuple(out)
+
+
 def qcpd_batch_destroy(h: BatchHandle):
     h.close()

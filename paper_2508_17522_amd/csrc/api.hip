@@ -48,6 +48,7 @@ struct qcpd_handle {
     LsqrState *st2 = nullptr;                // second state buffer of the deferred loop
     double *lpart[2] = {nullptr, nullptr};   // per-block partials of the deferred loop
     int loop_grid_F = 0, loop_grid_T = 0;    // workgroups of the two loop launches
+    int lpart_cap = 0;                       // workgroups lpart[] has room for
     LsqrState *host_st = nullptr;            // pinned
     int *host_flag = nullptr;                // pinned
     void *seg = nullptr;                     // device segment table for the NaN scan
@@ -64,6 +65,7 @@ namespace {
 
 constexpr int kMaxSeg = 8;
 constexpr int kEquilSweeps = 20;  // even: the result ends in the destination buffers
+constexpr int kLoopGrid = 512;    // default cap on the workgroups of each loop launch
 
 #define HIPCHK(expr)                              \
     do {                                          \
@@ -500,7 +502,7 @@ qcpd_status create_impl(qcpd_handle *h, const qcpd_csr *P, const qcpd_csr *A, co
     // launch's fixed-order reduction of their partial sums stays short (QCPD_LOOP_GRID
     // overrides the cap, for tuning)
     {
-        int cap = 512;
+        int cap = kLoopGrid;
         if (const char *env = getenv("QCPD_LOOP_GRID")) {
             const int e = atoi(env);
             if (e > 0) cap = e;
@@ -510,6 +512,7 @@ qcpd_status create_impl(qcpd_handle *h, const qcpd_csr *P, const qcpd_csr *A, co
         const int lp = std::max(h->loop_grid_F, h->loop_grid_T);
         ALLOC(h->lpart[0], 3LL * lp);
         ALLOC(h->lpart[1], 3LL * lp);
+        h->lpart_cap = lp;
         ALLOC(h->st2, 1);
     }
     ALLOC(h->partials, 3LL * h->nblk_max);
@@ -806,6 +809,38 @@ qcpd_status qcpd_vjp(qcpd_handle *h, const double *gx, const double *gy, const d
     HIPCHK(hipGetLastError());
     fill_info(h, info, rel, extra_iters, extra_flags);
     return h->host_st[0].conv ? QCPD_OK : QCPD_WARN_NOT_CONVERGED;
+}
+
+qcpd_status qcpd_set_launch(qcpd_handle *h, int32_t grid_F, int32_t grid_FT) {
+    if (!h || grid_F < 0 || grid_FT < 0) return QCPD_ERR_INVALID_ARG;
+    const int gF = std::max(1, std::min(h->rg.total(), grid_F ? grid_F : kLoopGrid));
+    const int gT = std::max(1, std::min(h->fg.nunits, grid_FT ? grid_FT : kLoopGrid));
+    const int need = std::max(gF, gT);
+    HIPCHK(hipStreamSynchronize(h->stream));
+    if (need > h->lpart_cap) {
+        for (int k = 0; k < 2; ++k) {
+            qcpd_status rc = dalloc(h, &h->lpart[k], 3 * (size_t)need);
+            if (rc != QCPD_OK) return rc;
+        }
+        h->lpart_cap = need;
+    }
+    h->loop_grid_F = gF;
+    h->loop_grid_T = gT;
+    for (int d = 0; d < 2; ++d)  // captured graphs hold the old launch shape
+        if (h->graph[d]) {
+            hipGraphExecDestroy(h->graph[d]);
+            h->graph[d] = nullptr;
+        }
+    return QCPD_OK;
+}
+
+qcpd_status qcpd_get_launch(qcpd_handle *h, int32_t *out) {
+    if (!h || !out) return QCPD_ERR_INVALID_ARG;
+    out[0] = h->loop_grid_F;
+    out[1] = h->loop_grid_T;
+    out[2] = h->rg.total();
+    out[3] = h->fg.nunits;
+    return QCPD_OK;
 }
 
 qcpd_status qcpd_features(qcpd_handle *h, float *feat) {

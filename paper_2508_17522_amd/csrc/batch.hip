@@ -560,6 +560,7 @@ struct qcpd_batch {
     BatchDev d{};
     int lds = 0;
     int grid = 0;
+    int grid_default = 0;  // all workgroups that fit on the device at once (capped at B)
     std::vector<void *> allocs;
     double *scale[2] = {nullptr, nullptr};
     int nnzP = 0, nnzA = 0;
@@ -814,6 +815,7 @@ qcpd_status batch_create_impl(qcpd_batch *h, const qcpd_batch_layout *L, const i
     BCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     BCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_batch_solve, kBlock, h->lds));
     h->grid = std::max(1, std::min(B, ncu * std::max(per_cu, 1)));
+    h->grid_default = h->grid;
     h->create_flags = h->host_flag[4] ? 2u : 0u;
     return h->host_flag[4] ? QCPD_WARN_NONDIFF : QCPD_OK;
 }
@@ -930,6 +932,19 @@ qcpd_status qcpd_batch_set_opts(qcpd_batch *h, const qcpd_opts *opts) {
         opts->precond < QCPD_PRECOND_NONE || opts->precond > QCPD_PRECOND_JACOBI)
         return QCPD_ERR_INVALID_ARG;
     h->opts = *opts;
+    return QCPD_OK;
+}
+
+qcpd_status qcpd_batch_set_launch(qcpd_batch *h, int32_t grid) {
+    if (!h || grid < 0) return QCPD_ERR_INVALID_ARG;
+    h->grid = grid ? std::min(grid, h->d.B) : h->grid_default;
+    return QCPD_OK;
+}
+
+qcpd_status qcpd_batch_get_launch(qcpd_batch *h, int32_t *out) {
+    if (!h || !out) return QCPD_ERR_INVALID_ARG;
+    out[0] = h->grid;
+    out[1] = h->grid_default;
     return QCPD_OK;
 }
 
