@@ -191,6 +191,48 @@ def run_batch(args):
     print(json.dumps(line), flush=True)
 
 
+def run_copy_calibration(mib: int):
+    """A plain device-to-device copy of known size (the reference for scaling the HBM byte
+    counters of a profiler run): reads and writes `mib` MiB per launch, 20 launches."""
+    import torch
+    n = mib * (1 << 20) // 8
+    src = torch.arange(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(20):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration": {"bytes_read_per_launch": n * 8,
+                                           "bytes_written_per_launch": n * 8, "launches": 20}}),
+          flush=True)
+
+
+def run_kernels_only(args):
+    """Setup of the workload, then each LSQR-loop kernel launched back to back (for counter
+    runs of a profiler: a few hundred dispatches instead of a whole solve)."""
+    import torch
+
+    import paper_2508_17522_amd as Q
+    import qcpgen
+    from qcpgen.torch_io import cones_of, to_device
+    q = qcpgen.make(args.workload, 0)
+    t = to_device(q)
+    prec = {"equil": Q.QCPD_PRECOND_EQUIL, "jacobi": Q.QCPD_PRECOND_JACOBI,
+            "none": Q.QCPD_PRECOND_NONE}[args.precond]
+    h = Q.qcpd_create(t["P"], t["A"], t["q"], t["b"], cones_of(q), t["x"], t["y"], t["s"],
+                      opts=Q.Opts(tol=args.tol, precond=prec))
+    ms = Q.qcpd_profile_kernels(h, reps=args.kernels_only)
+    h.close()
+    torch.cuda.synchronize()
+    print(json.dumps({"kernels_only": {"workload": q.name, "reps": args.kernels_only,
+                                       "avg_launch_us": {"rows_F": ms[0] * 1e3,
+                                                         "fused_FT": ms[1] * 1e3},
+                                       "bytes_per_launch": {
+                                           "rows_F": kernel_bytes(q, "rows_F"),
+                                           "fused_FT": kernel_bytes(q, "fused_FT")}}}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -207,12 +249,22 @@ def main():
                     help="problems per launch for --workload batch")
     ap.add_argument("--batch-plain", type=int, default=64,
                     help="problems timed on the single-problem path for --workload batch")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain copy of MIB MiB (profiler byte-counter reference)")
+    ap.add_argument("--kernels-only", type=int, default=0, metavar="REPS",
+                    help="only set up the workload and launch each loop kernel REPS times")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; the derivative of one QCP is not "
               "split across GPUs (see DESIGN.md for how it would shard).", file=sys.stderr)
         sys.exit(2)
 
+    if args.copy_calibration:
+        run_copy_calibration(args.copy_calibration)
+        return
+    if args.kernels_only:
+        run_kernels_only(args)
+        return
     if args.workload == "batch":
         run_batch(args)
         return

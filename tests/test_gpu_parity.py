@@ -156,24 +156,35 @@ def mixed_full():
 def test_mixed_full_size_properties(mixed_full, engine, precond):
     """At the benchmark size and tolerance: the JVP satisfies the linearised KKT system
     (oracle J and data, any size) and JVP/VJP satisfy the adjoint identity."""
-    q = mixed_full
+    check_full_size(mixed_full, engine, precond, "mixed full")
+
+
+def check_full_size(q, engine, precond, tag):
     h, t = make_handle(q, tol=1e-8, engine=engine, precond=precond)
     dx, dy, ds, info, st = gpu_jvp(h, t)
-    print(f"[mixed full] jvp iters={info.iters} rel_res={info.rel_residual:.2e} "
+    print(f"[{tag}] jvp iters={info.iters} rel_res={info.rel_residual:.2e} "
           f"ms={info.ms_total:.1f} st={st}", flush=True)
     assert st == Q.QCPD_OK and info.rel_residual <= 1e-8
     res = kkt_linearised_residual(q, dx, dy, ds)
-    print(f"[mixed full] linearised KKT residual {res:.2e}", flush=True)
+    print(f"[{tag}] linearised KKT residual {res:.2e}", flush=True)
     assert res <= 1e-6
     dP, dA, dq, db, info2, st2 = gpu_vjp(h, t)
-    print(f"[mixed full] vjp iters={info2.iters} rel_res={info2.rel_residual:.2e} "
+    print(f"[{tag}] vjp iters={info2.iters} rel_res={info2.rel_residual:.2e} "
           f"ms={info2.ms_total:.1f} st={st2}", flush=True)
     assert st2 == Q.QCPD_OK and info2.rel_residual <= 1e-8
     lhs = q.gx @ dx + q.gy @ dy + q.gs @ ds
     rhs = dP @ q.dP + dA @ q.dA + dq @ q.dq + db @ q.db
-    print(f"[mixed full] adjoint identity {lhs:.10e} {rhs:.10e}", flush=True)
+    print(f"[{tag}] adjoint identity {lhs:.10e} {rhs:.10e}", flush=True)
     assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
     h.close()
+
+
+def test_large_psd_soc_full_size_properties():
+    """n = 20 000, m = 290 000 (200 PSD cones of order 50, 2 000 SOC(10)): the same checks
+    at the full size, with the equilibrated solve."""
+    q = qcpgen.large_psd_soc(0)
+    print(f"[large] n={q.n} m={q.m} nnz P={q.P.nnz} nnz A={q.A.nnz}", flush=True)
+    check_full_size(q, Q.QCPD_ENGINE_GRAPH, Q.QCPD_PRECOND_EQUIL, "large psd/soc")
 
 
 # ---- edge cases and errors ----------------------------------------------------------------
