@@ -175,6 +175,12 @@ qcpd_status qcpd_get_diagnostics(qcpd_handle *h, double *d_jvp, double *d_vjp, d
  * between, not during, derivative evaluations. */
 qcpd_status qcpd_profile_kernels(qcpd_handle *h, int32_t reps, float *ms_out);
 
+/* One product with the operator of the least-squares problems, F = D_z N at z (Sec. 2.4):
+ * out = F in (transpose = 0) or out = F' in (transpose = 1), unscaled. in, out [device],
+ * n + m + 1 entries in the order (x | y | tau), distinct buffers. For users of the operator
+ * itself and for checking it against a reference. */
+qcpd_status qcpd_apply(qcpd_handle *h, int32_t transpose, const double *in, double *out);
+
 /* Launch shape of the LSQR loop, for tuning (an autotuner's choice): the product with F
  * over CSR rows runs on at most grid_F workgroups and the fused product with F' on at most
  * grid_FT (each loops over its work with a grid stride; 0 = the default cap, 512). Results

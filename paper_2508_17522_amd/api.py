@@ -238,6 +238,17 @@ def qcpd_profile_kernels(h: Handle, reps: int = 50):
     return list(out)
 
 
+def qcpd_apply(h: Handle, v, transpose: bool = False, out=None):
+    """out = F v (or F' v): the operator of the least-squares problems, unscaled."""
+    out = torch.empty(h.N, dtype=torch.float64, device=h.device) if out is None else out
+    with torch.cuda.device(h.device):
+        st = _lib().qcpd_apply(h.ptr, int(bool(transpose)), _ptr(v, torch.float64, "v", h.N),
+                               _ptr(out, torch.float64, "out", h.N))
+    if st < 0:
+        raise QCPDError(st, "qcpd_apply")
+    return out
+
+
 def qcpd_set_launch(h: Handle, grid_F: int = 0, grid_FT: int = 0):
     """Workgroup caps of the two LSQR-loop launches (0 = library default)."""
     with torch.cuda.device(h.device):

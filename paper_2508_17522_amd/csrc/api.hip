@@ -26,6 +26,7 @@ struct qcpd_handle {
     FusedGrid fg{};
     int lds = 0;
     int lds_fused = 0;
+    int lds_loop = 0;
     int persist_grid = 0;              // 0: cooperative launch unavailable
     double *persist_partials = nullptr;
     int nblk_max = 0;
@@ -48,7 +49,6 @@ struct qcpd_handle {
     LsqrState *st2 = nullptr;                // second state buffer of the deferred loop
     double *lpart[2] = {nullptr, nullptr};   // per-block partials of the deferred loop
     int loop_grid_F = 0, loop_grid_T = 0;    // workgroups of the two loop launches
-    int lpart_cap = 0;                       // workgroups lpart[] has room for
     LsqrState *host_st = nullptr;            // pinned
     int *host_flag = nullptr;                // pinned
     void *seg = nullptr;                     // device segment table for the NaN scan
@@ -65,7 +65,7 @@ namespace {
 
 constexpr int kMaxSeg = 8;
 constexpr int kEquilSweeps = 20;  // even: the result ends in the destination buffers
-constexpr int kLoopGrid = 512;    // default cap on the workgroups of each loop launch
+constexpr int kLoopGrid = kMaxLoopGrid;  // default cap on the workgroups of a loop launch
 
 #define HIPCHK(expr)                              \
     do {                                          \
@@ -187,7 +187,6 @@ StepArgs base_args(const qcpd_handle *h, const double *sc, const double *scl = n
 void enqueue_iteration(const qcpd_handle *h, int dir, const double *sc, const double *scl,
                        hipStream_t s) {
     StepArgs a = base_args(h, sc, scl);
-    a.deferred = 1;
     StepArgs first = a, second = a;
     first.st = h->st;    first.part_prev = h->lpart[0]; first.st_next = h->st2; first.part_next = h->lpart[1];
     second.st = h->st2;  second.part_prev = h->lpart[1]; second.st_next = h->st; second.part_next = h->lpart[0];
@@ -195,20 +194,20 @@ void enqueue_iteration(const qcpd_handle *h, int dir, const double *sc, const do
         StepArgs &f = first;  // u~ <- F(sc o v) - alpha u~   (and the owed x, w update)
         f.in = h->v; f.in_nrm = NRM_ALPHA; f.in_is_v = 1;
         f.out = h->u; f.role = ROLE_U; f.do_update = 1;
-        launch_rows_F(h->p, f, h->rg, s, h->loop_grid_F);
+        launch_loop_F(h->p, f, h->rg, h->loop_grid_F, s);
         StepArgs &t = second;  // v~ <- sc o F'u - beta v~, then J(sc o v~) for the next product
         t.in = h->u; t.in_nrm = NRM_BETA;
         t.out = h->v; t.role = ROLE_V; t.out_is_v = 1; t.do_pre = 1;
-        launch_fused_FT(h->p, t, h->fg, h->lds_fused, s, h->loop_grid_T);
+        launch_loop_FT(h->p, t, h->fg, h->lds_loop, h->loop_grid_T, s);
     } else {
         StepArgs &t = first;  // u~ <- F'(sc o v) - alpha u~ (and the owed update), J(u~)
         t.in = h->v; t.in_nrm = NRM_ALPHA; t.in_is_v = 1; t.do_update = 1;
         t.out = h->u; t.role = ROLE_U; t.do_pre = 1;
-        launch_fused_FT(h->p, t, h->fg, h->lds_fused, s, h->loop_grid_T);
+        launch_loop_FT(h->p, t, h->fg, h->lds_loop, h->loop_grid_T, s);
         StepArgs &f = second;  // v~ <- sc o F u - beta v~
         f.in = h->u; f.in_nrm = NRM_BETA;
         f.out = h->v; f.role = ROLE_V; f.out_is_v = 1;
-        launch_rows_F(h->p, f, h->rg, s, h->loop_grid_F);
+        launch_loop_F(h->p, f, h->rg, h->loop_grid_F, s);
     }
 }
 
@@ -496,6 +495,7 @@ qcpd_status create_impl(qcpd_handle *h, const qcpd_csr *P, const qcpd_csr *A, co
         h->fg.lx = rg.lx;
         h->fg.ly = rg.ly;
         h->lds_fused = fused_lds_bytes(kmax);
+        h->lds_loop = loop_lds_bytes(kmax);
     }
     h->nblk_max = std::max({cg.total(), rg.total(), h->fg.nunits, div_up(N, kBlock), 1});
     // the two launches of the deferred LSQR loop: at most `cap` workgroups each, so the next
@@ -507,12 +507,11 @@ qcpd_status create_impl(qcpd_handle *h, const qcpd_csr *P, const qcpd_csr *A, co
             const int e = atoi(env);
             if (e > 0) cap = e;
         }
+        cap = std::min(cap, kMaxLoopGrid);
         h->loop_grid_F = std::max(1, std::min(rg.total(), cap));
         h->loop_grid_T = std::max(1, std::min(h->fg.nunits, cap));
-        const int lp = std::max(h->loop_grid_F, h->loop_grid_T);
-        ALLOC(h->lpart[0], 3LL * lp);
-        ALLOC(h->lpart[1], 3LL * lp);
-        h->lpart_cap = lp;
+        ALLOC(h->lpart[0], 3LL * kMaxLoopGrid);
+        ALLOC(h->lpart[1], 3LL * kMaxLoopGrid);
         ALLOC(h->st2, 1);
     }
     ALLOC(h->partials, 3LL * h->nblk_max);
@@ -571,6 +570,7 @@ qcpd_status create_impl(qcpd_handle *h, const qcpd_csr *P, const qcpd_csr *A, co
     if (h->host_flag[2]) return QCPD_ERR_CONE;  // projection root-find or eigensolver failed
     if (h->lds > 0) set_cone_kernel_lds(h->lds);
     set_fused_kernel_lds(h->lds_fused);
+    set_loop_kernel_lds(h->lds_loop);
     // persistent LSQR: as many co-resident workgroups as the work needs, at most one wave of
     // the whole device (QCPD_PERSIST_GRID overrides the count, for tuning)
     {
@@ -811,19 +811,34 @@ qcpd_status qcpd_vjp(qcpd_handle *h, const double *gx, const double *gy, const d
     return h->host_st[0].conv ? QCPD_OK : QCPD_WARN_NOT_CONVERGED;
 }
 
+qcpd_status qcpd_apply(qcpd_handle *h, int32_t transpose, const double *in, double *out) {
+    if (!h || !in || !out || in == out || (transpose != 0 && transpose != 1))
+        return QCPD_ERR_INVALID_ARG;
+    hipStream_t s = h->stream;
+    StepArgs r = base_args(h, nullptr, nullptr);
+    r.st = h->st_res;
+    r.wy = h->wy_res;
+    r.in = in;
+    r.in_nrm = NRM_ONE;
+    r.out = out;
+    launch_state_init(h->st_res, 0.0, 1, s);
+    if (!transpose) {
+        launch_cone_pre(h->p, r, h->cg, h->lds, s);  // J in_y and the tau-row dot
+        launch_rows_F(h->p, r, h->rg, s);
+    } else {
+        launch_adj_dot(h->p, r, s);
+        launch_fused_FT(h->p, r, h->fg, h->lds_fused, s);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    return QCPD_OK;
+}
+
 qcpd_status qcpd_set_launch(qcpd_handle *h, int32_t grid_F, int32_t grid_FT) {
     if (!h || grid_F < 0 || grid_FT < 0) return QCPD_ERR_INVALID_ARG;
-    const int gF = std::max(1, std::min(h->rg.total(), grid_F ? grid_F : kLoopGrid));
-    const int gT = std::max(1, std::min(h->fg.nunits, grid_FT ? grid_FT : kLoopGrid));
-    const int need = std::max(gF, gT);
+    const int gF = std::max(1, std::min({h->rg.total(), grid_F ? grid_F : kLoopGrid, kMaxLoopGrid}));
+    const int gT = std::max(1, std::min({h->fg.nunits, grid_FT ? grid_FT : kLoopGrid, kMaxLoopGrid}));
     HIPCHK(hipStreamSynchronize(h->stream));
-    if (need > h->lpart_cap) {
-        for (int k = 0; k < 2; ++k) {
-            qcpd_status rc = dalloc(h, &h->lpart[k], 3 * (size_t)need);
-            if (rc != QCPD_OK) return rc;
-        }
-        h->lpart_cap = need;
-    }
     h->loop_grid_F = gF;
     h->loop_grid_T = gT;
     for (int d = 0; d < 2; ++d)  // captured graphs hold the old launch shape
@@ -838,8 +853,8 @@ qcpd_status qcpd_get_launch(qcpd_handle *h, int32_t *out) {
     if (!h || !out) return QCPD_ERR_INVALID_ARG;
     out[0] = h->loop_grid_F;
     out[1] = h->loop_grid_T;
-    out[2] = h->rg.total();
-    out[3] = h->fg.nunits;
+    out[2] = std::min(h->rg.total(), kMaxLoopGrid);
+    out[3] = std::min(h->fg.nunits, kMaxLoopGrid);
     return QCPD_OK;
 }
 
@@ -895,7 +910,6 @@ qcpd_status qcpd_profile_kernels(qcpd_handle *h, int32_t reps, float *ms_out) {
     HIPCHK(hipMemsetAsync(h->lpart[0], 0, 3 * sizeof(double) * img.pend_blocks, s));
     HIPCHK(hipMemsetAsync(h->lpart[1], 0, 3 * sizeof(double) * img.pend_blocks, s));
     StepArgs a = base_args(h, sc, scl);
-    a.deferred = 1;
     a.st = h->st; a.part_prev = h->lpart[0]; a.st_next = h->st2; a.part_next = h->lpart[1];
     StepArgs f = a;
     f.in = h->v; f.in_is_v = 1; f.out = h->scratch;
@@ -903,8 +917,8 @@ qcpd_status qcpd_profile_kernels(qcpd_handle *h, int32_t reps, float *ms_out) {
     t.in = h->u; t.out = h->scratch; t.do_pre = 1; t.out_is_v = 1;
     for (int kid = 0; kid < 2; ++kid) {
         auto launch = [&]() {
-            if (kid == 0) launch_rows_F(h->p, f, h->rg, s, h->loop_grid_F);
-            else launch_fused_FT(h->p, t, h->fg, h->lds_fused, s, h->loop_grid_T);
+            if (kid == 0) launch_loop_F(h->p, f, h->rg, h->loop_grid_F, s);
+            else launch_loop_FT(h->p, t, h->fg, h->lds_loop, h->loop_grid_T, s);
         };
         launch();  // warm
         HIPCHK(hipEventRecord(h->ev0, s));

@@ -12,13 +12,13 @@
 //             J(A r_x - b r_N - r_y) + r_y,
 //             q'r_x + b'r_y + x'Px r_N).
 //
-// One LSQR iteration is three launches:
-//   rows_F  : CSR rows of P and A' (x rows), A (y rows), the tau row   -> product with F
-//   rows_FT : CSR rows of P and A' (x rows), A (y rows)                -> staged in tmp
-//   cone_FT : per cone block J(tmp_y) + r_y, the tau entry             -> product with F'
-// The J needed by the next product with F is applied inside cone_FT (block-local), and the
-// tau-row dot products of each product are accumulated by the kernel that produces its
-// input, so no launch waits on a reduction of its own.
+// The kernels here serve the steps outside the LSQR loop (its first product, the explicit
+// residual, the persistent driver): one product with F over CSR rows (k_rows_F) and one
+// fused product with F' in which each workgroup forms the rows of a work unit and applies
+// that unit's block of J in LDS (k_fused_FT). The J needed by the next product with F is
+// applied inside the fused product (block-local), and the tau-row dot products of each
+// product are accumulated by the kernel that produces its input. The loop itself runs the
+// latency-overlapped kernels of loop.hip.
 #include <hip/hip_cooperative_groups.h>
 
 #include <algorithm>
@@ -91,17 +91,6 @@ __device__ inline void rows_F_vblock(const Problem &p, const StepArgs &a, const 
 }
 
 __global__ __launch_bounds__(kBlock) void k_rows_F(Problem p, StepArgs a, RowGrid g) {
-    if (a.deferred) {
-        __shared__ LsqrState S;
-        if (!deferred_enter(a, &S, 0)) return;
-        StepArgs b = a;
-        b.st = &S;
-        const Ctx c = make_ctx(b, p.N - 1);
-        double s0 = 0.0, s1 = 0.0;
-        for (int vb = blockIdx.x; vb < g.bx + g.by; vb += gridDim.x) rows_F_vblock(p, b, c, g, vb, s0, s1);
-        deferred_leave(a, s0, s1);
-        return;
-    }
     LsqrState *st = a.st;
     if (a.check_done && st->done) return;
     const Ctx c = make_ctx(a, p.N - 1);
@@ -109,7 +98,7 @@ __global__ __launch_bounds__(kBlock) void k_rows_F(Problem p, StepArgs a, RowGri
     rows_F_vblock(p, a, c, g, blockIdx.x, s0, s1);
     double tot[3];
     if (last_block_sum3(s0, s1, 0.0, a.partials, a.counter, gridDim.x, tot) && threadIdx.x == 0)
-        finalize(st, a.role, tot, false);
+        finalize(st, a.role, tot[0], tot[1], false);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -123,27 +112,6 @@ __global__ __launch_bounds__(kBlock) void k_rows_F(Problem p, StepArgs a, RowGri
 
 __global__ __launch_bounds__(kBlock) void k_fused_FT(Problem p, StepArgs a, FusedGrid g) {
     extern __shared__ double sm[];
-    if (a.deferred) {
-        __shared__ LsqrState S;
-        if (!deferred_enter(a, &S, 1)) return;
-        StepArgs b = a;
-        b.st = &S;
-        const Ctx c = make_ctx(b, p.N - 1);
-        double s0 = 0.0, s1 = 0.0;
-        for (int ui = blockIdx.x; ui < g.nunits; ui += gridDim.x) {
-            fused_unit(p, b, c, g.lx, g.ly, g.units[ui], sm, s0, s1);
-            __syncthreads();
-        }
-        if (blockIdx.x == 0 && threadIdx.x == 0) {  // the tau entry
-            const int N = p.N;
-            const double o = role_value(b, c, N - 1, S.dot_adj * c.inv + p.xPx * c.in_N);
-            b.out[N - 1] = o;
-            s0 += o * o;
-            if (b.do_update) lsqr_update(b, c, N - 1);
-        }
-        deferred_leave(a, s0, s1);
-        return;
-    }
     LsqrState *st = a.st;
     if (a.check_done && st->done) return;
     const int N = p.N;
@@ -160,7 +128,7 @@ __global__ __launch_bounds__(kBlock) void k_fused_FT(Problem p, StepArgs a, Fuse
     }
     double tot[3];
     if (last_block_sum3(s0, s1, 0.0, a.partials, a.counter, gridDim.x, tot) && tid == 0)
-        finalize(st, a.role, tot, true);
+        finalize(st, a.role, tot[0], tot[1], true);
 }
 
 void set_fused_kernel_lds(int bytes) {
@@ -227,7 +195,7 @@ __global__ __launch_bounds__(kBlock) void k_lsqr_persistent(Problem p, StepArgs 
             block_sum3(t0, t1, t2);
             if (tid == 0) {
                 const double tot[3] = {t0, t1, 0.0};
-                finalize(&S, a.role, tot, !isF);
+                finalize(&S, a.role, tot[0], tot[1], !isF);
             }
             __syncthreads();
             if (S.done) break;
@@ -345,6 +313,17 @@ __global__ __launch_bounds__(kBlock) void k_flush(Problem p, StepArgs a, double 
         st->pending = 0;
         (a.st_next ? a.st_next : st)->dot_adj = tot[1];  // for a product with F' at sol
     }
+}
+
+// q'in_x + b'in_y (the tau-row dot of a product with F' at `in`) into st->dot_adj.
+__global__ __launch_bounds__(kBlock) void k_adj_dot(Problem p, StepArgs a) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    double s1 = 0.0;
+    if (i < p.n) s1 = p.q[i] * a.in[i];
+    else if (i < p.N - 1) s1 = p.b[i - p.n] * a.in[i];
+    double tot[3];
+    if (last_block_sum3(0.0, s1, 0.0, a.partials, a.counter, gridDim.x, tot) && threadIdx.x == 0)
+        a.st->dot_adj = tot[1];
 }
 
 // JVP right-hand side (Sec. 2.4, D_theta N at z_N = 1, Pi z = (x, y, 1)):
@@ -553,6 +532,9 @@ void launch_fill(double *ptr, long long n, double v, hipStream_t s) {
     if (n <= 0) return;
     int blocks = (int)std::min<long long>((n + kBlock - 1) / kBlock, 4096);
     hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(kBlock), 0, s, ptr, n, v);
+}
+void launch_adj_dot(const Problem &p, const StepArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(k_adj_dot, dim3(div_up(p.N, kBlock)), dim3(kBlock), 0, s, p, a);
 }
 void launch_flush(const Problem &p, const StepArgs &a, double *sol, int nblk, hipStream_t s) {
     hipLaunchKernelGGL(k_flush, dim3(nblk), dim3(kBlock), 0, s, p, a, sol);

@@ -54,7 +54,7 @@ __device__ inline void blk_reduce_finalize(LsqrState *S, int role, double s0, do
     block_sum3(s0, s1, s2);
     if (threadIdx.x == 0) {
         const double tot[3] = {s0, s1, s2};
-        finalize(S, role, tot, dot_is_fwd);
+        finalize(S, role, tot[0], tot[1], dot_is_fwd);
     }
     __syncthreads();
 }

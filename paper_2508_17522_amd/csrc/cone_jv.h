@@ -120,6 +120,6 @@ __device__ inline void psd_jv(const Problem &p, int cone, double *sm, IN in, OUT
     __syncthreads();
 }
 
-__device__ inline int psd_stage_offset(int k) { return 3 * k * (k | 1); }
+__host__ __device__ inline int psd_stage_offset(int k) { return 3 * k * (k | 1); }
 
 }  // namespace qcpd

@@ -11,32 +11,34 @@ namespace qcpd {
 // LSQR bookkeeping
 // ---------------------------------------------------------------------------------------
 
-__device__ inline void finalize(LsqrState *st, int role, const double tot[3], bool dot_is_fwd) {
+// t0: the sum of squares of the launch's output; t1: the dot product it accumulated (or, for
+// ROLE_RESID, the squared norm of the right-hand side)
+__device__ inline void finalize(LsqrState *st, int role, double t0, double t1, bool dot_is_fwd) {
     switch (role) {
     case ROLE_U: {
-        const double beta = sqrt(tot[0]);
+        const double beta = sqrt(t0);
         st->beta = beta;
         st->pending = 0;
-        if (dot_is_fwd) st->dot_fwd = tot[1]; else st->dot_adj = tot[1];
+        if (dot_is_fwd) st->dot_fwd = t1; else st->dot_adj = t1;
         if (!(beta > 0.0)) { st->done = 1; st->conv = 1; }
         break;
     }
     case ROLE_V0: {
-        const double alpha = sqrt(tot[0]);
+        const double alpha = sqrt(t0);
         st->alpha = alpha;
         st->rhobar = alpha;
         st->phibar = st->beta1;
         st->phr = 0.0;
         st->thr = 0.0;
         st->pending = 0;
-        if (dot_is_fwd) st->dot_fwd = tot[1]; else st->dot_adj = tot[1];
+        if (dot_is_fwd) st->dot_fwd = t1; else st->dot_adj = t1;
         if (!(alpha > 0.0)) { st->done = 1; st->conv = 1; }
         break;
     }
     case ROLE_V: {
         // plane rotation that eliminates beta (Paige & Saunders), then the x/w update is
         // owed to the next iteration's first kernel (or the final flush)
-        const double alpha = sqrt(tot[0]);
+        const double alpha = sqrt(t0);
         const double beta = st->beta, rhobar = st->rhobar;
         const double rho = hypot(rhobar, beta);
         if (!(rho > 0.0)) { st->done = 1; st->conv = 1; st->pending = 0; break; }
@@ -50,7 +52,7 @@ __device__ inline void finalize(LsqrState *st, int role, const double tot[3], bo
         st->pending = 1;
         st->iters += 1;
         st->alpha = alpha;
-        if (dot_is_fwd) st->dot_fwd = tot[1]; else st->dot_adj = tot[1];
+        if (dot_is_fwd) st->dot_fwd = t1; else st->dot_adj = t1;
         if (st->phibar <= st->tol * st->beta1 || !(alpha > 0.0)) {
             st->done = 1;
             st->conv = 1;
@@ -60,55 +62,13 @@ __device__ inline void finalize(LsqrState *st, int role, const double tot[3], bo
         break;
     }
     case ROLE_RESID:
-        st->resid = sqrt(tot[0]);
-        st->tau_rhs = sqrt(tot[1]);  // ||rhs|| of the unscaled system
+        st->resid = sqrt(t0);
+        st->tau_rhs = sqrt(t1);  // ||rhs|| of the unscaled system
         break;
     default:
-        if (dot_is_fwd) st->dot_fwd = tot[1]; else st->dot_adj = tot[1];
+        if (dot_is_fwd) st->dot_fwd = t1; else st->dot_adj = t1;
         break;
     }
-}
-
-// Entry of a deferred-protocol launch (see StepArgs): all threads call it; returns false in
-// every thread when the loop has finished. S is the workgroup's LDS copy of the state.
-__device__ inline bool deferred_enter(const StepArgs &a, LsqrState *S, int my_fwd) {
-    const int tid = threadIdx.x;
-    if (tid == 0) *S = *a.st;
-    __syncthreads();
-    if (S->done) {
-        if (blockIdx.x == 0 && tid == 0) *a.st_next = *S;
-        return false;
-    }
-    if (S->pend_role >= 0) {
-        double t0 = 0.0, t1 = 0.0, t2 = 0.0;
-        for (int i = tid; i < S->pend_blocks; i += kBlock) {
-            t0 += a.part_prev[3 * i];
-            t1 += a.part_prev[3 * i + 1];
-        }
-        block_sum3(t0, t1, t2);
-        if (tid == 0) {
-            const double tot[3] = {t0, t1, 0.0};
-            finalize(S, S->pend_role, tot, S->pend_fwd != 0);
-        }
-        __syncthreads();
-    }
-    if (tid == 0) {
-        if (S->done) {
-            S->pend_role = -1;
-        } else {
-            S->pend_role = a.role;
-            S->pend_blocks = gridDim.x;
-            S->pend_fwd = my_fwd;
-        }
-        if (blockIdx.x == 0) {
-            *a.st_next = *S;
-            // on the stop decision both buffers get the final state (any block still reading
-            // the input buffer then also sees `done` and exits without working)
-            if (S->done) *a.st = *S;
-        }
-    }
-    __syncthreads();
-    return !S->done;
 }
 
 // Exit of a deferred-protocol launch: this workgroup's partial sums, plain stores.

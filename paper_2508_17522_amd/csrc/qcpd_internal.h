@@ -12,6 +12,7 @@ namespace qcpd {
 constexpr int kBlock = 256;      // threads per workgroup (4 wavefronts)
 constexpr int kWave = 64;
 constexpr int kMaxPsd = 64;      // largest PSD order kept in LDS
+constexpr int kMaxLoopGrid = 1024;  // most workgroups of one LSQR-loop launch
 
 // LSQR scalars live in device memory so that a captured graph of many iterations runs
 // without host round trips; the host only reads `done` once per graph launch.
@@ -185,10 +186,10 @@ struct StepArgs {
     int *counter;
     LsqrState *st;
     int check_done;     // return at once when st->done is set (kernels inside the loop)
-    // deferred protocol (LSQR loop): read the state from st and the previous launch's
-    // partials from part_prev, finalise them at entry, write the state to st_next and this
-    // launch's partials to part_next. No fences or atomics: launch order gives visibility.
-    int deferred;
+    // LSQR loop (loop.hip): read the state from st and the previous launch's partials from
+    // part_prev (kMaxLoopGrid slots), finalise them at entry, write the state to st_next and
+    // this launch's partials to part_next. No fences or atomics: launch order gives
+    // visibility.
     LsqrState *st_next;
     const double *part_prev;
     double *part_next;
@@ -224,6 +225,7 @@ void launch_cone_pre(const Problem &p, const StepArgs &a, const ConeGrid &g, int
 void launch_state_init(LsqrState *st, double tol, int max_iter, hipStream_t s);
 void launch_fill(double *p, long long n, double v, hipStream_t s);
 void launch_flush(const Problem &p, const StepArgs &a, double *sol, int nblk, hipStream_t s);
+void launch_adj_dot(const Problem &p, const StepArgs &a, hipStream_t s);
 void launch_jvp_rhs(const Problem &p, const StepArgs &a, const RowGrid &g, const double *dP,
                     const double *dA, const double *dq, const double *db, hipStream_t s);
 void launch_vjp_rhs(const Problem &p, const StepArgs &a, const ConeGrid &g, int lds_bytes,
@@ -234,6 +236,13 @@ void launch_vjp_out(const Problem &p, const RowGrid &g, const double *w, double 
                     double *dA, double *dq, double *db, hipStream_t s);
 void launch_nan_scan(const double *const *ptrs, const long long *lens, int nseg, int *flag,
                      hipStream_t s);
+
+// the LSQR loop (loop.hip)
+int loop_lds_bytes(int kmax);
+void set_loop_kernel_lds(int bytes);
+void launch_loop_F(const Problem &p, const StepArgs &a, const RowGrid &g, int grid, hipStream_t s);
+void launch_loop_FT(const Problem &p, const StepArgs &a, const FusedGrid &g, int lds, int grid,
+                    hipStream_t s);
 
 // learned preconditioner (learned.hip)
 struct FeatMeta {
