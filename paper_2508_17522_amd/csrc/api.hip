@@ -90,9 +90,19 @@ qcpd_status dalloc(qcpd_handle *h, T **ptr, size_t count) {
         if (s_ != QCPD_OK) return s_;                       \
     } while (0)
 
-int lanes_for(double avg) {
+// Lanes per CSR row: the largest power of two (<= 64) that still gives each lane about
+// `per_lane` stored entries. The product with F runs best with one entry per lane (most
+// parallel), the fused product with F' with two (fewer, fuller work units); measured on
+// MI355X. QCPD_NNZ_PER_LANE_F / _FT override the two for tuning.
+int nnz_per_lane(const char *env, int dflt) {
+    const char *e = getenv(env);
+    const int x = e ? atoi(e) : 0;
+    return x > 0 ? x : dflt;
+}
+
+int lanes_for(double avg, int per_lane) {
     int L = 1;
-    while (L < 64 && 2 * L <= avg) L *= 2;
+    while (L < 64 && 2 * L * per_lane <= avg) L *= 2;
     return L;
 }
 
@@ -417,8 +427,12 @@ qcpd_status create_impl(qcpd_handle *h, const qcpd_csr *P, const qcpd_csr *A, co
     HIPCHK(hipMemsetAsync(h->wy, 0, sizeof(double) * std::max(m, 1), st));
     // --- grids ----------------------------------------------------------------------------
     RowGrid &rg = h->rg;
-    rg.lx = lanes_for(n ? (double)(P->nnz + A->nnz) / n : 1.0);
-    rg.ly = lanes_for(m ? (double)A->nnz / m : 1.0);
+    const double avg_x = n ? (double)(P->nnz + A->nnz) / n : 1.0;
+    const double avg_y = m ? (double)A->nnz / m : 1.0;
+    const int npl_F = nnz_per_lane("QCPD_NNZ_PER_LANE_F", 1);
+    const int npl_T = nnz_per_lane("QCPD_NNZ_PER_LANE_FT", 2);
+    rg.lx = lanes_for(avg_x, npl_F);
+    rg.ly = lanes_for(avg_y, npl_F);
     rg.bx = div_up((long long)n * rg.lx, kBlock);
     rg.by = div_up((long long)(m + 1) * rg.ly, kBlock);
     // cone tables
@@ -465,13 +479,22 @@ qcpd_status create_impl(qcpd_handle *h, const qcpd_csr *P, const qcpd_csr *A, co
     cg.bX = div_up(K->n_exp, kBlock);
     cg.bP = K->n_psd;
     h->lds = kmax ? (3 * kmax * (kmax | 1) + kmax * (kmax + 1) / 2) * (int)sizeof(double) : 0;
-    // work units of the fused product with F'
+    // work units of the fused product with F', longest first (PSD cones by order, then
+    // exponential and SOC runs, then CSR rows) so that the long ones start in the first
+    // round of workgroups
     {
-        std::vector<Unit> units;
-        const int rpx = kBlock / rg.lx, rpy = kBlock / rg.ly;
-        for (int r = 0; r < n; r += rpx) units.push_back({U_XROWS, r, std::min(n, r + rpx), 0});
+        h->fg.lx = lanes_for(avg_x, npl_T);
+        h->fg.ly = lanes_for(avg_y, npl_T);
+        std::vector<Unit> units, soc_units, exp_units, row_units;
+        std::vector<int> order(K->n_psd);
+        for (int i = 0; i < K->n_psd; ++i) order[i] = i;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int a, int b) { return K->psd_orders[a] > K->psd_orders[b]; });
+        for (int i : order) units.push_back({U_PSD, i, i + 1, psd_row[i]});
+        const int rpx = kBlock / h->fg.lx, rpy = kBlock / h->fg.ly;
         for (int r = 0; r < p.n_diag; r += rpy)
-            units.push_back({U_DIAG, r, std::min(p.n_diag, r + rpy), 0});
+            row_units.push_back({U_DIAG, r, std::min(p.n_diag, r + rpy), 0});
+        for (int r = 0; r < n; r += rpx) row_units.push_back({U_XROWS, r, std::min(n, r + rpx), 0});
         const int target = 256;  // y rows per SOC / exponential unit
         for (int i = 0; i < K->n_soc;) {
             int j = i, rws = 0;
@@ -481,21 +504,23 @@ qcpd_status create_impl(qcpd_handle *h, const qcpd_csr *P, const qcpd_csr *A, co
                 ++j;
             }
             if (j == i) return QCPD_ERR_CONE;  // a single cone larger than kUnitRows rows
-            units.push_back({U_SOC, i, j, soc_row[i]});
+            soc_units.push_back({U_SOC, i, j, soc_row[i]});
             i = j;
         }
+        // an exponential unit stages 9 doubles per cone in a kUnitRows buffer of the loop kernel
+        static_assert((256 / 3) * 9 <= kUnitRows, "exponential unit size");
         for (int i = 0; i < K->n_exp; i += target / 3)
-            units.push_back({U_EXP, i, std::min(K->n_exp, i + target / 3), p.exp_row0 + 3 * i});
-        for (int i = 0; i < K->n_psd; ++i) units.push_back({U_PSD, i, i + 1, psd_row[i]});
+            exp_units.push_back({U_EXP, i, std::min(K->n_exp, i + target / 3), p.exp_row0 + 3 * i});
+        units.insert(units.end(), exp_units.begin(), exp_units.end());
+        units.insert(units.end(), soc_units.begin(), soc_units.end());
+        units.insert(units.end(), row_units.begin(), row_units.end());
         Unit *du;
         ALLOC(du, units.size());
         HIPCHK(hipMemcpy(du, units.data(), sizeof(Unit) * units.size(), hipMemcpyHostToDevice));
         h->fg.nunits = (int)units.size();
         h->fg.units = du;
-        h->fg.lx = rg.lx;
-        h->fg.ly = rg.ly;
         h->lds_fused = fused_lds_bytes(kmax);
-        h->lds_loop = loop_lds_bytes(kmax);
+        h->lds_loop = loop_lds_bytes(K->psd_orders, K->n_psd);
     }
     h->nblk_max = std::max({cg.total(), rg.total(), h->fg.nunits, div_up(N, kBlock), 1});
     // the two launches of the deferred LSQR loop: at most `cap` workgroups each, so the next

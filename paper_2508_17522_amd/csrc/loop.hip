@@ -26,6 +26,73 @@ namespace qcpd {
 constexpr int kPartRegs = kMaxLoopGrid / kBlock;  // previous-launch partials per thread
 
 // ---------------------------------------------------------------------------------------
+// reductions on DPP lane moves (a __shfl_xor step is an LDS permute on this GPU; a DPP move
+// is a register operand modifier)
+// ---------------------------------------------------------------------------------------
+
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ inline double dpp_mov(double v) {  // lanes without a source read 0
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    return __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, CTRL, ROW_MASK, 0xf, true),
+                            __builtin_amdgcn_update_dpp(0, lo, CTRL, ROW_MASK, 0xf, true));
+}
+
+// Sum over aligned groups of L lanes (L a power of two <= 64), valid in every lane of the
+// group: butterflies within a row of 16 lanes (xor 1, xor 2, half-row mirror, row mirror),
+// then permutes across rows.
+__device__ inline double group_sum_dpp(double v, int L) {
+    if (L >= 2) v += dpp_mov<0xB1>(v);    // quad_perm [1,0,3,2]
+    if (L >= 4) v += dpp_mov<0x4E>(v);    // quad_perm [2,3,0,1]
+    if (L >= 8) v += dpp_mov<0x141>(v);   // row_half_mirror
+    if (L >= 16) v += dpp_mov<0x140>(v);  // row_mirror
+    if (L >= 32) v += __shfl_xor(v, 16);
+    if (L >= 64) v += __shfl_xor(v, 32);
+    return v;
+}
+
+// Sum over the wave, valid in lane 63: row sums, then row_bcast15 / row_bcast31.
+__device__ inline double wave_total_dpp(double v) {
+    v += dpp_mov<0xB1>(v);
+    v += dpp_mov<0x4E>(v);
+    v += dpp_mov<0x141>(v);
+    v += dpp_mov<0x140>(v);
+    v += dpp_mov<0x142, 0xa>(v);
+    v += dpp_mov<0x143, 0xc>(v);
+    return v;
+}
+
+// Sums of a and b over the workgroup, valid in thread 0 (fixed order: waves 0..3).
+__device__ inline void block_sum2(double &a, double &b) {
+    __shared__ double sh[2][kBlock / kWave];
+    a = wave_total_dpp(a);
+    b = wave_total_dpp(b);
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    if (lane == kWave - 1) {
+        sh[0][w] = a;
+        sh[1][w] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a = sh[0][0];
+        b = sh[1][0];
+        for (int i = 1; i < kBlock / kWave; ++i) {
+            a += sh[0][i];
+            b += sh[1][i];
+        }
+    }
+    __syncthreads();
+}
+
+// This workgroup's partial sums for the next launch (plain stores).
+__device__ inline void leave(const StepArgs &a, double s0, double s1) {
+    block_sum2(s0, s1);
+    if (threadIdx.x == 0) {
+        a.part_next[3 * blockIdx.x] = s0;
+        a.part_next[3 * blockIdx.x + 1] = s1;
+    }
+}
+
+// ---------------------------------------------------------------------------------------
 // entry: state and the previous launch's partial sums
 // ---------------------------------------------------------------------------------------
 
@@ -53,7 +120,7 @@ __device__ inline bool entry_finish(const StepArgs &a, const Entry &e, LsqrState
         if (blockIdx.x == 0 && tid == 0) *a.st_next = e.st;
         return false;
     }
-    double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+    double t0 = 0.0, t1 = 0.0;
     if (e.st.pend_role >= 0) {
 #pragma unroll
         for (int j = 0; j < kPartRegs; ++j)
@@ -61,7 +128,7 @@ __device__ inline bool entry_finish(const StepArgs &a, const Entry &e, LsqrState
                 t0 += e.pa[j];
                 t1 += e.pb[j];
             }
-        block_sum3(t0, t1, t2);
+        block_sum2(t0, t1);
     }
     if (tid == 0) {
         LsqrState s = e.st;
@@ -105,6 +172,38 @@ __device__ inline Ptrs ptrs_of(const StepArgs &a) {
 __device__ inline double in_raw(const StepArgs &a, const Ptrs &q, int j) {
     const double v = a.in[j];
     return q.isc ? v * q.isc[j] : v;
+}
+
+// Strided CSR dot product sum_k val[k] (sc o x)[col[k] + off] over k = k0 + lane, k0 + lane
+// + L, ... below k1, with sc absent meaning all ones. Four entries per pass, each pass's loads
+// issued together: indices past k1 are clamped to k1 - 1 (a valid entry) and their value is
+// replaced by zero, so the loop body has no branch between its loads.
+template <bool SC>
+__device__ inline double csr_dot4(const int *col, const double *val, int k0, int k1, int lane,
+                                  int L, const double *x, const double *sc, int off) {
+    double acc = 0.0;
+    for (int k = k0 + lane; k < k1; k += 4 * L) {
+        int j[4];
+        double v[4], xv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int kk = min(k + u * L, k1 - 1);
+            j[u] = col[kk] + off;
+            v[u] = val[kk];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) xv[u] = SC ? x[j[u]] * sc[j[u]] : x[j[u]];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (k + u * L < k1) acc += v[u] * xv[u];
+    }
+    return acc;
+}
+
+__device__ inline double csr_dot(const int *col, const double *val, int k0, int k1, int lane,
+                                 int L, const double *x, const double *sc, int off) {
+    return sc ? csr_dot4<true>(col, val, k0, k1, lane, L, x, sc, off)
+              : csr_dot4<false>(col, val, k0, k1, lane, L, x, sc, off);
 }
 
 struct Fin {
@@ -189,24 +288,21 @@ __device__ inline void rows_pre(const Problem &p, const StepArgs &a, const Ptrs 
         if (row < n) {
             const int k0 = p.Prp[row], k1 = p.Prp[row + 1];
             const int t0 = p.Trp[row], t1 = p.Trp[row + 1];
-#pragma unroll 4
-            for (int k = k0 + lane; k < k1; k += L) acc += p.Pv[k] * in_raw(a, q, p.Pci[k]);
-#pragma unroll 4
-            for (int t = t0 + lane; t < t1; t += L) accT += p.Tv[t] * a.wy[p.Tci[t]];
+            acc = csr_dot(p.Pci, p.Pv, k0, k1, lane, L, a.in, q.isc, 0);
+            accT = csr_dot(p.Tci, p.Tv, t0, t1, lane, L, a.wy, nullptr, 0);
             idx = row;
         }
     } else {
         if (row < m) {
             const int k0 = p.Arp[row], k1 = p.Arp[row + 1];
-#pragma unroll 4
-            for (int k = k0 + lane; k < k1; k += L) acc += p.Av[k] * in_raw(a, q, p.Aci[k]);
+            acc = csr_dot(p.Aci, p.Av, k0, k1, lane, L, a.in, q.isc, 0);
             idx = n + row;
         } else if (row == m) {
             idx = N - 1;
         }
     }
-    r.acc = group_sum(acc, L);
-    r.accT = group_sum(accT, L);
+    r.acc = group_sum_dpp(acc, L);
+    r.accT = group_sum_dpp(accT, L);
     r.idx = (lane == 0) ? idx : -1;
     double qb = 0.0, self = 0.0, wyr = 0.0;
     if (r.idx >= 0) {
@@ -256,7 +352,7 @@ __global__ __launch_bounds__(kBlock) void k_loop_F(Problem p, StepArgs a, RowGri
         rows_pre(p, a, q, g, vb, r);
         rows_post(p, a, c, S, r, s0, s1);
     }
-    deferred_leave(a, s0, s1);
+    leave(a, s0, s1);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -267,11 +363,39 @@ struct UnitPre {
     int idx;                   // entry of this thread (x / diagonal rows: lane 0), or -1
     double acc, accT, self, coef, jd;
     double bv;                 // cone units: b at this thread's first row
+    double cp[4];              // SOC factors of this thread's cone: mode, 1/|u|, c1, c2
     Fin f;
 };
 
-// LDS layout of a cone unit: [PSD scratch X, T, V][tb: raw rows][rb: raw r_y, then the
-// scaled outputs][jt: J applied]
+// LDS of a cone unit. Runs of SOC / exponential cones: tb (raw rows), rb (raw r_y, then the
+// scaled outputs), jt (J applied), ub (SOC: u/|u| at each row; exponential: each cone's
+// 3x3 Jacobian), kUnitRows each. One PSD cone of order k: X, T, V and, when it fits, B as
+// kp x ld matrices (kp = k rounded up to a multiple of 16, zero-padded, ld = kp + 1), then
+// tb, rb, jt (k(k+1)/2 each).
+constexpr int kPsdLdsCap = 16384;  // doubles a PSD unit may stage B into
+constexpr int kPsdPref = 4;        // V, B entries per thread loaded ahead (kp*kp <= 1024)
+constexpr int kSocPref = 8;        // u entries per cone loaded ahead (dimensions <= 9)
+
+struct PsdLds {
+    int kp, ld, nr, b, tb;  // b: offset of B, or -1 when B is read from global memory
+};
+
+__host__ __device__ inline PsdLds psd_lds(int k) {
+    PsdLds L;
+    L.kp = (k + 15) / 16 * 16;
+    L.ld = L.kp + 1;
+    L.nr = k * (k + 1) / 2;
+    const int mat = L.kp * L.ld;
+    if (4 * mat + 3 * L.nr <= kPsdLdsCap) {
+        L.b = 3 * mat;
+        L.tb = 4 * mat;
+    } else {
+        L.b = -1;
+        L.tb = 3 * mat;
+    }
+    return L;
+}
+
 __device__ inline int unit_rows(const Problem &p, const Unit &u, int &r0) {
     if (u.type == U_PSD) {
         const int k = p.psd_k[u.begin];
@@ -284,12 +408,125 @@ __device__ inline int unit_rows(const Problem &p, const Unit &u, int &r0) {
     return r1 - r0;
 }
 
-__device__ inline double *unit_base(const Problem &p, const Unit &u, double *sm) {
+__device__ inline void unit_bufs(const Problem &p, const Unit &u, double *sm, int nr,
+                                 double *&tb, double *&rb, double *&jt, double *&ub) {
     if (u.type == U_PSD) {
-        const int k = p.psd_k[u.begin];
-        return sm + psd_stage_offset(k);
+        tb = sm + psd_lds(p.psd_k[u.begin]).tb;
+        rb = tb + nr;
+        jt = rb + nr;
+        ub = nullptr;
+    } else {
+        tb = sm;
+        rb = sm + kUnitRows;
+        jt = sm + 2 * kUnitRows;
+        ub = sm + 3 * kUnitRows;
     }
-    return sm;
+}
+
+// SOC Jacobian (see soc_jv) on unit-relative rows [i0, i0 + dim), u/|u| read from ub
+template <class IN, class OUT>
+__device__ inline void soc_apply(const double *cp, const double *ub, int i0, int dim, IN in,
+                                 OUT out) {
+    const int mode = (int)cp[0];
+    if (mode == 0) {
+        for (int i = 0; i < dim; ++i) out(i0 + i, 0.0);
+        return;
+    }
+    if (mode == 1) {
+        for (int i = 0; i < dim; ++i) out(i0 + i, in(i0 + i));
+        return;
+    }
+    const double c1 = cp[2], c2 = cp[3];
+    const double dt = in(i0);
+    double a = 0.0;
+    for (int i = 1; i < dim; ++i) a += ub[i0 + i] * in(i0 + i);
+    out(i0, 0.5 * (dt + a));
+    for (int i = 1; i < dim; ++i) {
+        const double uh = ub[i0 + i];
+        out(i0 + i, 0.5 * uh * dt + c1 * in(i0 + i) - c2 * a * uh);
+    }
+}
+
+template <class IN, class OUT>
+__device__ inline void exp_apply(const double *J, int i0, IN in, OUT out) {
+    const double a = in(i0), b = in(i0 + 1), c = in(i0 + 2);
+    out(i0, J[0] * a + J[1] * b + J[2] * c);
+    out(i0 + 1, J[3] * a + J[4] * b + J[5] * c);
+    out(i0 + 2, J[6] * a + J[7] * b + J[8] * c);
+}
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// One kp x kp product C = op(A) op(B) of LDS matrices (leading dimension ld, zero-padded)
+// on the FP64 matrix cores: wave w computes the 16 x 16 tiles w, w + 4, ... in row-major tile
+// order with V_MFMA_F64_16X16X4F64. In each step lane l supplies A[i0 + l%16][k0 + l/16] and
+// B[k0 + l/16][j0 + l%16]; accumulator entry r of lane l is C[i0 + 4r + l/16][j0 + l%16].
+// epi(i, j, acc) receives i = i0 + l/16 (rows i + 4r) and j = j0 + l%16.
+template <bool TA, bool TB, class EPI>
+__device__ inline void mfma_product(int kp, int ld, const double *A, const double *B, EPI epi) {
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int li = lane & 15, lk = lane >> 4, nt = kp / 16;
+    for (int t = wave; t < nt * nt; t += kBlock / kWave) {
+        const int i0 = (t / nt) * 16, j0 = (t - (t / nt) * nt) * 16;
+        dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+        for (int k0 = 0; k0 < kp; k0 += 16) {  // kp is a multiple of 16: four steps per pass
+            double av[4], bv[4];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {  // operand loads first, so they overlap
+                const int kk = k0 + 4 * s + lk;
+                av[s] = TA ? A[kk * ld + i0 + li] : A[(i0 + li) * ld + kk];
+                bv[s] = TB ? B[(j0 + li) * ld + kk] : B[kk * ld + j0 + li];
+            }
+#pragma unroll
+            for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], bv[s], acc, 0, 0, 0);
+        }
+        epi(i0 + lk, j0 + li, acc);
+    }
+}
+
+// PSD Jacobian J[dZ] = V (B o (V' dZ V)) V' (see psd_jv) on unit-relative svec rows, with V
+// (and B) staged in LDS; the four products on the matrix cores.
+template <class IN, class OUT>
+__device__ inline void psd_apply(int k, const PsdLds &L, double *sm, const double *Bg, IN in,
+                                 OUT out) {
+    const int kp = L.kp, ld = L.ld, mat = kp * ld;
+    double *X = sm, *T = sm + mat;
+    const double *V = sm + 2 * mat, *B = L.b >= 0 ? sm + L.b : nullptr;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < kp * kp; e += kBlock) {  // X = smat(in), zero-padded
+        const int i = e / kp, j = e - (e / kp) * kp;
+        double v = 0.0;
+        if (i < k && j < k) {
+            v = in(i >= j ? svec_index(i, j, k) : svec_index(j, i, k));
+            if (i != j) v *= kRsqrt2;
+        }
+        X[i * ld + j] = v;
+    }
+    __syncthreads();
+    mfma_product<false, false>(kp, ld, X, V, [&](int i, int j, const dbl4 &c) {  // T = X V
+        for (int r = 0; r < 4; ++r) T[(i + 4 * r) * ld + j] = c[r];
+    });
+    __syncthreads();
+    mfma_product<true, false>(kp, ld, V, T, [&](int i, int j, const dbl4 &c) {  // X = B o (V'T)
+        for (int r = 0; r < 4; ++r) {
+            const int ii = i + 4 * r;
+            double bij = 0.0;
+            if (ii < k && j < k) bij = B ? B[ii * ld + j] : Bg[ii * k + j];
+            X[ii * ld + j] = bij * c[r];
+        }
+    });
+    __syncthreads();
+    mfma_product<false, false>(kp, ld, V, X, [&](int i, int j, const dbl4 &c) {  // T = V X
+        for (int r = 0; r < 4; ++r) T[(i + 4 * r) * ld + j] = c[r];
+    });
+    __syncthreads();
+    mfma_product<false, true>(kp, ld, T, V, [&](int i, int j, const dbl4 &c) {  // Y = T V'
+        for (int r = 0; r < 4; ++r) {
+            const int ii = i + 4 * r;
+            if (ii < k && j <= ii) out(svec_index(ii, j, k), ii == j ? c[r] : c[r] * kSqrt2);
+        }
+    });
+    __syncthreads();
 }
 
 __device__ inline void unit_pre(const Problem &p, const StepArgs &a, const Ptrs &q, int lx,
@@ -304,13 +541,11 @@ __device__ inline void unit_pre(const Problem &p, const StepArgs &a, const Ptrs 
         if (row < u.end) {
             const int k0 = p.Prp[row], k1 = p.Prp[row + 1];
             const int t0 = p.Trp[row], t1 = p.Trp[row + 1];
-#pragma unroll 4
-            for (int k = k0 + lane; k < k1; k += L) acc += p.Pv[k] * in_raw(a, q, p.Pci[k]);
-#pragma unroll 4
-            for (int t = t0 + lane; t < t1; t += L) accT += p.Tv[t] * in_raw(a, q, n + p.Tci[t]);
+            acc = csr_dot(p.Pci, p.Pv, k0, k1, lane, L, a.in, q.isc, 0);
+            accT = csr_dot(p.Tci, p.Tv, t0, t1, lane, L, a.in, q.isc, n);
         }
-        P.acc = group_sum(acc, L);
-        P.accT = group_sum(accT, L);
+        P.acc = group_sum_dpp(acc, L);
+        P.accT = group_sum_dpp(accT, L);
         if (row < u.end && lane == 0) {
             P.idx = row;
             P.coef = p.c[row];
@@ -323,10 +558,9 @@ __device__ inline void unit_pre(const Problem &p, const StepArgs &a, const Ptrs 
         double acc = 0.0;
         if (r < u.end) {
             const int k0 = p.Arp[r], k1 = p.Arp[r + 1];
-#pragma unroll 4
-            for (int k = k0 + lane; k < k1; k += L) acc += p.Av[k] * in_raw(a, q, p.Aci[k]);
+            acc = csr_dot(p.Aci, p.Av, k0, k1, lane, L, a.in, q.isc, 0);
         }
-        P.acc = group_sum(acc, L);
+        P.acc = group_sum_dpp(acc, L);
         if (r < u.end && lane == 0) {
             P.idx = n + r;
             P.self = in_raw(a, q, n + r);
@@ -336,44 +570,111 @@ __device__ inline void unit_pre(const Problem &p, const StepArgs &a, const Ptrs 
         }
         return;
     }
-    // cone units: raw rows t = A r_x - b r_N - r_y (unnormalised) into tb, then J t into jt
+    // cone units: issue the loads of the cone factors and of this thread's finish operands,
+    // then the raw rows t = A r_x - b r_N - r_y (unnormalised) into tb, then stage the
+    // factors in LDS and apply J to t into jt. Each cone kind has its own branch so that
+    // the registers holding its prefetched factors are not live in the others.
     int r0;
     const int nr = unit_rows(p, u, r0);
-    double *tb = unit_base(p, u, sm), *rb = tb + nr, *jt = rb + nr;
-    int L = ly;
-    while (L > 1 && L * nr > kBlock) L >>= 1;
-    const int lane = tid & (L - 1), grp = tid / L, ngrp = kBlock / L;
-    for (int i0 = 0; i0 < nr; i0 += ngrp) {
-        const int i = i0 + grp, r = r0 + i;
-        double acc = 0.0;
-        if (i < nr) {
-            const int k0 = p.Arp[r], k1 = p.Arp[r + 1];
-#pragma unroll 4
-            for (int k = k0 + lane; k < k1; k += L) acc += p.Av[k] * in_raw(a, q, p.Aci[k]);
-        }
-        acc = group_sum(acc, L);
-        if (i < nr && lane == 0) {
-            const double ry = in_raw(a, q, n + r);
-            rb[i] = ry;
-            tb[i] = acc - p.b[r] * in_N_raw - ry;
-        }
-    }
+    double *tb, *rb, *jt, *ub;
+    unit_bufs(p, u, sm, nr, tb, rb, jt, ub);
     if (tid < nr) {
         P.idx = n + r0 + tid;
         P.bv = p.b[r0 + tid];
         fin_load(a, q, n + r0 + tid, P.f);
     }
-    __syncthreads();
-    auto tin = [&](int r) { return tb[r - r0]; };
-    auto jout = [&](int r, double v) { jt[r - r0] = v; };
-    if (u.type == U_PSD) {
-        psd_jv(p, u.begin, sm, tin, jout);  // ends with a barrier
-    } else {
-        const int cone = u.begin + tid;
-        if (cone < u.end) {
-            if (u.type == U_SOC) soc_jv(p, cone, tin, jout);
-            else exp_jv(p, cone, tin, jout);
+    auto yrows = [&]() {
+        int L = ly;
+        while (L > 1 && L * nr > kBlock) L >>= 1;
+        const int lane = tid & (L - 1), grp = tid / L, ngrp = kBlock / L;
+        for (int i0 = 0; i0 < nr; i0 += ngrp) {
+            const int i = i0 + grp, r = r0 + i;
+            double acc = 0.0;
+            if (i < nr) {
+                const int k0 = p.Arp[r], k1 = p.Arp[r + 1];
+                acc = csr_dot(p.Aci, p.Av, k0, k1, lane, L, a.in, q.isc, 0);
+            }
+            acc = group_sum_dpp(acc, L);
+            if (i < nr && lane == 0) {
+                const double ry = in_raw(a, q, n + r);
+                rb[i] = ry;
+                tb[i] = acc - p.b[r] * in_N_raw - ry;
+            }
         }
+    };
+    auto tin = [&](int i) { return tb[i]; };
+    auto jout = [&](int i, double v) { jt[i] = v; };
+    const int cone = u.begin + tid;
+    if (u.type == U_PSD) {
+        const int k = p.psd_k[u.begin];
+        const PsdLds Ld = psd_lds(k);
+        const int kp = Ld.kp;
+        const double *Vg = p.psd_pool + p.psd_off[u.begin], *Bg = Vg + k * k;
+        double *V = sm + 2 * kp * Ld.ld, *B = Ld.b >= 0 ? sm + Ld.b : nullptr;
+        if (kp * kp <= kPsdPref * kBlock) {
+            double vpre[kPsdPref], bpre[kPsdPref];
+#pragma unroll
+            for (int j = 0; j < kPsdPref; ++j) {
+                const int e = tid + j * kBlock, i = e / kp, jj = e - (e / kp) * kp;
+                const bool in_k = e < kp * kp && i < k && jj < k;
+                vpre[j] = in_k ? Vg[i * k + jj] : 0.0;
+                bpre[j] = (in_k && B) ? Bg[i * k + jj] : 0.0;
+            }
+            yrows();
+#pragma unroll
+            for (int j = 0; j < kPsdPref; ++j) {
+                const int e = tid + j * kBlock, i = e / kp, jj = e - (e / kp) * kp;
+                if (e < kp * kp) {
+                    V[i * Ld.ld + jj] = vpre[j];
+                    if (B) B[i * Ld.ld + jj] = bpre[j];
+                }
+            }
+        } else {
+            yrows();
+            for (int e = tid; e < kp * kp; e += kBlock) {
+                const int i = e / kp, jj = e - (e / kp) * kp;
+                const bool in_k = i < k && jj < k;
+                V[i * Ld.ld + jj] = in_k ? Vg[i * k + jj] : 0.0;
+                if (B) B[i * Ld.ld + jj] = in_k ? Bg[i * k + jj] : 0.0;
+            }
+        }
+        __syncthreads();
+        psd_apply(k, Ld, sm, Bg, tin, jout);  // ends with a barrier
+    } else if (u.type == U_SOC) {
+        int cr0 = 0, cdim = 0;
+        if (cone < u.end) {
+            const double *par = p.soc_par + 4 * cone;
+            P.cp[0] = par[0]; P.cp[1] = par[1]; P.cp[2] = par[2]; P.cp[3] = par[3];
+            cr0 = p.soc_row[cone];
+            cdim = p.soc_dim[cone];
+        }
+        if (cdim - 1 <= kSocPref) {
+            double upre[kSocPref];
+#pragma unroll
+            for (int j = 0; j < kSocPref; ++j) upre[j] = j < cdim - 1 ? p.zy[cr0 + 1 + j] : 0.0;
+            yrows();
+#pragma unroll
+            for (int j = 0; j < kSocPref; ++j)
+                if (j < cdim - 1) ub[cr0 - r0 + 1 + j] = upre[j] * P.cp[1];
+        } else {
+            yrows();
+            for (int j = 0; j < cdim - 1; ++j) ub[cr0 - r0 + 1 + j] = p.zy[cr0 + 1 + j] * P.cp[1];
+        }
+        __syncthreads();
+        if (cone < u.end) soc_apply(P.cp, ub, cr0 - r0, cdim, tin, jout);
+        __syncthreads();
+    } else {  // exponential cones: each cone's 3x3 Jacobian staged in ub
+        double J[9];
+        const bool own = cone < u.end;
+#pragma unroll
+        for (int j = 0; j < 9; ++j) J[j] = own ? p.exp_J[9 * cone + j] : 0.0;
+        yrows();
+        if (own) {
+#pragma unroll
+            for (int j = 0; j < 9; ++j) ub[9 * tid + j] = J[j];
+        }
+        __syncthreads();
+        if (own) exp_apply(J, exp_row(p, cone) - r0, tin, jout);
         __syncthreads();
     }
 }
@@ -404,7 +705,8 @@ __device__ inline void unit_post(const Problem &p, const StepArgs &a, const Ptrs
     }
     int r0;
     const int nr = unit_rows(p, u, r0);
-    double *tb = unit_base(p, u, sm), *rb = tb + nr, *jt = rb + nr;
+    double *tb, *rb, *jt, *ub;
+    unit_bufs(p, u, sm, nr, tb, rb, jt, ub);
     for (int i = tid; i < nr; i += kBlock) {
         Fin f;
         if (i == tid) f = P.f;
@@ -414,16 +716,18 @@ __device__ inline void unit_post(const Problem &p, const StepArgs &a, const Ptrs
     }
     if (!a.do_pre) return;
     __syncthreads();
-    // J of the next product with F, on the scaled outputs
-    auto oin = [&](int r) { return rb[r - r0]; };
-    auto jout = [&](int r, double v) { jt[r - r0] = v; };
+    // J of the next product with F, on the scaled outputs (factors still staged)
+    auto oin = [&](int i) { return rb[i]; };
+    auto jout = [&](int i, double v) { jt[i] = v; };
     if (u.type == U_PSD) {
-        psd_jv(p, u.begin, sm, oin, jout);
+        const int k = p.psd_k[u.begin];
+        const double *Bg = p.psd_pool + p.psd_off[u.begin] + k * k;
+        psd_apply(k, psd_lds(k), sm, Bg, oin, jout);
     } else {
         const int cone = u.begin + tid;
         if (cone < u.end) {
-            if (u.type == U_SOC) soc_jv(p, cone, oin, jout);
-            else exp_jv(p, cone, oin, jout);
+            if (u.type == U_SOC) soc_apply(P.cp, ub, p.soc_row[cone] - r0, p.soc_dim[cone], oin, jout);
+            else exp_apply(ub + 9 * tid, exp_row(p, cone) - r0, oin, jout);
         }
         __syncthreads();
     }
@@ -461,16 +765,20 @@ __global__ __launch_bounds__(kBlock) void k_loop_FT(Problem p, StepArgs a, Fused
         const double o = fin_store(a, c, N - 1, f, S.dot_adj * c.inv + p.xPx * c.in_N, s0);
         (void)o;
     }
-    deferred_leave(a, s0, s1);
+    leave(a, s0, s1);
 }
 
 // ---------------------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------------------
 
-int loop_lds_bytes(int kmax) {
-    const int psd = kmax > 0 ? psd_stage_offset(kmax) + 3 * (kmax * (kmax + 1) / 2) : 0;
-    return (int)sizeof(double) * std::max(3 * kUnitRows, psd);
+int loop_lds_bytes(const int *psd_orders, int n_psd) {
+    int need = 4 * kUnitRows;
+    for (int i = 0; i < n_psd; ++i) {
+        const PsdLds L = psd_lds(psd_orders[i]);
+        need = std::max(need, L.tb + 3 * L.nr);
+    }
+    return (int)sizeof(double) * need;
 }
 
 void set_loop_kernel_lds(int bytes) {

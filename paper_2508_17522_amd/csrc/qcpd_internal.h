@@ -238,7 +238,7 @@ void launch_nan_scan(const double *const *ptrs, const long long *lens, int nseg,
                      hipStream_t s);
 
 // the LSQR loop (loop.hip)
-int loop_lds_bytes(int kmax);
+int loop_lds_bytes(const int *psd_orders, int n_psd);
 void set_loop_kernel_lds(int bytes);
 void launch_loop_F(const Problem &p, const StepArgs &a, const RowGrid &g, int grid, hipStream_t s);
 void launch_loop_FT(const Problem &p, const StepArgs &a, const FusedGrid &g, int lds, int grid,
