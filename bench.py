@@ -38,16 +38,35 @@ def kernel_bytes(q, which: str) -> float:
     N = n + m + 1
     nnzP, nnzA = q.P.nnz, q.A.nnz
     csr = 12.0 * (nnzP + 2 * nnzA) + 4.0 * (2 * n + m + 3)
-    if which == "rows_F":
+    if which == "k_loop_F":
         # in, scale, J-input wy, q, b, out read+write, LSQR x and w read+write
         vec = 8.0 * (N + N + m + n + m + 2 * N + 4 * N)
         return csr + vec
-    if which == "fused_FT":
+    if which == "k_loop_FT":
         c = q.cones
         fac = 8.0 * (4 * len(c.soc) + sum(c.soc) + 9 * c.n_exp + sum(2 * k * k for k in c.psd))
         # in, c, b, out read+write, scale, jdiag of diagonal rows, wy write
         return csr + fac + 8.0 * (N + n + m + 2 * N + N + c.n_zero + c.n_nonneg + m)
     raise ValueError(which)
+
+
+def profiled_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` from the committed profiler counters of this workload
+    (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy), or None when there are none or the
+    kernel's sources have changed since they were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"k_loop_{workload}.traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    h = hashlib.sha256()
+    for src in t["sources"]:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != t["sources_sha256"] or kernel not in t["kernels"]:
+        return None
+    return t["kernels"][kernel]["hbm_bytes_per_launch"]
 
 
 def cpu_baseline(q, iters_jvp, iters_vjp, budget_s=20.0):
@@ -143,7 +162,7 @@ def run_batch(args):
     it_v = [i.iters for i in last["iv"]]
     # roofline of the persistent batch kernel over the JVP launch: algorithmic bytes of every
     # problem's LSQR iterations / the launch's duration (HIP events on the library's stream)
-    per_iter = [kernel_bytes(q, "rows_F") + kernel_bytes(q, "fused_FT") for q in qs]
+    per_iter = [kernel_bytes(q, "k_loop_F") + kernel_bytes(q, "k_loop_FT") for q in qs]
     t_launch = last["ij"][0].ms_total * 1e-3
     nbytes = float(sum(b * k for b, k in zip(per_iter, it_j)))
     achieved = nbytes / t_launch / 1e9
@@ -225,11 +244,11 @@ def run_kernels_only(args):
     h.close()
     torch.cuda.synchronize()
     print(json.dumps({"kernels_only": {"workload": q.name, "reps": args.kernels_only,
-                                       "avg_launch_us": {"rows_F": ms[0] * 1e3,
-                                                         "fused_FT": ms[1] * 1e3},
+                                       "avg_launch_us": {"k_loop_F": ms[0] * 1e3,
+                                                         "k_loop_FT": ms[1] * 1e3},
                                        "bytes_per_launch": {
-                                           "rows_F": kernel_bytes(q, "rows_F"),
-                                           "fused_FT": kernel_bytes(q, "fused_FT")}}}),
+                                           "k_loop_F": kernel_bytes(q, "k_loop_F"),
+                                           "k_loop_FT": kernel_bytes(q, "k_loop_FT")}}}),
           flush=True)
 
 
@@ -330,14 +349,15 @@ def main():
     h = step(None)
     ms = Q.qcpd_profile_kernels(h, reps=200)
     h.close()
-    names = ["rows_F", "fused_FT"]
+    names = ["k_loop_F", "k_loop_FT"]
     iters_total = rec[-1]["ij"].iters + rec[-1]["iv"].iters
     dom = int(np.argmax(ms))
     dom_name = names[dom]
     nbytes = kernel_bytes(q, dom_name)
     achieved = nbytes / (ms[dom] * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+                "traffic": profiled_traffic(q.name, dom_name),
                 "kernel": dom_name, "avg_launch_us": round(ms[dom] * 1e3, 3),
                 "bytes_per_launch": int(nbytes),
                 "all_kernels_us": {k: round(v * 1e3, 3) for k, v in zip(names, ms)}}

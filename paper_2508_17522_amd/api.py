@@ -229,7 +229,7 @@ def qcpd_get_diagnostics(h: Handle):
 
 def qcpd_profile_kernels(h: Handle, reps: int = 50):
     """Average launch duration (ms) of the two LSQR-iteration kernels of the JVP:
-    (rows_F, fused_FT)."""
+    (k_loop_F: the product with F over CSR rows, k_loop_FT: the fused product with F')."""
     out = (ctypes.c_float * 2)()
     with torch.cuda.device(h.device):
         st = _lib().qcpd_profile_kernels(h.ptr, int(reps), out)
