@@ -129,7 +129,9 @@ def run_batch(args):
     print(f"[bench] generating {count} batch problems", file=sys.stderr, flush=True)
     qs = [qcpgen.batch_member(i) for i in range(count)]
     bt = batch_to_device(qs)
-    opts = Q.Opts(tol=args.tol, precond=Q.QCPD_PRECOND_JACOBI)
+    prec = {"equil": Q.QCPD_PRECOND_EQUIL, "jacobi": Q.QCPD_PRECOND_JACOBI,
+            "none": Q.QCPD_PRECOND_NONE}[args.precond]
+    opts = Q.Opts(tol=args.tol, precond=prec)
     torch.cuda.synchronize()
 
     def step(record):
@@ -160,8 +162,8 @@ def run_batch(args):
     last = rec[-1]
     it_j = [i.iters for i in last["ij"]]
     it_v = [i.iters for i in last["iv"]]
-    # roofline of the persistent batch kernel over the JVP launch: algorithmic bytes of every
-    # problem's LSQR iterations / the launch's duration (HIP events on the library's stream)
+    # roofline of the segmented LSQR loop over the whole JVP: algorithmic bytes of every
+    # problem's LSQR iterations / the JVP's duration (HIP events on the library's stream)
     per_iter = [kernel_bytes(q, "k_loop_F") + kernel_bytes(q, "k_loop_FT") for q in qs]
     t_launch = last["ij"][0].ms_total * 1e-3
     nbytes = float(sum(b * k for b, k in zip(per_iter, it_j)))
@@ -175,7 +177,7 @@ def run_batch(args):
                    "sum_N": int(sum(q.n + q.m + 1 for q in qs)),
                    "sum_nnz_P": int(sum(q.P.nnz for q in qs)),
                    "sum_nnz_A": int(sum(q.A.nnz for q in qs)), "tol": args.tol,
-                   "precond": "jacobi"},
+                   "precond": args.precond},
         "lsqr_iters": {"jvp_median": float(np.median(it_j)), "jvp_max": int(max(it_j)),
                        "vjp_median": float(np.median(it_v)), "vjp_max": int(max(it_v))},
         "max_rel_residual": {"jvp": max(i.rel_residual for i in last["ij"]),
@@ -185,8 +187,8 @@ def run_batch(args):
                      for k in ("setup", "jvp", "vjp")},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
-                     "kernel": "batch_solve (JVP launch)",
-                     "avg_launch_us": round(t_launch * 1e6, 3), "bytes_per_launch": int(nbytes)},
+                     "kernel": "k_seg_F + k_seg_FT (every iteration of the JVP)",
+                     "jvp_us": round(t_launch * 1e6, 3), "bytes": int(nbytes)},
     }
     if args.batch_plain > 0:
         k = min(args.batch_plain, count)
@@ -207,6 +209,21 @@ def run_batch(args):
         line["vs_plain"] = {"precond": "jacobi", "path": "one problem per call",
                             "problems": k, "value": round(k / tp, 3), "unit": "solves/s",
                             "speedup": round(value / (k / tp), 3)}
+        if args.precond != "jacobi":  # the same preconditioner, one problem per call
+            o3 = Q.Opts(tol=args.tol, precond=prec)
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            for q, t in zip(qs[:k], tens):
+                h = Q.qcpd_create(t["P"], t["A"], t["q"], t["b"], cones_of(q), t["x"], t["y"],
+                                  t["s"], opts=o3)
+                Q.qcpd_jvp(h, t["dP"], t["dA"], t["dq"], t["db"])
+                Q.qcpd_vjp(h, t["gx"], t["gy"], t["gs"])
+                h.close()
+            torch.cuda.synchronize()
+            ts = time.perf_counter() - ts
+            line["vs_single_same_precond"] = {"precond": args.precond, "path": "one problem per call",
+                                              "problems": k, "value": round(k / ts, 3),
+                                              "unit": "solves/s", "speedup": round(value / (k / ts), 3)}
     print(json.dumps(line), flush=True)
 
 

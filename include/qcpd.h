@@ -253,10 +253,11 @@ qcpd_status qcpd_mlp_adam(const float *grad, float *weights, float *adam_m, floa
                           int32_t step, float lr, void *stream);
 
 /* ---------------------------------------------------------------------------------------
- * Batched form: many QCPs of uneven sizes evaluated in one launch (a persistent kernel in
- * which each workgroup takes whole problems from a work queue, longest first). Each problem
- * keeps its own LSQR iteration count and stopping test, so the results equal those of
- * qcpd_jvp / qcpd_vjp on each problem up to rounding. The vjp of the batch is the per-problem
+ * Batched form: many QCPs of uneven sizes evaluated together. The LSQR iterations of all
+ * problems advance in the same two launches per iteration (work items grouped by problem,
+ * captured in HIP graphs); each problem keeps its own LSQR state, iteration count and
+ * stopping test, so the results equal those of qcpd_jvp / qcpd_vjp on each problem up to
+ * rounding. The vjp of the batch is the per-problem
  * adjoint of Sec. 3.2, the jvp the per-problem derivative of Sec. 3.1.
  * ------------------------------------------------------------------------------------- */
 typedef struct qcpd_batch qcpd_batch;
@@ -275,7 +276,8 @@ typedef struct {
  * problem after problem: P_rowptr has sum(n_i + 1) entries (each problem's local row
  * pointers, starting at 0), P_colind / P_val sum(nnz_P) entries with local column indices;
  * A likewise with sum(m_i + 1) row pointers; q, x: sum(n_i); b, y, s: sum(m_i).
- * opts->precond may be NONE or JACOBI; graph_chunk is ignored. */
+ * opts->precond may be NONE or JACOBI; graph_chunk is the number of LSQR iterations (of all
+ * problems) per captured HIP graph launch. */
 qcpd_status qcpd_batch_create(qcpd_batch **hb, const qcpd_batch_layout *layout,
                               const int32_t *P_rowptr, const int32_t *P_colind, const double *P_val,
                               const int32_t *A_rowptr, const int32_t *A_colind, const double *A_val,
@@ -298,9 +300,10 @@ qcpd_status qcpd_batch_vjp(qcpd_batch *hb, const double *gx, const double *gy, c
 /* Replace the batch's LSQR options (tolerance, iteration cap, NONE or JACOBI). */
 qcpd_status qcpd_batch_set_opts(qcpd_batch *hb, const qcpd_opts *opts);
 
-/* Persistent workgroups of the batch kernel (each takes whole problems from the queue until
- * it is empty): grid >= 1, capped at the number of problems; 0 restores the default (all
- * workgroups that fit on the device at once). For tuning. */
+/* Persistent workgroups of the batch's per-problem phases (right-hand side and first product
+ * before the LSQR loop; owed update, residual and outputs after it), each taking whole
+ * problems from a queue until it is empty: grid >= 1, capped at the number of problems; 0
+ * restores the default (all workgroups that fit on the device at once). For tuning. */
 qcpd_status qcpd_batch_set_launch(qcpd_batch *hb, int32_t grid);
 
 /* out [host] 2 entries: the current grid and the default. */

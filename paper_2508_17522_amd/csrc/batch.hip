@@ -4,11 +4,14 @@
 // and Jacobi scales are exactly those of the single-problem path), except for the per-problem
 // tau entries (x'Px and the tau scales). The vectors of the batch are laid out as
 //   [ x of every problem | y of every problem | tau of every problem ].
-// The derivative evaluations run as one persistent kernel: each workgroup takes a problem
-// from an atomic work queue (longest first) and runs that problem's whole LSQR -- right-hand
-// side, iterations, explicit residual, outputs -- with workgroup barriers only and its LSQR
-// scalars in LDS, then takes the next problem. Every problem keeps its own iteration count
-// and stopping test, so results match the single-problem path up to rounding.
+// A derivative evaluation runs in three phases. Begin and end are persistent kernels in which
+// each workgroup takes whole problems from an atomic work queue (longest first): the begin
+// kernel forms a problem's right-hand side and the first product of its bidiagonalisation,
+// the end kernel applies the owed update, recomputes the explicit residual and forms the
+// outputs. In between, the LSQR iterations of all problems advance together in the segmented
+// loop kernels (loop.hip), two launches per iteration captured in HIP graphs, each work item
+// within one problem and each problem with its own state and stopping test, so results match
+// the single-problem path up to rounding.
 #include <math.h>
 #include <string.h>
 
@@ -34,7 +37,11 @@ struct BatchDev {
     const int *order;
     int *queue;
     double *u, *v, *xk, *wk, *rhs, *sol, *wy, *scratch;
-    const double *sc;  // diagonal scale of the current direction, or null
+    double *wy_res;    // J applied to the solution, for the explicit residual and outputs
+    const double *sc;  // column (v-side) scale of the current direction, or null
+    const double *scl; // row (u-side) scale of the current direction, or null
+    int *resume;       // per problem: LSQR resumed after its explicit residual check
+    int *nresumed;
     LsqrState *st_out;
     double tol;
     int max_iter;
@@ -132,10 +139,10 @@ __device__ void blk_fused_FT(const Problem &p, const BatchDev &d, const StepArgs
 
 // wy = J(s o in_y) (raw) and the F tau-row dot c'(s o in)_x - b'wy, over the problem's units
 __device__ void blk_pre(const Problem &p, const BatchDev &d, const double *in, const double *scl,
-                        const BCtx &bc, double *sm, double &s1) {
+                        double *wy, const BCtx &bc, double *sm, double &s1) {
     const int n = p.n, tid = threadIdx.x;
     auto ld = [&](int idx) { return scl ? scl[idx] * in[idx] : in[idx]; };
-    auto wout = [&](int r, double w) { d.wy[r] = w; s1 -= p.b[r] * w; };
+    auto wout = [&](int r, double w) { wy[r] = w; s1 -= p.b[r] * w; };
     for (int ui = bc.u0; ui < bc.u1; ++ui) {
         const Unit u = d.units[ui];
         if (u.type == U_XROWS) {
@@ -173,11 +180,12 @@ __device__ void blk_jvp_rhs(const Problem &p, const BatchDev &d, const BCtx &bc,
             acc = group_sum(acc, L);
             accT = group_sum(accT, L);
             if (row < bc.n1 && lane == 0) {
-                const double o = -(acc + accT + dq[row]);
-                d.u[row] = o;
+                // LSQR starts from u~ = L(-d) (L the row scale); -d itself is kept in rhs
+                const double o = -(acc + accT + dq[row]), l = d.scl ? d.scl[row] : 1.0;
+                d.u[row] = l * o;
                 d.rhs[row] = o;
-                s0 += o * o;
-                s1 += p.q[row] * o;
+                s0 += l * o * l * o;
+                s1 += p.q[row] * o * l * l;
                 s2 += p.x[row] * acc + dq[row] * p.x[row];
             }
         }
@@ -191,11 +199,11 @@ __device__ void blk_jvp_rhs(const Problem &p, const BatchDev &d, const BCtx &bc,
                 for (int k = p.Arp[r] + lane; k < p.Arp[r + 1]; k += L) acc += dA[k] * p.x[p.Aci[k]];
             acc = group_sum(acc, L);
             if (r < bc.m1 && lane == 0) {
-                const double o = acc - db[r];
-                d.u[n + r] = o;
+                const double o = acc - db[r], l = d.scl ? d.scl[n + r] : 1.0;
+                d.u[n + r] = l * o;
                 d.rhs[n + r] = o;
-                s0 += o * o;
-                s1 += p.b[r] * o;
+                s0 += l * o * l * o;
+                s1 += p.b[r] * o * l * l;
                 s2 += db[r] * p.y[r];
             }
         }
@@ -206,7 +214,12 @@ __device__ void blk_jvp_rhs(const Problem &p, const BatchDev &d, const BCtx &bc,
 __device__ void blk_vjp_rhs(const Problem &p, const BatchDev &d, const BCtx &bc, const double *gx,
                             const double *gy, const double *gs, double *sm, double &s0, double &s2) {
     const int n = p.n, tid = threadIdx.x;
-    auto put = [&](int idx, double o) { d.u[idx] = o; d.rhs[idx] = o; s0 += o * o; };
+    auto put = [&](int idx, double o) {  // u~ = L o, o kept in rhs
+        const double l = d.scl ? d.scl[idx] : 1.0;
+        d.u[idx] = l * o;
+        d.rhs[idx] = o;
+        s0 += l * o * l * o;
+    };
     auto gsum = [&](int r) { return gy[r] + gs[r]; };
     auto yout = [&](int r, double jt) {
         put(n + r, -(jt - gs[r]));
@@ -234,20 +247,32 @@ __device__ void blk_vjp_rhs(const Problem &p, const BatchDev &d, const BCtx &bc,
     }
 }
 
-// Evaluate one problem's JVP (dir 0) or VJP (dir 1) end to end.
-__device__ void solve_one(const BatchDev &d, int dir, int b, LsqrState *S, double *sm,
-                          const double *i0, const double *i1, const double *i2, const double *i3,
-                          double *o0, double *o1, double *o2, double *o3) {
-    const Problem &p = d.p;
-    const int tid = threadIdx.x, n = p.n;
+__device__ inline BCtx bctx_of(const BatchDev &d, int b) {
     BCtx bc;
     bc.b = b;
     bc.n0 = d.n_off[b]; bc.n1 = d.n_off[b + 1];
     bc.m0 = d.m_off[b]; bc.m1 = d.m_off[b + 1];
-    bc.tix = p.n + p.m + b;
+    bc.tix = d.p.n + d.p.m + b;
     bc.lx = d.lxs[b]; bc.ly = d.lys[b];
     bc.u0 = d.u_off[b]; bc.u1 = d.u_off[b + 1];
     bc.xPx = d.xPx[b];
+    return bc;
+}
+
+__device__ inline StepArgs base_of(const BatchDev &d, LsqrState *S) {
+    StepArgs base{};
+    base.sc = d.sc; base.scl = d.scl; base.wy = d.wy; base.xk = d.xk; base.wk = d.wk; base.rhs = d.rhs;
+    base.st = S; base.in_nrm = NRM_ONE; base.role = ROLE_PLAIN;
+    return base;
+}
+
+// One problem's JVP (dir 0) or VJP (dir 1) up to its LSQR loop: state, right-hand side and
+// the first product of the bidiagonalisation (state in S, LDS).
+__device__ void solve_begin(const BatchDev &d, int dir, int b, LsqrState *S, double *sm,
+                            const double *i0, const double *i1, const double *i2, const double *i3) {
+    const Problem &p = d.p;
+    const int tid = threadIdx.x, n = p.n;
+    const BCtx bc = bctx_of(d, b);
     const int Nb = (bc.n1 - bc.n0) + (bc.m1 - bc.m0) + 1;
     if (tid == 0) {
         LsqrState z = {};
@@ -264,19 +289,17 @@ __device__ void solve_one(const BatchDev &d, int dir, int b, LsqrState *S, doubl
     each_index([&](int i) { d.xk[i] = 0.0; d.wk[i] = 0.0; });
     __syncthreads();
 
-    StepArgs base{};
-    base.sc = d.sc; base.wy = d.wy; base.xk = d.xk; base.wk = d.wk; base.rhs = d.rhs;
-    base.st = S; base.in_nrm = NRM_ONE; base.role = ROLE_PLAIN;
+    const StepArgs base = base_of(d, S);
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
 
     if (dir == 0) {
         blk_jvp_rhs(p, d, bc, i0, i1, i2, i3, s0, s1, s2);
         block_sum3(s0, s1, s2);
         if (tid == 0) {
-            const double oN = s2;
-            d.u[bc.tix] = oN;
+            const double oN = s2, lN = d.scl ? d.scl[bc.tix] : 1.0;
+            d.u[bc.tix] = lN * oN;
             d.rhs[bc.tix] = oN;
-            const double beta = sqrt(s0 + oN * oN);
+            const double beta = sqrt(s0 + lN * oN * lN * oN);
             S->beta = beta; S->beta1 = beta; S->phibar = beta; S->dot_adj = s1;
             if (!(beta > 0.0)) { S->done = 1; S->conv = 1; }
         }
@@ -289,40 +312,21 @@ __device__ void solve_one(const BatchDev &d, int dir, int b, LsqrState *S, doubl
             blk_fused_FT(p, d, t, c, bc, sm, s0, s1);
             blk_reduce_finalize(S, ROLE_V0, s0, s1, 0.0, true);
         }
-        while (!S->done) {
-            StepArgs f = base;  // u~ <- F(sc o v) - alpha u~ (with the owed x, w update)
-            f.in = d.v; f.in_nrm = NRM_ALPHA; f.in_is_v = 1; f.out = d.u; f.role = ROLE_U; f.do_update = 1;
-            {
-                const Ctx c = make_ctx(f, bc.tix);
-                s0 = s1 = 0.0;
-                blk_rows_F(p, f, c, bc, s0, s1);
-            }
-            blk_reduce_finalize(S, ROLE_U, s0, s1, 0.0, false);
-            if (S->done) break;
-            StepArgs t = base;  // v~ <- sc o F'u - beta v~, J(sc o v~)
-            t.in = d.u; t.in_nrm = NRM_BETA; t.out = d.v; t.role = ROLE_V; t.out_is_v = 1; t.do_pre = 1;
-            {
-                const Ctx c = make_ctx(t, bc.tix);
-                s0 = s1 = 0.0;
-                blk_fused_FT(p, d, t, c, bc, sm, s0, s1);
-            }
-            blk_reduce_finalize(S, ROLE_V, s0, s1, 0.0, true);
-        }
     } else {
         blk_vjp_rhs(p, d, bc, i0, i1, i2, sm, s0, s2);
         block_sum3(s0, s1, s2);
         if (tid == 0) {
-            const double oN = s2;
-            d.u[bc.tix] = oN;
+            const double oN = s2, lN = d.scl ? d.scl[bc.tix] : 1.0;
+            d.u[bc.tix] = lN * oN;
             d.rhs[bc.tix] = oN;
-            const double beta = sqrt(s0 + oN * oN);
+            const double beta = sqrt(s0 + lN * oN * lN * oN);
             S->beta = beta; S->beta1 = beta; S->phibar = beta;
             if (!(beta > 0.0)) { S->done = 1; S->conv = 1; }
         }
         __syncthreads();
         if (!S->done) {  // J(u~) and the F tau-row dot, then v~ = sc o F u
             s1 = 0.0;
-            blk_pre(p, d, d.u, nullptr, bc, sm, s1);
+            blk_pre(p, d, d.u, d.scl, d.wy, bc, sm, s1);
             block_sum3(s0, s1, s2);
             if (tid == 0) S->dot_fwd = s1;
             __syncthreads();
@@ -333,27 +337,23 @@ __device__ void solve_one(const BatchDev &d, int dir, int b, LsqrState *S, doubl
             blk_rows_F(p, f, c, bc, s0, s1);
             blk_reduce_finalize(S, ROLE_V0, s0, s1, 0.0, false);
         }
-        while (!S->done) {
-            StepArgs t = base;  // u~ <- F'(sc o v) - alpha u~ (with the owed update), J(u~)
-            t.in = d.v; t.in_nrm = NRM_ALPHA; t.in_is_v = 1; t.out = d.u; t.role = ROLE_U;
-            t.do_update = 1; t.do_pre = 1;
-            {
-                const Ctx c = make_ctx(t, bc.tix);
-                s0 = s1 = 0.0;
-                blk_fused_FT(p, d, t, c, bc, sm, s0, s1);
-            }
-            blk_reduce_finalize(S, ROLE_U, s0, s1, 0.0, true);
-            if (S->done) break;
-            StepArgs f = base;  // v~ <- sc o F u - beta v~
-            f.in = d.u; f.in_nrm = NRM_BETA; f.out = d.v; f.role = ROLE_V; f.out_is_v = 1;
-            {
-                const Ctx c = make_ctx(f, bc.tix);
-                s0 = s1 = 0.0;
-                blk_rows_F(p, f, c, bc, s0, s1);
-            }
-            blk_reduce_finalize(S, ROLE_V, s0, s1, 0.0, false);
-        }
     }
+}
+
+// One problem's evaluation after its LSQR loop (final state in S): the owed update, the
+// explicit residual and the outputs.
+__device__ void solve_end(const BatchDev &d, int dir, int b, LsqrState *S, double *sm,
+                          double *o0, double *o1, double *o2, double *o3) {
+    const Problem &p = d.p;
+    const int tid = threadIdx.x, n = p.n;
+    const BCtx bc = bctx_of(d, b);
+    auto each_index = [&](auto f) {
+        for (int i = bc.n0 + tid; i < bc.n1; i += kBlock) f(i);
+        for (int r = bc.m0 + tid; r < bc.m1; r += kBlock) f(n + r);
+        if (tid == 0) f(bc.tix);
+    };
+    const StepArgs base = base_of(d, S);
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     // owed x update, sol = sc o x, q'sol_x + b'sol_y for a product with F'
     {
         const bool pend = S->pending != 0;
@@ -376,12 +376,13 @@ __device__ void solve_one(const BatchDev &d, int dir, int b, LsqrState *S, doubl
     if (dir == 0) {
         // explicit residual ||F sol + d|| and (dx, dy, ds) = D phi sol
         s1 = 0.0;
-        blk_pre(p, d, d.sol, nullptr, bc, sm, s1);
+        blk_pre(p, d, d.sol, nullptr, d.wy_res, bc, sm, s1);
         s0 = s2 = 0.0;
         block_sum3(s0, s1, s2);
         if (tid == 0) S->dot_fwd = s1;
         __syncthreads();
-        StepArgs f = base;
+        StepArgs f = base;  // the unscaled operator
+        f.sc = nullptr; f.scl = nullptr; f.wy = d.wy_res;
         f.in = d.sol; f.in_nrm = NRM_ONE; f.out = d.scratch; f.role = ROLE_RESID;
         {
             const Ctx c = make_ctx(f, bc.tix);
@@ -392,13 +393,14 @@ __device__ void solve_one(const BatchDev &d, int dir, int b, LsqrState *S, doubl
         const double dzN = d.sol[bc.tix];
         for (int i = bc.n0 + tid; i < bc.n1; i += kBlock) o0[i] = d.sol[i] - dzN * p.x[i];
         for (int r = bc.m0 + tid; r < bc.m1; r += kBlock) {
-            const double jd = d.wy[r];
+            const double jd = d.wy_res[r];
             o1[r] = jd - dzN * p.y[r];
             o2[r] = jd - d.sol[n + r] - dzN * p.s[r];
         }
     } else {
         // explicit residual ||F'sol + dz|| and dtheta = D_theta N'[sol]
-        StepArgs t = base;
+        StepArgs t = base;  // the unscaled operator
+        t.sc = nullptr; t.scl = nullptr;
         t.in = d.sol; t.in_nrm = NRM_ONE; t.out = d.scratch; t.role = ROLE_RESID;
         {
             const Ctx c = make_ctx(t, bc.tix);
@@ -443,23 +445,147 @@ __device__ void solve_one(const BatchDev &d, int dir, int b, LsqrState *S, doubl
     __syncthreads();
 }
 
-__global__ __launch_bounds__(kBlock) void k_batch_solve(BatchDev d, int dir, const double *i0,
+// Begin and end phases: persistent workgroups taking problems from queue[q] (longest first).
+__device__ inline int next_problem(const BatchDev &d, int q) {
+    __shared__ int next;
+    if (threadIdx.x == 0) {
+        const int t = atomicAdd(d.queue + q, 1);
+        next = t < d.B ? d.order[t] : -1;
+    }
+    __syncthreads();
+    const int b = next;
+    __syncthreads();
+    return b;
+}
+
+__global__ __launch_bounds__(kBlock) void k_batch_begin(BatchDev d, int dir, const double *i0,
                                                         const double *i1, const double *i2,
-                                                        const double *i3, double *o0, double *o1,
-                                                        double *o2, double *o3) {
+                                                        const double *i3, LsqrState *st_loop,
+                                                        int *ndone) {
     extern __shared__ double sm[];
     __shared__ LsqrState S;
-    __shared__ int next;
-    for (;;) {
+    for (int b = next_problem(d, 0); b >= 0; b = next_problem(d, 0)) {
+        solve_begin(d, dir, b, &S, sm, i0, i1, i2, i3);
         if (threadIdx.x == 0) {
-            const int t = atomicAdd(d.queue, 1);
-            next = t < d.B ? d.order[t] : -1;
+            LsqrState s = S;
+            s.pend_role = -1;  // the first product finalised its own reduction
+            st_loop[b] = s;
+            if (s.done) atomicAdd(ndone, 1);
         }
         __syncthreads();
-        const int b = next;
+    }
+}
+
+// With a row scaling the LSQR stopping test sees the scaled residual: a problem whose
+// explicit (unscaled) relative residual is above tol resumes its LSQR from its loop state with
+// a tighter internal tolerance (at most a few times, as the single-problem path does).
+__global__ __launch_bounds__(kBlock) void k_batch_end(BatchDev d, int dir, double *o0, double *o1,
+                                                      double *o2, double *o3, LsqrState *st0,
+                                                      LsqrState *st1, int only_resumed,
+                                                      int allow_resume) {
+    extern __shared__ double sm[];
+    __shared__ LsqrState S;
+    for (int b = next_problem(d, 1); b >= 0; b = next_problem(d, 1)) {
+        if (only_resumed && !d.resume[b]) continue;
+        if (threadIdx.x == 0) S = st0[b];
         __syncthreads();
-        if (b < 0) break;
-        solve_one(d, dir, b, &S, sm, i0, i1, i2, i3, o0, o1, o2, o3);
+        const LsqrState loop_state = S;
+        solve_end(d, dir, b, &S, sm, o0, o1, o2, o3);
+        if (threadIdx.x == 0) {
+            const double rel = S.tau_rhs > 0.0 ? S.resid / S.tau_rhs : 0.0;
+            const bool again = allow_resume && d.scl && !(rel <= d.tol) && loop_state.conv &&
+                               loop_state.iters < loop_state.max_iter && loop_state.tol > 0.0;
+            d.resume[b] = again ? 1 : 0;
+            if (again) {
+                LsqrState r = loop_state;
+                r.tol *= fmax(0.02, 0.5 * d.tol / rel);
+                r.done = 0;
+                r.conv = 0;
+                r.phr = 0.0;       // the owed x update was applied above
+                r.pending = 0;
+                r.pend_role = -1;
+                st0[b] = r;
+                st1[b] = r;
+                atomicAdd(d.nresumed, 1);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// One two-sided 2-norm balancing sweep of every problem's F with each cone block's Jacobian
+// replaced by its diagonal (see k_equil_sweep of the single-problem path), one workgroup per
+// problem: its x rows (P, A'), y rows (A) and its own tau row and column.
+__global__ __launch_bounds__(kBlock) void k_batch_equil_sweep(BatchDev d, const double *DL,
+                                                              const double *DR, double *DLo,
+                                                              double *DRo) {
+    const Problem &p = d.p;
+    const BCtx bc = bctx_of(d, blockIdx.x);
+    const int n = p.n, tid = threadIdx.x, tix = bc.tix;
+    const double dlN = DL[tix], drN = DR[tix];
+    auto upd = [&](int i, double rsum, double csum) {
+        const double rn = DL[i] * sqrt(rsum), cn = DR[i] * sqrt(csum);
+        DLo[i] = rn > 0.0 ? DL[i] / sqrt(rn) : DL[i];
+        DRo[i] = cn > 0.0 ? DR[i] / sqrt(cn) : DR[i];
+    };
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    {
+        const int L = bc.lx, lane = tid & (L - 1), grp = tid / L, ngrp = kBlock / L;
+        for (int rb = bc.n0; rb < bc.n1; rb += ngrp) {
+            const int row = rb + grp;
+            double rs = 0.0, cs = 0.0;
+            if (row < bc.n1) {
+                for (int k = p.Prp[row] + lane; k < p.Prp[row + 1]; k += L) {
+                    const double v2 = p.Pv[k] * p.Pv[k];
+                    const int j = p.Pci[k];
+                    rs += v2 * DR[j] * DR[j];
+                    cs += v2 * DL[j] * DL[j];
+                }
+                for (int t = p.Trp[row] + lane; t < p.Trp[row + 1]; t += L) {
+                    const int r = p.Tci[t];
+                    const double v2 = p.Tv[t] * p.Tv[t], jd = p.jdiag[r];
+                    rs += v2 * jd * jd * DR[n + r] * DR[n + r];
+                    cs += v2 * DL[n + r] * DL[n + r];
+                }
+            }
+            rs = group_sum(rs, L);
+            cs = group_sum(cs, L);
+            if (row < bc.n1 && lane == 0) {
+                const double q = p.q[row], c = p.c[row];
+                upd(row, rs + q * q * drN * drN, cs + c * c * dlN * dlN);
+                s0 += c * c * DR[row] * DR[row];
+                s1 += q * q * DL[row] * DL[row];
+            }
+        }
+    }
+    {
+        const int L = bc.ly, lane = tid & (L - 1), grp = tid / L, ngrp = kBlock / L;
+        for (int rb = bc.m0; rb < bc.m1; rb += ngrp) {
+            const int r = rb + grp;
+            double rs = 0.0, cs = 0.0;
+            if (r < bc.m1)
+                for (int k = p.Arp[r] + lane; k < p.Arp[r + 1]; k += L) {
+                    const double v2 = p.Av[k] * p.Av[k];
+                    const int j = p.Aci[k];
+                    rs += v2 * DR[j] * DR[j];
+                    cs += v2 * DL[j] * DL[j];
+                }
+            rs = group_sum(rs, L);
+            cs = group_sum(cs, L);
+            if (r < bc.m1 && lane == 0) {
+                const int i = n + r;
+                const double jd = p.jdiag[r], bb = p.b[r], o = 1.0 - jd;
+                upd(i, rs + o * o * DR[i] * DR[i] + bb * bb * drN * drN,
+                    jd * jd * cs + o * o * DL[i] * DL[i] + bb * bb * jd * jd * dlN * dlN);
+                s0 += bb * bb * jd * jd * DR[i] * DR[i];
+                s1 += bb * bb * DL[i] * DL[i];
+            }
+        }
+    }
+    block_sum3(s0, s1, s2);
+    if (tid == 0) {
+        const double x2 = bc.xPx * bc.xPx;
+        upd(tix, s0 + x2 * drN * drN, s1 + x2 * dlN * dlN);
     }
 }
 
@@ -562,13 +688,26 @@ struct qcpd_batch {
     int grid = 0;
     int grid_default = 0;  // all workgroups that fit on the device at once (capped at B)
     std::vector<void *> allocs;
-    double *scale[2] = {nullptr, nullptr};
+    double *scale[2] = {nullptr, nullptr};  // Jacobi: [0] columns of F, [1] columns of F'
+    double *equil[2] = {nullptr, nullptr};  // two-sided equilibration: [0] columns, [1] rows
+    const double *graph_scl[2] = {nullptr, nullptr};
     int nnzP = 0, nnzA = 0;
     int *flag = nullptr, *host_flag = nullptr;
     LsqrState *st = nullptr;
     std::vector<LsqrState> host_st;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     uint32_t create_flags = 0;
+    // segmented LSQR loop
+    hipStream_t cap = nullptr;  // private stream used only for graph capture
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    int graph_chunk[2] = {0, 0};
+    const double *graph_sc[2] = {nullptr, nullptr};
+    SegGrid seg{};
+    int lds_seg = 0;
+    LsqrState *stl[2] = {nullptr, nullptr};  // one state per problem, double-buffered
+    double *spart[2] = {nullptr, nullptr};   // per-item partial sums, double-buffered
+    int *host_ndone = nullptr;               // pinned
+    std::vector<int> nb_rows;                // n + m + 1 per problem
 };
 
 namespace {
@@ -619,6 +758,10 @@ void free_batch(qcpd_batch *h) {
     if (!h) return;
     for (void *p : h->allocs) hipFree(p);
     if (h->host_flag) hipHostFree(h->host_flag);
+    if (h->host_ndone) hipHostFree(h->host_ndone);
+    for (int d = 0; d < 2; ++d)
+        if (h->graph[d]) hipGraphExecDestroy(h->graph[d]);
+    if (h->cap) hipStreamDestroy(h->cap);
     if (h->ev0) hipEventDestroy(h->ev0);
     if (h->ev1) hipEventDestroy(h->ev1);
     delete h;
@@ -751,6 +894,40 @@ qcpd_status batch_create_impl(qcpd_batch *h, const qcpd_batch_layout *L, const i
         u_off[b + 1] = (int)units.size();
         cost[b] = 12.0 * (L->nnz_P[b] + 2.0 * L->nnz_A[b]) + 40.0 * (nb + mb) + psd_cost;
     }
+    // work items of the segmented loop, grouped by problem: the product with F over chunks of
+    // x rows and of y rows; the fused product with F' over PSD cones (longest first), runs of
+    // exponential and SOC cones, chunks of diagonal rows and of x rows
+    std::vector<SegItem> fitems;
+    std::vector<Unit> tunits;
+    std::vector<int> tprob, foff(B + 1, 0), toff(B + 1, 0);
+    h->nb_rows.resize(B);
+    for (int b = 0; b < B; ++b) {
+        const int rx = kBlock / lx[b], ry = kBlock / ly[b];
+        h->nb_rows[b] = L->n[b] + L->m[b] + 1;
+        for (int r = n_off[b]; r < n_off[b + 1]; r += rx)
+            fitems.push_back({0, r, std::min(n_off[b + 1], r + rx), b});
+        for (int r = m_off[b]; r < m_off[b + 1]; r += ry)
+            fitems.push_back({1, r, std::min(m_off[b + 1], r + ry), b});
+        foff[b + 1] = (int)fitems.size();
+        std::vector<Unit> mine(units.begin() + u_off[b], units.begin() + u_off[b + 1]);
+        std::stable_sort(mine.begin(), mine.end(), [&](const Unit &x, const Unit &y) {
+            auto rank = [](int t) { return t == U_PSD ? 0 : t == U_EXP ? 1 : t == U_SOC ? 2 : t == U_DIAG ? 3 : 4; };
+            return rank(x.type) < rank(y.type);
+        });
+        for (const Unit &u : mine) {
+            if (u.type == U_XROWS || u.type == U_DIAG) {
+                const int step = u.type == U_XROWS ? rx : ry;
+                for (int r = u.begin; r < u.end; r += step) {
+                    tunits.push_back({u.type, r, std::min(u.end, r + step), 0});
+                    tprob.push_back(b);
+                }
+            } else {
+                tunits.push_back(u);
+                tprob.push_back(b);
+            }
+        }
+        toff[b + 1] = (int)tunits.size();
+    }
     // longest problems first (a greedy longest-processing-time schedule for the queue)
     std::vector<int> order(B);
     std::iota(order.begin(), order.end(), 0);
@@ -802,22 +979,113 @@ qcpd_status batch_create_impl(qcpd_batch *h, const qcpd_batch_layout *L, const i
     BatchDev &d = h->d;
     d.B = B; d.n_off = d_noff; d.m_off = d_moff; d.u_off = d_uoff; d.lxs = d_lx; d.lys = d_ly;
     d.units = d_units; d.xPx = xpx; d.order = d_order;
-    BALLOC(d.queue, 1);
+    BALLOC(d.queue, 2);
     BALLOC(d.u, NT); BALLOC(d.v, NT); BALLOC(d.xk, NT); BALLOC(d.wk, NT); BALLOC(d.rhs, NT);
-    BALLOC(d.sol, NT); BALLOC(d.scratch, NT); BALLOC(d.wy, m);
+    BALLOC(d.sol, NT); BALLOC(d.scratch, NT); BALLOC(d.wy, m); BALLOC(d.wy_res, m);
+    BALLOC(d.resume, B); BALLOC(d.nresumed, 1);
+    BCHK(hipMemsetAsync(d.resume, 0, sizeof(int) * B, st));
+    // two-sided equilibration of every problem (even number of sweeps: ends in equil[])
+    {
+        double *tl, *tr;
+        BALLOC(h->equil[0], NT); BALLOC(h->equil[1], NT); BALLOC(tl, NT); BALLOC(tr, NT);
+        launch_fill(h->equil[0], NT, 1.0, st);
+        launch_fill(h->equil[1], NT, 1.0, st);
+        BatchDev de = d;
+        de.p = p;
+        for (int k = 0; k < 20; ++k) {
+            const bool even = (k % 2) == 0;
+            hipLaunchKernelGGL(k_batch_equil_sweep, dim3(B), dim3(kBlock), 0, st, de,
+                               even ? h->equil[1] : tl, even ? h->equil[0] : tr,
+                               even ? tl : h->equil[1], even ? tr : h->equil[0]);
+        }
+        BCHK(hipGetLastError());
+    }
     BALLOC(h->st, B);
     d.st_out = h->st;
     h->host_st.resize(B);
     h->lds = fused_lds_bytes(kmax);
-    hipFuncSetAttribute((const void *)k_batch_solve, hipFuncAttributeMaxDynamicSharedMemorySize, h->lds);
+    BCHK(hipFuncSetAttribute((const void *)k_batch_begin, hipFuncAttributeMaxDynamicSharedMemorySize, h->lds));
+    BCHK(hipFuncSetAttribute((const void *)k_batch_end, hipFuncAttributeMaxDynamicSharedMemorySize, h->lds));
+    // the segmented loop
+    {
+        SegItem *d_fitems;
+        Unit *d_tunits;
+        int *d_tprob, *d_foff, *d_toff;
+        UPLOAD(d_fitems, fitems); UPLOAD(d_tunits, tunits); UPLOAD(d_tprob, tprob);
+        UPLOAD(d_foff, foff); UPLOAD(d_toff, toff);
+        SegGrid &g = h->seg;
+        g.B = B; g.nf = (int)fitems.size(); g.nt = (int)tunits.size();
+        g.fitems = d_fitems; g.foff = d_foff; g.tunits = d_tunits; g.tprob = d_tprob; g.toff = d_toff;
+        g.lxs = d_lx; g.lys = d_ly; g.xPx = xpx;
+        BALLOC(g.ndone, 1);
+        const int slots = std::max(g.nf, g.nt);
+        BALLOC(h->spart[0], 3LL * slots); BALLOC(h->spart[1], 3LL * slots);
+        BALLOC(h->stl[0], B); BALLOC(h->stl[1], B);
+        h->lds_seg = loop_lds_bytes(psd_k.data(), (int)psd_k.size());
+        set_seg_kernel_lds(h->lds_seg);
+        if (hipHostMalloc((void **)&h->host_ndone, sizeof(int), hipHostMallocDefault) != hipSuccess)
+            return QCPD_ERR_OOM;
+        BCHK(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+    }
     int dev = 0, ncu = 0, per_cu = 0;
     BCHK(hipGetDevice(&dev));
     BCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    BCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_batch_solve, kBlock, h->lds));
+    BCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_batch_begin, kBlock, h->lds));
     h->grid = std::max(1, std::min(B, ncu * std::max(per_cu, 1)));
     h->grid_default = h->grid;
     h->create_flags = h->host_flag[4] ? 2u : 0u;
     return h->host_flag[4] ? QCPD_WARN_NONDIFF : QCPD_OK;
+}
+
+// One LSQR iteration of every problem (two launches, states and partials double-buffered).
+void enqueue_seg_iteration(const qcpd_batch *h, int dir, hipStream_t s) {
+    const BatchDev &d = h->d;
+    StepArgs a{};
+    a.sc = d.sc; a.scl = d.scl; a.wy = d.wy; a.xk = d.xk; a.wk = d.wk;
+    StepArgs first = a, second = a;
+    first.st = h->stl[0]; first.st_next = h->stl[1]; first.part_prev = h->spart[0]; first.part_next = h->spart[1];
+    second.st = h->stl[1]; second.st_next = h->stl[0]; second.part_prev = h->spart[1]; second.part_next = h->spart[0];
+    if (dir == 0) {
+        StepArgs &f = first;  // u~ <- F(sc o v) - alpha u~ (and the owed x, w update)
+        f.in = d.v; f.in_nrm = NRM_ALPHA; f.in_is_v = 1; f.out = d.u; f.role = ROLE_U; f.do_update = 1;
+        launch_seg_F(d.p, f, h->seg, s);
+        StepArgs &t = second;  // v~ <- sc o F'u - beta v~, then J(sc o v~)
+        t.in = d.u; t.in_nrm = NRM_BETA; t.out = d.v; t.role = ROLE_V; t.out_is_v = 1; t.do_pre = 1;
+        launch_seg_FT(d.p, t, h->seg, h->lds_seg, s);
+    } else {
+        StepArgs &t = first;  // u~ <- F'(sc o v) - alpha u~ (and the owed update), J(u~)
+        t.in = d.v; t.in_nrm = NRM_ALPHA; t.in_is_v = 1; t.out = d.u; t.role = ROLE_U;
+        t.do_update = 1; t.do_pre = 1;
+        launch_seg_FT(d.p, t, h->seg, h->lds_seg, s);
+        StepArgs &f = second;  // v~ <- sc o F u - beta v~
+        f.in = d.u; f.in_nrm = NRM_BETA; f.out = d.v; f.role = ROLE_V; f.out_is_v = 1;
+        launch_seg_F(d.p, f, h->seg, s);
+    }
+}
+
+qcpd_status seg_graph(qcpd_batch *h, int dir) {
+    const int chunk = std::max(1, h->opts.graph_chunk);
+    if (h->graph[dir] && h->graph_chunk[dir] == chunk && h->graph_sc[dir] == h->d.sc &&
+        h->graph_scl[dir] == h->d.scl)
+        return QCPD_OK;
+    if (h->graph[dir]) {
+        hipGraphExecDestroy(h->graph[dir]);
+        h->graph[dir] = nullptr;
+    }
+    hipGraph_t g = nullptr;
+    BCHK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+    for (int i = 0; i < chunk; ++i) enqueue_seg_iteration(h, dir, h->cap);
+    BCHK(hipStreamEndCapture(h->cap, &g));
+    const hipError_t e = hipGraphInstantiate(&h->graph[dir], g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        h->graph[dir] = nullptr;
+        return QCPD_ERR_HIP;
+    }
+    h->graph_chunk[dir] = chunk;
+    h->graph_sc[dir] = h->d.sc;
+    h->graph_scl[dir] = h->d.scl;
+    return QCPD_OK;
 }
 
 qcpd_status batch_run(qcpd_batch *h, int dir, const double *i0, const double *i1, const double *i2,
@@ -825,13 +1093,45 @@ qcpd_status batch_run(qcpd_batch *h, int dir, const double *i0, const double *i1
                       qcpd_info *info) {
     hipStream_t s = h->stream;
     BCHK(hipEventRecord(h->ev0, s));
-    h->d.sc = (h->opts.precond == QCPD_PRECOND_NONE) ? nullptr : h->scale[dir];
+    switch (h->opts.precond) {  // as the single-problem path: the VJP swaps the two sides
+    case QCPD_PRECOND_JACOBI: h->d.sc = h->scale[dir]; h->d.scl = nullptr; break;
+    case QCPD_PRECOND_EQUIL: h->d.sc = h->equil[dir]; h->d.scl = h->equil[1 - dir]; break;
+    default: h->d.sc = nullptr; h->d.scl = nullptr; break;
+    }
     h->d.tol = h->opts.tol;
     h->d.max_iter = h->opts.max_iter;
-    BCHK(hipMemsetAsync(h->d.queue, 0, sizeof(int), s));
-    hipLaunchKernelGGL(k_batch_solve, dim3(h->grid), dim3(kBlock), h->lds, s, h->d, dir, i0, i1, i2,
-                       i3, o0, o1, o2, o3);
+    qcpd_status rc = seg_graph(h, dir);
+    if (rc != QCPD_OK) return rc;
+    BCHK(hipMemsetAsync(h->d.queue, 0, 2 * sizeof(int), s));
+    BCHK(hipMemsetAsync(h->seg.ndone, 0, sizeof(int), s));
+    hipLaunchKernelGGL(k_batch_begin, dim3(h->grid), dim3(kBlock), h->lds, s, h->d, dir, i0, i1, i2,
+                       i3, h->stl[0], h->seg.ndone);
     BCHK(hipGetLastError());
+    // iterate until every problem's LSQR has stopped (each stops by its own iteration cap at
+    // the latest)
+    long long cap_iter = 0;
+    for (int b = 0; b < h->d.B; ++b)
+        cap_iter = std::max<long long>(cap_iter, h->opts.max_iter > 0 ? h->opts.max_iter : 100LL * h->nb_rows[b]);
+    const long long max_launch = cap_iter / h->graph_chunk[dir] + 4;
+    for (int round = 0;; ++round) {
+        for (long long l = 0;; ++l) {
+            BCHK(hipMemcpyAsync(h->host_ndone, h->seg.ndone, sizeof(int), hipMemcpyDeviceToHost, s));
+            BCHK(hipStreamSynchronize(s));
+            if (*h->host_ndone >= h->d.B || l >= max_launch) break;
+            BCHK(hipGraphLaunch(h->graph[dir], s));
+        }
+        BCHK(hipMemsetAsync(h->d.queue + 1, 0, sizeof(int), s));
+        BCHK(hipMemsetAsync(h->d.nresumed, 0, sizeof(int), s));
+        hipLaunchKernelGGL(k_batch_end, dim3(h->grid), dim3(kBlock), h->lds, s, h->d, dir, o0, o1,
+                           o2, o3, h->stl[0], h->stl[1], round > 0 ? 1 : 0, round < 8 ? 1 : 0);
+        BCHK(hipGetLastError());
+        BCHK(hipMemcpyAsync(h->host_ndone, h->d.nresumed, sizeof(int), hipMemcpyDeviceToHost, s));
+        BCHK(hipStreamSynchronize(s));
+        const int resumed = *h->host_ndone;
+        if (resumed == 0) break;
+        *h->host_ndone = h->d.B - resumed;  // the resumed problems count as running again
+        BCHK(hipMemcpyAsync(h->seg.ndone, h->host_ndone, sizeof(int), hipMemcpyHostToDevice, s));
+    }
     BCHK(hipEventRecord(h->ev1, s));
     BCHK(hipMemcpyAsync(h->host_st.data(), h->st, sizeof(LsqrState) * h->d.B, hipMemcpyDeviceToHost, s));
     BCHK(hipStreamSynchronize(s));
@@ -844,7 +1144,7 @@ qcpd_status batch_run(qcpd_batch *h, int dir, const double *i0, const double *i1
         if (info) {
             info[b].iters = st.iters;
             info[b].est_residual = st.beta1 > 0.0 ? st.phibar / st.beta1 : 0.0;
-            info[b].rel_residual = st.beta1 > 0.0 ? st.resid / st.beta1 : 0.0;
+            info[b].rel_residual = st.tau_rhs > 0.0 ? st.resid / st.tau_rhs : 0.0;
             info[b].flags = (st.conv ? 0u : 1u) | h->create_flags;
             info[b].ms_total = ms;
         }
@@ -891,7 +1191,9 @@ qcpd_status qcpd_batch_create(qcpd_batch **out, const qcpd_batch_layout *L, cons
     qcpd_opts o;
     qcpd_opts_default(&o);
     if (opts) o = *opts;
-    if (!(o.tol >= 0.0) || o.max_iter < 0 || o.precond < QCPD_PRECOND_NONE || o.precond > QCPD_PRECOND_JACOBI)
+    if (!(o.tol >= 0.0) || o.max_iter < 0 ||
+        (o.precond != QCPD_PRECOND_NONE && o.precond != QCPD_PRECOND_JACOBI &&
+         o.precond != QCPD_PRECOND_EQUIL) || o.graph_chunk < 1 || o.graph_chunk > 4096)
         return QCPD_ERR_INVALID_ARG;
     qcpd_batch *h = new (std::nothrow) qcpd_batch();
     if (!h) return QCPD_ERR_OOM;
@@ -929,7 +1231,8 @@ qcpd_status qcpd_batch_vjp(qcpd_batch *h, const double *gx, const double *gy, co
 
 qcpd_status qcpd_batch_set_opts(qcpd_batch *h, const qcpd_opts *opts) {
     if (!h || !opts || !(opts->tol >= 0.0) || opts->max_iter < 0 ||
-        opts->precond < QCPD_PRECOND_NONE || opts->precond > QCPD_PRECOND_JACOBI)
+        (opts->precond != QCPD_PRECOND_NONE && opts->precond != QCPD_PRECOND_JACOBI &&
+         opts->precond != QCPD_PRECOND_EQUIL) || opts->graph_chunk < 1 || opts->graph_chunk > 4096)
         return QCPD_ERR_INVALID_ARG;
     h->opts = *opts;
     return QCPD_OK;

@@ -769,6 +769,167 @@ __global__ __launch_bounds__(kBlock) void k_loop_FT(Problem p, StepArgs a, Fused
 }
 
 // ---------------------------------------------------------------------------------------
+// segmented form: the LSQR loops of many problems (the batch, one block-diagonal union)
+// advanced together. Every work item belongs to one problem; each problem has its own state
+// (double-buffered, one per problem) and reduces its own items' partial sums, in item order,
+// at the entry of the next launch. Items of finished problems exit at entry; the first item
+// of a problem counts the problem in *ndone when its stop decision is taken.
+// ---------------------------------------------------------------------------------------
+
+struct SegEntry {
+    LsqrState st;
+    double pa[kPartRegs], pb[kPartRegs];
+    int c0, cnt;  // the problem's partial slots in the previous launch
+};
+
+__device__ inline void seg_entry_issue(const StepArgs &a, int b, const int *prev_off, SegEntry &e) {
+    e.st = a.st[b];
+    e.c0 = prev_off[b];
+    e.cnt = prev_off[b + 1] - e.c0;
+#pragma unroll
+    for (int j = 0; j < kPartRegs; ++j) {
+        const int i = threadIdx.x + j * kBlock;
+        const int slot = e.c0 + min(i, max(e.cnt - 1, 0));  // in bounds; masked below
+        e.pa[j] = a.part_prev[3 * slot];
+        e.pb[j] = a.part_prev[3 * slot + 1];
+    }
+}
+
+__device__ inline bool seg_entry_finish(const StepArgs &a, const SegEntry &e, int b, bool first,
+                                        int *ndone, LsqrState *S, int my_fwd) {
+    const int tid = threadIdx.x;
+    if (e.st.done) {
+        if (first && tid == 0) a.st_next[b] = e.st;
+        return false;
+    }
+    double t0 = 0.0, t1 = 0.0;
+    if (e.st.pend_role >= 0) {
+#pragma unroll
+        for (int j = 0; j < kPartRegs; ++j)
+            if (tid + j * kBlock < e.cnt) {
+                t0 += e.pa[j];
+                t1 += e.pb[j];
+            }
+        for (int i = tid + kPartRegs * kBlock; i < e.cnt; i += kBlock) {  // very large problems
+            t0 += a.part_prev[3 * (e.c0 + i)];
+            t1 += a.part_prev[3 * (e.c0 + i) + 1];
+        }
+        block_sum2(t0, t1);
+    }
+    if (tid == 0) {
+        LsqrState s = e.st;
+        if (s.pend_role >= 0) finalize(&s, s.pend_role, t0, t1, s.pend_fwd != 0);
+        if (s.done) {
+            s.pend_role = -1;
+        } else {
+            s.pend_role = a.role;
+            s.pend_fwd = my_fwd;
+        }
+        if (first) {
+            a.st_next[b] = s;
+            if (s.done) {
+                a.st[b] = s;
+                atomicAdd(ndone, 1);
+            }
+        }
+        *S = s;
+    }
+    __syncthreads();
+    return !S->done;
+}
+
+// rows of one item of the product with F (x rows: P and A'wy; y rows: A), as rows_pre
+__device__ inline void seg_rows_pre(const Problem &p, const StepArgs &a, const Ptrs &q,
+                                    const SegItem &it, int L, RowPre &r) {
+    const int n = p.n;
+    const int tid = threadIdx.x, lane = tid & (L - 1), row = it.begin + tid / L;
+    double acc = 0.0, accT = 0.0;
+    if (row < it.end) {
+        if (it.type == 0) {
+            acc = csr_dot(p.Pci, p.Pv, p.Prp[row], p.Prp[row + 1], lane, L, a.in, q.isc, 0);
+            accT = csr_dot(p.Tci, p.Tv, p.Trp[row], p.Trp[row + 1], lane, L, a.wy, nullptr, 0);
+        } else {
+            acc = csr_dot(p.Aci, p.Av, p.Arp[row], p.Arp[row + 1], lane, L, a.in, q.isc, 0);
+        }
+    }
+    r.acc = group_sum_dpp(acc, L);
+    r.accT = group_sum_dpp(accT, L);
+    r.idx = (lane == 0 && row < it.end) ? (it.type == 0 ? row : n + row) : -1;
+    double qb = 0.0, self = 0.0, wyr = 0.0;
+    if (r.idx >= 0) {
+        fin_load(a, q, r.idx, r.f);
+        if (it.type == 0) {
+            qb = p.q[row];
+        } else {
+            qb = p.b[row];
+            self = in_raw(a, q, r.idx);
+            wyr = a.wy[row];
+        }
+    }
+    r.qb = qb;
+    r.self = self;
+    r.wyr = wyr;
+}
+
+__device__ inline void seg_rows_post(const StepArgs &a, const Ctx &c, const SegItem &it,
+                                     const RowPre &r, double &s0, double &s1) {
+    if (r.idx < 0) return;
+    const double val = it.type == 0 ? (r.acc + r.accT) * c.inv + r.qb * c.in_N
+                                    : (r.self - r.acc - r.wyr) * c.inv + r.qb * c.in_N;
+    const double o = fin_store(a, c, r.idx, r.f, val, s0);
+    s1 += r.qb * r.f.nxs * o;
+}
+
+__global__ __launch_bounds__(kBlock) void k_seg_F(Problem p, StepArgs a, SegGrid g) {
+    __shared__ LsqrState S;
+    const SegItem it = g.fitems[blockIdx.x];
+    const int b = it.prob;
+    const bool first = (int)blockIdx.x == g.foff[b];
+    SegEntry e;
+    seg_entry_issue(a, b, g.toff, e);
+    const Ptrs q = ptrs_of(a);
+    const int tix = p.n + p.m + b;
+    const double in_N_raw = in_raw(a, q, tix);
+    RowPre r;
+    seg_rows_pre(p, a, q, it, it.type == 0 ? g.lxs[b] : g.lys[b], r);
+    if (!seg_entry_finish(a, e, b, first, g.ndone, &S, 0)) return;
+    const Ctx c = scalars(a, S, q, in_N_raw);
+    double s0 = 0.0, s1 = 0.0;
+    seg_rows_post(a, c, it, r, s0, s1);
+    if (first && threadIdx.x == 0) {  // the problem's tau entry
+        Fin f;
+        fin_load(a, q, tix, f);
+        fin_store(a, c, tix, f, S.dot_fwd * c.inv + g.xPx[b] * c.in_N, s0);
+    }
+    leave(a, s0, s1);
+}
+
+__global__ __launch_bounds__(kBlock) void k_seg_FT(Problem p, StepArgs a, SegGrid g) {
+    extern __shared__ double sm[];
+    __shared__ LsqrState S;
+    const Unit u = g.tunits[blockIdx.x];
+    const int b = g.tprob[blockIdx.x];
+    const bool first = (int)blockIdx.x == g.toff[b];
+    SegEntry e;
+    seg_entry_issue(a, b, g.foff, e);
+    const Ptrs q = ptrs_of(a);
+    const int tix = p.n + p.m + b;
+    const double in_N_raw = in_raw(a, q, tix);
+    UnitPre P;
+    unit_pre(p, a, q, g.lxs[b], g.lys[b], u, sm, in_N_raw, P);
+    if (!seg_entry_finish(a, e, b, first, g.ndone, &S, 1)) return;
+    const Ctx c = scalars(a, S, q, in_N_raw);
+    double s0 = 0.0, s1 = 0.0;
+    unit_post(p, a, q, c, u, sm, P, s0, s1);
+    if (first && threadIdx.x == 0) {  // the problem's tau entry
+        Fin f;
+        fin_load(a, q, tix, f);
+        fin_store(a, c, tix, f, S.dot_adj * c.inv + g.xPx[b] * c.in_N, s0);
+    }
+    leave(a, s0, s1);
+}
+
+// ---------------------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------------------
 
@@ -792,6 +953,18 @@ void launch_loop_F(const Problem &p, const StepArgs &a, const RowGrid &g, int gr
 void launch_loop_FT(const Problem &p, const StepArgs &a, const FusedGrid &g, int lds, int grid,
                     hipStream_t s) {
     hipLaunchKernelGGL(k_loop_FT, dim3(grid), dim3(kBlock), lds, s, p, a, g);
+}
+
+void set_seg_kernel_lds(int bytes) {
+    (void)hipFuncSetAttribute((const void *)k_seg_FT, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+void launch_seg_F(const Problem &p, const StepArgs &a, const SegGrid &g, hipStream_t s) {
+    hipLaunchKernelGGL(k_seg_F, dim3(g.nf), dim3(kBlock), 0, s, p, a, g);
+}
+
+void launch_seg_FT(const Problem &p, const StepArgs &a, const SegGrid &g, int lds, hipStream_t s) {
+    hipLaunchKernelGGL(k_seg_FT, dim3(g.nt), dim3(kBlock), lds, s, p, a, g);
 }
 
 }  // namespace qcpd

@@ -237,6 +237,29 @@ void launch_vjp_out(const Problem &p, const RowGrid &g, const double *w, double 
 void launch_nan_scan(const double *const *ptrs, const long long *lens, int nseg, int *flag,
                      hipStream_t s);
 
+// segmented LSQR loop of a batch (loop.hip): items of the product with F (x rows or y rows
+// of one problem, at most kBlock / lanes rows) and units of the fused product with F' (each
+// within one problem, at most kBlock / lanes rows for x and diagonal units), both grouped by
+// problem; st / st_next of the StepArgs point to one state per problem.
+struct SegItem {
+    int type;  // 0: x rows, 1: y rows
+    int begin, end, prob;
+};
+struct SegGrid {
+    int B, nf, nt;
+    const SegItem *fitems;
+    const int *foff;      // B + 1: items of problem b are [foff[b], foff[b + 1])
+    const Unit *tunits;
+    const int *tprob;     // problem of each F' unit
+    const int *toff;      // B + 1
+    const int *lxs, *lys; // lanes per CSR row, per problem
+    const double *xPx;    // per problem
+    int *ndone;           // problems whose LSQR has stopped
+};
+void set_seg_kernel_lds(int bytes);
+void launch_seg_F(const Problem &p, const StepArgs &a, const SegGrid &g, hipStream_t s);
+void launch_seg_FT(const Problem &p, const StepArgs &a, const SegGrid &g, int lds, hipStream_t s);
+
 // the LSQR loop (loop.hip)
 int loop_lds_bytes(const int *psd_orders, int n_psd);
 void set_loop_kernel_lds(int bytes);

@@ -42,10 +42,14 @@ def split(v, sizes):
     return np.split(v, np.cumsum(sizes)[:-1])
 
 
-def test_batch_matches_oracle_uneven():
+PRECONDS = [Q.QCPD_PRECOND_JACOBI, Q.QCPD_PRECOND_EQUIL]
+
+
+@pytest.mark.parametrize("precond", PRECONDS)
+def test_batch_matches_oracle_uneven(precond):
     qs = uneven_small()
     bt = batch_to_device(qs)
-    h = Q.qcpd_batch_create(*batch_create_args(bt), opts=Q.Opts(tol=1e-12))
+    h = Q.qcpd_batch_create(*batch_create_args(bt), opts=Q.Opts(tol=1e-12, precond=precond))
     dx, dy, ds, infos, st = Q.qcpd_batch_jvp(h, bt["dP"], bt["dA"], bt["dq"], bt["db"])
     print("jvp iters", [i.iters for i in infos], "status", st, flush=True)
     assert st == Q.QCPD_OK
@@ -71,30 +75,33 @@ def test_batch_matches_oracle_uneven():
     h.close()
 
 
-def test_batch_of_one_matches_single_path():
+@pytest.mark.parametrize("precond", PRECONDS)
+def test_batch_of_one_matches_single_path(precond):
     q = qcpgen.small_mixed(0)
     bt = batch_to_device([q])
-    h = Q.qcpd_batch_create(*batch_create_args(bt), opts=Q.Opts(tol=1e-12))
+    h = Q.qcpd_batch_create(*batch_create_args(bt), opts=Q.Opts(tol=1e-12, precond=precond))
     dx, dy, ds, infos, st = Q.qcpd_batch_jvp(h, bt["dP"], bt["dA"], bt["dq"], bt["db"])
     from qcpgen.torch_io import cones_of, to_device
     t = to_device(q)
     hs = Q.qcpd_create(t["P"], t["A"], t["q"], t["b"], cones_of(q), t["x"], t["y"], t["s"],
-                       opts=Q.Opts(tol=1e-12))
+                       opts=Q.Opts(tol=1e-12, precond=precond))
     sx, sy, ss, info, st1 = Q.qcpd_jvp(hs, t["dP"], t["dA"], t["dq"], t["db"])
     for a, b in zip((dx, dy, ds), (sx, sy, ss)):
         assert rel(a.cpu().numpy(), b.cpu().numpy()) <= 1e-9
 
 
-def test_batch_family_members_properties():
-    """Members of the uneven 20 <= n <= 400 family at the benchmark tolerance: the adjoint
-    identity per problem."""
+@pytest.mark.parametrize("precond", PRECONDS)
+def test_batch_family_members_properties(precond):
+    """Members of the uneven 20 <= n <= 400 family at the benchmark tolerance: the explicit
+    relative residual of every problem and the adjoint identity per problem."""
     qs = [qcpgen.batch_member(i) for i in range(6)]
     bt = batch_to_device(qs)
-    h = Q.qcpd_batch_create(*batch_create_args(bt), opts=Q.Opts(tol=1e-8))
+    h = Q.qcpd_batch_create(*batch_create_args(bt), opts=Q.Opts(tol=1e-8, precond=precond))
     dx, dy, ds, i1, st = Q.qcpd_batch_jvp(h, bt["dP"], bt["dA"], bt["dq"], bt["db"])
     dP, dA, dq, db, i2, st2 = Q.qcpd_batch_vjp(h, bt["gx"], bt["gy"], bt["gs"])
     print("iters", [i.iters for i in i1], [i.iters for i in i2], st, st2, flush=True)
     assert st == Q.QCPD_OK and st2 == Q.QCPD_OK
+    assert max(i.rel_residual for i in i1 + i2) <= 1e-8
     parts = [split(t.cpu().numpy(), s) for t, s in
              ((dx, bt["n"]), (dy, bt["m"]), (ds, bt["m"]), (dP, bt["nnz_P"]), (dA, bt["nnz_A"]),
               (dq, bt["n"]), (db, bt["m"]))]
