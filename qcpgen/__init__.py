@@ -367,13 +367,37 @@ def mixed_qcp(idx=0) -> QCP:
     return qcp
 
 
+def _face_rows_independent(qcp) -> bool:
+    """The rows of A that the solution holds fixed (active nonnegative rows and every row of
+    an SOC whose s is zero) are linearly independent (a plain rank test on those rows)."""
+    A = qcp.A.toarray()
+    c = qcp.cones
+    rows = [i for i in range(c.n_zero, c.n_zero + c.n_nonneg) if qcp.s[i] == 0.0]
+    r = c.n_zero + c.n_nonneg
+    for k, st in zip(c.soc, qcp.meta.get("soc_states", [])):
+        if st == "y_int":
+            rows += list(range(r, r + k))
+        r += k
+    rows += list(range(c.n_zero))
+    return not rows or np.linalg.matrix_rank(A[rows]) == len(rows)
+
+
 def batch_member(idx=0) -> QCP:
     """One problem of the 512-problem uneven family: n ~ U{20..400}, m ~ U{1.5n..3n};
     rows PSD (k in 4..12) up to 15%, SOC (dims 3..8) up to 25%, rest nonneg; A density
-    0.05; P = BB' with B n x ceil(n/10) (dense P). Face codimension aimed at 0.85 n: at
-    0.95 n the reduced KKT matrix has condition numbers near 1e6, at 0.8 n about one seed in
-    six is singular."""
-    rng = np.random.default_rng([2, idx, 0])
+    0.05; P = BB' with B n x ceil(n/10) (dense P). Face codimension aimed at 0.92 n, inside
+    [0.9 n, n], so that the free directions (at most 0.1 n) do not outnumber the rank of P;
+    a draw whose fixed constraint rows are linearly dependent (small n with sparse A) is
+    replaced by the next draw of the same index."""
+    for attempt in range(16):
+        qcp = _batch_member_draw(idx, attempt)
+        if _face_rows_independent(qcp):
+            return qcp
+    return qcp
+
+
+def _batch_member_draw(idx, attempt) -> QCP:
+    rng = np.random.default_rng([2, idx, attempt])
     n = int(rng.integers(20, 401))
     m_target = int(rng.integers(math.ceil(1.5 * n), math.floor(3 * n) + 1))
     psd, soc = [], []
@@ -398,7 +422,7 @@ def batch_member(idx=0) -> QCP:
     Pd = 0.5 * (Pd + Pd.T)
     P = _csr(sp.csr_matrix(np.ones((n, n))))
     P.data = Pd.reshape(-1).copy()
-    target = int(round(0.85 * n))
+    target = int(round(0.92 * n))
     soc_states = [('s_int', 'y_int', 'bnd')[int(rng.integers(0, 3))] for _ in soc]
     psd_ranks = [int(rng.integers(1, max(2, k // 2 + 1))) for k in psd]
 
@@ -417,7 +441,7 @@ def batch_member(idx=0) -> QCP:
     qcp = build(rng, f"batch_member_{idx}", n, cones, A_density=0.05, P=P,
                 nonneg_active=n_act, soc_states=soc_states, psd_ranks=psd_ranks,
                 tol=1e-8)
-    qcp.meta["seed"] = [2, idx, 0]
+    qcp.meta["seed"] = [2, idx, attempt]
     return qcp
 
 
