@@ -48,6 +48,9 @@ struct qcpd_handle {
     LsqrState *st = nullptr;
     LsqrState *st2 = nullptr;                // second state buffer of the deferred loop
     double *lpart[2] = {nullptr, nullptr};   // per-block partials of the deferred loop
+    // values of P, A, A' with a scale folded into each entry (val * s[col]), for the loop
+    // kernels: [0] the column scale sc of the current solve, [1] the row scale scl
+    double *sval[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
     int loop_grid_F = 0, loop_grid_T = 0;    // workgroups of the two loop launches
     LsqrState *host_st = nullptr;            // pinned
     int *host_flag = nullptr;                // pinned
@@ -190,6 +193,37 @@ StepArgs base_args(const qcpd_handle *h, const double *sc, const double *scl = n
     return a;
 }
 
+// Fold the solve's scales into copies of the CSR values (once per solve: the loop kernels
+// then read one value per entry instead of a value and a gathered scale).
+qcpd_status bake_scales(qcpd_handle *h, const double *sc, const double *scl) {
+    const Problem &p = h->p;
+    const double *sv[2] = {sc, scl};
+    for (int j = 0; j < 2; ++j) {
+        if (!sv[j] || p.nnzP == 0 || p.nnzA == 0) continue;
+        if (!h->sval[j][0]) {
+            ALLOC(h->sval[j][0], p.nnzP);
+            ALLOC(h->sval[j][1], p.nnzA);
+            ALLOC(h->sval[j][2], p.nnzA);
+        }
+        launch_scale_vals(p.Pci, p.Pv, p.nnzP, sv[j], 0, h->sval[j][0], h->stream);
+        launch_scale_vals(p.Aci, p.Av, p.nnzA, sv[j], 0, h->sval[j][1], h->stream);
+        launch_scale_vals(p.Tci, p.Tv, p.nnzA, sv[j], p.n, h->sval[j][2], h->stream);
+    }
+    HIPCHK(hipGetLastError());
+    return QCPD_OK;
+}
+
+// the folded values for a loop launch's input scale (after bake_scales with the same scales)
+void set_baked(const qcpd_handle *h, StepArgs &a) {
+    const int j = a.in_is_v ? 0 : 1;
+    const double *isc = a.in_is_v ? a.sc : a.scl;
+    if (isc && h->sval[j][0]) {
+        a.Pvs = h->sval[j][0];
+        a.Avs = h->sval[j][1];
+        a.Tvs = h->sval[j][2];
+    }
+}
+
 // One LSQR iteration. JVP: the LSQR matrix is F diag(sc); VJP: it is F' diag(sc).
 // One LSQR iteration (two launches, deferred protocol). JVP: the LSQR matrix is F diag(sc),
 // VJP: F' diag(sc). The first launch of an iteration reads state buffer 0 and the second
@@ -204,19 +238,23 @@ void enqueue_iteration(const qcpd_handle *h, int dir, const double *sc, const do
         StepArgs &f = first;  // u~ <- F(sc o v) - alpha u~   (and the owed x, w update)
         f.in = h->v; f.in_nrm = NRM_ALPHA; f.in_is_v = 1;
         f.out = h->u; f.role = ROLE_U; f.do_update = 1;
+        set_baked(h, f);
         launch_loop_F(h->p, f, h->rg, h->loop_grid_F, s);
         StepArgs &t = second;  // v~ <- sc o F'u - beta v~, then J(sc o v~) for the next product
         t.in = h->u; t.in_nrm = NRM_BETA;
         t.out = h->v; t.role = ROLE_V; t.out_is_v = 1; t.do_pre = 1;
+        set_baked(h, t);
         launch_loop_FT(h->p, t, h->fg, h->lds_loop, h->loop_grid_T, s);
     } else {
         StepArgs &t = first;  // u~ <- F'(sc o v) - alpha u~ (and the owed update), J(u~)
         t.in = h->v; t.in_nrm = NRM_ALPHA; t.in_is_v = 1; t.do_update = 1;
         t.out = h->u; t.role = ROLE_U; t.do_pre = 1;
+        set_baked(h, t);
         launch_loop_FT(h->p, t, h->fg, h->lds_loop, h->loop_grid_T, s);
         StepArgs &f = second;  // v~ <- sc o F u - beta v~
         f.in = h->u; f.in_nrm = NRM_BETA;
         f.out = h->v; f.role = ROLE_V; f.out_is_v = 1;
+        set_baked(h, f);
         launch_loop_F(h->p, f, h->rg, h->loop_grid_F, s);
     }
 }
@@ -336,6 +374,8 @@ qcpd_status explicit_residual(qcpd_handle *h, int dir, double *rel) {
 // each stop the explicit residual is checked and, if it is too large, LSQR resumes from its
 // state with a tighter internal tolerance.
 qcpd_status solve(qcpd_handle *h, int dir, const double *sc, const double *scl, double *rel) {
+    qcpd_status rc0 = bake_scales(h, sc, scl);
+    if (rc0 != QCPD_OK) return rc0;
     lsqr_start(h, dir, sc, scl);
     qcpd_status rc = lsqr_iterate(h, dir, sc, scl);
     if (rc != QCPD_OK) return rc;
@@ -519,6 +559,7 @@ qcpd_status create_impl(qcpd_handle *h, const qcpd_csr *P, const qcpd_csr *A, co
         HIPCHK(hipMemcpy(du, units.data(), sizeof(Unit) * units.size(), hipMemcpyHostToDevice));
         h->fg.nunits = (int)units.size();
         h->fg.units = du;
+        fill_unit_ranges(p, du, h->fg.nunits, st);
         h->lds_fused = fused_lds_bytes(kmax);
         h->lds_loop = loop_lds_bytes(K->psd_orders, K->n_psd);
     }
@@ -936,10 +977,14 @@ qcpd_status qcpd_profile_kernels(qcpd_handle *h, int32_t reps, float *ms_out) {
     HIPCHK(hipMemsetAsync(h->lpart[1], 0, 3 * sizeof(double) * img.pend_blocks, s));
     StepArgs a = base_args(h, sc, scl);
     a.st = h->st; a.part_prev = h->lpart[0]; a.st_next = h->st2; a.part_next = h->lpart[1];
+    qcpd_status rc = bake_scales(h, sc, scl);
+    if (rc != QCPD_OK) return rc;
     StepArgs f = a;
     f.in = h->v; f.in_is_v = 1; f.out = h->scratch;
+    set_baked(h, f);
     StepArgs t = a;
     t.in = h->u; t.out = h->scratch; t.do_pre = 1; t.out_is_v = 1;
+    set_baked(h, t);
     for (int kid = 0; kid < 2; ++kid) {
         auto launch = [&]() {
             if (kid == 0) launch_loop_F(h->p, f, h->rg, h->loop_grid_F, s);

@@ -1016,6 +1016,7 @@ qcpd_status batch_create_impl(qcpd_batch *h, const qcpd_batch_layout *L, const i
         SegGrid &g = h->seg;
         g.B = B; g.nf = (int)fitems.size(); g.nt = (int)tunits.size();
         g.fitems = d_fitems; g.foff = d_foff; g.tunits = d_tunits; g.tprob = d_tprob; g.toff = d_toff;
+        fill_unit_ranges(p, d_tunits, g.nt, st);
         g.lxs = d_lx; g.lys = d_ly; g.xPx = xpx;
         BALLOC(g.ndone, 1);
         const int slots = std::max(g.nf, g.nt);

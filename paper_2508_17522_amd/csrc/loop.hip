@@ -7,14 +7,17 @@
 // (the 1/alpha or 1/beta factor is applied afterwards), the cone Jacobians are linear too,
 // and the operands of the role update (old output, scales, x and w of the owed update) are
 // plain loads. Each workgroup therefore
-//   1. issues the loads of the state and of its share of the previous launch's partials,
-//   2. computes the state-free part of its first work item (CSR sums, and for cone units
+//   1. computes the state-free part of its first work item (CSR sums, and for cone units
 //      the Jacobian applied to the raw rows, in LDS) and prefetches the update operands,
+//   2. issues the loads of the state and of the previous launch's partials (after the work
+//      item's own loads: a wait for a load also waits for all loads issued before it, and
+//      the partials, read by every workgroup, arrive last),
 //   3. finalises the previous launch's reduction (fixed order, every workgroup the same),
 //   4. finishes its work item (normalisation, role update, owed x/w update, stores), then
 //      any further items it owns, and leaves its own partial sums for the next launch.
-// Steps 1 and 2 run concurrently in the memory system. Cone units finish one thread per
-// row, and their Jacobian applications read and write LDS only.
+// Cone units finish one thread per row, and their Jacobian applications read and write LDS
+// only. Where the solve has diagonal scales, the CSR values come with the input scale
+// folded in, so a product reads one value per entry and gathers only the input.
 #include <algorithm>
 
 #include "cone_jv.h"
@@ -103,6 +106,8 @@ struct Entry {
 
 // Issue the loads (values are consumed in entry_finish). The partial buffers hold
 // kMaxLoopGrid slots, so the loads stay in bounds; slots beyond pend_blocks are ignored.
+// A wait for a load also waits for every load issued before it, so the kernels issue these
+// after the first loads of their own work.
 __device__ inline void entry_issue(const StepArgs &a, Entry &e) {
     e.st = *a.st;
 #pragma unroll
@@ -159,11 +164,20 @@ __device__ inline bool entry_finish(const StepArgs &a, const Entry &e, LsqrState
 
 struct Ptrs {  // scales by role; none depends on the LSQR scalars
     const double *isc, *osc, *nxs;
+    // CSR values of the products with the input: the input scale folded in (Pv o isc[col]
+    // etc., prepared per solve) when the launch has them, then gsc is null; else the plain
+    // values, gathered with gsc = isc
+    const double *Pv, *Av, *Tv, *gsc;
 };
 
-__device__ inline Ptrs ptrs_of(const StepArgs &a) {
+__device__ inline Ptrs ptrs_of(const Problem &p, const StepArgs &a) {
     Ptrs q;
     q.isc = a.in_is_v ? a.sc : a.scl;
+    const bool baked = q.isc && a.Pvs;
+    q.Pv = baked ? a.Pvs : p.Pv;
+    q.Av = baked ? a.Avs : p.Av;
+    q.Tv = baked ? a.Tvs : p.Tv;
+    q.gsc = baked ? nullptr : q.isc;
     q.osc = (a.role == ROLE_U) ? a.scl : (a.role == ROLE_V || a.role == ROLE_V0) ? a.sc : nullptr;
     q.nxs = a.out_is_v ? a.sc : a.scl;
     return q;
@@ -288,14 +302,14 @@ __device__ inline void rows_pre(const Problem &p, const StepArgs &a, const Ptrs 
         if (row < n) {
             const int k0 = p.Prp[row], k1 = p.Prp[row + 1];
             const int t0 = p.Trp[row], t1 = p.Trp[row + 1];
-            acc = csr_dot(p.Pci, p.Pv, k0, k1, lane, L, a.in, q.isc, 0);
+            acc = csr_dot(p.Pci, q.Pv, k0, k1, lane, L, a.in, q.gsc, 0);
             accT = csr_dot(p.Tci, p.Tv, t0, t1, lane, L, a.wy, nullptr, 0);
             idx = row;
         }
     } else {
         if (row < m) {
             const int k0 = p.Arp[row], k1 = p.Arp[row + 1];
-            acc = csr_dot(p.Aci, p.Av, k0, k1, lane, L, a.in, q.isc, 0);
+            acc = csr_dot(p.Aci, q.Av, k0, k1, lane, L, a.in, q.gsc, 0);
             idx = n + row;
         } else if (row == m) {
             idx = N - 1;
@@ -339,11 +353,11 @@ __device__ inline void rows_post(const Problem &p, const StepArgs &a, const Ctx 
 __global__ __launch_bounds__(kBlock) void k_loop_F(Problem p, StepArgs a, RowGrid g) {
     __shared__ LsqrState S;
     Entry e;
-    entry_issue(a, e);
-    const Ptrs q = ptrs_of(a);
+    const Ptrs q = ptrs_of(p, a);
     const double in_N_raw = in_raw(a, q, p.N - 1);
     RowPre r;
     rows_pre(p, a, q, g, blockIdx.x, r);
+    entry_issue(a, e);  // after the row loads: the memory counter is in order
     if (!entry_finish(a, e, &S, 0)) return;
     const Ctx c = scalars(a, S, q, in_N_raw);
     double s0 = 0.0, s1 = 0.0;
@@ -371,13 +385,18 @@ struct UnitPre {
 // scaled outputs), jt (J applied), ub (SOC: u/|u| at each row; exponential: each cone's
 // 3x3 Jacobian), kUnitRows each. One PSD cone of order k: X, T, V and, when it fits, B as
 // kp x ld matrices (kp = k rounded up to a multiple of 16, zero-padded, ld = kp + 1), then
-// tb, rb, jt (k(k+1)/2 each).
+// tb, rb, jt (k(k+1)/2 each). Each unit also has a gather buffer gb of kGather products for
+// its CSR rows, used before the cone factors are staged: jt and ub of a SOC / exponential
+// unit, X, T, V and B of a PSD unit when they are large enough, else after jt.
 constexpr int kPsdLdsCap = 16384;  // doubles a PSD unit may stage B into
 constexpr int kPsdPref = 4;        // V, B entries per thread loaded ahead (kp*kp <= 1024)
 constexpr int kSocPref = 8;        // u entries per cone loaded ahead (dimensions <= 9)
+constexpr int kGatherRegs = 8;     // CSR entries in flight per thread in a cone unit
+constexpr int kGather = kGatherRegs * kBlock;
+static_assert(kGather <= 2 * kUnitRows, "gather buffer of a SOC / exponential unit");
 
 struct PsdLds {
-    int kp, ld, nr, b, tb;  // b: offset of B, or -1 when B is read from global memory
+    int kp, ld, nr, b, tb, gb;  // b: offset of B, or -1 when B is read from global memory
 };
 
 __host__ __device__ inline PsdLds psd_lds(int k) {
@@ -393,10 +412,12 @@ __host__ __device__ inline PsdLds psd_lds(int k) {
         L.b = -1;
         L.tb = 3 * mat;
     }
+    L.gb = L.tb >= kGather ? 0 : L.tb + 3 * L.nr;
     return L;
 }
 
-__device__ inline int unit_rows(const Problem &p, const Unit &u, int &r0) {
+// rows of a cone run from the cone tables (fill_unit_ranges stores them in the unit)
+__device__ inline int unit_rows_of(const Problem &p, const Unit &u, int &r0) {
     if (u.type == U_PSD) {
         const int k = p.psd_k[u.begin];
         r0 = p.psd_row[u.begin];
@@ -408,19 +429,50 @@ __device__ inline int unit_rows(const Problem &p, const Unit &u, int &r0) {
     return r1 - r0;
 }
 
+__device__ inline int unit_rows(const Unit &u, int &r0) {
+    r0 = u.row0;
+    return u.nrows;
+}
+
 __device__ inline void unit_bufs(const Problem &p, const Unit &u, double *sm, int nr,
-                                 double *&tb, double *&rb, double *&jt, double *&ub) {
+                                 double *&tb, double *&rb, double *&jt, double *&ub,
+                                 double *&gb) {
     if (u.type == U_PSD) {
-        tb = sm + psd_lds(p.psd_k[u.begin]).tb;
+        const PsdLds L = psd_lds(u.k);
+        tb = sm + L.tb;
         rb = tb + nr;
         jt = rb + nr;
         ub = nullptr;
+        gb = sm + L.gb;
     } else {
         tb = sm;
         rb = sm + kUnitRows;
         jt = sm + 2 * kUnitRows;
         ub = sm + 3 * kUnitRows;
+        gb = jt;
     }
+}
+
+// Products val[k] * (sc o x)[col[k]] of the entries base .. base + cnt - 1 (1 <= cnt <=
+// kGather) into gb, kGatherRegs per thread with all loads issued before the first use;
+// entries past cnt load entry cnt - 1 (valid) and are not stored.
+template <bool SC>
+__device__ inline void gather_products(const int *col, const double *val, int base, int cnt,
+                                       const double *x, const double *sc, double *gb) {
+    const int tid = threadIdx.x;
+    int j[kGatherRegs];
+    double v[kGatherRegs], xv[kGatherRegs];
+#pragma unroll
+    for (int u = 0; u < kGatherRegs; ++u) {
+        const int k = base + min(tid + u * kBlock, cnt - 1);
+        j[u] = col[k];
+        v[u] = val[k];
+    }
+#pragma unroll
+    for (int u = 0; u < kGatherRegs; ++u) xv[u] = SC ? x[j[u]] * sc[j[u]] : x[j[u]];
+#pragma unroll
+    for (int u = 0; u < kGatherRegs; ++u)
+        if (tid + u * kBlock < cnt) gb[tid + u * kBlock] = v[u] * xv[u];
 }
 
 // SOC Jacobian (see soc_jv) on unit-relative rows [i0, i0 + dim), u/|u| read from ub
@@ -457,57 +509,69 @@ __device__ inline void exp_apply(const double *J, int i0, IN in, OUT out) {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-// One kp x kp product C = op(A) op(B) of LDS matrices (leading dimension ld, zero-padded)
-// on the FP64 matrix cores: wave w computes the 16 x 16 tiles w, w + 4, ... in row-major tile
-// order with V_MFMA_F64_16X16X4F64. In each step lane l supplies A[i0 + l%16][k0 + l/16] and
-// B[k0 + l/16][j0 + l%16]; accumulator entry r of lane l is C[i0 + 4r + l/16][j0 + l%16].
-// epi(i, j, acc) receives i = i0 + l/16 (rows i + 4r) and j = j0 + l%16.
-template <bool TA, bool TB, class EPI>
-__device__ inline void mfma_product(int kp, int ld, const double *A, const double *B, EPI epi) {
+// One KP x KP product C = A B on the FP64 matrix cores, operands read through af(i, kk) and
+// bf(kk, j) (LDS, zero beyond the cone's order): wave w computes the 16 x 16 tiles w, w + 4,
+// ... in row-major tile order with V_MFMA_F64_16X16X4F64. In step s lane l supplies
+// A[i0 + l%16][4s + l/16] and B[4s + l/16][j0 + l%16]; accumulator entry r of lane l is
+// C[i0 + 4r + l/16][j0 + l%16]. The operands of up to eight steps are loaded before the
+// first product, and even and odd steps accumulate separately (two short dependency chains
+// instead of one long one). epi(i, j, acc) receives i = i0 + l/16 (rows i + 4r) and
+// j = j0 + l%16.
+template <int KP, class AF, class BF, class EPI>
+__device__ inline void mfma_product(AF af, BF bf, EPI epi) {
+    constexpr int NT = KP / 16, NS = KP / 4, CH = NS < 8 ? NS : 8;
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    const int li = lane & 15, lk = lane >> 4, nt = kp / 16;
-    for (int t = wave; t < nt * nt; t += kBlock / kWave) {
-        const int i0 = (t / nt) * 16, j0 = (t - (t / nt) * nt) * 16;
-        dbl4 acc = {0.0, 0.0, 0.0, 0.0};
-        for (int k0 = 0; k0 < kp; k0 += 16) {  // kp is a multiple of 16: four steps per pass
-            double av[4], bv[4];
+    const int li = lane & 15, lk = lane >> 4;
+#pragma unroll 1
+    for (int t = wave; t < NT * NT; t += kBlock / kWave) {
+        const int i0 = (t / NT) * 16, j0 = (t % NT) * 16;
+        dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+        for (int s0 = 0; s0 < NS; s0 += CH) {
+            double av[CH], bv[CH];
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {  // operand loads first, so they overlap
-                const int kk = k0 + 4 * s + lk;
-                av[s] = TA ? A[kk * ld + i0 + li] : A[(i0 + li) * ld + kk];
-                bv[s] = TB ? B[(j0 + li) * ld + kk] : B[kk * ld + j0 + li];
+            for (int s = 0; s < CH; ++s) {
+                const int kk = 4 * (s0 + s) + lk;
+                av[s] = af(i0 + li, kk);
+                bv[s] = bf(kk, j0 + li);
             }
 #pragma unroll
-            for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], bv[s], acc, 0, 0, 0);
+            for (int s = 0; s < CH; s += 2) {
+                acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], bv[s], acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s + 1], bv[s + 1], acc1, 0, 0, 0);
+            }
         }
-        epi(i0 + lk, j0 + li, acc);
+        epi(i0 + lk, j0 + li, acc0 + acc1);
     }
 }
 
 // PSD Jacobian J[dZ] = V (B o (V' dZ V)) V' (see psd_jv) on unit-relative svec rows, with V
-// (and B) staged in LDS; the four products on the matrix cores.
-template <class IN, class OUT>
-__device__ inline void psd_apply(int k, const PsdLds &L, double *sm, const double *Bg, IN in,
-                                 OUT out) {
-    const int kp = L.kp, ld = L.ld, mat = kp * ld;
+// (and B) staged in LDS as KP x (KP + 1) matrices; the four products on the matrix cores.
+// The first product reads dZ = smat(in) straight from the svec rows.
+template <int KP, class IN, class OUT>
+__device__ inline void psd_apply_kp(int k, const PsdLds &L, double *sm, const double *Bg,
+                                    IN in, OUT out) {
+    constexpr int ld = KP + 1, mat = KP * ld;
     double *X = sm, *T = sm + mat;
     const double *V = sm + 2 * mat, *B = L.b >= 0 ? sm + L.b : nullptr;
-    const int tid = threadIdx.x;
-    for (int e = tid; e < kp * kp; e += kBlock) {  // X = smat(in), zero-padded
-        const int i = e / kp, j = e - (e / kp) * kp;
+    auto xf = [&](int i, int j) {  // smat(in), zero-padded
         double v = 0.0;
         if (i < k && j < k) {
             v = in(i >= j ? svec_index(i, j, k) : svec_index(j, i, k));
             if (i != j) v *= kRsqrt2;
         }
-        X[i * ld + j] = v;
-    }
-    __syncthreads();
-    mfma_product<false, false>(kp, ld, X, V, [&](int i, int j, const dbl4 &c) {  // T = X V
+        return v;
+    };
+    auto vf = [&](int i, int j) { return V[i * ld + j]; };
+    auto vt = [&](int i, int j) { return V[j * ld + i]; };
+    auto tf = [&](int i, int j) { return T[i * ld + j]; };
+    auto xm = [&](int i, int j) { return X[i * ld + j]; };
+    auto to_t = [&](int i, int j, const dbl4 &c) {
         for (int r = 0; r < 4; ++r) T[(i + 4 * r) * ld + j] = c[r];
-    });
+    };
+    mfma_product<KP>(xf, vf, to_t);  // T = smat(in) V
     __syncthreads();
-    mfma_product<true, false>(kp, ld, V, T, [&](int i, int j, const dbl4 &c) {  // X = B o (V'T)
+    mfma_product<KP>(vt, tf, [&](int i, int j, const dbl4 &c) {  // X = B o (V'T)
         for (int r = 0; r < 4; ++r) {
             const int ii = i + 4 * r;
             double bij = 0.0;
@@ -516,17 +580,26 @@ __device__ inline void psd_apply(int k, const PsdLds &L, double *sm, const doubl
         }
     });
     __syncthreads();
-    mfma_product<false, false>(kp, ld, V, X, [&](int i, int j, const dbl4 &c) {  // T = V X
-        for (int r = 0; r < 4; ++r) T[(i + 4 * r) * ld + j] = c[r];
-    });
+    mfma_product<KP>(vf, xm, to_t);  // T = V X
     __syncthreads();
-    mfma_product<false, true>(kp, ld, T, V, [&](int i, int j, const dbl4 &c) {  // Y = T V'
+    mfma_product<KP>(tf, vt, [&](int i, int j, const dbl4 &c) {  // Y = T V'
         for (int r = 0; r < 4; ++r) {
             const int ii = i + 4 * r;
             if (ii < k && j <= ii) out(svec_index(ii, j, k), ii == j ? c[r] : c[r] * kSqrt2);
         }
     });
     __syncthreads();
+}
+
+template <class IN, class OUT>
+__device__ inline void psd_apply(int k, const PsdLds &L, double *sm, const double *Bg, IN in,
+                                 OUT out) {
+    switch (L.kp) {
+    case 16: psd_apply_kp<16>(k, L, sm, Bg, in, out); break;
+    case 32: psd_apply_kp<32>(k, L, sm, Bg, in, out); break;
+    case 48: psd_apply_kp<48>(k, L, sm, Bg, in, out); break;
+    default: psd_apply_kp<64>(k, L, sm, Bg, in, out); break;
+    }
 }
 
 __device__ inline void unit_pre(const Problem &p, const StepArgs &a, const Ptrs &q, int lx,
@@ -541,8 +614,8 @@ __device__ inline void unit_pre(const Problem &p, const StepArgs &a, const Ptrs 
         if (row < u.end) {
             const int k0 = p.Prp[row], k1 = p.Prp[row + 1];
             const int t0 = p.Trp[row], t1 = p.Trp[row + 1];
-            acc = csr_dot(p.Pci, p.Pv, k0, k1, lane, L, a.in, q.isc, 0);
-            accT = csr_dot(p.Tci, p.Tv, t0, t1, lane, L, a.in, q.isc, n);
+            acc = csr_dot(p.Pci, q.Pv, k0, k1, lane, L, a.in, q.gsc, 0);
+            accT = csr_dot(p.Tci, q.Tv, t0, t1, lane, L, a.in, q.gsc, n);
         }
         P.acc = group_sum_dpp(acc, L);
         P.accT = group_sum_dpp(accT, L);
@@ -558,7 +631,7 @@ __device__ inline void unit_pre(const Problem &p, const StepArgs &a, const Ptrs 
         double acc = 0.0;
         if (r < u.end) {
             const int k0 = p.Arp[r], k1 = p.Arp[r + 1];
-            acc = csr_dot(p.Aci, p.Av, k0, k1, lane, L, a.in, q.isc, 0);
+            acc = csr_dot(p.Aci, q.Av, k0, k1, lane, L, a.in, q.gsc, 0);
         }
         P.acc = group_sum_dpp(acc, L);
         if (r < u.end && lane == 0) {
@@ -575,38 +648,52 @@ __device__ inline void unit_pre(const Problem &p, const StepArgs &a, const Ptrs 
     // factors in LDS and apply J to t into jt. Each cone kind has its own branch so that
     // the registers holding its prefetched factors are not live in the others.
     int r0;
-    const int nr = unit_rows(p, u, r0);
-    double *tb, *rb, *jt, *ub;
-    unit_bufs(p, u, sm, nr, tb, rb, jt, ub);
+    const int nr = unit_rows(u, r0);
+    double *tb, *rb, *jt, *ub, *gb;
+    unit_bufs(p, u, sm, nr, tb, rb, jt, ub, gb);
+    int rs = 0, re = 0;
+    double ry = 0.0;
     if (tid < nr) {
         P.idx = n + r0 + tid;
         P.bv = p.b[r0 + tid];
+        rs = p.Arp[r0 + tid];
+        re = p.Arp[r0 + tid + 1];
+        ry = in_raw(a, q, n + r0 + tid);
         fin_load(a, q, n + r0 + tid, P.f);
     }
+    // raw rows t = A r_x - b r_N - r_y of the unit (unnormalised). The unit's rows are
+    // consecutive CSR rows, so their entries are one range [e0, e1): the workgroup gathers
+    // the products of kGather entries at a time into gb, then each row adds its own entries
+    // in CSR order (a fixed order, whatever the launch shape).
     auto yrows = [&]() {
-        int L = ly;
-        while (L > 1 && L * nr > kBlock) L >>= 1;
-        const int lane = tid & (L - 1), grp = tid / L, ngrp = kBlock / L;
-        for (int i0 = 0; i0 < nr; i0 += ngrp) {
-            const int i = i0 + grp, r = r0 + i;
-            double acc = 0.0;
-            if (i < nr) {
-                const int k0 = p.Arp[r], k1 = p.Arp[r + 1];
-                acc = csr_dot(p.Aci, p.Av, k0, k1, lane, L, a.in, q.isc, 0);
+        const int e0 = u.e0, e1 = u.e1;
+        for (int base = e0; base < e1; base += kGather) {
+            const int cnt = min(e1 - base, kGather);
+            if (q.gsc) gather_products<true>(p.Aci, q.Av, base, cnt, a.in, q.gsc, gb);
+            else gather_products<false>(p.Aci, q.Av, base, cnt, a.in, nullptr, gb);
+            __syncthreads();
+            for (int i = tid; i < nr; i += kBlock) {
+                const int k0 = max(i == tid ? rs : p.Arp[r0 + i], base);
+                const int k1 = min(i == tid ? re : p.Arp[r0 + i + 1], base + cnt);
+                double acc = base == e0 ? 0.0 : tb[i];
+                for (int k = k0; k < k1; ++k) acc += gb[k - base];
+                tb[i] = acc;
             }
-            acc = group_sum_dpp(acc, L);
-            if (i < nr && lane == 0) {
-                const double ry = in_raw(a, q, n + r);
-                rb[i] = ry;
-                tb[i] = acc - p.b[r] * in_N_raw - ry;
-            }
+            __syncthreads();
+        }
+        for (int i = tid; i < nr; i += kBlock) {
+            const int r = r0 + i;
+            const double y = i == tid ? ry : in_raw(a, q, n + r);
+            const double bb = i == tid ? P.bv : p.b[r];
+            rb[i] = y;
+            tb[i] = (e1 > e0 ? tb[i] : 0.0) - bb * in_N_raw - y;
         }
     };
     auto tin = [&](int i) { return tb[i]; };
     auto jout = [&](int i, double v) { jt[i] = v; };
     const int cone = u.begin + tid;
     if (u.type == U_PSD) {
-        const int k = p.psd_k[u.begin];
+        const int k = u.k;
         const PsdLds Ld = psd_lds(k);
         const int kp = Ld.kp;
         const double *Vg = p.psd_pool + p.psd_off[u.begin], *Bg = Vg + k * k;
@@ -648,18 +735,16 @@ __device__ inline void unit_pre(const Problem &p, const StepArgs &a, const Ptrs 
             cr0 = p.soc_row[cone];
             cdim = p.soc_dim[cone];
         }
-        if (cdim - 1 <= kSocPref) {
-            double upre[kSocPref];
+        // the first kSocPref entries of u are loaded ahead, the rest (longer cones) after the
+        // rows; yrows has barriers, so every thread takes the same path to it
+        double upre[kSocPref];
 #pragma unroll
-            for (int j = 0; j < kSocPref; ++j) upre[j] = j < cdim - 1 ? p.zy[cr0 + 1 + j] : 0.0;
-            yrows();
+        for (int j = 0; j < kSocPref; ++j) upre[j] = j < cdim - 1 ? p.zy[cr0 + 1 + j] : 0.0;
+        yrows();
 #pragma unroll
-            for (int j = 0; j < kSocPref; ++j)
-                if (j < cdim - 1) ub[cr0 - r0 + 1 + j] = upre[j] * P.cp[1];
-        } else {
-            yrows();
-            for (int j = 0; j < cdim - 1; ++j) ub[cr0 - r0 + 1 + j] = p.zy[cr0 + 1 + j] * P.cp[1];
-        }
+        for (int j = 0; j < kSocPref; ++j)
+            if (j < cdim - 1) ub[cr0 - r0 + 1 + j] = upre[j] * P.cp[1];
+        for (int j = kSocPref; j < cdim - 1; ++j) ub[cr0 - r0 + 1 + j] = p.zy[cr0 + 1 + j] * P.cp[1];
         __syncthreads();
         if (cone < u.end) soc_apply(P.cp, ub, cr0 - r0, cdim, tin, jout);
         __syncthreads();
@@ -704,9 +789,10 @@ __device__ inline void unit_post(const Problem &p, const StepArgs &a, const Ptrs
         return;
     }
     int r0;
-    const int nr = unit_rows(p, u, r0);
-    double *tb, *rb, *jt, *ub;
-    unit_bufs(p, u, sm, nr, tb, rb, jt, ub);
+    const int nr = unit_rows(u, r0);
+    double *tb, *rb, *jt, *ub, *gb;
+    unit_bufs(p, u, sm, nr, tb, rb, jt, ub, gb);
+    (void)gb;
     for (int i = tid; i < nr; i += kBlock) {
         Fin f;
         if (i == tid) f = P.f;
@@ -720,7 +806,7 @@ __device__ inline void unit_post(const Problem &p, const StepArgs &a, const Ptrs
     auto oin = [&](int i) { return rb[i]; };
     auto jout = [&](int i, double v) { jt[i] = v; };
     if (u.type == U_PSD) {
-        const int k = p.psd_k[u.begin];
+        const int k = u.k;
         const double *Bg = p.psd_pool + p.psd_off[u.begin] + k * k;
         psd_apply(k, psd_lds(k), sm, Bg, oin, jout);
     } else {
@@ -742,20 +828,21 @@ __global__ __launch_bounds__(kBlock) void k_loop_FT(Problem p, StepArgs a, Fused
     extern __shared__ double sm[];
     __shared__ LsqrState S;
     Entry e;
-    entry_issue(a, e);
-    const Ptrs q = ptrs_of(a);
+    const Ptrs q = ptrs_of(p, a);
     const double in_N_raw = in_raw(a, q, p.N - 1);
     UnitPre P;
-    Unit u = g.units[blockIdx.x];
-    unit_pre(p, a, q, g.lx, g.ly, u, sm, in_N_raw, P);
-    if (!entry_finish(a, e, &S, 1)) return;
-    const Ctx c = scalars(a, S, q, in_N_raw);
+    Ctx c;
     double s0 = 0.0, s1 = 0.0;
-    unit_post(p, a, q, c, u, sm, P, s0, s1);
-    for (int ui = blockIdx.x + gridDim.x; ui < g.nunits; ui += gridDim.x) {
-        __syncthreads();  // LDS of the previous unit is free
-        u = g.units[ui];
+    // one copy of the unit code: the first unit's pre phase overlaps the entry reduction
+    for (int ui = blockIdx.x; ui < g.nunits; ui += gridDim.x) {
+        if (ui != (int)blockIdx.x) __syncthreads();  // LDS of the previous unit is free
+        const Unit u = g.units[ui];
         unit_pre(p, a, q, g.lx, g.ly, u, sm, in_N_raw, P);
+        if (ui == (int)blockIdx.x) {
+            entry_issue(a, e);  // after the unit's loads: the memory counter is in order
+            if (!entry_finish(a, e, &S, 1)) return;
+            c = scalars(a, S, q, in_N_raw);
+        }
         unit_post(p, a, q, c, u, sm, P, s0, s1);
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {  // the tau entry
@@ -846,10 +933,10 @@ __device__ inline void seg_rows_pre(const Problem &p, const StepArgs &a, const P
     double acc = 0.0, accT = 0.0;
     if (row < it.end) {
         if (it.type == 0) {
-            acc = csr_dot(p.Pci, p.Pv, p.Prp[row], p.Prp[row + 1], lane, L, a.in, q.isc, 0);
+            acc = csr_dot(p.Pci, q.Pv, p.Prp[row], p.Prp[row + 1], lane, L, a.in, q.gsc, 0);
             accT = csr_dot(p.Tci, p.Tv, p.Trp[row], p.Trp[row + 1], lane, L, a.wy, nullptr, 0);
         } else {
-            acc = csr_dot(p.Aci, p.Av, p.Arp[row], p.Arp[row + 1], lane, L, a.in, q.isc, 0);
+            acc = csr_dot(p.Aci, q.Av, p.Arp[row], p.Arp[row + 1], lane, L, a.in, q.gsc, 0);
         }
     }
     r.acc = group_sum_dpp(acc, L);
@@ -887,7 +974,7 @@ __global__ __launch_bounds__(kBlock) void k_seg_F(Problem p, StepArgs a, SegGrid
     const bool first = (int)blockIdx.x == g.foff[b];
     SegEntry e;
     seg_entry_issue(a, b, g.toff, e);
-    const Ptrs q = ptrs_of(a);
+    const Ptrs q = ptrs_of(p, a);
     const int tix = p.n + p.m + b;
     const double in_N_raw = in_raw(a, q, tix);
     RowPre r;
@@ -912,7 +999,7 @@ __global__ __launch_bounds__(kBlock) void k_seg_FT(Problem p, StepArgs a, SegGri
     const bool first = (int)blockIdx.x == g.toff[b];
     SegEntry e;
     seg_entry_issue(a, b, g.foff, e);
-    const Ptrs q = ptrs_of(a);
+    const Ptrs q = ptrs_of(p, a);
     const int tix = p.n + p.m + b;
     const double in_N_raw = in_raw(a, q, tix);
     UnitPre P;
@@ -933,11 +1020,43 @@ __global__ __launch_bounds__(kBlock) void k_seg_FT(Problem p, StepArgs a, SegGri
 // launchers
 // ---------------------------------------------------------------------------------------
 
+__global__ void k_unit_ranges(Problem p, Unit *units, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    Unit u = units[i];
+    u.nrows = u.e0 = u.e1 = u.k = 0;
+    if (u.type == U_PSD || u.type == U_SOC || u.type == U_EXP) {
+        int r0;
+        u.nrows = unit_rows_of(p, u, r0);
+        u.e0 = p.Arp[r0];
+        u.e1 = p.Arp[r0 + u.nrows];
+        if (u.type == U_PSD) u.k = p.psd_k[u.begin];
+    }
+    units[i] = u;
+}
+
+__global__ void k_scale_vals(const int *col, const double *val, long long nnz, const double *sc,
+                             int off, double *out) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nnz) out[i] = val[i] * sc[off + col[i]];
+}
+
+void launch_scale_vals(const int *col, const double *val, long long nnz, const double *sc,
+                       int off, double *out, hipStream_t s) {
+    if (nnz > 0)
+        hipLaunchKernelGGL(k_scale_vals, dim3((unsigned)((nnz + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                           col, val, nnz, sc, off, out);
+}
+
+void fill_unit_ranges(const Problem &p, Unit *units, int n, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_unit_ranges, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, p, units, n);
+}
+
 int loop_lds_bytes(const int *psd_orders, int n_psd) {
     int need = 4 * kUnitRows;
     for (int i = 0; i < n_psd; ++i) {
         const PsdLds L = psd_lds(psd_orders[i]);
-        need = std::max(need, L.tb + 3 * L.nr);
+        need = std::max({need, L.tb + 3 * L.nr, L.gb + kGather});
     }
     return (int)sizeof(double) * need;
 }

@@ -193,6 +193,10 @@ struct StepArgs {
     LsqrState *st_next;
     const double *part_prev;
     double *part_next;
+    // values of P, A and A' with the input scale of the launch folded into each entry
+    // (val * isc[col], isc = sc or scl as in_is_v says), or null: the loop kernels then
+    // gather isc per entry
+    const double *Pvs, *Avs, *Tvs;
 };
 
 // Work units of the fused product with F' (one workgroup each): x rows, diagonal y rows,
@@ -201,6 +205,9 @@ struct StepArgs {
 enum UnitType { U_XROWS = 0, U_DIAG = 1, U_SOC = 2, U_EXP = 3, U_PSD = 4 };
 struct Unit {
     int type, begin, end, row0;  // row0: first y row of a cone run (SOC / exp / PSD)
+    // cone runs, filled on the device once the CSR copies exist (fill_unit_ranges): the
+    // number of y rows, the range [e0, e1) of their CSR entries in A, and a PSD cone's order
+    int nrows, e0, e1, k;
 };
 constexpr int kUnitRows = 1024;   // most y rows staged by one SOC / exp unit
 
@@ -261,6 +268,9 @@ void launch_seg_F(const Problem &p, const StepArgs &a, const SegGrid &g, hipStre
 void launch_seg_FT(const Problem &p, const StepArgs &a, const SegGrid &g, int lds, hipStream_t s);
 
 // the LSQR loop (loop.hip)
+void fill_unit_ranges(const Problem &p, Unit *units, int n, hipStream_t s);
+void launch_scale_vals(const int *col, const double *val, long long nnz, const double *sc,
+                       int off, double *out, hipStream_t s);
 int loop_lds_bytes(const int *psd_orders, int n_psd);
 void set_loop_kernel_lds(int bytes);
 void launch_loop_F(const Problem &p, const StepArgs &a, const RowGrid &g, int grid, hipStream_t s);
