@@ -824,35 +824,58 @@ __device__ inline void unit_post(const Problem &p, const StepArgs &a, const Ptrs
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_loop_FT(Problem p, StepArgs a, FusedGrid g) {
-    extern __shared__ double sm[];
-    __shared__ LsqrState S;
+// MULTI: a workgroup runs units blockIdx.x, blockIdx.x + gridDim.x, ... (launches with
+// fewer workgroups than units); else exactly unit blockIdx.x. The single-unit form needs
+// about half the registers (a loop around the unit code keeps more of it live), so it runs
+// at twice the occupancy.
+template <bool MULTI>
+__device__ inline void loop_FT_body(const Problem &p, const StepArgs &a, const FusedGrid &g,
+                                    double *sm, LsqrState &S) {
     Entry e;
     const Ptrs q = ptrs_of(p, a);
     const double in_N_raw = in_raw(a, q, p.N - 1);
     UnitPre P;
     Ctx c;
     double s0 = 0.0, s1 = 0.0;
-    // one copy of the unit code: the first unit's pre phase overlaps the entry reduction
-    for (int ui = blockIdx.x; ui < g.nunits; ui += gridDim.x) {
-        if (ui != (int)blockIdx.x) __syncthreads();  // LDS of the previous unit is free
-        const Unit u = g.units[ui];
+    if (!MULTI) {
+        const Unit u = g.units[blockIdx.x];
         unit_pre(p, a, q, g.lx, g.ly, u, sm, in_N_raw, P);
-        if (ui == (int)blockIdx.x) {
-            entry_issue(a, e);  // after the unit's loads: the memory counter is in order
-            if (!entry_finish(a, e, &S, 1)) return;
-            c = scalars(a, S, q, in_N_raw);
-        }
+        entry_issue(a, e);  // after the unit's loads: the memory counter is in order
+        if (!entry_finish(a, e, &S, 1)) return;
+        c = scalars(a, S, q, in_N_raw);
         unit_post(p, a, q, c, u, sm, P, s0, s1);
+    } else {
+        for (int ui = blockIdx.x; ui < g.nunits; ui += gridDim.x) {
+            if (ui != (int)blockIdx.x) __syncthreads();  // LDS of the previous unit is free
+            const Unit u = g.units[ui];
+            unit_pre(p, a, q, g.lx, g.ly, u, sm, in_N_raw, P);
+            if (ui == (int)blockIdx.x) {
+                entry_issue(a, e);
+                if (!entry_finish(a, e, &S, 1)) return;
+                c = scalars(a, S, q, in_N_raw);
+            }
+            unit_post(p, a, q, c, u, sm, P, s0, s1);
+        }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {  // the tau entry
         const int N = p.N;
         Fin f;
         fin_load(a, q, N - 1, f);
-        const double o = fin_store(a, c, N - 1, f, S.dot_adj * c.inv + p.xPx * c.in_N, s0);
-        (void)o;
+        fin_store(a, c, N - 1, f, S.dot_adj * c.inv + p.xPx * c.in_N, s0);
     }
     leave(a, s0, s1);
+}
+
+__global__ __launch_bounds__(kBlock) void k_loop_FT(Problem p, StepArgs a, FusedGrid g) {
+    extern __shared__ double sm[];
+    __shared__ LsqrState S;
+    loop_FT_body<false>(p, a, g, sm, S);
+}
+
+__global__ __launch_bounds__(kBlock) void k_loop_FT_multi(Problem p, StepArgs a, FusedGrid g) {
+    extern __shared__ double sm[];
+    __shared__ LsqrState S;
+    loop_FT_body<true>(p, a, g, sm, S);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1063,6 +1086,7 @@ int loop_lds_bytes(const int *psd_orders, int n_psd) {
 
 void set_loop_kernel_lds(int bytes) {
     (void)hipFuncSetAttribute((const void *)k_loop_FT, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    (void)hipFuncSetAttribute((const void *)k_loop_FT_multi, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 void launch_loop_F(const Problem &p, const StepArgs &a, const RowGrid &g, int grid, hipStream_t s) {
@@ -1071,7 +1095,10 @@ void launch_loop_F(const Problem &p, const StepArgs &a, const RowGrid &g, int gr
 
 void launch_loop_FT(const Problem &p, const StepArgs &a, const FusedGrid &g, int lds, int grid,
                     hipStream_t s) {
-    hipLaunchKernelGGL(k_loop_FT, dim3(grid), dim3(kBlock), lds, s, p, a, g);
+    if (grid >= g.nunits)
+        hipLaunchKernelGGL(k_loop_FT, dim3(g.nunits), dim3(kBlock), lds, s, p, a, g);
+    else
+        hipLaunchKernelGGL(k_loop_FT_multi, dim3(grid), dim3(kBlock), lds, s, p, a, g);
 }
 
 void set_seg_kernel_lds(int bytes) {
