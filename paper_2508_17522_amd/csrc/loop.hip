@@ -240,12 +240,13 @@ __device__ inline void fin_load(const StepArgs &a, const Ptrs &q, int idx, Fin &
 // LSQR scalars of this launch, from the finalised state
 __device__ inline Ctx scalars(const StepArgs &a, const LsqrState &S, const Ptrs &q,
                               double in_N_raw) {
-    const double *sv = reinterpret_cast<const double *>(&S);
+    // two independent reciprocals instead of four dependent quotients
+    const double ia = 1.0 / S.alpha, ib = 1.0 / S.beta;
     Ctx c;
-    c.inv = 1.0 / sv[a.in_nrm];
-    c.cU = (a.role == ROLE_U) ? S.alpha / S.beta : 0.0;
-    c.cV = (a.role == ROLE_V) ? S.beta / S.alpha : 0.0;
-    c.inv_alpha_up = a.do_update ? 1.0 / S.alpha : 0.0;
+    c.inv = a.in_nrm == NRM_ALPHA ? ia : a.in_nrm == NRM_BETA ? ib : 1.0 / S.one;
+    c.cU = (a.role == ROLE_U) ? S.alpha * ib : 0.0;
+    c.cV = (a.role == ROLE_V) ? S.beta * ia : 0.0;
+    c.inv_alpha_up = a.do_update ? ia : 0.0;
     c.phr = S.phr;
     c.thr = S.thr;
     c.isc = q.isc;
@@ -378,6 +379,7 @@ struct UnitPre {
     double acc, accT, self, coef, jd;
     double bv;                 // cone units: b at this thread's first row
     double cp[4];              // SOC factors of this thread's cone: mode, 1/|u|, c1, c2
+    int ii, jj;                // PSD units: the matrix entry of this thread's first row
     Fin f;
 };
 
@@ -545,23 +547,16 @@ __device__ inline void mfma_product(AF af, BF bf, EPI epi) {
     }
 }
 
-// PSD Jacobian J[dZ] = V (B o (V' dZ V)) V' (see psd_jv) on unit-relative svec rows, with V
-// (and B) staged in LDS as KP x (KP + 1) matrices; the four products on the matrix cores.
-// The first product reads dZ = smat(in) straight from the svec rows.
-template <int KP, class IN, class OUT>
-__device__ inline void psd_apply_kp(int k, const PsdLds &L, double *sm, const double *Bg,
-                                    IN in, OUT out) {
+// PSD Jacobian Y = J[X] = V (B o (V' X V)) V' (see psd_jv) of the symmetric matrix X held
+// in the X region (zero beyond the order), with V (and B) staged in LDS as KP x (KP + 1)
+// matrices; the four products on the matrix cores. Y replaces X (zero beyond the order, as
+// V is). The callers write X from the svec rows and read Y back into them (svec_rc), so the
+// products themselves do no index arithmetic.
+template <int KP>
+__device__ inline void psd_apply_kp(int k, const PsdLds &L, double *sm, const double *Bg) {
     constexpr int ld = KP + 1, mat = KP * ld;
     double *X = sm, *T = sm + mat;
     const double *V = sm + 2 * mat, *B = L.b >= 0 ? sm + L.b : nullptr;
-    auto xf = [&](int i, int j) {  // smat(in), zero-padded
-        double v = 0.0;
-        if (i < k && j < k) {
-            v = in(i >= j ? svec_index(i, j, k) : svec_index(j, i, k));
-            if (i != j) v *= kRsqrt2;
-        }
-        return v;
-    };
     auto vf = [&](int i, int j) { return V[i * ld + j]; };
     auto vt = [&](int i, int j) { return V[j * ld + i]; };
     auto tf = [&](int i, int j) { return T[i * ld + j]; };
@@ -569,7 +564,7 @@ __device__ inline void psd_apply_kp(int k, const PsdLds &L, double *sm, const do
     auto to_t = [&](int i, int j, const dbl4 &c) {
         for (int r = 0; r < 4; ++r) T[(i + 4 * r) * ld + j] = c[r];
     };
-    mfma_product<KP>(xf, vf, to_t);  // T = smat(in) V
+    mfma_product<KP>(xm, vf, to_t);  // T = X V
     __syncthreads();
     mfma_product<KP>(vt, tf, [&](int i, int j, const dbl4 &c) {  // X = B o (V'T)
         for (int r = 0; r < 4; ++r) {
@@ -582,24 +577,49 @@ __device__ inline void psd_apply_kp(int k, const PsdLds &L, double *sm, const do
     __syncthreads();
     mfma_product<KP>(vf, xm, to_t);  // T = V X
     __syncthreads();
-    mfma_product<KP>(tf, vt, [&](int i, int j, const dbl4 &c) {  // Y = T V'
-        for (int r = 0; r < 4; ++r) {
-            const int ii = i + 4 * r;
-            if (ii < k && j <= ii) out(svec_index(ii, j, k), ii == j ? c[r] : c[r] * kSqrt2);
-        }
+    mfma_product<KP>(tf, vt, [&](int i, int j, const dbl4 &c) {  // X = Y = T V'
+        for (int r = 0; r < 4; ++r) X[(i + 4 * r) * ld + j] = c[r];
     });
     __syncthreads();
 }
 
-template <class IN, class OUT>
-__device__ inline void psd_apply(int k, const PsdLds &L, double *sm, const double *Bg, IN in,
-                                 OUT out) {
+__device__ inline void psd_apply(int k, const PsdLds &L, double *sm, const double *Bg) {
     switch (L.kp) {
-    case 16: psd_apply_kp<16>(k, L, sm, Bg, in, out); break;
-    case 32: psd_apply_kp<32>(k, L, sm, Bg, in, out); break;
-    case 48: psd_apply_kp<48>(k, L, sm, Bg, in, out); break;
-    default: psd_apply_kp<64>(k, L, sm, Bg, in, out); break;
+    case 16: psd_apply_kp<16>(k, L, sm, Bg); break;
+    case 32: psd_apply_kp<32>(k, L, sm, Bg); break;
+    case 48: psd_apply_kp<48>(k, L, sm, Bg); break;
+    default: psd_apply_kp<64>(k, L, sm, Bg); break;
     }
+}
+
+// svec row i of an order-k cone is the matrix entry (ii, jj), ii >= jj (column jj holds the
+// rows ii = jj .. k-1)
+__device__ inline void svec_rc(int i, int k, int &ii, int &jj) {
+    // column j starts at row off(j) = j (2k + 1 - j) / 2: the root of off(j) = i, rounded
+    // down, then corrected by one either way for the rounding of the square root
+    const int b = 2 * k + 1;
+    int j = (int)((b - sqrtf((float)(b * b - 8 * i))) * 0.5f);
+    j = max(0, min(j, k - 1));
+    if (j * (b - j) / 2 > i) --j;
+    else if ((j + 1) * (b - j - 1) / 2 <= i) ++j;
+    jj = j;
+    ii = j + (i - j * (b - j) / 2);
+}
+
+// svec value v of entry (ii, jj) into the symmetric matrix X (both triangles)
+__device__ inline void smat_put(double *X, int ld, int ii, int jj, double v) {
+    if (ii == jj) {
+        X[ii * ld + ii] = v;
+    } else {
+        v *= kRsqrt2;
+        X[ii * ld + jj] = v;
+        X[jj * ld + ii] = v;
+    }
+}
+
+// svec value of entry (ii, jj) of the symmetric matrix Y
+__device__ inline double smat_get(const double *Y, int ld, int ii, int jj) {
+    return ii == jj ? Y[ii * ld + ii] : Y[ii * ld + jj] * kSqrt2;
 }
 
 __device__ inline void unit_pre(const Problem &p, const StepArgs &a, const Ptrs &q, int lx,
@@ -707,6 +727,7 @@ __device__ inline void unit_pre(const Problem &p, const StepArgs &a, const Ptrs 
                 vpre[j] = in_k ? Vg[i * k + jj] : 0.0;
                 bpre[j] = (in_k && B) ? Bg[i * k + jj] : 0.0;
             }
+            if (tid < nr) svec_rc(tid, k, P.ii, P.jj);  // while the loads are in flight
             yrows();
 #pragma unroll
             for (int j = 0; j < kPsdPref; ++j) {
@@ -714,19 +735,28 @@ __device__ inline void unit_pre(const Problem &p, const StepArgs &a, const Ptrs 
                 if (e < kp * kp) {
                     V[i * Ld.ld + jj] = vpre[j];
                     if (B) B[i * Ld.ld + jj] = bpre[j];
+                    if (i >= k || jj >= k) sm[i * Ld.ld + jj] = 0.0;  // X beyond order k
                 }
             }
         } else {
+            if (tid < nr) svec_rc(tid, k, P.ii, P.jj);
             yrows();
             for (int e = tid; e < kp * kp; e += kBlock) {
                 const int i = e / kp, jj = e - (e / kp) * kp;
                 const bool in_k = i < k && jj < k;
                 V[i * Ld.ld + jj] = in_k ? Vg[i * k + jj] : 0.0;
                 if (B) B[i * Ld.ld + jj] = in_k ? Bg[i * k + jj] : 0.0;
+                if (!in_k) sm[i * Ld.ld + jj] = 0.0;
             }
         }
+        // the raw rows as the symmetric matrix X (the gather buffer may have used the region)
+        for (int i = tid; i < nr; i += kBlock) {
+            int ii = P.ii, jj = P.jj;
+            if (i != tid) svec_rc(i, k, ii, jj);
+            smat_put(sm, Ld.ld, ii, jj, tb[i]);
+        }
         __syncthreads();
-        psd_apply(k, Ld, sm, Bg, tin, jout);  // ends with a barrier
+        psd_apply(k, Ld, sm, Bg);  // ends with a barrier; J t in the X region
     } else if (u.type == U_SOC) {
         int cr0 = 0, cdim = 0;
         if (cone < u.end) {
@@ -793,22 +823,34 @@ __device__ inline void unit_post(const Problem &p, const StepArgs &a, const Ptrs
     double *tb, *rb, *jt, *ub, *gb;
     unit_bufs(p, u, sm, nr, tb, rb, jt, ub, gb);
     (void)gb;
+    const bool psd = u.type == U_PSD;
+    const int k = u.k, ld = psd ? psd_lds(k).ld : 0;
     for (int i = tid; i < nr; i += kBlock) {
         Fin f;
         if (i == tid) f = P.f;
         else fin_load(a, q, n + r0 + i, f);
-        const double o = fin_store(a, c, n + r0 + i, f, (jt[i] + rb[i]) * c.inv, s0);
+        int ii = P.ii, jj = P.jj;
+        if (psd && i != tid) svec_rc(i, k, ii, jj);
+        // PSD: J t is the matrix Y in the X region; each thread reads its own lower-triangle
+        // entries before it writes them, and no thread reads the upper triangle
+        const double jv = psd ? smat_get(sm, ld, ii, jj) : jt[i];
+        const double o = fin_store(a, c, n + r0 + i, f, (jv + rb[i]) * c.inv, s0);
         rb[i] = f.nxs * o;  // the next product's input, in place of r_y
+        if (psd && a.do_pre) smat_put(sm, ld, ii, jj, rb[i]);
     }
     if (!a.do_pre) return;
     __syncthreads();
     // J of the next product with F, on the scaled outputs (factors still staged)
     auto oin = [&](int i) { return rb[i]; };
     auto jout = [&](int i, double v) { jt[i] = v; };
-    if (u.type == U_PSD) {
-        const int k = u.k;
+    if (psd) {
         const double *Bg = p.psd_pool + p.psd_off[u.begin] + k * k;
-        psd_apply(k, psd_lds(k), sm, Bg, oin, jout);
+        psd_apply(k, psd_lds(k), sm, Bg);  // Y in the X region
+        for (int i = tid; i < nr; i += kBlock) {
+            int ii = P.ii, jj = P.jj;
+            if (i != tid) svec_rc(i, k, ii, jj);
+            jt[i] = smat_get(sm, ld, ii, jj);
+        }
     } else {
         const int cone = u.begin + tid;
         if (cone < u.end) {

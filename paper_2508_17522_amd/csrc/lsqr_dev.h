@@ -38,17 +38,22 @@ __device__ inline void finalize(LsqrState *st, int role, double t0, double t1, b
     case ROLE_V: {
         // plane rotation that eliminates beta (Paige & Saunders), then the x/w update is
         // owed to the next iteration's first kernel (or the final flush)
+        // one thread evaluates this between two barriers of every launch, so the chain of
+        // dependent FP64 operations is kept short: rho = sqrt(rhobar^2 + beta^2) (both are
+        // norms of scaled vectors, far from overflow) and one reciprocal for the four
+        // quotients by rho
         const double alpha = sqrt(t0);
         const double beta = st->beta, rhobar = st->rhobar;
-        const double rho = hypot(rhobar, beta);
+        const double rho = sqrt(rhobar * rhobar + beta * beta);
         if (!(rho > 0.0)) { st->done = 1; st->conv = 1; st->pending = 0; break; }
-        const double c = rhobar / rho, s = beta / rho;
+        const double ri = 1.0 / rho;
+        const double c = rhobar * ri, s = beta * ri;
         const double theta = s * alpha;
         const double phi = c * st->phibar;
         st->rhobar = -c * alpha;
         st->phibar = s * st->phibar;
-        st->phr = phi / rho;
-        st->thr = theta / rho;
+        st->phr = phi * ri;
+        st->thr = theta * ri;
         st->pending = 1;
         st->iters += 1;
         st->alpha = alpha;
