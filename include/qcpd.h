@@ -276,8 +276,9 @@ typedef struct {
  * problem after problem: P_rowptr has sum(n_i + 1) entries (each problem's local row
  * pointers, starting at 0), P_colind / P_val sum(nnz_P) entries with local column indices;
  * A likewise with sum(m_i + 1) row pointers; q, x: sum(n_i); b, y, s: sum(m_i).
- * opts->precond may be NONE or JACOBI; graph_chunk is the number of LSQR iterations (of all
- * problems) per captured HIP graph launch. */
+ * opts->precond may be NONE, JACOBI or EQUIL (each problem's two-sided equilibration is
+ * computed here, 20 sweeps); graph_chunk is the number of LSQR iterations (of all problems)
+ * per captured HIP graph launch. */
 qcpd_status qcpd_batch_create(qcpd_batch **hb, const qcpd_batch_layout *layout,
                               const int32_t *P_rowptr, const int32_t *P_colind, const double *P_val,
                               const int32_t *A_rowptr, const int32_t *A_colind, const double *A_val,
@@ -297,7 +298,7 @@ qcpd_status qcpd_batch_vjp(qcpd_batch *hb, const double *gx, const double *gy, c
                            double *dP_val, double *dA_val, double *dq, double *db,
                            qcpd_info *info);
 
-/* Replace the batch's LSQR options (tolerance, iteration cap, NONE or JACOBI). */
+/* Replace the batch's LSQR options (tolerance, iteration cap, NONE, JACOBI or EQUIL). */
 qcpd_status qcpd_batch_set_opts(qcpd_batch *hb, const qcpd_opts *opts);
 
 /* Persistent workgroups of the batch's per-problem phases (right-hand side and first product
