@@ -708,6 +708,20 @@ struct qcpd_batch {
     double *spart[2] = {nullptr, nullptr};   // per-item partial sums, double-buffered
     int *host_ndone = nullptr;               // pinned
     std::vector<int> nb_rows;                // n + m + 1 per problem
+    // work lists of the running problems only: host copies of the full lists, device
+    // buffers for the compacted ones, and the running count at the last compaction
+    std::vector<SegItem> h_fitems;
+    std::vector<Unit> h_tunits;
+    std::vector<int> h_tprob;
+    const SegItem *full_fitems = nullptr;
+    const Unit *full_tunits = nullptr;
+    const int *full_tprob = nullptr;
+    SegItem *c_fitems = nullptr;
+    Unit *c_tunits = nullptr;
+    int *c_tprob = nullptr, *c_fslot = nullptr, *c_tslot = nullptr;
+    int running_at = 0;
+    int seg_version = 0;
+    int graph_version[2] = {-1, -1};
 };
 
 namespace {
@@ -748,9 +762,12 @@ qcpd_status upload(qcpd_batch *h, T **dst, const std::vector<T> &src) {
         if (s_ != QCPD_OK) return s_;                    \
     } while (0)
 
+// Lanes per CSR row of the batched loop: a power of two (<= 64) that gives each lane about
+// kSegPerLane entries (the loop kernels keep that many in flight per lane).
+constexpr double kSegPerLane = 16.0;
 int lanes_of(double avg) {
     int L = 1;
-    while (L < 64 && 2 * L <= avg) L *= 2;
+    while (L < 64 && 2 * L * kSegPerLane <= avg) L *= 2;
     return L;
 }
 
@@ -1016,7 +1033,17 @@ qcpd_status batch_create_impl(qcpd_batch *h, const qcpd_batch_layout *L, const i
         SegGrid &g = h->seg;
         g.B = B; g.nf = (int)fitems.size(); g.nt = (int)tunits.size();
         g.fitems = d_fitems; g.foff = d_foff; g.tunits = d_tunits; g.tprob = d_tprob; g.toff = d_toff;
+        g.fslot = g.tslot = nullptr;
         fill_unit_ranges(p, d_tunits, g.nt, st);
+        h->h_fitems = fitems;
+        h->h_tunits.resize(tunits.size());
+        BCHK(hipMemcpyAsync(h->h_tunits.data(), d_tunits, sizeof(Unit) * tunits.size(),
+                            hipMemcpyDeviceToHost, st));
+        BCHK(hipStreamSynchronize(st));
+        h->h_tprob = tprob;
+        h->full_fitems = d_fitems; h->full_tunits = d_tunits; h->full_tprob = d_tprob;
+        BALLOC(h->c_fitems, g.nf); BALLOC(h->c_tunits, g.nt); BALLOC(h->c_tprob, g.nt);
+        BALLOC(h->c_fslot, g.nf); BALLOC(h->c_tslot, g.nt);
         g.lxs = d_lx; g.lys = d_ly; g.xPx = xpx;
         BALLOC(g.ndone, 1);
         const int slots = std::max(g.nf, g.nt);
@@ -1064,10 +1091,53 @@ void enqueue_seg_iteration(const qcpd_batch *h, int dir, hipStream_t s) {
     }
 }
 
+// Launch lists of the segmented loop: every item (all = true), or only the items of the
+// problems still running (their LSQR state not done; a stop is written to both state
+// buffers, so either shows it). Items keep their partial-sum slot, so the per-problem slot
+// ranges and the entry reductions are unchanged. Called between graph launches.
+qcpd_status seg_lists(qcpd_batch *h, bool all) {
+    SegGrid &g = h->seg;
+    const int B = h->d.B;
+    if (all) {
+        g.fitems = h->full_fitems; g.tunits = h->full_tunits; g.tprob = h->full_tprob;
+        g.fslot = g.tslot = nullptr;
+        g.nf = (int)h->h_fitems.size(); g.nt = (int)h->h_tunits.size();
+        h->running_at = B;
+        ++h->seg_version;
+        return QCPD_OK;
+    }
+    BCHK(hipMemcpyAsync(h->host_st.data(), h->stl[0], sizeof(LsqrState) * B, hipMemcpyDeviceToHost,
+                        h->stream));
+    BCHK(hipStreamSynchronize(h->stream));
+    std::vector<SegItem> fi;
+    std::vector<Unit> tu;
+    std::vector<int> tp, fs, ts;
+    int running = 0;
+    for (int b = 0; b < B; ++b) running += h->host_st[b].done ? 0 : 1;
+    for (size_t i = 0; i < h->h_fitems.size(); ++i)
+        if (!h->host_st[h->h_fitems[i].prob].done) { fi.push_back(h->h_fitems[i]); fs.push_back((int)i); }
+    for (size_t i = 0; i < h->h_tunits.size(); ++i)
+        if (!h->host_st[h->h_tprob[i]].done) {
+            tu.push_back(h->h_tunits[i]); tp.push_back(h->h_tprob[i]); ts.push_back((int)i);
+        }
+    if (fi.empty() || tu.empty()) return QCPD_OK;  // nothing runs: the caller stops
+    BCHK(hipMemcpyAsync(h->c_fitems, fi.data(), sizeof(SegItem) * fi.size(), hipMemcpyHostToDevice, h->stream));
+    BCHK(hipMemcpyAsync(h->c_fslot, fs.data(), sizeof(int) * fs.size(), hipMemcpyHostToDevice, h->stream));
+    BCHK(hipMemcpyAsync(h->c_tunits, tu.data(), sizeof(Unit) * tu.size(), hipMemcpyHostToDevice, h->stream));
+    BCHK(hipMemcpyAsync(h->c_tprob, tp.data(), sizeof(int) * tp.size(), hipMemcpyHostToDevice, h->stream));
+    BCHK(hipMemcpyAsync(h->c_tslot, ts.data(), sizeof(int) * ts.size(), hipMemcpyHostToDevice, h->stream));
+    BCHK(hipStreamSynchronize(h->stream));  // the host vectors go out of scope
+    g.fitems = h->c_fitems; g.fslot = h->c_fslot; g.nf = (int)fi.size();
+    g.tunits = h->c_tunits; g.tprob = h->c_tprob; g.tslot = h->c_tslot; g.nt = (int)tu.size();
+    h->running_at = running;
+    ++h->seg_version;
+    return QCPD_OK;
+}
+
 qcpd_status seg_graph(qcpd_batch *h, int dir) {
     const int chunk = std::max(1, h->opts.graph_chunk);
     if (h->graph[dir] && h->graph_chunk[dir] == chunk && h->graph_sc[dir] == h->d.sc &&
-        h->graph_scl[dir] == h->d.scl)
+        h->graph_scl[dir] == h->d.scl && h->graph_version[dir] == h->seg_version)
         return QCPD_OK;
     if (h->graph[dir]) {
         hipGraphExecDestroy(h->graph[dir]);
@@ -1086,6 +1156,7 @@ qcpd_status seg_graph(qcpd_batch *h, int dir) {
     h->graph_chunk[dir] = chunk;
     h->graph_sc[dir] = h->d.sc;
     h->graph_scl[dir] = h->d.scl;
+    h->graph_version[dir] = h->seg_version;
     return QCPD_OK;
 }
 
@@ -1101,7 +1172,9 @@ qcpd_status batch_run(qcpd_batch *h, int dir, const double *i0, const double *i1
     }
     h->d.tol = h->opts.tol;
     h->d.max_iter = h->opts.max_iter;
-    qcpd_status rc = seg_graph(h, dir);
+    qcpd_status rc = seg_lists(h, true);
+    if (rc != QCPD_OK) return rc;
+    rc = seg_graph(h, dir);
     if (rc != QCPD_OK) return rc;
     BCHK(hipMemsetAsync(h->d.queue, 0, 2 * sizeof(int), s));
     BCHK(hipMemsetAsync(h->seg.ndone, 0, sizeof(int), s));
@@ -1119,6 +1192,12 @@ qcpd_status batch_run(qcpd_batch *h, int dir, const double *i0, const double *i1
             BCHK(hipMemcpyAsync(h->host_ndone, h->seg.ndone, sizeof(int), hipMemcpyDeviceToHost, s));
             BCHK(hipStreamSynchronize(s));
             if (*h->host_ndone >= h->d.B || l >= max_launch) break;
+            // once half of the problems launched for have stopped, launch only the rest
+            if (2 * (h->d.B - *h->host_ndone) <= h->running_at) {
+                rc = seg_lists(h, false);
+                if (rc == QCPD_OK) rc = seg_graph(h, dir);
+                if (rc != QCPD_OK) return rc;
+            }
             BCHK(hipGraphLaunch(h->graph[dir], s));
         }
         BCHK(hipMemsetAsync(h->d.queue + 1, 0, sizeof(int), s));
@@ -1132,6 +1211,9 @@ qcpd_status batch_run(qcpd_batch *h, int dir, const double *i0, const double *i1
         if (resumed == 0) break;
         *h->host_ndone = h->d.B - resumed;  // the resumed problems count as running again
         BCHK(hipMemcpyAsync(h->seg.ndone, h->host_ndone, sizeof(int), hipMemcpyHostToDevice, s));
+        rc = seg_lists(h, false);
+        if (rc == QCPD_OK) rc = seg_graph(h, dir);
+        if (rc != QCPD_OK) return rc;
     }
     BCHK(hipEventRecord(h->ev1, s));
     BCHK(hipMemcpyAsync(h->host_st.data(), h->st, sizeof(LsqrState) * h->d.B, hipMemcpyDeviceToHost, s));

@@ -87,11 +87,11 @@ __device__ inline void block_sum2(double &a, double &b) {
 }
 
 // This workgroup's partial sums for the next launch (plain stores).
-__device__ inline void leave(const StepArgs &a, double s0, double s1) {
+__device__ inline void leave(const StepArgs &a, double s0, double s1, int slot) {
     block_sum2(s0, s1);
     if (threadIdx.x == 0) {
-        a.part_next[3 * blockIdx.x] = s0;
-        a.part_next[3 * blockIdx.x + 1] = s1;
+        a.part_next[3 * slot] = s0;
+        a.part_next[3 * slot + 1] = s1;
     }
 }
 
@@ -218,6 +218,42 @@ __device__ inline double csr_dot(const int *col, const double *val, int k0, int 
                                  int L, const double *x, const double *sc, int off) {
     return sc ? csr_dot4<true>(col, val, k0, k1, lane, L, x, sc, off)
               : csr_dot4<false>(col, val, k0, k1, lane, L, x, sc, off);
+}
+
+// As csr_dot4 with kDeep entries per lane in flight: the batched loop gives each lane about
+// that many entries (fewer lanes per row, more rows per workgroup), so a launch needs far
+// fewer workgroups and each keeps more of the memory system busy.
+constexpr int kDeep = 16;
+
+template <bool SC>
+__device__ inline double csr_dot_deep(const int *col, const double *val, int k0, int k1,
+                                      int lane, int L, const double *x, const double *sc,
+                                      int off) {
+    double acc = 0.0;
+    for (int k = k0 + lane; k < k1; k += kDeep * L) {
+        int j[kDeep];
+        double v[kDeep], xv[kDeep];
+#pragma unroll
+        for (int u = 0; u < kDeep; ++u) {
+            const int kk = min(k + u * L, k1 - 1);
+            j[u] = col[kk] + off;
+            v[u] = val[kk];
+        }
+#pragma unroll
+        for (int u = 0; u < kDeep; ++u) xv[u] = SC ? x[j[u]] * sc[j[u]] : x[j[u]];
+#pragma unroll
+        for (int u = 0; u < kDeep; ++u)
+            if (k + u * L < k1) acc += v[u] * xv[u];
+    }
+    return acc;
+}
+
+template <bool DEEP>
+__device__ inline double csr_dot_d(const int *col, const double *val, int k0, int k1, int lane,
+                                   int L, const double *x, const double *sc, int off) {
+    if (!DEEP) return csr_dot(col, val, k0, k1, lane, L, x, sc, off);
+    return sc ? csr_dot_deep<true>(col, val, k0, k1, lane, L, x, sc, off)
+              : csr_dot_deep<false>(col, val, k0, k1, lane, L, x, sc, off);
 }
 
 struct Fin {
@@ -367,7 +403,7 @@ __global__ __launch_bounds__(kBlock) void k_loop_F(Problem p, StepArgs a, RowGri
         rows_pre(p, a, q, g, vb, r);
         rows_post(p, a, c, S, r, s0, s1);
     }
-    leave(a, s0, s1);
+    leave(a, s0, s1, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -622,6 +658,8 @@ __device__ inline double smat_get(const double *Y, int ld, int ii, int jj) {
     return ii == jj ? Y[ii * ld + ii] : Y[ii * ld + jj] * kSqrt2;
 }
 
+// DEEP: the row units' CSR sums keep kDeep entries per lane in flight (batched loop)
+template <bool DEEP = false>
 __device__ inline void unit_pre(const Problem &p, const StepArgs &a, const Ptrs &q, int lx,
                                 int ly, const Unit &u, double *sm, double in_N_raw,
                                 UnitPre &P) {
@@ -634,8 +672,8 @@ __device__ inline void unit_pre(const Problem &p, const StepArgs &a, const Ptrs 
         if (row < u.end) {
             const int k0 = p.Prp[row], k1 = p.Prp[row + 1];
             const int t0 = p.Trp[row], t1 = p.Trp[row + 1];
-            acc = csr_dot(p.Pci, q.Pv, k0, k1, lane, L, a.in, q.gsc, 0);
-            accT = csr_dot(p.Tci, q.Tv, t0, t1, lane, L, a.in, q.gsc, n);
+            acc = csr_dot_d<DEEP>(p.Pci, q.Pv, k0, k1, lane, L, a.in, q.gsc, 0);
+            accT = csr_dot_d<DEEP>(p.Tci, q.Tv, t0, t1, lane, L, a.in, q.gsc, n);
         }
         P.acc = group_sum_dpp(acc, L);
         P.accT = group_sum_dpp(accT, L);
@@ -651,7 +689,7 @@ __device__ inline void unit_pre(const Problem &p, const StepArgs &a, const Ptrs 
         double acc = 0.0;
         if (r < u.end) {
             const int k0 = p.Arp[r], k1 = p.Arp[r + 1];
-            acc = csr_dot(p.Aci, q.Av, k0, k1, lane, L, a.in, q.gsc, 0);
+            acc = csr_dot_d<DEEP>(p.Aci, q.Av, k0, k1, lane, L, a.in, q.gsc, 0);
         }
         P.acc = group_sum_dpp(acc, L);
         if (r < u.end && lane == 0) {
@@ -905,7 +943,7 @@ __device__ inline void loop_FT_body(const Problem &p, const StepArgs &a, const F
         fin_load(a, q, N - 1, f);
         fin_store(a, c, N - 1, f, S.dot_adj * c.inv + p.xPx * c.in_N, s0);
     }
-    leave(a, s0, s1);
+    leave(a, s0, s1, blockIdx.x);
 }
 
 __global__ __launch_bounds__(kBlock) void k_loop_FT(Problem p, StepArgs a, FusedGrid g) {
@@ -998,10 +1036,10 @@ __device__ inline void seg_rows_pre(const Problem &p, const StepArgs &a, const P
     double acc = 0.0, accT = 0.0;
     if (row < it.end) {
         if (it.type == 0) {
-            acc = csr_dot(p.Pci, q.Pv, p.Prp[row], p.Prp[row + 1], lane, L, a.in, q.gsc, 0);
-            accT = csr_dot(p.Tci, p.Tv, p.Trp[row], p.Trp[row + 1], lane, L, a.wy, nullptr, 0);
+            acc = csr_dot_d<true>(p.Pci, q.Pv, p.Prp[row], p.Prp[row + 1], lane, L, a.in, q.gsc, 0);
+            accT = csr_dot_d<true>(p.Tci, p.Tv, p.Trp[row], p.Trp[row + 1], lane, L, a.wy, nullptr, 0);
         } else {
-            acc = csr_dot(p.Aci, q.Av, p.Arp[row], p.Arp[row + 1], lane, L, a.in, q.gsc, 0);
+            acc = csr_dot_d<true>(p.Aci, q.Av, p.Arp[row], p.Arp[row + 1], lane, L, a.in, q.gsc, 0);
         }
     }
     r.acc = group_sum_dpp(acc, L);
@@ -1035,8 +1073,9 @@ __device__ inline void seg_rows_post(const StepArgs &a, const Ctx &c, const SegI
 __global__ __launch_bounds__(kBlock) void k_seg_F(Problem p, StepArgs a, SegGrid g) {
     __shared__ LsqrState S;
     const SegItem it = g.fitems[blockIdx.x];
+    const int slot = g.fslot ? g.fslot[blockIdx.x] : (int)blockIdx.x;
     const int b = it.prob;
-    const bool first = (int)blockIdx.x == g.foff[b];
+    const bool first = slot == g.foff[b];
     SegEntry e;
     seg_entry_issue(a, b, g.toff, e);
     const Ptrs q = ptrs_of(p, a);
@@ -1053,7 +1092,7 @@ __global__ __launch_bounds__(kBlock) void k_seg_F(Problem p, StepArgs a, SegGrid
         fin_load(a, q, tix, f);
         fin_store(a, c, tix, f, S.dot_fwd * c.inv + g.xPx[b] * c.in_N, s0);
     }
-    leave(a, s0, s1);
+    leave(a, s0, s1, slot);
 }
 
 __global__ __launch_bounds__(kBlock) void k_seg_FT(Problem p, StepArgs a, SegGrid g) {
@@ -1061,14 +1100,15 @@ __global__ __launch_bounds__(kBlock) void k_seg_FT(Problem p, StepArgs a, SegGri
     __shared__ LsqrState S;
     const Unit u = g.tunits[blockIdx.x];
     const int b = g.tprob[blockIdx.x];
-    const bool first = (int)blockIdx.x == g.toff[b];
+    const int slot = g.tslot ? g.tslot[blockIdx.x] : (int)blockIdx.x;
+    const bool first = slot == g.toff[b];
     SegEntry e;
     seg_entry_issue(a, b, g.foff, e);
     const Ptrs q = ptrs_of(p, a);
     const int tix = p.n + p.m + b;
     const double in_N_raw = in_raw(a, q, tix);
     UnitPre P;
-    unit_pre(p, a, q, g.lxs[b], g.lys[b], u, sm, in_N_raw, P);
+    unit_pre<true>(p, a, q, g.lxs[b], g.lys[b], u, sm, in_N_raw, P);
     if (!seg_entry_finish(a, e, b, first, g.ndone, &S, 1)) return;
     const Ctx c = scalars(a, S, q, in_N_raw);
     double s0 = 0.0, s1 = 0.0;
@@ -1078,7 +1118,7 @@ __global__ __launch_bounds__(kBlock) void k_seg_FT(Problem p, StepArgs a, SegGri
         fin_load(a, q, tix, f);
         fin_store(a, c, tix, f, S.dot_adj * c.inv + g.xPx[b] * c.in_N, s0);
     }
-    leave(a, s0, s1);
+    leave(a, s0, s1, slot);
 }
 
 // ---------------------------------------------------------------------------------------

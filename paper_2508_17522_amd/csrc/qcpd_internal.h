@@ -253,12 +253,15 @@ struct SegItem {
     int begin, end, prob;
 };
 struct SegGrid {
-    int B, nf, nt;
+    int B, nf, nt;        // items launched (all, or those of the running problems)
     const SegItem *fitems;
-    const int *foff;      // B + 1: items of problem b are [foff[b], foff[b + 1])
+    const int *foff;      // B + 1: items of problem b are [foff[b], foff[b + 1]) (all items)
     const Unit *tunits;
     const int *tprob;     // problem of each F' unit
     const int *toff;      // B + 1
+    // launched item i is item fslot[i] / tslot[i] of the full lists (its partial-sum slot);
+    // null: the launch covers every item in order
+    const int *fslot, *tslot;
     const int *lxs, *lys; // lanes per CSR row, per problem
     const double *xPx;    // per problem
     int *ndone;           // problems whose LSQR has stopped
