@@ -764,7 +764,7 @@ qcpd_status upload(qcpd_batch *h, T **dst, const std::vector<T> &src) {
 
 // Lanes per CSR row of the batched loop: a power of two (<= 64) that gives each lane about
 // kSegPerLane entries (the loop kernels keep that many in flight per lane).
-constexpr double kSegPerLane = 16.0;
+constexpr double kSegPerLane = 32.0;
 int lanes_of(double avg) {
     int L = 1;
     while (L < 64 && 2 * L * kSegPerLane <= avg) L *= 2;
