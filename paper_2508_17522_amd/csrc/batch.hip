@@ -721,6 +721,8 @@ struct qcpd_batch {
     int *c_tprob = nullptr, *c_fslot = nullptr, *c_tslot = nullptr;
     int running_at = 0;
     int seg_version = 0;
+    // values of the union's P, A, A' with a scale folded in: [0] sc, [1] scl (per run)
+    double *sval[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
     int graph_version[2] = {-1, -1};
 };
 
@@ -1066,6 +1068,36 @@ qcpd_status batch_create_impl(qcpd_batch *h, const qcpd_batch_layout *L, const i
 }
 
 // One LSQR iteration of every problem (two launches, states and partials double-buffered).
+// Fold the run's scales into copies of the union's CSR values (the loop kernels then read
+// one value per entry instead of a value and a gathered scale).
+qcpd_status seg_bake(qcpd_batch *h) {
+    const Problem &p = h->d.p;
+    const double *sv[2] = {h->d.sc, h->d.scl};
+    for (int j = 0; j < 2; ++j) {
+        if (!sv[j] || p.nnzP == 0 || p.nnzA == 0) continue;
+        if (!h->sval[j][0]) {
+            BALLOC(h->sval[j][0], p.nnzP);
+            BALLOC(h->sval[j][1], p.nnzA);
+            BALLOC(h->sval[j][2], p.nnzA);
+        }
+        launch_scale_vals(p.Pci, p.Pv, p.nnzP, sv[j], 0, h->sval[j][0], h->stream);
+        launch_scale_vals(p.Aci, p.Av, p.nnzA, sv[j], 0, h->sval[j][1], h->stream);
+        launch_scale_vals(p.Tci, p.Tv, p.nnzA, sv[j], p.n, h->sval[j][2], h->stream);
+    }
+    BCHK(hipGetLastError());
+    return QCPD_OK;
+}
+
+void seg_baked(const qcpd_batch *h, StepArgs &a) {
+    const int j = a.in_is_v ? 0 : 1;
+    const double *isc = a.in_is_v ? a.sc : a.scl;
+    if (isc && h->sval[j][0]) {
+        a.Pvs = h->sval[j][0];
+        a.Avs = h->sval[j][1];
+        a.Tvs = h->sval[j][2];
+    }
+}
+
 void enqueue_seg_iteration(const qcpd_batch *h, int dir, hipStream_t s) {
     const BatchDev &d = h->d;
     StepArgs a{};
@@ -1076,17 +1108,21 @@ void enqueue_seg_iteration(const qcpd_batch *h, int dir, hipStream_t s) {
     if (dir == 0) {
         StepArgs &f = first;  // u~ <- F(sc o v) - alpha u~ (and the owed x, w update)
         f.in = d.v; f.in_nrm = NRM_ALPHA; f.in_is_v = 1; f.out = d.u; f.role = ROLE_U; f.do_update = 1;
+        seg_baked(h, f);
         launch_seg_F(d.p, f, h->seg, s);
         StepArgs &t = second;  // v~ <- sc o F'u - beta v~, then J(sc o v~)
         t.in = d.u; t.in_nrm = NRM_BETA; t.out = d.v; t.role = ROLE_V; t.out_is_v = 1; t.do_pre = 1;
+        seg_baked(h, t);
         launch_seg_FT(d.p, t, h->seg, h->lds_seg, s);
     } else {
         StepArgs &t = first;  // u~ <- F'(sc o v) - alpha u~ (and the owed update), J(u~)
         t.in = d.v; t.in_nrm = NRM_ALPHA; t.in_is_v = 1; t.out = d.u; t.role = ROLE_U;
         t.do_update = 1; t.do_pre = 1;
+        seg_baked(h, t);
         launch_seg_FT(d.p, t, h->seg, h->lds_seg, s);
         StepArgs &f = second;  // v~ <- sc o F u - beta v~
         f.in = d.u; f.in_nrm = NRM_BETA; f.out = d.v; f.role = ROLE_V; f.out_is_v = 1;
+        seg_baked(h, f);
         launch_seg_F(d.p, f, h->seg, s);
     }
 }
@@ -1172,7 +1208,9 @@ qcpd_status batch_run(qcpd_batch *h, int dir, const double *i0, const double *i1
     }
     h->d.tol = h->opts.tol;
     h->d.max_iter = h->opts.max_iter;
-    qcpd_status rc = seg_lists(h, true);
+    qcpd_status rc = seg_bake(h);
+    if (rc != QCPD_OK) return rc;
+    rc = seg_lists(h, true);
     if (rc != QCPD_OK) return rc;
     rc = seg_graph(h, dir);
     if (rc != QCPD_OK) return rc;
