@@ -118,7 +118,29 @@ __device__ inline void entry_issue(const StepArgs &a, Entry &e) {
     }
 }
 
-// Finalise the previous launch's reduction into S; false in every thread once LSQR stopped.
+// Sums of a and b over the workgroup, valid in every thread (the same fixed order as
+// block_sum2, so every thread holds the same bits).
+__device__ inline void block_sum2_all(double &a, double &b) {
+    __shared__ double sh[2][kBlock / kWave];
+    a = wave_total_dpp(a);
+    b = wave_total_dpp(b);
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    if (lane == kWave - 1) {
+        sh[0][w] = a;
+        sh[1][w] = b;
+    }
+    __syncthreads();
+    a = sh[0][0];
+    b = sh[1][0];
+    for (int i = 1; i < kBlock / kWave; ++i) {
+        a += sh[0][i];
+        b += sh[1][i];
+    }
+}
+
+// Finalise the previous launch's reduction into S (a copy per thread: every thread holds
+// the totals and evaluates the same scalars, so no broadcast or second barrier is needed);
+// false in every thread once LSQR stopped.
 __device__ inline bool entry_finish(const StepArgs &a, const Entry &e, LsqrState *S, int my_fwd) {
     const int tid = threadIdx.x;
     if (e.st.done) {
@@ -133,29 +155,24 @@ __device__ inline bool entry_finish(const StepArgs &a, const Entry &e, LsqrState
                 t0 += e.pa[j];
                 t1 += e.pb[j];
             }
-        block_sum2(t0, t1);
+        block_sum2_all(t0, t1);
     }
-    if (tid == 0) {
-        LsqrState s = e.st;
-        if (s.pend_role >= 0) {
-            finalize(&s, s.pend_role, t0, t1, s.pend_fwd != 0);
-        }
-        if (s.done) {
-            s.pend_role = -1;
-        } else {
-            s.pend_role = a.role;
-            s.pend_blocks = gridDim.x;
-            s.pend_fwd = my_fwd;
-        }
-        if (blockIdx.x == 0) {
-            *a.st_next = s;
-            // on the stop decision both buffers get the final state
-            if (s.done) *a.st = s;
-        }
-        *S = s;
+    LsqrState s = e.st;
+    if (s.pend_role >= 0) finalize(&s, s.pend_role, t0, t1, s.pend_fwd != 0);
+    if (s.done) {
+        s.pend_role = -1;
+    } else {
+        s.pend_role = a.role;
+        s.pend_blocks = gridDim.x;
+        s.pend_fwd = my_fwd;
     }
-    __syncthreads();
-    return !S->done;
+    if (blockIdx.x == 0 && tid == 0) {
+        *a.st_next = s;
+        // on the stop decision both buffers get the final state
+        if (s.done) *a.st = s;
+    }
+    *S = s;
+    return !s.done;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -388,7 +405,7 @@ __device__ inline void rows_post(const Problem &p, const StepArgs &a, const Ctx 
 }
 
 __global__ __launch_bounds__(kBlock) void k_loop_F(Problem p, StepArgs a, RowGrid g) {
-    __shared__ LsqrState S;
+    LsqrState S;  // per thread (entry_finish)
     Entry e;
     const Ptrs q = ptrs_of(p, a);
     const double in_N_raw = in_raw(a, q, p.N - 1);
@@ -948,13 +965,13 @@ __device__ inline void loop_FT_body(const Problem &p, const StepArgs &a, const F
 
 __global__ __launch_bounds__(kBlock) void k_loop_FT(Problem p, StepArgs a, FusedGrid g) {
     extern __shared__ double sm[];
-    __shared__ LsqrState S;
+    LsqrState S;  // per thread (entry_finish)
     loop_FT_body<false>(p, a, g, sm, S);
 }
 
 __global__ __launch_bounds__(kBlock) void k_loop_FT_multi(Problem p, StepArgs a, FusedGrid g) {
     extern __shared__ double sm[];
-    __shared__ LsqrState S;
+    LsqrState S;  // per thread (entry_finish)
     loop_FT_body<true>(p, a, g, sm, S);
 }
 
@@ -1004,28 +1021,25 @@ __device__ inline bool seg_entry_finish(const StepArgs &a, const SegEntry &e, in
             t0 += a.part_prev[3 * (e.c0 + i)];
             t1 += a.part_prev[3 * (e.c0 + i) + 1];
         }
-        block_sum2(t0, t1);
+        block_sum2_all(t0, t1);
     }
-    if (tid == 0) {
-        LsqrState s = e.st;
-        if (s.pend_role >= 0) finalize(&s, s.pend_role, t0, t1, s.pend_fwd != 0);
+    LsqrState s = e.st;  // per thread, as entry_finish
+    if (s.pend_role >= 0) finalize(&s, s.pend_role, t0, t1, s.pend_fwd != 0);
+    if (s.done) {
+        s.pend_role = -1;
+    } else {
+        s.pend_role = a.role;
+        s.pend_fwd = my_fwd;
+    }
+    if (first && tid == 0) {
+        a.st_next[b] = s;
         if (s.done) {
-            s.pend_role = -1;
-        } else {
-            s.pend_role = a.role;
-            s.pend_fwd = my_fwd;
+            a.st[b] = s;
+            atomicAdd(ndone, 1);
         }
-        if (first) {
-            a.st_next[b] = s;
-            if (s.done) {
-                a.st[b] = s;
-                atomicAdd(ndone, 1);
-            }
-        }
-        *S = s;
     }
-    __syncthreads();
-    return !S->done;
+    *S = s;
+    return !s.done;
 }
 
 // rows of one item of the product with F (x rows: P and A'wy; y rows: A), as rows_pre
@@ -1071,7 +1085,7 @@ __device__ inline void seg_rows_post(const StepArgs &a, const Ctx &c, const SegI
 }
 
 __global__ __launch_bounds__(kBlock) void k_seg_F(Problem p, StepArgs a, SegGrid g) {
-    __shared__ LsqrState S;
+    LsqrState S;  // per thread (entry_finish)
     const SegItem it = g.fitems[blockIdx.x];
     const int slot = g.fslot ? g.fslot[blockIdx.x] : (int)blockIdx.x;
     const int b = it.prob;
@@ -1097,7 +1111,7 @@ __global__ __launch_bounds__(kBlock) void k_seg_F(Problem p, StepArgs a, SegGrid
 
 __global__ __launch_bounds__(kBlock) void k_seg_FT(Problem p, StepArgs a, SegGrid g) {
     extern __shared__ double sm[];
-    __shared__ LsqrState S;
+    LsqrState S;  // per thread (entry_finish)
     const Unit u = g.tunits[blockIdx.x];
     const int b = g.tprob[blockIdx.x];
     const int slot = g.tslot ? g.tslot[blockIdx.x] : (int)blockIdx.x;
