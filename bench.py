@@ -260,12 +260,13 @@ def run_kernels_only(args):
     ms = Q.qcpd_profile_kernels(h, reps=args.kernels_only)
     h.close()
     torch.cuda.synchronize()
+    us = {"k_loop_F": ms[0] * 1e3, "k_loop_FT": ms[1] * 1e3}
+    nb = {k: kernel_bytes(q, k) for k in us}
+    gbs = {k: nb[k] / us[k] / 1e3 for k in us}
     print(json.dumps({"kernels_only": {"workload": q.name, "reps": args.kernels_only,
-                                       "avg_launch_us": {"k_loop_F": ms[0] * 1e3,
-                                                         "k_loop_FT": ms[1] * 1e3},
-                                       "bytes_per_launch": {
-                                           "k_loop_F": kernel_bytes(q, "k_loop_F"),
-                                           "k_loop_FT": kernel_bytes(q, "k_loop_FT")}}}),
+                                       "avg_launch_us": us, "bytes_per_launch": nb,
+                                       "achieved_GBps": gbs,
+                                       "frac_of_hbm_peak": {k: gbs[k] / HBM_PEAK_GBS for k in us}}}),
           flush=True)
 
 

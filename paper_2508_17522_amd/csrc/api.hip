@@ -469,8 +469,18 @@ qcpd_status create_impl(qcpd_handle *h, const qcpd_csr *P, const qcpd_csr *A, co
     RowGrid &rg = h->rg;
     const double avg_x = n ? (double)(P->nnz + A->nnz) / n : 1.0;
     const double avg_y = m ? (double)A->nnz / m : 1.0;
+    // Large problems (the product with F at one entry per lane would need more workgroups
+    // than a loop launch has) switch the F' loop kernel to deep CSR sums: about 32 entries
+    // per lane, kDeep of them in flight, so each workgroup streams more per round. The
+    // product with F stays at one entry per lane (measured faster at both large sizes).
+    // QCPD_DEEP=0/1 forces the choice (tuning).
+    bool deep = div_up((long long)n * lanes_for(avg_x, 1), kBlock) +
+                    div_up((long long)(m + 1) * lanes_for(avg_y, 1), kBlock) >
+                kLoopGrid;
+    if (const char *e = getenv("QCPD_DEEP")) deep = atoi(e) != 0;
     const int npl_F = nnz_per_lane("QCPD_NNZ_PER_LANE_F", 1);
-    const int npl_T = nnz_per_lane("QCPD_NNZ_PER_LANE_FT", 2);
+    const int npl_T = nnz_per_lane("QCPD_NNZ_PER_LANE_FT", deep ? 32 : 2);
+    h->fg.deep = deep ? 1 : 0;
     rg.lx = lanes_for(avg_x, npl_F);
     rg.ly = lanes_for(avg_y, npl_F);
     rg.bx = div_up((long long)n * rg.lx, kBlock);

@@ -342,6 +342,7 @@ struct RowPre {
     Fin f;
 };
 
+template <bool DEEP>
 __device__ inline void rows_pre(const Problem &p, const StepArgs &a, const Ptrs &q,
                                 const RowGrid &g, int vb, RowPre &r) {
     const int n = p.n, m = p.m, N = p.N;
@@ -356,14 +357,14 @@ __device__ inline void rows_pre(const Problem &p, const StepArgs &a, const Ptrs 
         if (row < n) {
             const int k0 = p.Prp[row], k1 = p.Prp[row + 1];
             const int t0 = p.Trp[row], t1 = p.Trp[row + 1];
-            acc = csr_dot(p.Pci, q.Pv, k0, k1, lane, L, a.in, q.gsc, 0);
-            accT = csr_dot(p.Tci, p.Tv, t0, t1, lane, L, a.wy, nullptr, 0);
+            acc = csr_dot_d<DEEP>(p.Pci, q.Pv, k0, k1, lane, L, a.in, q.gsc, 0);
+            accT = csr_dot_d<DEEP>(p.Tci, p.Tv, t0, t1, lane, L, a.wy, nullptr, 0);
             idx = row;
         }
     } else {
         if (row < m) {
             const int k0 = p.Arp[row], k1 = p.Arp[row + 1];
-            acc = csr_dot(p.Aci, q.Av, k0, k1, lane, L, a.in, q.gsc, 0);
+            acc = csr_dot_d<DEEP>(p.Aci, q.Av, k0, k1, lane, L, a.in, q.gsc, 0);
             idx = n + row;
         } else if (row == m) {
             idx = N - 1;
@@ -404,24 +405,30 @@ __device__ inline void rows_post(const Problem &p, const StepArgs &a, const Ctx 
     if (r.idx < N - 1) s1 += r.qb * r.f.nxs * o;
 }
 
-__global__ __launch_bounds__(kBlock) void k_loop_F(Problem p, StepArgs a, RowGrid g) {
+template <bool DEEP>
+__device__ inline void loop_F_body(const Problem &p, const StepArgs &a, const RowGrid &g) {
     LsqrState S;  // per thread (entry_finish)
     Entry e;
     const Ptrs q = ptrs_of(p, a);
     const double in_N_raw = in_raw(a, q, p.N - 1);
     RowPre r;
-    rows_pre(p, a, q, g, blockIdx.x, r);
+    rows_pre<DEEP>(p, a, q, g, blockIdx.x, r);
     entry_issue(a, e);  // after the row loads: the memory counter is in order
     if (!entry_finish(a, e, &S, 0)) return;
     const Ctx c = scalars(a, S, q, in_N_raw);
     double s0 = 0.0, s1 = 0.0;
     rows_post(p, a, c, S, r, s0, s1);
     for (int vb = blockIdx.x + gridDim.x; vb < g.bx + g.by; vb += gridDim.x) {
-        rows_pre(p, a, q, g, vb, r);
+        rows_pre<DEEP>(p, a, q, g, vb, r);
         rows_post(p, a, c, S, r, s0, s1);
     }
     leave(a, s0, s1, blockIdx.x);
 }
+
+__global__ __launch_bounds__(kBlock) void k_loop_F(Problem p, StepArgs a, RowGrid g) {
+    loop_F_body<false>(p, a, g);
+}
+
 
 // ---------------------------------------------------------------------------------------
 // product with F', fused with the cone Jacobians (work units as in k_fused_FT)
@@ -925,7 +932,7 @@ __device__ inline void unit_post(const Problem &p, const StepArgs &a, const Ptrs
 // fewer workgroups than units); else exactly unit blockIdx.x. The single-unit form needs
 // about half the registers (a loop around the unit code keeps more of it live), so it runs
 // at twice the occupancy.
-template <bool MULTI>
+template <bool MULTI, bool DEEP>
 __device__ inline void loop_FT_body(const Problem &p, const StepArgs &a, const FusedGrid &g,
                                     double *sm, LsqrState &S) {
     Entry e;
@@ -936,7 +943,7 @@ __device__ inline void loop_FT_body(const Problem &p, const StepArgs &a, const F
     double s0 = 0.0, s1 = 0.0;
     if (!MULTI) {
         const Unit u = g.units[blockIdx.x];
-        unit_pre(p, a, q, g.lx, g.ly, u, sm, in_N_raw, P);
+        unit_pre<DEEP>(p, a, q, g.lx, g.ly, u, sm, in_N_raw, P);
         entry_issue(a, e);  // after the unit's loads: the memory counter is in order
         if (!entry_finish(a, e, &S, 1)) return;
         c = scalars(a, S, q, in_N_raw);
@@ -945,7 +952,7 @@ __device__ inline void loop_FT_body(const Problem &p, const StepArgs &a, const F
         for (int ui = blockIdx.x; ui < g.nunits; ui += gridDim.x) {
             if (ui != (int)blockIdx.x) __syncthreads();  // LDS of the previous unit is free
             const Unit u = g.units[ui];
-            unit_pre(p, a, q, g.lx, g.ly, u, sm, in_N_raw, P);
+            unit_pre<DEEP>(p, a, q, g.lx, g.ly, u, sm, in_N_raw, P);
             if (ui == (int)blockIdx.x) {
                 entry_issue(a, e);
                 if (!entry_finish(a, e, &S, 1)) return;
@@ -966,13 +973,25 @@ __device__ inline void loop_FT_body(const Problem &p, const StepArgs &a, const F
 __global__ __launch_bounds__(kBlock) void k_loop_FT(Problem p, StepArgs a, FusedGrid g) {
     extern __shared__ double sm[];
     LsqrState S;  // per thread (entry_finish)
-    loop_FT_body<false>(p, a, g, sm, S);
+    loop_FT_body<false, false>(p, a, g, sm, S);
 }
 
 __global__ __launch_bounds__(kBlock) void k_loop_FT_multi(Problem p, StepArgs a, FusedGrid g) {
     extern __shared__ double sm[];
-    LsqrState S;  // per thread (entry_finish)
-    loop_FT_body<true>(p, a, g, sm, S);
+    LsqrState S;
+    loop_FT_body<true, false>(p, a, g, sm, S);
+}
+
+__global__ __launch_bounds__(kBlock) void k_loop_FT_deep(Problem p, StepArgs a, FusedGrid g) {
+    extern __shared__ double sm[];
+    LsqrState S;
+    loop_FT_body<false, true>(p, a, g, sm, S);
+}
+
+__global__ __launch_bounds__(kBlock) void k_loop_FT_multi_deep(Problem p, StepArgs a, FusedGrid g) {
+    extern __shared__ double sm[];
+    LsqrState S;
+    loop_FT_body<true, true>(p, a, g, sm, S);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1183,6 +1202,8 @@ int loop_lds_bytes(const int *psd_orders, int n_psd) {
 void set_loop_kernel_lds(int bytes) {
     (void)hipFuncSetAttribute((const void *)k_loop_FT, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     (void)hipFuncSetAttribute((const void *)k_loop_FT_multi, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    (void)hipFuncSetAttribute((const void *)k_loop_FT_deep, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    (void)hipFuncSetAttribute((const void *)k_loop_FT_multi_deep, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 void launch_loop_F(const Problem &p, const StepArgs &a, const RowGrid &g, int grid, hipStream_t s) {
@@ -1191,10 +1212,12 @@ void launch_loop_F(const Problem &p, const StepArgs &a, const RowGrid &g, int gr
 
 void launch_loop_FT(const Problem &p, const StepArgs &a, const FusedGrid &g, int lds, int grid,
                     hipStream_t s) {
-    if (grid >= g.nunits)
-        hipLaunchKernelGGL(k_loop_FT, dim3(g.nunits), dim3(kBlock), lds, s, p, a, g);
+    const bool one = grid >= g.nunits;
+    if (one) grid = g.nunits;
+    if (g.deep)
+        hipLaunchKernelGGL(one ? k_loop_FT_deep : k_loop_FT_multi_deep, dim3(grid), dim3(kBlock), lds, s, p, a, g);
     else
-        hipLaunchKernelGGL(k_loop_FT_multi, dim3(grid), dim3(kBlock), lds, s, p, a, g);
+        hipLaunchKernelGGL(one ? k_loop_FT : k_loop_FT_multi, dim3(grid), dim3(kBlock), lds, s, p, a, g);
 }
 
 void set_seg_kernel_lds(int bytes) {

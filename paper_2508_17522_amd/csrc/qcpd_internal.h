@@ -215,6 +215,7 @@ struct FusedGrid {
     int nunits;
     const Unit *units;   // device table
     int lx, ly;
+    int deep = 0;        // the loop kernel keeps kDeep CSR entries per lane in flight
 };
 
 // host launchers (apply.hip)
