@@ -237,6 +237,40 @@ __device__ inline double csr_dot(const int *col, const double *val, int k0, int 
               : csr_dot4<false>(col, val, k0, k1, lane, L, x, sc, off);
 }
 
+// Two strided CSR dot products of one row (P and A' of an x row) in the same passes, so
+// the loads of both are in flight together: pass i issues four entries of each.
+template <bool SCA, bool SCB>
+__device__ inline void csr_dot_pair(const int *colA, const double *valA, int a0, int a1,
+                                    const double *xA, const double *scA, int offA,
+                                    const int *colB, const double *valB, int b0, int b1,
+                                    const double *xB, const double *scB, int offB, int lane,
+                                    int L, double &accA, double &accB) {
+    accA = 0.0;
+    accB = 0.0;
+    for (int ka = a0 + lane, kb = b0 + lane; ka < a1 || kb < b1; ka += 4 * L, kb += 4 * L) {
+        int ja[4], jb[4];
+        double va[4], vb[4], xa[4], xb[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int ia = max(min(ka + u * L, a1 - 1), 0), ib = max(min(kb + u * L, b1 - 1), 0);
+            ja[u] = a1 > a0 ? colA[ia] + offA : 0;
+            va[u] = a1 > a0 ? valA[ia] : 0.0;
+            jb[u] = b1 > b0 ? colB[ib] + offB : 0;
+            vb[u] = b1 > b0 ? valB[ib] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            xa[u] = SCA ? xA[ja[u]] * scA[ja[u]] : xA[ja[u]];
+            xb[u] = SCB ? xB[jb[u]] * scB[jb[u]] : xB[jb[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (ka + u * L < a1) accA += va[u] * xa[u];
+            if (kb + u * L < b1) accB += vb[u] * xb[u];
+        }
+    }
+}
+
 // As csr_dot4 with kDeep entries per lane in flight: the batched loop gives each lane about
 // that many entries (fewer lanes per row, more rows per workgroup), so a launch needs far
 // fewer workgroups and each keeps more of the memory system busy.
@@ -357,6 +391,7 @@ __device__ inline void rows_pre(const Problem &p, const StepArgs &a, const Ptrs 
         if (row < n) {
             const int k0 = p.Prp[row], k1 = p.Prp[row + 1];
             const int t0 = p.Trp[row], t1 = p.Trp[row + 1];
+            // two separate passes measure faster here than csr_dot_pair (fewer registers)
             acc = csr_dot_d<DEEP>(p.Pci, q.Pv, k0, k1, lane, L, a.in, q.gsc, 0);
             accT = csr_dot_d<DEEP>(p.Tci, p.Tv, t0, t1, lane, L, a.wy, nullptr, 0);
             idx = row;
@@ -696,8 +731,16 @@ __device__ inline void unit_pre(const Problem &p, const StepArgs &a, const Ptrs 
         if (row < u.end) {
             const int k0 = p.Prp[row], k1 = p.Prp[row + 1];
             const int t0 = p.Trp[row], t1 = p.Trp[row + 1];
-            acc = csr_dot_d<DEEP>(p.Pci, q.Pv, k0, k1, lane, L, a.in, q.gsc, 0);
-            accT = csr_dot_d<DEEP>(p.Tci, q.Tv, t0, t1, lane, L, a.in, q.gsc, n);
+            if (DEEP) {
+                acc = csr_dot_d<DEEP>(p.Pci, q.Pv, k0, k1, lane, L, a.in, q.gsc, 0);
+                accT = csr_dot_d<DEEP>(p.Tci, q.Tv, t0, t1, lane, L, a.in, q.gsc, n);
+            } else if (q.gsc) {
+                csr_dot_pair<true, true>(p.Pci, q.Pv, k0, k1, a.in, q.gsc, 0, p.Tci, q.Tv, t0, t1,
+                                         a.in, q.gsc, n, lane, L, acc, accT);
+            } else {
+                csr_dot_pair<false, false>(p.Pci, q.Pv, k0, k1, a.in, nullptr, 0, p.Tci, q.Tv, t0,
+                                           t1, a.in, nullptr, n, lane, L, acc, accT);
+            }
         }
         P.acc = group_sum_dpp(acc, L);
         P.accT = group_sum_dpp(accT, L);
