@@ -1036,6 +1036,7 @@ qcpd_status batch_create_impl(qcpd_batch *h, const qcpd_batch_layout *L, const i
         g.B = B; g.nf = (int)fitems.size(); g.nt = (int)tunits.size();
         g.fitems = d_fitems; g.foff = d_foff; g.tunits = d_tunits; g.tprob = d_tprob; g.toff = d_toff;
         g.fslot = g.tslot = nullptr;
+        g.small_psd = kmax <= 16 ? 1 : 0;
         fill_unit_ranges(p, d_tunits, g.nt, st);
         h->h_fitems = fitems;
         h->h_tunits.resize(tunits.size());

@@ -678,7 +678,13 @@ __device__ inline void psd_apply_kp(int k, const PsdLds &L, double *sm, const do
     __syncthreads();
 }
 
+// MAXKP: the largest padded order the caller can meet (fewer instances, fewer registers)
+template <int MAXKP = 64>
 __device__ inline void psd_apply(int k, const PsdLds &L, double *sm, const double *Bg) {
+    if (MAXKP <= 16) {
+        psd_apply_kp<16>(k, L, sm, Bg);
+        return;
+    }
     switch (L.kp) {
     case 16: psd_apply_kp<16>(k, L, sm, Bg); break;
     case 32: psd_apply_kp<32>(k, L, sm, Bg); break;
@@ -718,7 +724,7 @@ __device__ inline double smat_get(const double *Y, int ld, int ii, int jj) {
 }
 
 // DEEP: the row units' CSR sums keep kDeep entries per lane in flight (batched loop)
-template <bool DEEP = false>
+template <bool DEEP = false, int MAXKP = 64>
 __device__ inline void unit_pre(const Problem &p, const StepArgs &a, const Ptrs &q, int lx,
                                 int ly, const Unit &u, double *sm, double in_N_raw,
                                 UnitPre &P) {
@@ -861,7 +867,7 @@ __device__ inline void unit_pre(const Problem &p, const StepArgs &a, const Ptrs 
             smat_put(sm, Ld.ld, ii, jj, tb[i]);
         }
         __syncthreads();
-        psd_apply(k, Ld, sm, Bg);  // ends with a barrier; J t in the X region
+        psd_apply<MAXKP>(k, Ld, sm, Bg);  // ends with a barrier; J t in the X region
     } else if (u.type == U_SOC) {
         int cr0 = 0, cdim = 0;
         if (cone < u.end) {
@@ -899,6 +905,7 @@ __device__ inline void unit_pre(const Problem &p, const StepArgs &a, const Ptrs 
     }
 }
 
+template <int MAXKP = 64>
 __device__ inline void unit_post(const Problem &p, const StepArgs &a, const Ptrs &q,
                                  const Ctx &c, const Unit &u, double *sm, const UnitPre &P,
                                  double &s0, double &s1) {
@@ -950,7 +957,7 @@ __device__ inline void unit_post(const Problem &p, const StepArgs &a, const Ptrs
     auto jout = [&](int i, double v) { jt[i] = v; };
     if (psd) {
         const double *Bg = p.psd_pool + p.psd_off[u.begin] + k * k;
-        psd_apply(k, psd_lds(k), sm, Bg);  // Y in the X region
+        psd_apply<MAXKP>(k, psd_lds(k), sm, Bg);  // Y in the X region
         for (int i = tid; i < nr; i += kBlock) {
             int ii = P.ii, jj = P.jj;
             if (i != tid) svec_rc(i, k, ii, jj);
@@ -1171,8 +1178,9 @@ __global__ __launch_bounds__(kBlock) void k_seg_F(Problem p, StepArgs a, SegGrid
     leave(a, s0, s1, slot);
 }
 
-__global__ __launch_bounds__(kBlock) void k_seg_FT(Problem p, StepArgs a, SegGrid g) {
-    extern __shared__ double sm[];
+template <int MAXKP>
+__device__ inline void seg_FT_body(const Problem &p, const StepArgs &a, const SegGrid &g,
+                                   double *sm) {
     LsqrState S;  // per thread (entry_finish)
     const Unit u = g.tunits[blockIdx.x];
     const int b = g.tprob[blockIdx.x];
@@ -1184,17 +1192,28 @@ __global__ __launch_bounds__(kBlock) void k_seg_FT(Problem p, StepArgs a, SegGri
     const int tix = p.n + p.m + b;
     const double in_N_raw = in_raw(a, q, tix);
     UnitPre P;
-    unit_pre<true>(p, a, q, g.lxs[b], g.lys[b], u, sm, in_N_raw, P);
+    unit_pre<true, MAXKP>(p, a, q, g.lxs[b], g.lys[b], u, sm, in_N_raw, P);
     if (!seg_entry_finish(a, e, b, first, g.ndone, &S, 1)) return;
     const Ctx c = scalars(a, S, q, in_N_raw);
     double s0 = 0.0, s1 = 0.0;
-    unit_post(p, a, q, c, u, sm, P, s0, s1);
+    unit_post<MAXKP>(p, a, q, c, u, sm, P, s0, s1);
     if (first && threadIdx.x == 0) {  // the problem's tau entry
         Fin f;
         fin_load(a, q, tix, f);
         fin_store(a, c, tix, f, S.dot_adj * c.inv + g.xPx[b] * c.in_N, s0);
     }
     leave(a, s0, s1, slot);
+}
+
+__global__ __launch_bounds__(kBlock) void k_seg_FT(Problem p, StepArgs a, SegGrid g) {
+    extern __shared__ double sm[];
+    seg_FT_body<64>(p, a, g, sm);
+}
+
+// batches whose PSD cones all have order <= 16: one product instance, fewer registers
+__global__ __launch_bounds__(kBlock) void k_seg_FT_small(Problem p, StepArgs a, SegGrid g) {
+    extern __shared__ double sm[];
+    seg_FT_body<16>(p, a, g, sm);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1265,6 +1284,7 @@ void launch_loop_FT(const Problem &p, const StepArgs &a, const FusedGrid &g, int
 
 void set_seg_kernel_lds(int bytes) {
     (void)hipFuncSetAttribute((const void *)k_seg_FT, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    (void)hipFuncSetAttribute((const void *)k_seg_FT_small, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 void launch_seg_F(const Problem &p, const StepArgs &a, const SegGrid &g, hipStream_t s) {
@@ -1272,7 +1292,10 @@ void launch_seg_F(const Problem &p, const StepArgs &a, const SegGrid &g, hipStre
 }
 
 void launch_seg_FT(const Problem &p, const StepArgs &a, const SegGrid &g, int lds, hipStream_t s) {
-    hipLaunchKernelGGL(k_seg_FT, dim3(g.nt), dim3(kBlock), lds, s, p, a, g);
+    if (g.small_psd)
+        hipLaunchKernelGGL(k_seg_FT_small, dim3(g.nt), dim3(kBlock), lds, s, p, a, g);
+    else
+        hipLaunchKernelGGL(k_seg_FT, dim3(g.nt), dim3(kBlock), lds, s, p, a, g);
 }
 
 }  // namespace qcpd

@@ -263,6 +263,7 @@ struct SegGrid {
     // launched item i is item fslot[i] / tslot[i] of the full lists (its partial-sum slot);
     // null: the launch covers every item in order
     const int *fslot, *tslot;
+    int small_psd;        // every PSD cone of the batch has order <= 16
     const int *lxs, *lys; // lanes per CSR row, per problem
     const double *xPx;    // per problem
     int *ndone;           // problems whose LSQR has stopped

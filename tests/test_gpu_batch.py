@@ -75,6 +75,28 @@ def test_batch_matches_oracle_uneven(precond):
     h.close()
 
 
+def test_batch_with_larger_psd_orders():
+    """A PSD cone of order 20 in the batch (padded order 32) runs the batch's general F'
+    kernel; the others have small cones only."""
+    qs = [qcpgen.small_mixed(300, n=70, n_zero=5, n_nonneg=30, soc=(4, 3), psd=(20, 2),
+                             n_exp=1, A_density=0.1, P_rank=60, P_eps=0.05, nonneg_active=10,
+                             psd_ranks=(4, 1)),
+          qcpgen.small_mixed(301, n=30, n_zero=3, n_nonneg=12, soc=(3,), psd=(3,), n_exp=0,
+                             A_density=0.15, P_rank=25, P_eps=0.05, nonneg_active=4)]
+    bt = batch_to_device(qs)
+    h = Q.qcpd_batch_create(*batch_create_args(bt), opts=Q.Opts(tol=1e-12))
+    dx, dy, ds, infos, st = Q.qcpd_batch_jvp(h, bt["dP"], bt["dA"], bt["dq"], bt["db"])
+    print("jvp iters", [i.iters for i in infos], "status", st, flush=True)
+    assert st == Q.QCPD_OK
+    dxs, dys, dss = (split(v.cpu().numpy(), s) for v, s in
+                     ((dx, bt["n"]), (dy, bt["m"]), (ds, bt["m"])))
+    for k, q in enumerate(qs):
+        ref = D.jvp_dense(q, q.dP, q.dA, q.dq, q.db)
+        errs = [rel(a, r) for a, r in zip((dxs[k], dys[k], dss[k]), ref)]
+        assert max(errs) <= BAR, (k, errs)
+    h.close()
+
+
 @pytest.mark.parametrize("precond", PRECONDS)
 def test_batch_of_one_matches_single_path(precond):
     q = qcpgen.small_mixed(0)
