@@ -586,8 +586,8 @@ qcpd_status create_impl(qcpd_handle *h, const qcpd_csr *P, const qcpd_csr *A, co
         cap = std::min(cap, kMaxLoopGrid);
         h->loop_grid_F = std::max(1, std::min(rg.total(), cap));
         h->loop_grid_T = std::max(1, std::min(h->fg.nunits, cap));
-        ALLOC(h->lpart[0], 3LL * kMaxLoopGrid);
-        ALLOC(h->lpart[1], 3LL * kMaxLoopGrid);
+        ALLOC(h->lpart[0], 2LL * kMaxLoopGrid);
+        ALLOC(h->lpart[1], 2LL * kMaxLoopGrid);
         ALLOC(h->st2, 1);
     }
     ALLOC(h->partials, 3LL * h->nblk_max);
@@ -983,8 +983,8 @@ qcpd_status qcpd_profile_kernels(qcpd_handle *h, int32_t reps, float *ms_out) {
     img.pend_fwd = 0;
     *h->host_st = img;
     HIPCHK(hipMemcpyAsync(h->st, h->host_st, sizeof(LsqrState), hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemsetAsync(h->lpart[0], 0, 3 * sizeof(double) * img.pend_blocks, s));
-    HIPCHK(hipMemsetAsync(h->lpart[1], 0, 3 * sizeof(double) * img.pend_blocks, s));
+    HIPCHK(hipMemsetAsync(h->lpart[0], 0, 2 * sizeof(double) * img.pend_blocks, s));
+    HIPCHK(hipMemsetAsync(h->lpart[1], 0, 2 * sizeof(double) * img.pend_blocks, s));
     StepArgs a = base_args(h, sc, scl);
     a.st = h->st; a.part_prev = h->lpart[0]; a.st_next = h->st2; a.part_next = h->lpart[1];
     qcpd_status rc = bake_scales(h, sc, scl);

@@ -1050,7 +1050,7 @@ qcpd_status batch_create_impl(qcpd_batch *h, const qcpd_batch_layout *L, const i
         g.lxs = d_lx; g.lys = d_ly; g.xPx = xpx;
         BALLOC(g.ndone, 1);
         const int slots = std::max(g.nf, g.nt);
-        BALLOC(h->spart[0], 3LL * slots); BALLOC(h->spart[1], 3LL * slots);
+        BALLOC(h->spart[0], 2LL * slots); BALLOC(h->spart[1], 2LL * slots);
         BALLOC(h->stl[0], B); BALLOC(h->stl[1], B);
         h->lds_seg = loop_lds_bytes(psd_k.data(), (int)psd_k.size());
         set_seg_kernel_lds(h->lds_seg);

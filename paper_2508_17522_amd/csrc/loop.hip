@@ -90,8 +90,7 @@ __device__ inline void block_sum2(double &a, double &b) {
 __device__ inline void leave(const StepArgs &a, double s0, double s1, int slot) {
     block_sum2(s0, s1);
     if (threadIdx.x == 0) {
-        a.part_next[3 * slot] = s0;
-        a.part_next[3 * slot + 1] = s1;
+        reinterpret_cast<double2 *>(a.part_next)[slot] = make_double2(s0, s1);
     }
 }
 
@@ -113,8 +112,9 @@ __device__ inline void entry_issue(const StepArgs &a, Entry &e) {
 #pragma unroll
     for (int j = 0; j < kPartRegs; ++j) {
         const int i = threadIdx.x + j * kBlock;
-        e.pa[j] = a.part_prev[3 * i];
-        e.pb[j] = a.part_prev[3 * i + 1];
+        const double2 v = reinterpret_cast<const double2 *>(a.part_prev)[i];  // one 16-byte load
+        e.pa[j] = v.x;
+        e.pb[j] = v.y;
     }
 }
 
@@ -1066,8 +1066,9 @@ __device__ inline void seg_entry_issue(const StepArgs &a, int b, const int *prev
     for (int j = 0; j < kPartRegs; ++j) {
         const int i = threadIdx.x + j * kBlock;
         const int slot = e.c0 + min(i, max(e.cnt - 1, 0));  // in bounds; masked below
-        e.pa[j] = a.part_prev[3 * slot];
-        e.pb[j] = a.part_prev[3 * slot + 1];
+        const double2 v = reinterpret_cast<const double2 *>(a.part_prev)[slot];
+        e.pa[j] = v.x;
+        e.pb[j] = v.y;
     }
 }
 
@@ -1087,8 +1088,9 @@ __device__ inline bool seg_entry_finish(const StepArgs &a, const SegEntry &e, in
                 t1 += e.pb[j];
             }
         for (int i = tid + kPartRegs * kBlock; i < e.cnt; i += kBlock) {  // very large problems
-            t0 += a.part_prev[3 * (e.c0 + i)];
-            t1 += a.part_prev[3 * (e.c0 + i) + 1];
+            const double2 v = reinterpret_cast<const double2 *>(a.part_prev)[e.c0 + i];
+            t0 += v.x;
+            t1 += v.y;
         }
         block_sum2_all(t0, t1);
     }

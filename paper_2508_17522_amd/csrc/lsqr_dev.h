@@ -76,16 +76,6 @@ __device__ inline void finalize(LsqrState *st, int role, double t0, double t1, b
     }
 }
 
-// Exit of a deferred-protocol launch: this workgroup's partial sums, plain stores.
-__device__ inline void deferred_leave(const StepArgs &a, double s0, double s1) {
-    double z = 0.0;
-    block_sum3(s0, s1, z);
-    if (threadIdx.x == 0) {
-        a.part_next[3 * blockIdx.x] = s0;
-        a.part_next[3 * blockIdx.x + 1] = s1;
-    }
-}
-
 struct Ctx {  // per-launch scalars every thread derives from the state block
     double inv, cU, cV, inv_alpha_up, phr, thr, in_N;
     const double *isc;  // scale applied when reading the input (sc for v, scl for u)

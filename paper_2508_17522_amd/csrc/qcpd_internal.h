@@ -187,9 +187,9 @@ struct StepArgs {
     LsqrState *st;
     int check_done;     // return at once when st->done is set (kernels inside the loop)
     // LSQR loop (loop.hip): read the state from st and the previous launch's partials from
-    // part_prev (kMaxLoopGrid slots), finalise them at entry, write the state to st_next and
-    // this launch's partials to part_next. No fences or atomics: launch order gives
-    // visibility.
+    // part_prev (kMaxLoopGrid slots of two doubles, 16-byte aligned), finalise them at entry,
+    // write the state to st_next and this launch's partials to part_next. No fences or
+    // atomics: launch order gives visibility.
     LsqrState *st_next;
     const double *part_prev;
     double *part_next;
