@@ -122,6 +122,26 @@ def test_psd_max_order():
     check_jvp_vjp_dense(q)
 
 
+@pytest.mark.parametrize("precond", [Q.QCPD_PRECOND_JACOBI, Q.QCPD_PRECOND_EQUIL])
+def test_deep_csr_form_matches_oracle(precond, monkeypatch):
+    """The F' loop kernel's deep-CSR form (chosen by the library for large problems) forced
+    on a small one with every cone type, in its single-unit and looping launch shapes."""
+    q = qcpgen.small_mixed(1)
+    monkeypatch.setenv("QCPD_DEEP", "1")
+    check_jvp_vjp_dense(q, precond=precond)
+    h, t = make_handle(q, precond=precond)
+    monkeypatch.delenv("QCPD_DEEP")
+    gF, gT, mF, mT = Q.qcpd_get_launch(h)
+    Q.qcpd_set_launch(h, gF, max(1, mT // 3))  # fewer workgroups than units: looping form
+    dx, dy, ds, info, st = gpu_jvp(h, t)
+    assert st == Q.QCPD_OK
+    ref = D.jvp_dense(q, q.dP, q.dA, q.dq, q.db)
+    errs = [rel(a, b) for a, b in zip((dx, dy, ds), ref)]
+    print(f"deep, looping form: iters={info.iters} errors {errs}", flush=True)
+    assert max(errs) <= BAR
+    h.close()
+
+
 def test_only_zero_cone_and_graph_chunk_one():
     q = qcpgen.small_mixed(3, n=30, n_zero=12, n_nonneg=0, soc=(), psd=(), n_exp=0,
                            A_density=0.3, P_rank=25, P_eps=0.1)
