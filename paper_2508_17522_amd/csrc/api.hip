@@ -638,7 +638,12 @@ qcpd_status create_impl(qcpd_handle *h, const qcpd_csr *P, const qcpd_csr *A, co
     // two-sided equilibration of F (column scale in equil[0], row scale in equil[1])
     launch_fill(h->equil[0], N, 1.0, st);
     launch_fill(h->equil[1], N, 1.0, st);
-    launch_equilibrate(p, rg, h->equil[1], h->equil[0], h->tmp, h->scratch, kEquilSweeps,
+    int sweeps = kEquilSweeps;  // QCPD_EQUIL_SWEEPS overrides (tuning; rounded up to even)
+    if (const char *e = getenv("QCPD_EQUIL_SWEEPS")) {
+        const int v = atoi(e);
+        if (v > 0) sweeps = (v + 1) / 2 * 2;
+    }
+    launch_equilibrate(p, rg, h->equil[1], h->equil[0], h->tmp, h->scratch, sweeps,
                        h->partials, h->counter, st);
     HIPCHK(hipMemcpyAsync(h->host_flag, h->flag, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
