@@ -94,9 +94,9 @@ qcpd_status dalloc(qcpd_handle *h, T **ptr, size_t count) {
     } while (0)
 
 // Lanes per CSR row: the largest power of two (<= 64) that still gives each lane about
-// `per_lane` stored entries. The product with F runs best with one entry per lane (most
-// parallel), the fused product with F' with two (fewer, fuller work units); measured on
-// MI355X. QCPD_NNZ_PER_LANE_F / _FT override the two for tuning.
+// `per_lane` stored entries. The product with F runs best with two entries per lane, the
+// fused product with F' with four (fewer, fuller work units); measured on MI355X.
+// QCPD_NNZ_PER_LANE_F / _FT override the two for tuning.
 int nnz_per_lane(const char *env, int dflt) {
     const char *e = getenv(env);
     const int x = e ? atoi(e) : 0;
@@ -472,14 +472,14 @@ qcpd_status create_impl(qcpd_handle *h, const qcpd_csr *P, const qcpd_csr *A, co
     // Large problems (the product with F at one entry per lane would need more workgroups
     // than a loop launch has) switch the F' loop kernel to deep CSR sums: about 32 entries
     // per lane, kDeep of them in flight, so each workgroup streams more per round. The
-    // product with F stays at one entry per lane (measured faster at both large sizes).
+    // product with F keeps its shallow sums (measured faster at both large sizes).
     // QCPD_DEEP=0/1 forces the choice (tuning).
     bool deep = div_up((long long)n * lanes_for(avg_x, 1), kBlock) +
                     div_up((long long)(m + 1) * lanes_for(avg_y, 1), kBlock) >
                 kLoopGrid;
     if (const char *e = getenv("QCPD_DEEP")) deep = atoi(e) != 0;
-    const int npl_F = nnz_per_lane("QCPD_NNZ_PER_LANE_F", 1);
-    const int npl_T = nnz_per_lane("QCPD_NNZ_PER_LANE_FT", deep ? 32 : 2);
+    const int npl_F = nnz_per_lane("QCPD_NNZ_PER_LANE_F", 2);
+    const int npl_T = nnz_per_lane("QCPD_NNZ_PER_LANE_FT", deep ? 32 : 4);
     h->fg.deep = deep ? 1 : 0;
     rg.lx = lanes_for(avg_x, npl_F);
     rg.ly = lanes_for(avg_y, npl_F);
