@@ -96,7 +96,7 @@ typedef struct {
     double  tol;          /* stop when the LSQR residual estimate <= tol * ||rhs||  (1e-8)   */
     int32_t max_iter;     /* iteration cap; 0 = 100 * (n + m + 1)                             */
     int32_t precond;      /* QCPD_PRECOND_*                                   (JACOBI)         */
-    int32_t graph_chunk;  /* LSQR iterations per captured HIP graph launch     (32)            */
+    int32_t graph_chunk;  /* LSQR iterations per captured HIP graph launch     (128)           */
     int32_t check_symmetry; /* verify that P is symmetric at create              (1)           */
     int32_t engine;       /* LSQR driver: QCPD_ENGINE_AUTO, _GRAPH, _PERSISTENT (AUTO)         */
 } qcpd_opts;
@@ -278,7 +278,8 @@ typedef struct {
  * A likewise with sum(m_i + 1) row pointers; q, x: sum(n_i); b, y, s: sum(m_i).
  * opts->precond may be NONE, JACOBI or EQUIL (each problem's two-sided equilibration is
  * computed here, 20 sweeps); graph_chunk is the number of LSQR iterations (of all problems)
- * per captured HIP graph launch. */
+ * per captured HIP graph launch, at most 32 here (the host shrinks the launch lists to the
+ * running problems between graph launches). */
 qcpd_status qcpd_batch_create(qcpd_batch **hb, const qcpd_batch_layout *layout,
                               const int32_t *P_rowptr, const int32_t *P_colind, const double *P_val,
                               const int32_t *A_rowptr, const int32_t *A_colind, const double *A_val,

@@ -62,7 +62,7 @@ class Opts:
     tol: float = 1e-8
     max_iter: int = 0
     precond: int = C.QCPD_PRECOND_JACOBI
-    graph_chunk: int = 32
+    graph_chunk: int = 128
     check_symmetry: int = 1
     engine: int = C.QCPD_ENGINE_AUTO
 

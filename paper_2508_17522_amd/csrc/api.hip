@@ -715,7 +715,7 @@ void qcpd_opts_default(qcpd_opts *o) {
     o->tol = 1e-8;
     o->max_iter = 0;
     o->precond = QCPD_PRECOND_JACOBI;
-    o->graph_chunk = 32;
+    o->graph_chunk = 128;
     o->check_symmetry = 1;
     o->engine = QCPD_ENGINE_AUTO;
 }

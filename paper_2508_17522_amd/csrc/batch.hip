@@ -1171,8 +1171,13 @@ qcpd_status seg_lists(qcpd_batch *h, bool all) {
     return QCPD_OK;
 }
 
+// Iterations per graph launch of the segmented loop: at most 32, so the host can shrink the
+// launch lists (and stop) soon after problems finish (measured: 32 beats 128 here, while
+// the single-problem loop prefers 128).
+constexpr int kSegChunkMax = 32;
+
 qcpd_status seg_graph(qcpd_batch *h, int dir) {
-    const int chunk = std::max(1, h->opts.graph_chunk);
+    const int chunk = std::min(kSegChunkMax, std::max(1, h->opts.graph_chunk));
     if (h->graph[dir] && h->graph_chunk[dir] == chunk && h->graph_sc[dir] == h->d.sc &&
         h->graph_scl[dir] == h->d.scl && h->graph_version[dir] == h->seg_version)
         return QCPD_OK;
