@@ -112,14 +112,14 @@ int lanes_for(double avg, int per_lane) {
 void free_handle(qcpd_handle *h) {
     if (!h) return;
     for (int d = 0; d < 2; ++d)
-        if (h->graph[d]) hipGraphExecDestroy(h->graph[d]);
-    for (void *p : h->allocs) hipFree(p);
-    if (h->host_st) hipHostFree(h->host_st);
-    if (h->host_flag) hipHostFree(h->host_flag);
-    if (h->host_seg) hipHostFree(h->host_seg);
-    if (h->cap) hipStreamDestroy(h->cap);
-    if (h->ev0) hipEventDestroy(h->ev0);
-    if (h->ev1) hipEventDestroy(h->ev1);
+        if (h->graph[d]) (void)hipGraphExecDestroy(h->graph[d]);
+    for (void *p : h->allocs) (void)hipFree(p);
+    if (h->host_st) (void)hipHostFree(h->host_st);
+    if (h->host_flag) (void)hipHostFree(h->host_flag);
+    if (h->host_seg) (void)hipHostFree(h->host_seg);
+    if (h->cap) (void)hipStreamDestroy(h->cap);
+    if (h->ev0) (void)hipEventDestroy(h->ev0);
+    if (h->ev1) (void)hipEventDestroy(h->ev1);
     delete h;
 }
 
@@ -265,7 +265,7 @@ qcpd_status ensure_graph(qcpd_handle *h, int dir, const double *sc, const double
         h->graph_scl[dir] == scl)
         return QCPD_OK;
     if (h->graph[dir]) {
-        hipGraphExecDestroy(h->graph[dir]);
+        (void)hipGraphExecDestroy(h->graph[dir]);
         h->graph[dir] = nullptr;
     }
     hipGraph_t g = nullptr;
@@ -273,7 +273,7 @@ qcpd_status ensure_graph(qcpd_handle *h, int dir, const double *sc, const double
     for (int i = 0; i < chunk; ++i) enqueue_iteration(h, dir, sc, scl, h->cap);
     HIPCHK(hipStreamEndCapture(h->cap, &g));
     hipError_t e = hipGraphInstantiate(&h->graph[dir], g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
         h->graph[dir] = nullptr;
         return QCPD_ERR_HIP;
@@ -410,7 +410,7 @@ void fill_info(qcpd_handle *h, qcpd_info *info, double rel, int extra_iters = 0,
     info->rel_residual = rel;
     info->flags = (st.conv ? 0u : 1u) | h->create_flags | extra_flags;
     float ms = 0.f;
-    hipEventElapsedTime(&ms, h->ev0, h->ev1);
+    (void)hipEventElapsedTime(&ms, h->ev0, h->ev1);
     info->ms_total = ms;
 }
 
@@ -924,7 +924,7 @@ qcpd_status qcpd_set_launch(qcpd_handle *h, int32_t grid_F, int32_t grid_FT) {
     h->loop_grid_T = gT;
     for (int d = 0; d < 2; ++d)  // captured graphs hold the old launch shape
         if (h->graph[d]) {
-            hipGraphExecDestroy(h->graph[d]);
+            (void)hipGraphExecDestroy(h->graph[d]);
             h->graph[d] = nullptr;
         }
     return QCPD_OK;

@@ -132,7 +132,7 @@ __global__ __launch_bounds__(kBlock) void k_fused_FT(Problem p, StepArgs a, Fuse
 }
 
 void set_fused_kernel_lds(int bytes) {
-    hipFuncSetAttribute((const void *)k_fused_FT, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    (void)hipFuncSetAttribute((const void *)k_fused_FT, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 int fused_lds_bytes(int kmax) {
@@ -220,7 +220,7 @@ hipError_t launch_lsqr_persistent(const Problem &p, const StepArgs &fa, const St
     RowGrid r = rg;
     FusedGrid u = fg;
     void *args[] = {&pp, &f, &t, &r, &u, &dir, &st, &partials};
-    hipFuncSetAttribute((const void *)k_lsqr_persistent, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void *)k_lsqr_persistent, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     return hipLaunchCooperativeKernel((const void *)k_lsqr_persistent, dim3(grid), dim3(kBlock), args,
                                       (unsigned)lds, s);
 }
@@ -563,8 +563,8 @@ void launch_nan_scan(const double *const *ptrs, const long long *lens, int nseg,
 
 // the cone kernels may need more than the default 64 KB of dynamic LDS for PSD blocks
 void set_cone_kernel_lds(int bytes) {
-    hipFuncSetAttribute((const void *)k_cone_pre, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    hipFuncSetAttribute((const void *)k_vjp_rhs, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    (void)hipFuncSetAttribute((const void *)k_cone_pre, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    (void)hipFuncSetAttribute((const void *)k_vjp_rhs, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 
 }
 

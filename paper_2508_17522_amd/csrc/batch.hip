@@ -614,7 +614,7 @@ __global__ void k_batch_csr(const int *rp_loc, const int *ci_loc, const int *row
         if (j < 0 || j >= nc) atomicOr(flag, 1);
         ci[z0 + k] = j + c0;
     }
-    if (b == gridDim.x - 1 && threadIdx.x == 0) rp[last_row] = z0 + nz;
+    if (b == (int)gridDim.x - 1 && threadIdx.x == 0) rp[last_row] = z0 + nz;
 }
 
 // per problem: x'Px (P x is already in c = -2Px - q: x'Px = -(x'c + x'q)/2 would lose
@@ -775,14 +775,14 @@ int lanes_of(double avg) {
 
 void free_batch(qcpd_batch *h) {
     if (!h) return;
-    for (void *p : h->allocs) hipFree(p);
-    if (h->host_flag) hipHostFree(h->host_flag);
-    if (h->host_ndone) hipHostFree(h->host_ndone);
+    for (void *p : h->allocs) (void)hipFree(p);
+    if (h->host_flag) (void)hipHostFree(h->host_flag);
+    if (h->host_ndone) (void)hipHostFree(h->host_ndone);
     for (int d = 0; d < 2; ++d)
-        if (h->graph[d]) hipGraphExecDestroy(h->graph[d]);
-    if (h->cap) hipStreamDestroy(h->cap);
-    if (h->ev0) hipEventDestroy(h->ev0);
-    if (h->ev1) hipEventDestroy(h->ev1);
+        if (h->graph[d]) (void)hipGraphExecDestroy(h->graph[d]);
+    if (h->cap) (void)hipStreamDestroy(h->cap);
+    if (h->ev0) (void)hipEventDestroy(h->ev0);
+    if (h->ev1) (void)hipEventDestroy(h->ev1);
     delete h;
 }
 
@@ -1182,7 +1182,7 @@ qcpd_status seg_graph(qcpd_batch *h, int dir) {
         h->graph_scl[dir] == h->d.scl && h->graph_version[dir] == h->seg_version)
         return QCPD_OK;
     if (h->graph[dir]) {
-        hipGraphExecDestroy(h->graph[dir]);
+        (void)hipGraphExecDestroy(h->graph[dir]);
         h->graph[dir] = nullptr;
     }
     hipGraph_t g = nullptr;

@@ -78,10 +78,10 @@ hipError_t csr_transpose(int nrows, int ncols, int nnz, const int *rp, const int
                        keys_out, nnz, ncols, trp);
     e = hipStreamSynchronize(s);
 done:
-    hipFree(rowidx);
-    hipFree(keys_out);
-    hipFree(iota);
-    hipFree(temp);
+    (void)hipFree(rowidx);
+    (void)hipFree(keys_out);
+    (void)hipFree(iota);
+    (void)hipFree(temp);
     return e;
 }
 
@@ -665,7 +665,7 @@ void launch_cone_factors(const Problem &p, const ConeHost &ch, double *jdiag, do
         hipLaunchKernelGGL(k_exp_factors, dim3(div_up(p.n_exp, 64)), dim3(64), 0, s, p.zy,
                            p.exp_row0, p.exp_rows, p.n_exp, exp_J, jdiag, nondiff, fail);
     if (p.n_psd > 0) {
-        hipFuncSetAttribute((const void *)k_psd_factors, hipFuncAttributeMaxDynamicSharedMemorySize, psd_lds);
+        (void)hipFuncSetAttribute((const void *)k_psd_factors, hipFuncAttributeMaxDynamicSharedMemorySize, psd_lds);
         hipLaunchKernelGGL(k_psd_factors, dim3(p.n_psd), dim3(kBlock), psd_lds, s, p.zy, p.psd_row,
                            p.psd_k, p.psd_off, pool, jdiag, nondiff, fail);
     }
