@@ -109,6 +109,14 @@ int lanes_for(double avg, int per_lane) {
     return L;
 }
 
+// Deep CSR sums: the power of two (1..64) nearest, on a log scale, to avg / target entries
+// per lane (measured best near 25 entries per lane on both large workloads).
+int lanes_near(double avg, double target) {
+    int L = 1;
+    while (L < 64 && avg / (2.0 * L) >= target / 1.41421356237309504880) L *= 2;
+    return L;
+}
+
 void free_handle(qcpd_handle *h) {
     if (!h) return;
     for (int d = 0; d < 2; ++d)
@@ -470,7 +478,7 @@ qcpd_status create_impl(qcpd_handle *h, const qcpd_csr *P, const qcpd_csr *A, co
     const double avg_x = n ? (double)(P->nnz + A->nnz) / n : 1.0;
     const double avg_y = m ? (double)A->nnz / m : 1.0;
     // Large problems (the product with F at one entry per lane would need more workgroups
-    // than a loop launch has) switch the F' loop kernel to deep CSR sums: about 32 entries
+    // than a loop launch has) switch the F' loop kernel to deep CSR sums: about 25 entries
     // per lane, kDeep of them in flight, so each workgroup streams more per round. The
     // product with F keeps its shallow sums (measured faster at both large sizes).
     // QCPD_DEEP=0/1 forces the choice (tuning).
@@ -479,7 +487,8 @@ qcpd_status create_impl(qcpd_handle *h, const qcpd_csr *P, const qcpd_csr *A, co
                 kLoopGrid;
     if (const char *e = getenv("QCPD_DEEP")) deep = atoi(e) != 0;
     const int npl_F = nnz_per_lane("QCPD_NNZ_PER_LANE_F", 2);
-    const int npl_T = nnz_per_lane("QCPD_NNZ_PER_LANE_FT", deep ? 32 : 4);
+    const int npl_T = nnz_per_lane("QCPD_NNZ_PER_LANE_FT", 4);
+    const bool npl_T_set = getenv("QCPD_NNZ_PER_LANE_FT") != nullptr;
     h->fg.deep = deep ? 1 : 0;
     rg.lx = lanes_for(avg_x, npl_F);
     rg.ly = lanes_for(avg_y, npl_F);
@@ -533,8 +542,8 @@ qcpd_status create_impl(qcpd_handle *h, const qcpd_csr *P, const qcpd_csr *A, co
     // exponential and SOC runs, then CSR rows) so that the long ones start in the first
     // round of workgroups
     {
-        h->fg.lx = lanes_for(avg_x, npl_T);
-        h->fg.ly = lanes_for(avg_y, npl_T);
+        h->fg.lx = deep && !npl_T_set ? lanes_near(avg_x, 25.0) : lanes_for(avg_x, npl_T);
+        h->fg.ly = deep && !npl_T_set ? lanes_near(avg_y, 25.0) : lanes_for(avg_y, npl_T);
         std::vector<Unit> units, soc_units, exp_units, row_units;
         std::vector<int> order(K->n_psd);
         for (int i = 0; i < K->n_psd; ++i) order[i] = i;
