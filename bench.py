@@ -159,6 +159,12 @@ def run_batch(args):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     value = count * args.steps / elapsed
+    bad = [i for i, r in enumerate(rec)
+           if r["sj"] != 0 or r["sv"] != 0
+           or max(x.rel_residual for x in r["ij"] + r["iv"]) > args.tol]
+    if bad:
+        print(f"[bench] WARNING: {len(bad)} timed step(s) did not converge: {bad}",
+              file=sys.stderr, flush=True)
     last = rec[-1]
     it_j = [i.iters for i in last["ij"]]
     it_v = [i.iters for i in last["iv"]]
@@ -183,6 +189,7 @@ def run_batch(args):
         "max_rel_residual": {"jvp": max(i.rel_residual for i in last["ij"]),
                              "vjp": max(i.rel_residual for i in last["iv"])},
         "status": {"jvp": last["sj"], "vjp": last["sv"]},
+        "all_steps_converged": not bad,
         "split_ms": {k: round(1e3 * float(np.median([r[k] for r in rec])), 3)
                      for k in ("setup", "jvp", "vjp")},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
@@ -362,6 +369,14 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     value = args.steps / elapsed
+    # a timed step counts only if both solves converged: status OK and the recomputed
+    # relative residual at or below the tolerance
+    bad = [i for i, r in enumerate(rec)
+           if r["sj"] != 0 or r["sv"] != 0 or not (r["ij"].rel_residual <= args.tol)
+           or not (r["iv"].rel_residual <= args.tol)]
+    if bad:
+        print(f"[bench] WARNING: {len(bad)} timed step(s) did not converge: {bad}",
+              file=sys.stderr, flush=True)
 
     # roofline of the dominant kernel: average launch duration measured with HIP events
     h = step(None)
@@ -400,7 +415,9 @@ def main():
                              "soc": len(q.cones.soc), "psd": len(q.cones.psd),
                              "exp": q.cones.n_exp}},
         "lsqr_iters": {"jvp": rec[-1]["ij"].iters, "vjp": rec[-1]["iv"].iters},
-        "rel_residual": {"jvp": rec[-1]["ij"].rel_residual, "vjp": rec[-1]["iv"].rel_residual},
+        "rel_residual": {"jvp": max(r["ij"].rel_residual for r in rec),
+                         "vjp": max(r["iv"].rel_residual for r in rec)},
+        "all_steps_converged": not bad,
         "split_ms": {k: round(1e3 * float(np.median([r[k] for r in rec])), 3)
                      for k in ("setup", "jvp", "vjp")},
         "us_per_lsqr_iter": round(1e6 * float(np.median([r["jvp"] + r["vjp"] for r in rec]))

@@ -44,7 +44,9 @@ extern "C" {
 typedef int32_t qcpd_status;
 
 #define QCPD_OK                     0
-#define QCPD_WARN_NOT_CONVERGED     1   /* LSQR hit max_iter; outputs at the last iterate  */
+#define QCPD_WARN_NOT_CONVERGED     1   /* the explicitly recomputed relative residual is
+                                           above tol (LSQR hit max_iter, or its resumes ran
+                                           out); outputs are written at the last iterate     */
 #define QCPD_WARN_NONDIFF           2   /* a cone block lies within 1e-10 (relative) of a
                                            point where its projection is not differentiable;
                                            the listed tie-break rules were applied           */
@@ -116,7 +118,8 @@ typedef struct {
     double   est_residual;   /* LSQR estimate ||residual|| / ||rhs|| at exit                 */
     double   rel_residual;   /* explicit ||F dz + d|| / ||d|| (JVP) or ||F'w + dz|| / ||dz||
                                 (VJP), recomputed from the returned iterate                  */
-    uint32_t flags;          /* bit 0: not converged; bit 1: non-differentiable warning;
+    uint32_t flags;          /* bit 0: not converged (rel_residual > tol or LSQR stopped at
+                                the iteration cap); bit 1: non-differentiable warning;
                                 bit 2: LEARNED fell back to JACOBI                            */
     float    ms_total;       /* wall time of the call on its stream (HIP events)             */
 } qcpd_info;

@@ -409,6 +409,12 @@ qcpd_status solve(qcpd_handle *h, int dir, const double *sc, const double *scl, 
     return QCPD_OK;
 }
 
+// A solve has converged when LSQR stopped on its own test and the recomputed unscaled
+// relative residual meets the tolerance (the resumes of solve() may run out first).
+bool converged(const qcpd_handle *h, double rel) {
+    return h->host_st[0].conv && !(h->opts.tol > 0.0 && !(rel <= h->opts.tol));
+}
+
 void fill_info(qcpd_handle *h, qcpd_info *info, double rel, int extra_iters = 0,
                uint32_t extra_flags = 0) {
     if (!info) return;
@@ -416,7 +422,7 @@ void fill_info(qcpd_handle *h, qcpd_info *info, double rel, int extra_iters = 0,
     info->iters = st.iters + extra_iters;
     info->est_residual = st.beta1 > 0.0 ? st.phibar / st.beta1 : 0.0;
     info->rel_residual = rel;
-    info->flags = (st.conv ? 0u : 1u) | h->create_flags | extra_flags;
+    info->flags = (converged(h, rel) ? 0u : 1u) | h->create_flags | extra_flags;
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, h->ev0, h->ev1);
     info->ms_total = ms;
@@ -684,9 +690,7 @@ qcpd_status create_impl(qcpd_handle *h, const qcpd_csr *P, const qcpd_csr *A, co
 
 // A learned scaling is replaced by Jacobi when LSQR stopped at the iteration cap or the
 // explicit residual stayed above the tolerance.
-bool needs_fallback(const qcpd_handle *h, double rel) {
-    return !h->host_st[0].conv || (h->opts.tol > 0.0 && !(rel <= h->opts.tol));
-}
+bool needs_fallback(const qcpd_handle *h, double rel) { return !converged(h, rel); }
 
 // One derivative solve with the given scales: state, right-hand side, LSQR.
 qcpd_status jvp_solve(qcpd_handle *h, const double *dP, const double *dA, const double *dq,
@@ -864,7 +868,7 @@ qcpd_status qcpd_jvp(qcpd_handle *h, const double *dP, const double *dA, const d
     HIPCHK(hipStreamSynchronize(s));
     HIPCHK(hipGetLastError());
     fill_info(h, info, rel, extra_iters, extra_flags);
-    return h->host_st[0].conv ? QCPD_OK : QCPD_WARN_NOT_CONVERGED;
+    return converged(h, rel) ? QCPD_OK : QCPD_WARN_NOT_CONVERGED;
 }
 
 qcpd_status qcpd_vjp(qcpd_handle *h, const double *gx, const double *gy, const double *gs,
@@ -898,7 +902,7 @@ qcpd_status qcpd_vjp(qcpd_handle *h, const double *gx, const double *gy, const d
     HIPCHK(hipStreamSynchronize(s));
     HIPCHK(hipGetLastError());
     fill_info(h, info, rel, extra_iters, extra_flags);
-    return h->host_st[0].conv ? QCPD_OK : QCPD_WARN_NOT_CONVERGED;
+    return converged(h, rel) ? QCPD_OK : QCPD_WARN_NOT_CONVERGED;
 }
 
 qcpd_status qcpd_apply(qcpd_handle *h, int32_t transpose, const double *in, double *out) {

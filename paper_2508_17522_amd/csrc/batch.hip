@@ -1267,12 +1267,15 @@ qcpd_status batch_run(qcpd_batch *h, int dir, const double *i0, const double *i1
     bool all_conv = true;
     for (int b = 0; b < h->d.B; ++b) {
         const LsqrState &st = h->host_st[b];
-        all_conv = all_conv && st.conv;
+        // converged: LSQR stopped on its test AND the recomputed unscaled residual meets tol
+        const double rel = st.tau_rhs > 0.0 ? st.resid / st.tau_rhs : 0.0;
+        const bool conv = st.conv && !(h->opts.tol > 0.0 && !(rel <= h->opts.tol));
+        all_conv = all_conv && conv;
         if (info) {
             info[b].iters = st.iters;
             info[b].est_residual = st.beta1 > 0.0 ? st.phibar / st.beta1 : 0.0;
-            info[b].rel_residual = st.tau_rhs > 0.0 ? st.resid / st.tau_rhs : 0.0;
-            info[b].flags = (st.conv ? 0u : 1u) | h->create_flags;
+            info[b].rel_residual = rel;
+            info[b].flags = (conv ? 0u : 1u) | h->create_flags;
             info[b].ms_total = ms;
         }
     }

@@ -166,11 +166,11 @@ __device__ inline bool entry_finish(const StepArgs &a, const Entry &e, LsqrState
         s.pend_blocks = gridDim.x;
         s.pend_fwd = my_fwd;
     }
-    if (blockIdx.x == 0 && tid == 0) {
-        *a.st_next = s;
-        // on the stop decision both buffers get the final state
-        if (s.done) *a.st = s;
-    }
+    // Only the buffer of the next launch is written: other workgroups of this launch may
+    // still be loading *a.st. A stop decided here reaches the other buffer through the next
+    // launch's copy at its entry (every graph holds whole pairs of launches), so after a
+    // graph both buffers hold the final state.
+    if (blockIdx.x == 0 && tid == 0) *a.st_next = s;
     *S = s;
     return !s.done;
 }
@@ -1102,12 +1102,9 @@ __device__ inline bool seg_entry_finish(const StepArgs &a, const SegEntry &e, in
         s.pend_role = a.role;
         s.pend_fwd = my_fwd;
     }
-    if (first && tid == 0) {
+    if (first && tid == 0) {  // as entry_finish: never the buffer this launch reads
         a.st_next[b] = s;
-        if (s.done) {
-            a.st[b] = s;
-            atomicAdd(ndone, 1);
-        }
+        if (s.done) atomicAdd(ndone, 1);
     }
     *S = s;
     return !s.done;
