@@ -3,7 +3,8 @@
 jvp / vjp           -- the paper's steps (Sec. 3.1 and 3.2): z = (x, y - s, 1); the JVP solves
                        min ||F dz + D_theta N[dtheta]|| and maps dz through D phi; the VJP maps
                        the cotangent through D phi', solves min ||F' w + dz||, and returns
-                       D_theta N'[w] restricted to the stored patterns of P and A.
+                       D_theta N'[w] restricted to the stored patterns of P and A. The
+                       least-squares solver is LSQR or LSMR (the paper's), both matrix-free.
 jvp_dense/vjp_dense -- the implicit function theorem applied to the KKT conditions in Minty
                        form with tau fixed to 1 (Sec. 2.3, eq. minty-restrictions is equivalent
                        to eq. kkt-conds):
@@ -26,7 +27,10 @@ import scipy.linalg as sla
 
 from . import cones as C
 from .embedding import Embedding, _coords
+from .lsmr import lsmr
 from .lsqr import lsqr
+
+_SOLVERS = {"lsqr": lsqr, "lsmr": lsmr}
 
 
 # ----------------------------------------------------------------------------------------
@@ -71,12 +75,12 @@ def jacobi_scale_FT(emb: Embedding):
 # ----------------------------------------------------------------------------------------
 
 def jvp(qcp, dP, dA, dq, db, tol=None, max_iter=None, precond="jacobi", emb=None,
-        return_info=False):
+        return_info=False, solver="lsqr"):
     emb = emb or Embedding(qcp)
     tol = qcp.tol if tol is None else tol
     d = emb.dtheta(dP, dA, dq, db)
     scale = jacobi_scale_F(emb) if precond == "jacobi" else None
-    dz, info = lsqr(emb.F, emb.FT, -d, tol=tol, max_iter=max_iter, col_scale=scale)
+    dz, info = _SOLVERS[solver](emb.F, emb.FT, -d, tol=tol, max_iter=max_iter, col_scale=scale)
     dx, dy, ds = emb.dphi(dz)
     if return_info:
         bn = np.linalg.norm(d)
@@ -86,12 +90,12 @@ def jvp(qcp, dP, dA, dq, db, tol=None, max_iter=None, precond="jacobi", emb=None
 
 
 def vjp(qcp, gx, gy, gs, tol=None, max_iter=None, precond="jacobi", emb=None,
-        return_info=False):
+        return_info=False, solver="lsqr"):
     emb = emb or Embedding(qcp)
     tol = qcp.tol if tol is None else tol
     dz = emb.dphi_t(gx, gy, gs)
     scale = jacobi_scale_FT(emb) if precond == "jacobi" else None
-    w, info = lsqr(emb.FT, emb.F, -dz, tol=tol, max_iter=max_iter, col_scale=scale)
+    w, info = _SOLVERS[solver](emb.FT, emb.F, -dz, tol=tol, max_iter=max_iter, col_scale=scale)
     out = emb.dtheta_t(w)
     if return_info:
         bn = np.linalg.norm(dz)
@@ -138,6 +142,38 @@ def vjp_dense(qcp, gx, gy, gs):
     dP = -0.5 * (lx[Pi] * x[Pj] + x[Pi] * lx[Pj])
     dA = -(y[Ai] * lx[Aj] - ly[Ai] * x[Aj])
     return dP, dA, -lx, -ly
+
+
+def jvp_vjp_dense(qcp, dP, dA, dq, db, gx, gy, gs):
+    """jvp_dense and vjp_dense with one LU factorisation of K_red shared by both solves (the
+    same definitions; for the larger instances, where the factorisation dominates). A' J is
+    formed from the sparse A."""
+    eta = qcp.y - qcp.s
+    J = C.DualJacobian(eta, qcp.cones).dense_matrix()
+    n, m = qcp.n, qcp.m
+    K = np.empty((n + m, n + m))
+    K[:n, :n] = qcp.P.toarray()
+    K[:n, n:] = qcp.A.T @ J
+    K[n:, :n] = -qcp.A.toarray()
+    K[n:, n:] = np.eye(m) - J
+    lu = sla.lu_factor(K, overwrite_a=True, check_finite=False)
+    del K
+    dPm = qcp.P.copy()
+    dPm.data = np.asarray(dP, dtype=np.float64).copy()
+    dAm = qcp.A.copy()
+    dAm.data = np.asarray(dA, dtype=np.float64).copy()
+    rhs = -np.concatenate([dPm @ qcp.x + dAm.T @ qcp.y + dq, -(dAm @ qcp.x) + db])
+    sol = sla.lu_solve(lu, rhs, check_finite=False)
+    xi, et = sol[:n], sol[n:]
+    Je = J @ et
+    lam = sla.lu_solve(lu, np.concatenate([gx, J @ (gy + gs) - gs]), trans=1, check_finite=False)
+    lx, ly = lam[:n], lam[n:]
+    Pi, Pj = _coords(qcp.P)
+    Ai, Aj = _coords(qcp.A)
+    x, y = qcp.x, qcp.y
+    dPo = -0.5 * (lx[Pi] * x[Pj] + x[Pi] * lx[Pj])
+    dAo = -(y[Ai] * lx[Aj] - ly[Ai] * x[Aj])
+    return (xi, Je, Je - et), (dPo, dAo, -lx, -ly)
 
 
 def kred_cond(qcp):

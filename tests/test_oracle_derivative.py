@@ -142,3 +142,15 @@ def test_planted_dphi_error_is_caught(monkeypatch):
     got = D.jvp(q, q.dP, q.dA, q.dq, q.db, tol=1e-13)
     ref = D.qp_active_set_jvp(q, q.dP, q.dA, q.dq, q.db)
     assert rel(got[0], ref[0]) > 1e-6
+
+
+def test_shared_factorisation_equals_separate_dense_solves():
+    """jvp_vjp_dense (one LU for both directions, A'J from the sparse A) gives the same
+    numbers as jvp_dense and vjp_dense, which the other pins of this file anchor."""
+    q = qcpgen.small_mixed(1, n=120, A_density=0.08, P_rank=100, P_eps=0.1)
+    assert D.kred_cond(q) < 1e8
+    (dx, dy, ds), (dP, dA, dq, db) = D.jvp_vjp_dense(q, q.dP, q.dA, q.dq, q.db, q.gx, q.gy, q.gs)
+    for a, r in zip((dx, dy, ds), D.jvp_dense(q, q.dP, q.dA, q.dq, q.db)):
+        assert rel(a, r) < 1e-12
+    for a, r in zip((dP, dA, dq, db), D.vjp_dense(q, q.gx, q.gy, q.gs)):
+        assert rel(a, r) < 1e-12
