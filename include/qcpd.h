@@ -250,6 +250,19 @@ int64_t qcpd_mlp_workspace_floats(int32_t nrows);
 qcpd_status qcpd_mlp_grad(const float *feat, const float *target, int32_t nrows,
                           const float *weights, float *workspace, float *grad, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc): qcpd_mlp_grad with its workspace replaced by a
+ * fixed array inside the library, one per GPU, held until the process ends (5.27 MB: the
+ * partial gradients of the at most 256 workgroups one launch uses, so every nrows >= 1
+ * fits; a launch that would need more is rejected with QCPD_ERR_INVALID_ARG). Same
+ * arguments, kernels and summation order as qcpd_mlp_grad, so the results are identical.
+ * Calls no hipMalloc / hipFree. The first call on a device resolves the array's address
+ * (hipGetSymbolAddress); make that call outside graph capture. Every call on a GPU shares
+ * that GPU's array: calls that overlap on one GPU (different streams, or host threads
+ * without ordering) race and give wrong gradients. Asynchronous on the stream. */
+qcpd_status qcpd_mlp_grad_noalloc(const float *feat, const float *target, int32_t nrows,
+                                  const float *weights, float *grad, void *stream);
+
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8; step counts from 1) on the trained
  * parameters; adam_m, adam_v [device] QCPD_MLP_PARAMS floats, zero before step 1. */
 qcpd_status qcpd_mlp_adam(const float *grad, float *weights, float *adam_m, float *adam_v,

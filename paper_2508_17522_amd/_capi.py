@@ -77,7 +77,8 @@ EXPORTS = ["qcpd_opts_default", "qcpd_create", "qcpd_jvp", "qcpd_vjp", "qcpd_set
            "qcpd_batch_set_opts", "qcpd_batch_destroy", "qcpd_features", "qcpd_learned_targets",
            "qcpd_set_learned", "qcpd_mlp_init", "qcpd_mlp_predict", "qcpd_mlp_workspace_floats",
            "qcpd_mlp_grad", "qcpd_mlp_adam", "qcpd_set_launch", "qcpd_get_launch",
-           "qcpd_batch_set_launch", "qcpd_batch_get_launch", "qcpd_apply"]
+           "qcpd_batch_set_launch", "qcpd_batch_get_launch", "qcpd_apply",
+           "qcpd_mlp_grad_noalloc"]
 
 _lib = None
 
@@ -139,6 +140,9 @@ def load(path: str = LIB_PATH):
     lib.qcpd_mlp_grad.argtypes = [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p,
                                   c_void_p]
     lib.qcpd_mlp_grad.restype = c_int32
+    lib.qcpd_mlp_grad_noalloc.argtypes = [c_void_p, c_void_p, c_int32, c_void_p, c_void_p,
+                                          c_void_p]
+    lib.qcpd_mlp_grad_noalloc.restype = c_int32
     lib.qcpd_mlp_adam.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_int32,
                                   ctypes.c_float, c_void_p]
     lib.qcpd_mlp_adam.restype = c_int32

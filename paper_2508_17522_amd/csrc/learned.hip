@@ -16,6 +16,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "qcpd_internal.h"
 
@@ -214,7 +215,8 @@ __global__ __launch_bounds__(256) void k_mlp_scales(const float *feat, int N, co
 constexpr int kR = 16;
 constexpr int kOwn = (kNParam - kTrain0 + 255) / 256;
 
-int grad_blocks(int nrows) { return std::max(1, std::min(256, div_up(nrows, 4 * kR))); }
+constexpr int kMaxGradBlocks = 256;
+int grad_blocks(int nrows) { return std::max(1, std::min(kMaxGradBlocks, div_up(nrows, 4 * kR))); }
 
 __global__ __launch_bounds__(256) void k_mlp_grad(const float *feat, const float *target, int nrows,
                                                   const float *w, float *part) {
@@ -358,6 +360,36 @@ __global__ void k_adam(const float *grad, float *w, float *m, float *v, int step
 }
 
 // ---------------------------------------------------------------------------------------
+// fixed scratch of qcpd_mlp_grad_noalloc: the per-workgroup partial gradients of the largest
+// k_mlp_grad launch (kMaxGradBlocks workgroups), 5.27 MB, one copy per GPU for the life of
+// the process. In host code `scratch` names a host-side stand-in; kernels are given the
+// device address that hipGetSymbolAddress returns for the current device.
+// ---------------------------------------------------------------------------------------
+constexpr size_t kScratchFloats = (size_t)kMaxGradBlocks * (kNParam + 1);
+static __device__ __align__(256) float scratch[kScratchFloats];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float *g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, resolved once per device.
+hipError_t scratch_address(float **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_dev[dev] = static_cast<float *>(ptr);
+    }
+    *out = g_scratch_dev[dev];
+    return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------------------
 // launchers used by the handle API
 // ---------------------------------------------------------------------------------------
 
@@ -420,6 +452,21 @@ qcpd_status qcpd_mlp_grad(const float *feat, const float *target, int32_t nrows,
     const int nb = grad_blocks(nrows);
     hipLaunchKernelGGL(k_mlp_grad, dim3(nb), dim3(256), 0, s, feat, target, nrows, weights, workspace);
     hipLaunchKernelGGL(k_grad_reduce, dim3(div_up(kNParam + 1, 256)), dim3(256), 0, s, workspace, nb,
+                       nrows, grad);
+    return hipGetLastError() == hipSuccess ? QCPD_OK : QCPD_ERR_HIP;
+}
+
+qcpd_status qcpd_mlp_grad_noalloc(const float *feat, const float *target, int32_t nrows,
+                                  const float *weights, float *grad, void *stream) {
+    if (!feat || !target || nrows < 1 || !weights || !grad) return QCPD_ERR_INVALID_ARG;
+    const int nb = grad_blocks(nrows);
+    if ((size_t)nb * (kNParam + 1) > kScratchFloats) return QCPD_ERR_INVALID_ARG;
+    float *part = nullptr;
+    if (scratch_address(&part) != hipSuccess) return QCPD_ERR_HIP;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // k_mlp_grad writes every slot of its nb partial rows, so nothing needs clearing
+    hipLaunchKernelGGL(k_mlp_grad, dim3(nb), dim3(256), 0, s, feat, target, nrows, weights, part);
+    hipLaunchKernelGGL(k_grad_reduce, dim3(div_up(kNParam + 1, 256)), dim3(256), 0, s, part, nb,
                        nrows, grad);
     return hipGetLastError() == hipSuccess ? QCPD_OK : QCPD_ERR_HIP;
 }
