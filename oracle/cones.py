@@ -10,6 +10,9 @@ so per block:
   exponential      -> dual exponential cone via Moreau:
                       Pi_{exp*}(z) = z + Pi_exp(-z), DPi_{exp*}(z) = I - DPi_exp(-z)
                                                                        (App. A, "Dual exponential cone")
+  power (K_pow,a)  -> dual power cone via Moreau, as for the exponential cone
+                                                                       (App. A, "Dual power cone")
+  dual power       -> its dual is K_pow,a itself                       (App. A, "Power cone")
 Readings where the appendix is silent or garbled:
   * at kinks the cases are tested in the listed order with closed inequalities
     (nonneg: 1{z > 0}; SOC: ||u|| <= -t -> 0, ||u|| <= t -> I, else the formula);
@@ -309,7 +312,124 @@ def jac_exp_dual(z):
 
 
 # ----------------------------------------------------------------------------------------
-# product cone K* in this project's row order: zero, nonneg, SOC..., PSD..., exp...
+# power cone (App. A, "Power cone"), 0 < a < 1
+#   K_pow,a  = {(x,y,z): x^a y^(1-a) >= |z|, x >= 0, y >= 0}
+#   K_pow,a* = {(u,v,w): (u/a)^a (v/(1-a))^(1-a) >= |w|, u >= 0, v >= 0}
+#   polar    = -K_pow,a*
+# ----------------------------------------------------------------------------------------
+
+def in_pow(p, a):
+    x, y, z = p
+    return x >= 0 and y >= 0 and x ** a * y ** (1.0 - a) >= abs(z)
+
+
+def in_pow_dual(p, a):
+    u, v, w = p
+    return u >= 0 and v >= 0 and (u / a) ** a * (v / (1.0 - a)) ** (1.0 - a) >= abs(w)
+
+
+def in_pow_polar(p, a):
+    return in_pow_dual(-np.asarray(p, dtype=np.float64), a)
+
+
+def _half_root(x, t):
+    """(x + sqrt(x^2 + t)) / 2 for t >= 0; for x < 0 as t / (2 (sqrt(x^2 + t) - x)), the same
+    number without the cancellation."""
+    s = math.sqrt(x * x + t)
+    return 0.5 * (x + s) if x >= 0 else 0.5 * t / (s - x)
+
+
+def _pow_f(x, y, z, a, r):
+    """f_x(r), f_y(r) of eq. pow-system."""
+    az = abs(z)
+    fx = _half_root(x, 4.0 * a * r * (az - r))
+    fy = _half_root(y, 4.0 * (1.0 - a) * r * (az - r))
+    return fx, fy
+
+
+def _pow_root(p, a):
+    """The solution r in (0, |z|) of r = f_x(r)^a f_y(r)^(1-a) (eq. pow-system). Outside
+    K and its polar, h(r) = f_x^a f_y^(1-a) - r is positive just above 0 and negative at
+    |z|; plain bisection on the sign of h until the bracket stops shrinking."""
+    x, y, z = (float(t) for t in p)
+    lo, hi = 0.0, abs(z)
+
+    def h(r):
+        fx, fy = _pow_f(x, y, z, a, r)
+        return fx ** a * fy ** (1.0 - a) - r
+
+    for _ in range(400):
+        mid = 0.5 * (lo + hi)
+        if mid <= lo or mid >= hi:
+            break
+        if h(mid) > 0.0:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
+def proj_pow(p, a):
+    """Pi_pow,a by the appendix's four cases, tested in the listed order."""
+    p = np.asarray(p, dtype=np.float64)
+    x, y, z = p
+    if in_pow(p, a):
+        return p.copy()
+    if in_pow_polar(p, a):
+        return np.zeros(3)
+    if z == 0.0:
+        return np.array([max(x, 0.0), max(y, 0.0), 0.0])
+    r = _pow_root(p, a)
+    fx, fy = _pow_f(x, y, z, a, r)
+    return np.array([fx, fy, math.copysign(r, z)])
+
+
+def jac_pow(p, a):
+    """DPi_pow,a(p) (App. A, power cone derivative cases; the z != 0 case is the closed form
+    the appendix takes from Hien's Theorem 3.1)."""
+    p = np.asarray(p, dtype=np.float64)
+    x, y, z = p
+    if in_pow(p, a):
+        return np.eye(3)
+    if in_pow_polar(p, a):
+        return np.zeros((3, 3))
+    if z == 0.0:
+        if x > 0 and y < 0:
+            d = 1.0 if a > 0.5 else (0.0 if a < 0.5 else x / (2.0 * abs(y) + x))
+        elif x < 0 and y > 0:
+            d = 1.0 if a < 0.5 else (0.0 if a > 0.5 else y / (2.0 * abs(x) + y))
+        else:
+            d = 0.0
+        return np.diag([1.0 if x > 0 else 0.0, 1.0 if y > 0 else 0.0, d])
+    r = _pow_root(p, a)
+    fx, fy = _pow_f(x, y, z, a, r)
+    az, sz = abs(z), math.copysign(1.0, z)
+    gx, gy = 2.0 * fx - x, 2.0 * fy - y
+    T = -(a * x / gx + (1.0 - a) * y / gy)
+    L = 2.0 * (az - r) / (az + (az - 2.0 * r) * (a * x / gx + (1.0 - a) * y / gy))
+    J = np.empty((3, 3))
+    J[0, 0] = 0.5 + x / (2.0 * gx) + a * a * (az - 2.0 * r) * r * L / gx ** 2
+    J[0, 1] = J[1, 0] = (a - a * a) * (az - 2.0 * r) * r * L / (gx * gy)
+    J[0, 2] = J[2, 0] = sz * a * r * L / gx
+    J[1, 1] = 0.5 + y / (2.0 * gy) + (1.0 - a) ** 2 * (az - 2.0 * r) * r * L / gy ** 2
+    J[1, 2] = J[2, 1] = sz * (1.0 - a) * r * L / gy
+    J[2, 2] = r / az + (r / az) * T * L
+    return J
+
+
+def proj_pow_dual(zv, a):
+    """Pi onto K_pow,a* by Moreau (App. A, "Dual power cone"): z + Pi_pow,a(-z)."""
+    return np.asarray(zv, dtype=np.float64) + proj_pow(-np.asarray(zv, dtype=np.float64), a)
+
+
+def jac_pow_dual(zv, a):
+    return np.eye(3) - jac_pow(-np.asarray(zv, dtype=np.float64), a)
+
+
+# ----------------------------------------------------------------------------------------
+# product cone K* in this project's row order: zero, nonneg, SOC..., PSD..., exp...,
+# power..., dual power... For a power cone K_pow,a the dual cone K* is K_pow,a* (projected by
+# Moreau); for a dual power cone K_pow,a* it is K_pow,a itself.
 # ----------------------------------------------------------------------------------------
 
 def blocks(cones):
@@ -331,6 +451,12 @@ def blocks(cones):
     for _ in range(cones.n_exp):
         yield ("exp", off, 3)
         off += 3
+    for a in getattr(cones, "pow", ()):
+        yield (("pow", a), off, 3)
+        off += 3
+    for a in getattr(cones, "dpow", ()):
+        yield (("dpow", a), off, 3)
+        off += 3
 
 
 def proj_dual(zy, cones):
@@ -346,8 +472,12 @@ def proj_dual(zy, cones):
             out[a:a + r] = proj_soc(seg)
         elif kind == "psd":
             out[a:a + r] = proj_psd(seg)
-        else:
+        elif kind == "exp":
             out[a:a + r] = proj_exp_dual(seg)
+        elif kind[0] == "pow":        # K* = K_pow,a*
+            out[a:a + r] = proj_pow_dual(seg, kind[1])
+        else:                         # dual power cone: K* = K_pow,a
+            out[a:a + r] = proj_pow(seg, kind[1])
     return out
 
 
@@ -372,10 +502,15 @@ class DualJacobian:
                 dense.setdefault(r, ([], []))
                 dense[r][0].append(a)
                 dense[r][1].append(jac_soc(seg))
-            elif kind == "exp":
+            elif kind == "exp" or kind[0] in ("pow", "dpow"):
                 dense.setdefault(3, ([], []))
                 dense[3][0].append(a)
-                dense[3][1].append(jac_exp_dual(seg))
+                if kind == "exp":
+                    dense[3][1].append(jac_exp_dual(seg))
+                elif kind[0] == "pow":
+                    dense[3][1].append(jac_pow_dual(seg, kind[1]))
+                else:
+                    dense[3][1].append(jac_pow(seg, kind[1]))
             else:
                 k = psd_order(r)
                 V, B, _ = psd_factors(seg)

@@ -12,7 +12,8 @@ A complementary pair (s, y) is drawn per cone block, then q = -Px - A'y and b = 
 
 Row order of the cone (a layout convention of this project): zero, nonnegative, second-order
 cones, PSD cones (svec: lower triangle, column-major, off-diagonal entries scaled by sqrt 2),
-exponential cones (3 rows each, ordered (x, y, z) as in Appendix A).
+exponential cones, power cones, dual power cones (3 rows each, ordered (x, y, z) as in
+Appendix A).
 
 Seeds: numpy.random.default_rng([config_id, problem_idx, attempt]).
 """
@@ -35,11 +36,14 @@ class Cones:
     soc: List[int] = dataclasses.field(default_factory=list)   # dimension of each SOC
     psd: List[int] = dataclasses.field(default_factory=list)   # order k of each PSD block
     n_exp: int = 0
+    pow: List[float] = dataclasses.field(default_factory=list)   # alpha of each power cone
+    dpow: List[float] = dataclasses.field(default_factory=list)  # alpha of each dual power cone
 
     @property
     def m(self) -> int:
         return (self.n_zero + self.n_nonneg + sum(self.soc)
-                + sum(k * (k + 1) // 2 for k in self.psd) + 3 * self.n_exp)
+                + sum(k * (k + 1) // 2 for k in self.psd) + 3 * self.n_exp
+                + 3 * len(self.pow) + 3 * len(self.dpow))
 
 
 @dataclasses.dataclass
@@ -241,12 +245,43 @@ def _exp_pair(rng, state):
     return s, y, 1, {"r": r, "s2": s2, "mu": mu}
 
 
+def _pow_surface_pair(rng, a):
+    """A boundary point w = (x, y, +-x^a y^(1-a)) of K_pow,a and the normal
+    n = (a|z|/x, (1-a)|z|/y, -sign z) there, which lies on the boundary of K_pow,a* and is
+    orthogonal to w (x^a y^(1-a) is homogeneous of degree one)."""
+    x, y = rng.uniform(0.3, 2.0, size=2)
+    zz = x ** a * y ** (1.0 - a) * (1.0 if rng.uniform() < 0.5 else -1.0)
+    nrm = np.array([a * abs(zz) / x, (1.0 - a) * abs(zz) / y, -math.copysign(1.0, zz)])
+    return np.array([x, y, zz]), nrm
+
+
+def _pow_pair(rng, a, state, dual):
+    """Complementary pair for a power cone (dual=False: s in K_pow,a, y in K_pow,a*) or a
+    dual power cone (dual=True: s in K_pow,a*, y in K_pow,a). Returns s, y, hard codim."""
+    if state == 's_int' or state == 'y_int':
+        u, v = rng.uniform(0.3, 2.0, size=2)
+        interior_of_k = (state == 's_int') != dual   # the vector drawn lies in int K_pow,a
+        lim = u ** a * v ** (1.0 - a) if interior_of_k else \
+            (u / a) ** a * (v / (1.0 - a)) ** (1.0 - a)
+        w = rng.uniform(-0.8, 0.8) * lim
+        vec = np.array([u, v, w])
+        if state == 's_int':
+            return vec, np.zeros(3), 0
+        return np.zeros(3), vec, 3
+    pt, nrm = _pow_surface_pair(rng, a)
+    mu = rng.uniform(0.1, 1.0)
+    if not dual:
+        return pt, mu * nrm, 1
+    return mu * nrm, pt, 1
+
+
 # ----------------------------------------------------------------------------------------
 # generic builder
 # ----------------------------------------------------------------------------------------
 
 def build(rng, name, n, cones: Cones, *, A_density, P, nonneg_active=None, soc_states=None,
-          psd_ranks=None, exp_states=None, pert_std=1e-2, tol=1e-8, A=None) -> QCP:
+          psd_ranks=None, exp_states=None, pow_states=None, pert_std=1e-2, tol=1e-8,
+          A=None) -> QCP:
     m = cones.m
     if A is None:
         A = sparse_gaussian(rng, m, n, A_density)
@@ -293,6 +328,16 @@ def build(rng, name, n, cones: Cones, *, A_density, P, nonneg_active=None, soc_s
         codim += c_
         meta["exp_states"].append(st)
         meta["exp_params"].append(prm)
+    npow = len(cones.pow) + len(cones.dpow)
+    for i, (a_, dual) in enumerate([(a_, False) for a_ in cones.pow] +
+                                   [(a_, True) for a_ in cones.dpow]):
+        st = pow_states[i] if pow_states is not None else ('s_int', 'y_int', 'bnd')[i % 3]
+        s_, y_, c_ = _pow_pair(rng, a_, st, dual)
+        s_parts.append(s_)
+        y_parts.append(y_)
+        codim += c_
+        meta.setdefault("pow_states", []).append(st)
+    del npow
     s = np.concatenate(s_parts) if s_parts else np.zeros(0)
     y = np.concatenate(y_parts) if y_parts else np.zeros(0)
     assert s.size == m and y.size == m
@@ -462,35 +507,51 @@ def precond_family(idx=0) -> QCP:
     return qcp
 
 
-def large_psd_soc(idx=0) -> QCP:
-    """n=20000, m=290000: nonneg 15000, 2000 SOC(10), 200 PSD 50x50 (1275 svec rows
-    each). A has ~3M nnz; P = BB' with B 20000x200 at density 0.01."""
+def large_psd_soc(idx=0, scale=1.0) -> QCP:
+    """n=20000, m=290000: nonneg 15000, 2000 SOC(10), 200 PSD 50x50 (1275 svec rows each).
+    A has ~3M nnz (about 10.3 per row, N(0,1)); P = BB' with B 20000x200 at density 0.01.
+
+    Faces: PSD rank(Y) ~ U{3..12}, SOC one third per state (s interior, y interior, boundary
+    pair), and active nonnegative rows filling the hard face codimension (rows the solution
+    holds fixed: active nonnegative rows, y-interior SOC rows, the j(j+1)/2 directions of a
+    PSD block with rank(Y) = j, one per SOC boundary pair) to 0.8 n. The PSD cross directions
+    (j(k-j) per block) and the interior directions of SOC boundary pairs add curvature, so the
+    reduced Hessian is definite without the codimension reaching n - rank P; a codimension
+    close to n makes the fixed rows nearly square and the derivative badly conditioned (at
+    19 900 of 20 000, LSQR stalls above 1e-3).
+
+    scale < 1 shrinks every count by that factor (PSD order and SOC dimension unchanged, same
+    entries per row of A) for reduced instances of the same shape."""
     rng = np.random.default_rng([4, idx, 0])
-    n = 20000
-    cones = Cones(n_nonneg=15000, soc=[10] * 2000, psd=[50] * 200)
+    n = max(1, int(round(20000 * scale)))
+    n_nn = int(round(15000 * scale))
+    n_soc = int(round(2000 * scale))
+    n_psd = max(1, int(round(200 * scale)))
+    rank_p = max(1, int(round(200 * scale)))
+    cones = Cones(n_nonneg=n_nn, soc=[10] * n_soc, psd=[50] * n_psd)
     m = cones.m
-    B = sp.random(n, 200, density=0.01, random_state=rng,
+    B = sp.random(n, rank_p, density=0.01, random_state=rng,
                   data_rvs=rng.standard_normal, format="csr")
     P = psd_from_factor(B, 0.0)
-    psd_ranks = [int(j) for j in rng.integers(5, 16, size=200)]
-    soc_states = [('s_int', 'y_int', 'bnd')[i % 3] for i in range(2000)]
+    psd_ranks = [int(j) for j in rng.integers(3, 13, size=n_psd)]
+    soc_states = [('s_int', 'y_int', 'bnd')[i % 3] for i in range(n_soc)]
     cod = sum(j * (j + 1) // 2 for j in psd_ranks) + \
         sum({'s_int': 0, 'y_int': 10, 'bnd': 1}[s] for s in soc_states)
-    n_act = int(min(max(19900 - cod, 0), 15000))
-    qcp = build(rng, "large_psd_soc_n20000_m290000", n, cones, A_density=3.0e6 / (m * n),
-                P=P, nonneg_active=n_act, soc_states=soc_states, psd_ranks=psd_ranks,
-                tol=1e-8)
+    n_act = int(min(max(int(round(0.8 * n)) - cod, 0), n_nn))
+    name = "large_psd_soc_n20000_m290000" if scale == 1.0 else f"large_psd_soc_n{n}_m{m}"
+    qcp = build(rng, name, n, cones, A_density=(3.0e6 / 290000) / n, P=P,
+                nonneg_active=n_act, soc_states=soc_states, psd_ranks=psd_ranks, tol=1e-8)
     qcp.meta["seed"] = [4, idx, 0]
     return qcp
 
 
 def small_mixed(idx=0, n=40, n_zero=6, n_nonneg=30, soc=(3, 4, 5), psd=(2, 3, 4), n_exp=3,
                 A_density=0.15, P_rank=None, P_eps=0.0, nonneg_active=None,
-                psd_ranks=None) -> QCP:
+                psd_ranks=None, pow_alphas=(), dpow_alphas=()) -> QCP:
     """A small mixed-cone instance (every cone type) for pins and parity tests."""
     rng = np.random.default_rng([10, idx, n])
     cones = Cones(n_zero=n_zero, n_nonneg=n_nonneg, soc=list(soc), psd=list(psd),
-                  n_exp=n_exp)
+                  n_exp=n_exp, pow=list(pow_alphas), dpow=list(dpow_alphas))
     r = P_rank if P_rank is not None else max(1, n // 4)
     B = rng.standard_normal((n, r)) / math.sqrt(r)   # P entries O(1), like A's
     Pd = B @ B.T + P_eps * np.eye(n)
