@@ -1,17 +1,18 @@
 """Benchmark: JVP+VJP solves per second on one MI355X, FP64, LSQR relative residual 1e-8.
 
 One step (one "solve") = create a handle at the solution (setup: copies, A', Px, cone
-projections and Jacobian factors including the PSD eigendecompositions, Jacobi scales)
-+ one JVP + one VJP, on the mixed-cone workload n = 5000, m = 11000 (zero 1000, nonneg 5000,
-500 SOC(4), 10 PSD 20x20, 300 exponential cones), synthetic and seeded. All inputs are
-resident in HBM before the timed region.
+projections and Jacobian factors including the PSD eigendecompositions, scales) + one JVP +
+one VJP, on the PSD/SOC-heavy workload n = 20000, m = 290000 (nonneg 15000, 2000 SOC(10),
+200 PSD 50x50; A ~3M entries, P = BB' of rank 200), synthetic and seeded; --workload
+mixed_qcp runs the n = 5000, m = 11000 mixed-cone workload instead. All inputs are resident
+in HBM before the timed region.
 
 Prints ONE JSON line. Also reports the LSQR iteration counts, the setup/JVP/VJP split, the
 roofline position of the dominant kernel (algorithmic bytes per launch / its average launch
 time, measured with HIP events on the library's stream) and the CPU oracle timed on a
 bounded sample on this host.
 
-usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload mixed_qcp]
+usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large_psd_soc]
        python bench.py --workload batch [--batch-count 512]   (batched form, one launch)
 """
 from __future__ import annotations
@@ -69,47 +70,68 @@ def profiled_traffic(workload: str, kernel: str):
     return t["kernels"][kernel]["hbm_bytes_per_launch"]
 
 
-def cpu_baseline(q, iters_jvp, iters_vjp, budget_s=20.0):
-    """The oracle (numpy/scipy, as it stands) on a bounded sample: its setup at the solution
-    plus a fixed number of LSQR iterations of the JVP and of the VJP, single-threaded.
-    Scaled to solves/s with the GPU's iteration counts."""
+def _oracle_rates(q, threads, budget_s):
+    """Setup time and seconds per LSQR iteration of each direction of the oracle (numpy /
+    scipy as it stands) with `threads` BLAS threads: a short run of each direction and a
+    longer one sized to the budget; the difference of the two cancels the fixed costs
+    (right-hand side, scales, first products)."""
     from threadpoolctl import threadpool_limits
 
     from oracle import derivative as D
     from oracle import embedding as E
 
-    with threadpool_limits(limits=1):
+    with threadpool_limits(limits=threads):
         t0 = time.perf_counter()
         emb = E.Embedding(q)
         t_setup = time.perf_counter() - t0
-        # per-iteration cost measured on a short run of each direction
-        sample = 400
-        t0 = time.perf_counter()
-        D.jvp(q, q.dP, q.dA, q.dq, q.db, tol=1e-300, max_iter=sample, emb=emb)
-        t_jvp_it = (time.perf_counter() - t0) / sample
-        t0 = time.perf_counter()
-        D.vjp(q, q.gx, q.gy, q.gs, tol=1e-300, max_iter=sample, emb=emb)
-        t_vjp_it = (time.perf_counter() - t0) / sample
-        # a longer sample of the JVP if the budget allows
-        extra = int(max(0, budget_s - 2 * sample * (t_jvp_it + t_vjp_it) - t_setup) / max(t_jvp_it, 1e-9))
-        extra = min(extra, 20000)
-        if extra > 1000:
+
+        def run(direction, k):
             t0 = time.perf_counter()
-            D.jvp(q, q.dP, q.dA, q.dq, q.db, tol=1e-300, max_iter=extra, emb=emb)
-            t_jvp_it = (time.perf_counter() - t0) / extra
-    t_solve = t_setup + t_jvp_it * iters_jvp + t_vjp_it * iters_vjp
+            if direction == "jvp":
+                D.jvp(q, q.dP, q.dA, q.dq, q.db, tol=1e-300, max_iter=k, emb=emb)
+            else:
+                D.vjp(q, q.gx, q.gy, q.gs, tol=1e-300, max_iter=k, emb=emb)
+            return time.perf_counter() - t0
+
+        rates, counts = {}, {}
+        for direction in ("jvp", "vjp"):
+            k0 = 2
+            t_short = run(direction, k0)
+            per = max(t_short / k0, 1e-9)
+            k1 = int(min(20000, max(k0 + 8, 0.5 * budget_s / per)))
+            t_long = run(direction, k1)
+            rates[direction] = max(t_long - t_short, 1e-12) / (k1 - k0)
+            counts[direction] = k1
+    return t_setup, rates, counts
+
+
+def cpu_baseline(q, iters_jvp, iters_vjp, budget_s=20.0):
+    """The oracle on this host on a bounded sample, at one thread and with every core
+    available to its BLAS: per-iteration times of both directions x the GPU's iteration
+    counts, plus the oracle's setup at the solution. `value` is the faster of the two."""
+    ncores = len(os.sched_getaffinity(0)) or 1
+    if os.environ.get("OMP_NUM_THREADS", "").isdigit():  # the host's share for this process
+        ncores = max(1, min(ncores, int(os.environ["OMP_NUM_THREADS"])))
+    out = {}
+    for threads in (1, ncores):
+        t_setup, rates, counts = _oracle_rates(q, threads, budget_s / 2)
+        t_solve = t_setup + rates["jvp"] * iters_jvp + rates["vjp"] * iters_vjp
+        out[threads] = dict(value=1.0 / t_solve, setup_s=t_setup, s_per_iter_jvp=rates["jvp"],
+                            s_per_iter_vjp=rates["vjp"], sampled_iters=counts)
+    best = max(out, key=lambda k: out[k]["value"])
     return {
-        "value": 1.0 / t_solve,
+        "value": out[best]["value"],
         "unit": "solves/s",
-        "cores": 1,
+        "cores": best,
         "kind": "oracle",
-        "sample": (f"oracle setup at the solution + {sample} LSQR iterations of the VJP and "
-                   f"{max(sample, extra)} of the JVP on the same workload, 1 thread; "
+        "sample": (f"oracle (numpy/scipy) setup at the solution + {out[best]['sampled_iters']['jvp']} "
+                   f"LSQR iterations of the JVP and {out[best]['sampled_iters']['vjp']} of the VJP on "
+                   f"the same workload with {best} BLAS thread(s) (scipy's sparse products use one); "
                    f"per-iteration time x the GPU's iteration counts ({iters_jvp} JVP + "
-                   f"{iters_vjp} VJP)"),
-        "s_per_iter_jvp": t_jvp_it,
-        "s_per_iter_vjp": t_vjp_it,
-        "setup_s": t_setup,
+                   f"{iters_vjp} VJP); {ncores} cores available"),
+        "nproc": ncores,
+        "one_thread": {k: out[1][k] for k in ("value", "setup_s", "s_per_iter_jvp", "s_per_iter_vjp")},
+        "all_cores": {k: out[ncores][k] for k in ("value", "setup_s", "s_per_iter_jvp", "s_per_iter_vjp")},
     }
 
 
@@ -282,12 +304,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="mixed_qcp")
+    ap.add_argument("--workload", default="large_psd_soc")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precond", default="equil", choices=["equil", "jacobi", "none"])
     ap.add_argument("--no-plain", action="store_true",
                     help="skip the plain Jacobi-preconditioned LSQR comparison")
+    ap.add_argument("--plain-max-iter", type=int, default=100000,
+                    help="iteration cap of each direction of the plain Jacobi comparison")
     ap.add_argument("--engine", default="auto", choices=["auto", "graph", "persistent"])
     ap.add_argument("--batch-count", type=int, default=512,
                     help="problems per launch for --workload batch")
@@ -428,7 +452,8 @@ def main():
         # plain Jacobi-preconditioned LSQR on the same GPU, same stopping tolerance
         print("[bench] plain Jacobi LSQR for comparison", file=sys.stderr, flush=True)
         plain = []
-        o2 = Q.Opts(tol=args.tol, precond=Q.QCPD_PRECOND_JACOBI, engine=eng)
+        o2 = Q.Opts(tol=args.tol, precond=Q.QCPD_PRECOND_JACOBI, engine=eng,
+                    max_iter=args.plain_max_iter)
         torch.cuda.synchronize()
         tp = time.perf_counter()
         step(plain, o2).close()
@@ -438,7 +463,9 @@ def main():
                             "unit": "solves/s", "speedup": round(value * tp, 3),
                             "lsqr_iters": {"jvp": plain[0]["ij"].iters, "vjp": plain[0]["iv"].iters},
                             "rel_residual": {"jvp": plain[0]["ij"].rel_residual,
-                                             "vjp": plain[0]["iv"].rel_residual}}
+                                             "vjp": plain[0]["iv"].rel_residual},
+                            "max_iter": args.plain_max_iter,
+                            "converged": plain[0]["sj"] == 0 and plain[0]["sv"] == 0}
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(q, rec[-1]["ij"].iters, rec[-1]["iv"].iters)

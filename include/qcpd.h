@@ -21,8 +21,9 @@
  *     A perturbation dP must be symmetric on that pattern; the returned dP is symmetric.
  *     Inner products over dP, dA are sums over stored entries.
  *   - Cone rows are ordered: zero, nonnegative, second-order cones (t first), PSD cones
- *     (svec: lower triangle column-major, off-diagonals times sqrt 2), exponential cones
- *     (x, y, z) per Appendix A.
+ *     (svec: lower triangle column-major, off-diagonals times sqrt 2), exponential cones,
+ *     power cones, dual power cones ((x, y, z) each, per Appendix A). The batched form takes
+ *     no power cones.
  *   - Pointers marked [device] are device (HBM) pointers on the current HIP device; [host]
  *     are host pointers. The caller owns every buffer it passes. qcpd_create copies or
  *     derives everything it needs, so its inputs may be freed once it returns.
@@ -92,6 +93,10 @@ typedef struct {
     int32_t n_psd;               /* number of PSD cones                                     */
     const int32_t *psd_orders;   /* n_psd matrix orders k (1 <= k <= 64); k(k+1)/2 rows each */
     int32_t n_exp;               /* number of exponential cones, 3 rows each                */
+    int32_t n_pow;               /* number of power cones K_pow,a, 3 rows each              */
+    const double *pow_alpha;     /* n_pow exponents a, each in (0, 1)                       */
+    int32_t n_dpow;              /* number of dual power cones K_pow,a*, 3 rows each         */
+    const double *dpow_alpha;    /* n_dpow exponents a, each in (0, 1)                      */
 } qcpd_cones;
 
 typedef struct {
@@ -101,7 +106,21 @@ typedef struct {
     int32_t graph_chunk;  /* LSQR iterations per captured HIP graph launch     (128)           */
     int32_t check_symmetry; /* verify that P is symmetric at create              (1)           */
     int32_t engine;       /* LSQR driver: QCPD_ENGINE_AUTO, _GRAPH, _PERSISTENT (AUTO)         */
+    int32_t solver;       /* Krylov method: QCPD_SOLVER_LSQR or QCPD_SOLVER_LSMR (LSQR)      */
 } qcpd_opts;
+
+/* Krylov methods for the least-squares problems (Sec. 3.1-3.2). Both build the same
+ * Golub-Kahan bidiagonalisation from one product with the operator and one with its
+ * transpose per iteration, and on these consistent systems both converge to a least-squares
+ * solution, which gives the same outputs. LSQR (Paige & Saunders) minimises the residual
+ * over the Krylov space; LSMR (Fong & Saunders), the method the paper uses, minimises the
+ * norm of the transposed operator times the residual, and keeps one more direction vector.
+ * The stopping rule is the same for both: the method's estimate of ||residual|| / ||rhs||
+ * at or below tol, then the residual recomputed explicitly. LSMR runs on the GRAPH driver
+ * (AUTO picks it; PERSISTENT is rejected with QCPD_ERR_INVALID_ARG) with one more launch per
+ * iteration for its recurrences and iterate update. The batched form runs LSQR only. */
+#define QCPD_SOLVER_LSQR        0
+#define QCPD_SOLVER_LSMR        1
 
 /* LSQR drivers of the single-problem path. GRAPH: two launches per iteration, captured in
  * HIP graphs of graph_chunk iterations, the host polling a device stop flag per graph; each
@@ -115,7 +134,7 @@ typedef struct {
 
 typedef struct {
     int32_t  iters;          /* LSQR iterations                                              */
-    double   est_residual;   /* LSQR estimate ||residual|| / ||rhs|| at exit                 */
+    double   est_residual;   /* the Krylov method's estimate ||residual|| / ||rhs|| at exit  */
     double   rel_residual;   /* explicit ||F dz + d|| / ||d|| (JVP) or ||F'w + dz|| / ||dz||
                                 (VJP), recomputed from the returned iterate                  */
     uint32_t flags;          /* bit 0: not converged (rel_residual > tol or LSQR stopped at
@@ -315,7 +334,8 @@ qcpd_status qcpd_batch_vjp(qcpd_batch *hb, const double *gx, const double *gy, c
                            double *dP_val, double *dA_val, double *dq, double *db,
                            qcpd_info *info);
 
-/* Replace the batch's LSQR options (tolerance, iteration cap, NONE, JACOBI or EQUIL). */
+/* Replace the batch's LSQR options (tolerance, iteration cap, NONE, JACOBI or EQUIL;
+ * solver must be QCPD_SOLVER_LSQR). */
 qcpd_status qcpd_batch_set_opts(qcpd_batch *hb, const qcpd_opts *opts);
 
 /* Persistent workgroups of the batch's per-problem phases (right-hand side and first product

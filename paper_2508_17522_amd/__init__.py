@@ -8,6 +8,7 @@ from ._capi import (QCPD_OK, QCPD_WARN_NOT_CONVERGED, QCPD_WARN_NONDIFF, QCPD_ER
                     QCPD_ERR_OOM, QCPD_PRECOND_NONE, QCPD_PRECOND_JACOBI, QCPD_PRECOND_CUSTOM,
                     QCPD_PRECOND_EQUIL, QCPD_PRECOND_LEARNED, QCPD_FLAG_FALLBACK,
                     QCPD_ENGINE_AUTO, QCPD_ENGINE_GRAPH, QCPD_ENGINE_PERSISTENT,
+                    QCPD_SOLVER_LSQR, QCPD_SOLVER_LSMR,
                     LIB_PATH, EXPORTS)
 from .api import (Cones, Opts, Info, Handle, QCPDError, qcpd_create, qcpd_jvp, qcpd_vjp,
                   qcpd_destroy, qcpd_status_str, qcpd_opts_default, qcpd_set_opts,

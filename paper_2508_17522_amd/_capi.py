@@ -21,12 +21,15 @@ class qcpd_csr(ctypes.Structure):
 class qcpd_cones(ctypes.Structure):
     _fields_ = [("n_zero", c_int32), ("n_nonneg", c_int32), ("n_soc", c_int32),
                 ("soc_dims", ctypes.POINTER(c_int32)), ("n_psd", c_int32),
-                ("psd_orders", ctypes.POINTER(c_int32)), ("n_exp", c_int32)]
+                ("psd_orders", ctypes.POINTER(c_int32)), ("n_exp", c_int32),
+                ("n_pow", c_int32), ("pow_alpha", ctypes.POINTER(c_double)),
+                ("n_dpow", c_int32), ("dpow_alpha", ctypes.POINTER(c_double))]
 
 
 class qcpd_opts(ctypes.Structure):
     _fields_ = [("tol", c_double), ("max_iter", c_int32), ("precond", c_int32),
-                ("graph_chunk", c_int32), ("check_symmetry", c_int32), ("engine", c_int32)]
+                ("graph_chunk", c_int32), ("check_symmetry", c_int32), ("engine", c_int32),
+                ("solver", c_int32)]
 
 
 class qcpd_info(ctypes.Structure):
@@ -48,6 +51,9 @@ QCPD_ERR_OOM = -7
 QCPD_ENGINE_AUTO = 0
 QCPD_ENGINE_GRAPH = 1
 QCPD_ENGINE_PERSISTENT = 2
+
+QCPD_SOLVER_LSQR = 0
+QCPD_SOLVER_LSMR = 1
 
 QCPD_PRECOND_NONE = 0
 QCPD_PRECOND_JACOBI = 1

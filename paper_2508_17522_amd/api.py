@@ -50,11 +50,24 @@ class Cones:
     soc: Sequence[int] = ()
     psd: Sequence[int] = ()
     n_exp: int = 0
+    pow: Sequence[float] = ()    # exponent of each power cone
+    dpow: Sequence[float] = ()   # exponent of each dual power cone
 
     @property
     def m(self) -> int:
         return (self.n_zero + self.n_nonneg + sum(self.soc)
-                + sum(k * (k + 1) // 2 for k in self.psd) + 3 * self.n_exp)
+                + sum(k * (k + 1) // 2 for k in self.psd) + 3 * self.n_exp
+                + 3 * len(self.pow) + 3 * len(self.dpow))
+
+    def to_c(self):
+        """The C struct and the arrays it points into (keep both alive during the call)."""
+        soc = (C.c_int32 * max(len(self.soc), 1))(*self.soc)
+        psd = (C.c_int32 * max(len(self.psd), 1))(*self.psd)
+        pw = (C.c_double * max(len(self.pow), 1))(*self.pow)
+        dp = (C.c_double * max(len(self.dpow), 1))(*self.dpow)
+        K = C.qcpd_cones(self.n_zero, self.n_nonneg, len(self.soc), soc, len(self.psd), psd,
+                         self.n_exp, len(self.pow), pw, len(self.dpow), dp)
+        return K, (soc, psd, pw, dp)
 
 
 @dataclasses.dataclass
@@ -65,10 +78,11 @@ class Opts:
     graph_chunk: int = 128
     check_symmetry: int = 1
     engine: int = C.QCPD_ENGINE_AUTO
+    solver: int = C.QCPD_SOLVER_LSQR
 
     def to_c(self) -> C.qcpd_opts:
         return C.qcpd_opts(self.tol, self.max_iter, self.precond, self.graph_chunk,
-                           self.check_symmetry, self.engine)
+                           self.check_symmetry, self.engine, self.solver)
 
 
 @dataclasses.dataclass
@@ -117,7 +131,8 @@ def qcpd_status_str(status: int) -> str:
 def qcpd_opts_default() -> Opts:
     o = C.qcpd_opts()
     _lib().qcpd_opts_default(ctypes.byref(o))
-    return Opts(o.tol, o.max_iter, o.precond, o.graph_chunk, o.check_symmetry, o.engine)
+    return Opts(o.tol, o.max_iter, o.precond, o.graph_chunk, o.check_symmetry, o.engine,
+                o.solver)
 
 
 def _csr(rowptr, colind, val, nrows, ncols, name):
@@ -136,10 +151,7 @@ def qcpd_create(P: tuple, A: tuple, q, b, cones: Cones, x, y, s,
     m = int(b.numel())
     Pc = _csr(*P, n, n, "P")
     Ac = _csr(*A, m, n, "A")
-    soc = (C.c_int32 * max(len(cones.soc), 1))(*cones.soc)
-    psd = (C.c_int32 * max(len(cones.psd), 1))(*cones.psd)
-    K = C.qcpd_cones(cones.n_zero, cones.n_nonneg, len(cones.soc), soc, len(cones.psd), psd,
-                     cones.n_exp)
+    K, keep = cones.to_c()
     o = (opts or qcpd_opts_default()).to_c()
     dev = q.device
     strm = stream if stream is not None else torch.cuda.current_stream(dev)

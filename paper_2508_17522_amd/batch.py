@@ -49,10 +49,8 @@ def qcpd_batch_create(n: Sequence[int], m: Sequence[int], nnz_P: Sequence[int],
     keep = []
     cone_arr = (C.qcpd_cones * B)()
     for i, c in enumerate(cones):
-        soc = (C.c_int32 * max(len(c.soc), 1))(*c.soc)
-        psd = (C.c_int32 * max(len(c.psd), 1))(*c.psd)
-        keep += [soc, psd]
-        cone_arr[i] = C.qcpd_cones(c.n_zero, c.n_nonneg, len(c.soc), soc, len(c.psd), psd, c.n_exp)
+        cone_arr[i], arrays = c.to_c()
+        keep.append(arrays)
     L = C.qcpd_batch_layout(B, I32(*n), I32(*m), I32(*nnz_P), I32(*nnz_A), cone_arr)
     o = (opts or qcpd_opts_default()).to_c()
     dev = q.device

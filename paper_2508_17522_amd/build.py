@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libqcpd.so")
-SOURCES = ["api.hip", "apply.hip", "loop.hip", "setup.hip", "batch.hip", "learned.hip"]
+SOURCES = ["api.hip", "apply.hip", "loop.hip", "setup.hip", "batch.hip", "learned.hip", "lsmr.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

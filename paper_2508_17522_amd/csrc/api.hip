@@ -24,6 +24,11 @@ struct qcpd_handle {
     ConeGrid cg{};
     RowGrid rg{};
     FusedGrid fg{};
+    // LSQR loop with the PSD cones in a launch of their own (largest order above 32): the rows
+    // launch's units (U_PSDROWS in place of U_PSD) and the PSD launch's units
+    bool psd_split = false;
+    FusedGrid fg_rows{}, fg_psd{};
+    int lds_rows = 0, lds_psd = 0;
     int lds = 0;
     int lds_fused = 0;
     int lds_loop = 0;
@@ -47,6 +52,9 @@ struct qcpd_handle {
     int *flag = nullptr;
     LsqrState *st = nullptr;
     LsqrState *st2 = nullptr;                // second state buffer of the deferred loop
+    LsqrState *st3 = nullptr;                // LSMR: third state buffer (after the V launch)
+    LsmrState *lsmr = nullptr;               // LSMR: its scalars, two buffers
+    double *lsmr_h = nullptr, *lsmr_hb = nullptr;  // LSMR: directions h and hbar (N)
     double *lpart[2] = {nullptr, nullptr};   // per-block partials of the deferred loop
     // values of P, A, A' with a scale folded into each entry (val * s[col]), for the loop
     // kernels: [0] the column scale sc of the current solve, [1] the row scale scl
@@ -60,6 +68,7 @@ struct qcpd_handle {
     int graph_chunk[2] = {0, 0};
     const double *graph_sc[2] = {nullptr, nullptr};
     const double *graph_scl[2] = {nullptr, nullptr};
+    int graph_solver[2] = {-1, -1};
     uint32_t create_flags = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
@@ -134,7 +143,9 @@ void free_handle(qcpd_handle *h) {
 qcpd_status check_opts(const qcpd_opts *o) {
     if (!(o->tol >= 0.0) || o->max_iter < 0 || o->graph_chunk < 1 || o->graph_chunk > 4096 ||
         o->precond < QCPD_PRECOND_NONE || o->precond > QCPD_PRECOND_LEARNED ||
-        o->engine < QCPD_ENGINE_AUTO || o->engine > QCPD_ENGINE_PERSISTENT)
+        o->engine < QCPD_ENGINE_AUTO || o->engine > QCPD_ENGINE_PERSISTENT ||
+        (o->solver != QCPD_SOLVER_LSQR && o->solver != QCPD_SOLVER_LSMR) ||
+        (o->solver == QCPD_SOLVER_LSMR && o->engine == QCPD_ENGINE_PERSISTENT))
         return QCPD_ERR_INVALID_ARG;
     return QCPD_OK;
 }
@@ -232,45 +243,86 @@ void set_baked(const qcpd_handle *h, StepArgs &a) {
     }
 }
 
+// Work units of the loop's F' launch and its grid cap (the partial-sum slots of the PSD
+// launch come after those of the rows launch).
+int loop_units_T(const qcpd_handle *h) { return h->psd_split ? h->fg_rows.nunits : h->fg.nunits; }
+int loop_cap_T(const qcpd_handle *h) {
+    return h->psd_split ? kMaxLoopGrid - h->fg_psd.nunits : kMaxLoopGrid;
+}
+
+// The loop's product with F' (role and vectors in t): one launch of the fused units, or the
+// rows launch followed by the PSD launch reading the state the rows launch finalised.
+void launch_loop_FT_product(const qcpd_handle *h, StepArgs t, hipStream_t s) {
+    if (!h->psd_split) {
+        launch_loop_FT(h->p, t, h->fg, h->lds_loop, h->loop_grid_T, s);
+        return;
+    }
+    const int g = std::min(h->loop_grid_T, h->fg_rows.nunits);  // the grid the launch uses
+    StepArgs r = t;
+    r.extra_slots = h->fg_psd.nunits;
+    launch_loop_FT(h->p, r, h->fg_rows, h->lds_rows, g, s);
+    StepArgs c = t;
+    c.st = t.st_next;
+    c.slot0 = g;
+    launch_loop_FT_psd(h->p, c, h->fg_psd, h->lds_psd, s);
+}
+
+LsmrArgs lsmr_args(const qcpd_handle *h, const LsqrState *st, LsqrState *st_next) {
+    LsmrArgs l{};
+    l.st = st;
+    l.st_next = st_next;
+    l.part = h->lpart[0];
+    l.ls = h->lsmr;
+    l.v = h->v;
+    l.x = h->xk;
+    l.h = h->lsmr_h;
+    l.hb = h->lsmr_hb;
+    l.N = h->p.N;
+    return l;
+}
+
 // One LSQR iteration. JVP: the LSQR matrix is F diag(sc); VJP: it is F' diag(sc).
 // One LSQR iteration (two launches, deferred protocol). JVP: the LSQR matrix is F diag(sc),
 // VJP: F' diag(sc). The first launch of an iteration reads state buffer 0 and the second
 // launch's partials, the second reads buffer 1 and the first's partials.
 void enqueue_iteration(const qcpd_handle *h, int dir, const double *sc, const double *scl,
                        hipStream_t s) {
+    const bool lsmr = h->opts.solver == QCPD_SOLVER_LSMR;
     StepArgs a = base_args(h, sc, scl);
     StepArgs first = a, second = a;
     first.st = h->st;    first.part_prev = h->lpart[0]; first.st_next = h->st2; first.part_next = h->lpart[1];
     second.st = h->st2;  second.part_prev = h->lpart[1]; second.st_next = h->st; second.part_next = h->lpart[0];
+    if (lsmr) second.st_next = h->st3;  // the LSMR launch takes the V launch's partials
     if (dir == 0) {
         StepArgs &f = first;  // u~ <- F(sc o v) - alpha u~   (and the owed x, w update)
         f.in = h->v; f.in_nrm = NRM_ALPHA; f.in_is_v = 1;
-        f.out = h->u; f.role = ROLE_U; f.do_update = 1;
+        f.out = h->u; f.role = ROLE_U; f.do_update = lsmr ? 0 : 1;
         set_baked(h, f);
         launch_loop_F(h->p, f, h->rg, h->loop_grid_F, s);
         StepArgs &t = second;  // v~ <- sc o F'u - beta v~, then J(sc o v~) for the next product
         t.in = h->u; t.in_nrm = NRM_BETA;
         t.out = h->v; t.role = ROLE_V; t.out_is_v = 1; t.do_pre = 1;
         set_baked(h, t);
-        launch_loop_FT(h->p, t, h->fg, h->lds_loop, h->loop_grid_T, s);
+        launch_loop_FT_product(h, t, s);
     } else {
         StepArgs &t = first;  // u~ <- F'(sc o v) - alpha u~ (and the owed update), J(u~)
-        t.in = h->v; t.in_nrm = NRM_ALPHA; t.in_is_v = 1; t.do_update = 1;
+        t.in = h->v; t.in_nrm = NRM_ALPHA; t.in_is_v = 1; t.do_update = lsmr ? 0 : 1;
         t.out = h->u; t.role = ROLE_U; t.do_pre = 1;
         set_baked(h, t);
-        launch_loop_FT(h->p, t, h->fg, h->lds_loop, h->loop_grid_T, s);
+        launch_loop_FT_product(h, t, s);
         StepArgs &f = second;  // v~ <- sc o F u - beta v~
         f.in = h->u; f.in_nrm = NRM_BETA;
         f.out = h->v; f.role = ROLE_V; f.out_is_v = 1;
         set_baked(h, f);
         launch_loop_F(h->p, f, h->rg, h->loop_grid_F, s);
     }
+    if (lsmr) launch_lsmr_step(lsmr_args(h, h->st3, h->st), s);
 }
 
 qcpd_status ensure_graph(qcpd_handle *h, int dir, const double *sc, const double *scl) {
     const int chunk = h->opts.graph_chunk;
     if (h->graph[dir] && h->graph_chunk[dir] == chunk && h->graph_sc[dir] == sc &&
-        h->graph_scl[dir] == scl)
+        h->graph_scl[dir] == scl && h->graph_solver[dir] == h->opts.solver)
         return QCPD_OK;
     if (h->graph[dir]) {
         (void)hipGraphExecDestroy(h->graph[dir]);
@@ -289,6 +341,7 @@ qcpd_status ensure_graph(qcpd_handle *h, int dir, const double *sc, const double
     h->graph_chunk[dir] = chunk;
     h->graph_sc[dir] = sc;
     h->graph_scl[dir] = scl;
+    h->graph_solver[dir] = h->opts.solver;
     return QCPD_OK;
 }
 
@@ -311,6 +364,7 @@ void lsqr_start(qcpd_handle *h, int dir, const double *sc, const double *scl) {
         f.out = h->v; f.role = ROLE_V0; f.out_is_v = 1;
         launch_rows_F(h->p, f, h->rg, s);
     }
+    if (h->opts.solver == QCPD_SOLVER_LSMR) launch_lsmr_init(lsmr_args(h, h->st, nullptr), s);
 }
 
 // Iterates until the device stop flag is set, then maps the iterate back through the
@@ -377,10 +431,11 @@ qcpd_status explicit_residual(qcpd_handle *h, int dir, double *rel) {
     return QCPD_OK;
 }
 
-// LSQR from the right-hand side in place, to the caller's tolerance on the UNSCALED
-// relative residual: with a row scaling the stopping test sees the scaled residual, so after
-// each stop the explicit residual is checked and, if it is too large, LSQR resumes from its
-// state with a tighter internal tolerance.
+// LSQR (or LSMR) from the right-hand side in place, to the caller's tolerance on the
+// UNSCALED relative residual: with a row scaling the stopping test sees the scaled residual,
+// so after each stop the explicit residual is checked and, if it is too large, the method
+// resumes from its state with a tighter internal tolerance (at most 8 times, and not again
+// after a resume that failed to halve the explicit residual).
 qcpd_status solve(qcpd_handle *h, int dir, const double *sc, const double *scl, double *rel) {
     qcpd_status rc0 = bake_scales(h, sc, scl);
     if (rc0 != QCPD_OK) return rc0;
@@ -390,9 +445,14 @@ qcpd_status solve(qcpd_handle *h, int dir, const double *sc, const double *scl, 
     rc = explicit_residual(h, dir, rel);
     if (rc != QCPD_OK) return rc;
     const double tol = h->opts.tol;
+    double prev = 0.0;  // explicit relative residual before the last resume
     for (int attempt = 0; attempt < 8; ++attempt) {
         LsqrState st = h->host_st[0];
         if (*rel <= tol || !st.conv || st.iters >= st.max_iter || !(st.tol > 0.0)) break;
+        // a resume that did not halve the residual has met the rounding floor of the
+        // recomputed residual: further iterations only lower the method's own estimate
+        if (prev > 0.0 && *rel > 0.5 * prev) break;
+        prev = *rel;
         st.tol *= std::max(0.02, 0.5 * tol / *rel);
         st.done = 0;
         st.conv = 0;
@@ -401,6 +461,8 @@ qcpd_status solve(qcpd_handle *h, int dir, const double *sc, const double *scl, 
         h->host_st[0] = st;
         HIPCHK(hipMemcpyAsync(h->st, h->host_st, sizeof(LsqrState), hipMemcpyHostToDevice, h->stream));
         HIPCHK(hipMemcpyAsync(h->st2, h->host_st, sizeof(LsqrState), hipMemcpyHostToDevice, h->stream));
+        if (h->st3)
+            HIPCHK(hipMemcpyAsync(h->st3, h->host_st, sizeof(LsqrState), hipMemcpyHostToDevice, h->stream));
         rc = lsqr_iterate(h, dir, sc, scl);
         if (rc != QCPD_OK) return rc;
         rc = explicit_residual(h, dir, rel);
@@ -518,13 +580,24 @@ qcpd_status create_impl(qcpd_handle *h, const qcpd_csr *P, const qcpd_csr *A, co
     h->fmeta.n_diag = p.n_diag;
     h->fmeta.psd_end = row;
     h->fmeta.soc_end = K->n_psd ? psd_row[0] : row;
-    p.n_soc = K->n_soc; p.n_psd = K->n_psd; p.n_exp = K->n_exp;
+    // exponential, power and dual power cones are all 3 x 3 blocks of J after the PSD rows:
+    // the product kernels see them as one list (p.n_exp); their factors differ at setup
+    const int n_pow = K->n_pow + K->n_dpow;
+    p.n_soc = K->n_soc; p.n_psd = K->n_psd; p.n_exp = K->n_exp + n_pow;
     int *d_soc_row, *d_soc_dim, *d_psd_row, *d_psd_k;
     long long *d_psd_off;
     double *soc_par, *exp_J, *pool;
     ALLOC(d_soc_row, K->n_soc); ALLOC(d_soc_dim, K->n_soc); ALLOC(soc_par, 4LL * K->n_soc);
     ALLOC(d_psd_row, K->n_psd); ALLOC(d_psd_k, K->n_psd); ALLOC(d_psd_off, K->n_psd); ALLOC(pool, off);
-    ALLOC(exp_J, 9LL * K->n_exp);
+    ALLOC(exp_J, 9LL * p.n_exp);
+    double *pow_par;
+    ALLOC(pow_par, n_pow);
+    if (n_pow) {
+        std::vector<double> par;
+        for (int i = 0; i < K->n_pow; ++i) par.push_back(K->pow_alpha[i]);
+        for (int i = 0; i < K->n_dpow; ++i) par.push_back(-K->dpow_alpha[i]);
+        HIPCHK(hipMemcpy(pow_par, par.data(), sizeof(double) * n_pow, hipMemcpyHostToDevice));
+    }
     if (K->n_soc) {
         HIPCHK(hipMemcpy(d_soc_row, soc_row.data(), sizeof(int) * K->n_soc, hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(d_soc_dim, soc_dim.data(), sizeof(int) * K->n_soc, hipMemcpyHostToDevice));
@@ -541,7 +614,7 @@ qcpd_status create_impl(qcpd_handle *h, const qcpd_csr *P, const qcpd_csr *A, co
     cg.nE = n + p.n_diag + 1;
     cg.bE = div_up(cg.nE, kBlock);
     cg.bS = div_up(K->n_soc, kBlock);
-    cg.bX = div_up(K->n_exp, kBlock);
+    cg.bX = div_up(p.n_exp, kBlock);
     cg.bP = K->n_psd;
     h->lds = kmax ? (3 * kmax * (kmax | 1) + kmax * (kmax + 1) / 2) * (int)sizeof(double) : 0;
     // work units of the fused product with F', longest first (PSD cones by order, then
@@ -574,8 +647,8 @@ qcpd_status create_impl(qcpd_handle *h, const qcpd_csr *P, const qcpd_csr *A, co
         }
         // an exponential unit stages 9 doubles per cone in a kUnitRows buffer of the loop kernel
         static_assert((256 / 3) * 9 <= kUnitRows, "exponential unit size");
-        for (int i = 0; i < K->n_exp; i += target / 3)
-            exp_units.push_back({U_EXP, i, std::min(K->n_exp, i + target / 3), p.exp_row0 + 3 * i});
+        for (int i = 0; i < p.n_exp; i += target / 3)
+            exp_units.push_back({U_EXP, i, std::min(p.n_exp, i + target / 3), p.exp_row0 + 3 * i});
         units.insert(units.end(), exp_units.begin(), exp_units.end());
         units.insert(units.end(), soc_units.begin(), soc_units.end());
         units.insert(units.end(), row_units.begin(), row_units.end());
@@ -587,6 +660,30 @@ qcpd_status create_impl(qcpd_handle *h, const qcpd_csr *P, const qcpd_csr *A, co
         fill_unit_ranges(p, du, h->fg.nunits, st);
         h->lds_fused = fused_lds_bytes(kmax);
         h->lds_loop = loop_lds_bytes(K->psd_orders, K->n_psd);
+        // large PSD cones: their CSR rows join the row units of the loop's F' launch (raw rows
+        // to tmp) and their Jacobians run in a second launch, one workgroup per cone
+        h->psd_split = kmax > 32 && K->n_psd <= kMaxLoopGrid / 2;
+        if (h->psd_split) {
+            std::vector<Unit> ru(units.begin() + K->n_psd, units.end()), pu(units.begin(),
+                                                                           units.begin() + K->n_psd);
+            const int y0 = psd_row[0], y1 = p.exp_row0;  // the PSD cones' rows are contiguous
+            for (int r = y0; r < y1; r += rpy) ru.push_back({U_PSDROWS, r, std::min(y1, r + rpy), 0});
+            Unit *dr, *dp;
+            ALLOC(dr, ru.size());
+            ALLOC(dp, pu.size());
+            HIPCHK(hipMemcpy(dr, ru.data(), sizeof(Unit) * ru.size(), hipMemcpyHostToDevice));
+            HIPCHK(hipMemcpy(dp, pu.data(), sizeof(Unit) * pu.size(), hipMemcpyHostToDevice));
+            h->fg_rows = h->fg;
+            h->fg_rows.nunits = (int)ru.size();
+            h->fg_rows.units = dr;
+            h->fg_psd = h->fg;
+            h->fg_psd.nunits = (int)pu.size();
+            h->fg_psd.units = dp;
+            fill_unit_ranges(p, dr, h->fg_rows.nunits, st);
+            fill_unit_ranges(p, dp, h->fg_psd.nunits, st);
+            h->lds_rows = loop_lds_bytes(nullptr, 0);
+            h->lds_psd = h->lds_loop;
+        }
     }
     h->nblk_max = std::max({cg.total(), rg.total(), h->fg.nunits, div_up(N, kBlock), 1});
     // the two launches of the deferred LSQR loop: at most `cap` workgroups each, so the next
@@ -600,10 +697,14 @@ qcpd_status create_impl(qcpd_handle *h, const qcpd_csr *P, const qcpd_csr *A, co
         }
         cap = std::min(cap, kMaxLoopGrid);
         h->loop_grid_F = std::max(1, std::min(rg.total(), cap));
-        h->loop_grid_T = std::max(1, std::min(h->fg.nunits, cap));
+        h->loop_grid_T = std::max(1, std::min(loop_units_T(h), std::min(cap, loop_cap_T(h))));
         ALLOC(h->lpart[0], 2LL * kMaxLoopGrid);
         ALLOC(h->lpart[1], 2LL * kMaxLoopGrid);
         ALLOC(h->st2, 1);
+        ALLOC(h->st3, 1);
+        ALLOC(h->lsmr, 2);
+        ALLOC(h->lsmr_h, N);
+        ALLOC(h->lsmr_hb, N);
     }
     ALLOC(h->partials, 3LL * h->nblk_max);
     // --- validation on the device -----------------------------------------------------------
@@ -646,7 +747,7 @@ qcpd_status create_impl(qcpd_handle *h, const qcpd_csr *P, const qcpd_csr *A, co
     p.xPx = host_xpx;
     // --- cone factors -------------------------------------------------------------------------
     HIPCHK(hipMemsetAsync(h->flag, 0, 4 * sizeof(int), st));
-    ConeHost ch{K->n_zero};
+    ConeHost ch{K->n_zero, K->n_exp, n_pow, pow_par};
     launch_cone_factors(p, ch, h->jdiag, soc_par, exp_J, pool, h->flag + 1, h->flag + 2,
                         psd_factor_lds_bytes(kmax), st);
     launch_scales(p, rg, h->scale[0], h->scale[1], h->partials, h->counter, st);
@@ -731,6 +832,7 @@ void qcpd_opts_default(qcpd_opts *o) {
     o->graph_chunk = 128;
     o->check_symmetry = 1;
     o->engine = QCPD_ENGINE_AUTO;
+    o->solver = QCPD_SOLVER_LSQR;
 }
 
 const char *qcpd_status_str(qcpd_status s) {
@@ -761,10 +863,18 @@ qcpd_status qcpd_create(qcpd_handle **out, const qcpd_csr *P, const qcpd_csr *A,
     if ((P->nnz > 0 && (!P->colind || !P->val)) || (A->nnz > 0 && (!A->colind || !A->val)))
         return QCPD_ERR_INVALID_ARG;
     if (!q || !x || (m > 0 && (!b || !y || !s))) return QCPD_ERR_INVALID_ARG;
-    if (K->n_zero < 0 || K->n_nonneg < 0 || K->n_soc < 0 || K->n_psd < 0 || K->n_exp < 0)
+    if (K->n_zero < 0 || K->n_nonneg < 0 || K->n_soc < 0 || K->n_psd < 0 || K->n_exp < 0 ||
+        K->n_pow < 0 || K->n_dpow < 0)
         return QCPD_ERR_CONE;
-    if ((K->n_soc > 0 && !K->soc_dims) || (K->n_psd > 0 && !K->psd_orders)) return QCPD_ERR_CONE;
-    long long rows = (long long)K->n_zero + K->n_nonneg + 3LL * K->n_exp;
+    if ((K->n_soc > 0 && !K->soc_dims) || (K->n_psd > 0 && !K->psd_orders) ||
+        (K->n_pow > 0 && !K->pow_alpha) || (K->n_dpow > 0 && !K->dpow_alpha))
+        return QCPD_ERR_CONE;
+    for (int i = 0; i < K->n_pow; ++i)
+        if (!(K->pow_alpha[i] > 0.0 && K->pow_alpha[i] < 1.0)) return QCPD_ERR_CONE;
+    for (int i = 0; i < K->n_dpow; ++i)
+        if (!(K->dpow_alpha[i] > 0.0 && K->dpow_alpha[i] < 1.0)) return QCPD_ERR_CONE;
+    long long rows = (long long)K->n_zero + K->n_nonneg +
+                     3LL * ((long long)K->n_exp + K->n_pow + K->n_dpow);
     for (int i = 0; i < K->n_soc; ++i) {
         if (K->soc_dims[i] < 1 || K->soc_dims[i] > kUnitRows) return QCPD_ERR_CONE;
         rows += K->soc_dims[i];
@@ -931,7 +1041,7 @@ qcpd_status qcpd_apply(qcpd_handle *h, int32_t transpose, const double *in, doub
 qcpd_status qcpd_set_launch(qcpd_handle *h, int32_t grid_F, int32_t grid_FT) {
     if (!h || grid_F < 0 || grid_FT < 0) return QCPD_ERR_INVALID_ARG;
     const int gF = std::max(1, std::min({h->rg.total(), grid_F ? grid_F : kLoopGrid, kMaxLoopGrid}));
-    const int gT = std::max(1, std::min({h->fg.nunits, grid_FT ? grid_FT : kLoopGrid, kMaxLoopGrid}));
+    const int gT = std::max(1, std::min({loop_units_T(h), grid_FT ? grid_FT : kLoopGrid, loop_cap_T(h)}));
     HIPCHK(hipStreamSynchronize(h->stream));
     h->loop_grid_F = gF;
     h->loop_grid_T = gT;
@@ -948,7 +1058,7 @@ qcpd_status qcpd_get_launch(qcpd_handle *h, int32_t *out) {
     out[0] = h->loop_grid_F;
     out[1] = h->loop_grid_T;
     out[2] = std::min(h->rg.total(), kMaxLoopGrid);
-    out[3] = std::min(h->fg.nunits, kMaxLoopGrid);
+    out[3] = std::min(loop_units_T(h), loop_cap_T(h));
     return QCPD_OK;
 }
 
@@ -997,7 +1107,8 @@ qcpd_status qcpd_profile_kernels(qcpd_handle *h, int32_t reps, float *ms_out) {
     LsqrState img{};
     img.alpha = 1.0; img.beta = 1.0; img.one = 1.0; img.tol = 0.0; img.max_iter = 1 << 30;
     img.pend_role = ROLE_PLAIN;
-    img.pend_blocks = std::max(h->loop_grid_F, h->loop_grid_T);
+    img.pend_blocks = std::min(kMaxLoopGrid, std::max(h->loop_grid_F, h->loop_grid_T +
+                                                              (h->psd_split ? h->fg_psd.nunits : 0)));
     img.pend_fwd = 0;
     *h->host_st = img;
     HIPCHK(hipMemcpyAsync(h->st, h->host_st, sizeof(LsqrState), hipMemcpyHostToDevice, s));
@@ -1016,7 +1127,7 @@ qcpd_status qcpd_profile_kernels(qcpd_handle *h, int32_t reps, float *ms_out) {
     for (int kid = 0; kid < 2; ++kid) {
         auto launch = [&]() {
             if (kid == 0) launch_loop_F(h->p, f, h->rg, h->loop_grid_F, s);
-            else launch_loop_FT(h->p, t, h->fg, h->lds_loop, h->loop_grid_T, s);
+            else launch_loop_FT_product(h, t, s);
         };
         launch();  // warm
         HIPCHK(hipEventRecord(h->ev0, s));

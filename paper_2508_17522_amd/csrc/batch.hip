@@ -982,7 +982,7 @@ qcpd_status batch_create_impl(qcpd_batch *h, const qcpd_batch_layout *L, const i
     launch_px(p, pg, c, xpx_all, partials, counter, st);
     hipLaunchKernelGGL(k_batch_xpx, dim3(B), dim3(kBlock), 0, st, p, d_noff, xpx);
     launch_sub(dy_, ds_, zy, m, st);
-    ConeHost ch{0};
+    ConeHost ch{0, p.n_exp, 0, nullptr};
     launch_cone_factors(p, ch, jdiag, soc_par, exp_J, pool, h->flag + 4, h->flag + 3,
                         psd_factor_lds_bytes(kmax), st);
     hipLaunchKernelGGL(k_batch_diag, dim3(B), dim3(256), 0, st, zy, d_moff, d_nz, d_nn, jdiag, h->flag + 4);
@@ -1301,6 +1301,7 @@ qcpd_status qcpd_batch_create(qcpd_batch **out, const qcpd_batch_layout *L, cons
         const qcpd_cones &K = L->cones[i];
         if (L->n[i] < 1 || L->m[i] < 0 || L->nnz_P[i] < 0 || L->nnz_A[i] < 0) return QCPD_ERR_INVALID_ARG;
         if (K.n_zero < 0 || K.n_nonneg < 0 || K.n_soc < 0 || K.n_psd < 0 || K.n_exp < 0) return QCPD_ERR_CONE;
+        if (K.n_pow != 0 || K.n_dpow != 0) return QCPD_ERR_CONE;  // single-problem path only
         if ((K.n_soc > 0 && !K.soc_dims) || (K.n_psd > 0 && !K.psd_orders)) return QCPD_ERR_CONE;
         long long rows = (long long)K.n_zero + K.n_nonneg + 3LL * K.n_exp;
         for (int j = 0; j < K.n_soc; ++j) {

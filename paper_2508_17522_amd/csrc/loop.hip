@@ -163,7 +163,7 @@ __device__ inline bool entry_finish(const StepArgs &a, const Entry &e, LsqrState
         s.pend_role = -1;
     } else {
         s.pend_role = a.role;
-        s.pend_blocks = gridDim.x;
+        s.pend_blocks = gridDim.x + a.extra_slots;
         s.pend_fwd = my_fwd;
     }
     // Only the buffer of the next launch is written: other workgroups of this launch may
@@ -723,8 +723,10 @@ __device__ inline double smat_get(const double *Y, int ld, int ii, int jj) {
     return ii == jj ? Y[ii * ld + ii] : Y[ii * ld + jj] * kSqrt2;
 }
 
-// DEEP: the row units' CSR sums keep kDeep entries per lane in flight (batched loop)
-template <bool DEEP = false, int MAXKP = 64>
+// DEEP: the row units' CSR sums keep kDeep entries per lane in flight (batched loop).
+// TROWS: the raw rows of a PSD unit come from a.tmp (written by the rows launch of the same
+// product) instead of the unit's own CSR gather.
+template <bool DEEP = false, int MAXKP = 64, bool TROWS = false>
 __device__ inline void unit_pre(const Problem &p, const StepArgs &a, const Ptrs &q, int lx,
                                 int ly, const Unit &u, double *sm, double in_N_raw,
                                 UnitPre &P) {
@@ -774,6 +776,18 @@ __device__ inline void unit_pre(const Problem &p, const StepArgs &a, const Ptrs 
         }
         return;
     }
+    if (u.type == U_PSDROWS) {  // raw t of PSD rows for the PSD launch; nothing to finish
+        const int L = ly, lane = tid & (L - 1), r = u.begin + tid / L;
+        double acc = 0.0;
+        if (r < u.end) {
+            const int k0 = p.Arp[r], k1 = p.Arp[r + 1];
+            acc = csr_dot_d<DEEP>(p.Aci, q.Av, k0, k1, lane, L, a.in, q.gsc, 0);
+        }
+        acc = group_sum_dpp(acc, L);
+        if (r < u.end && lane == 0)
+            a.tmp[n + r] = acc - p.b[r] * in_N_raw - in_raw(a, q, n + r);
+        return;
+    }
     // cone units: issue the loads of the cone factors and of this thread's finish operands,
     // then the raw rows t = A r_x - b r_N - r_y (unnormalised) into tb, then stage the
     // factors in LDS and apply J to t into jt. Each cone kind has its own branch so that
@@ -820,6 +834,15 @@ __device__ inline void unit_pre(const Problem &p, const StepArgs &a, const Ptrs 
             tb[i] = (e1 > e0 ? tb[i] : 0.0) - bb * in_N_raw - y;
         }
     };
+    // the same rows from a.tmp (raw t of the rows launch) and the input
+    auto trows = [&]() {
+        for (int i = tid; i < nr; i += kBlock) {
+            const double y = i == tid ? ry : in_raw(a, q, n + r0 + i);
+            rb[i] = y;
+            tb[i] = a.tmp[n + r0 + i];
+        }
+        __syncthreads();
+    };
     auto tin = [&](int i) { return tb[i]; };
     auto jout = [&](int i, double v) { jt[i] = v; };
     const int cone = u.begin + tid;
@@ -839,7 +862,7 @@ __device__ inline void unit_pre(const Problem &p, const StepArgs &a, const Ptrs 
                 bpre[j] = (in_k && B) ? Bg[i * k + jj] : 0.0;
             }
             if (tid < nr) svec_rc(tid, k, P.ii, P.jj);  // while the loads are in flight
-            yrows();
+            if (TROWS) trows(); else yrows();
 #pragma unroll
             for (int j = 0; j < kPsdPref; ++j) {
                 const int e = tid + j * kBlock, i = e / kp, jj = e - (e / kp) * kp;
@@ -851,7 +874,7 @@ __device__ inline void unit_pre(const Problem &p, const StepArgs &a, const Ptrs 
             }
         } else {
             if (tid < nr) svec_rc(tid, k, P.ii, P.jj);
-            yrows();
+            if (TROWS) trows(); else yrows();
             for (int e = tid; e < kp * kp; e += kBlock) {
                 const int i = e / kp, jj = e - (e / kp) * kp;
                 const bool in_k = i < k && jj < k;
@@ -918,6 +941,7 @@ __device__ inline void unit_post(const Problem &p, const StepArgs &a, const Ptrs
         }
         return;
     }
+    if (u.type == U_PSDROWS) return;
     if (u.type == U_DIAG) {
         if (P.idx >= 0) {
             const double t = (P.acc - P.self) * c.inv - P.coef * c.in_N;
@@ -1042,6 +1066,25 @@ __global__ __launch_bounds__(kBlock) void k_loop_FT_multi_deep(Problem p, StepAr
     extern __shared__ double sm[];
     LsqrState S;
     loop_FT_body<true, true>(p, a, g, sm, S);
+}
+
+// The PSD cones of a product with F' whose rows launch (k_loop_FT*, U_PSDROWS units) left
+// their raw rows in a.tmp: one workgroup per cone, the scalars of the state that launch
+// finalised (a.st), partial sums from slot a.slot0 on. Large cones stage up to 130 KB of LDS;
+// in their own launch they no longer hold every other unit to one workgroup per CU.
+__global__ __launch_bounds__(kBlock) void k_loop_FT_psd(Problem p, StepArgs a, FusedGrid g) {
+    extern __shared__ double sm[];
+    const Ptrs q = ptrs_of(p, a);
+    const double in_N_raw = in_raw(a, q, p.N - 1);
+    const Unit u = g.units[blockIdx.x];
+    UnitPre P;
+    unit_pre<false, 64, true>(p, a, q, g.lx, g.ly, u, sm, in_N_raw, P);
+    const LsqrState S = *a.st;
+    if (S.done) return;
+    const Ctx c = scalars(a, S, q, in_N_raw);
+    double s0 = 0.0, s1 = 0.0;
+    unit_post(p, a, q, c, u, sm, P, s0, s1);
+    leave(a, s0, s1, a.slot0 + blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1261,6 +1304,7 @@ int loop_lds_bytes(const int *psd_orders, int n_psd) {
 }
 
 void set_loop_kernel_lds(int bytes) {
+    (void)hipFuncSetAttribute((const void *)k_loop_FT_psd, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     (void)hipFuncSetAttribute((const void *)k_loop_FT, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     (void)hipFuncSetAttribute((const void *)k_loop_FT_multi, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     (void)hipFuncSetAttribute((const void *)k_loop_FT_deep, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
@@ -1279,6 +1323,11 @@ void launch_loop_FT(const Problem &p, const StepArgs &a, const FusedGrid &g, int
         hipLaunchKernelGGL(one ? k_loop_FT_deep : k_loop_FT_multi_deep, dim3(grid), dim3(kBlock), lds, s, p, a, g);
     else
         hipLaunchKernelGGL(one ? k_loop_FT : k_loop_FT_multi, dim3(grid), dim3(kBlock), lds, s, p, a, g);
+}
+
+void launch_loop_FT_psd(const Problem &p, const StepArgs &a, const FusedGrid &g, int lds,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(k_loop_FT_psd, dim3(g.nunits), dim3(kBlock), lds, s, p, a, g);
 }
 
 void set_seg_kernel_lds(int bytes) {

@@ -197,12 +197,18 @@ struct StepArgs {
     // (val * isc[col], isc = sc or scl as in_is_v says), or null: the loop kernels then
     // gather isc per entry
     const double *Pvs, *Avs, *Tvs;
+    // a product with F' in two launches (rows, then the PSD cones): the rows launch counts
+    // extra_slots more partial sums for the next launch to reduce; the PSD launch writes its
+    // partials from slot slot0 on
+    int extra_slots, slot0;
 };
 
 // Work units of the fused product with F' (one workgroup each): x rows, diagonal y rows,
 // runs of whole SOC or exponential cones, or one PSD cone. Rows of D_u Q' r for the unit
 // are formed in LDS and the unit's block of J is applied to them in the same workgroup.
-enum UnitType { U_XROWS = 0, U_DIAG = 1, U_SOC = 2, U_EXP = 3, U_PSD = 4 };
+// U_PSDROWS (LSQR loop with the PSD cones in a launch of their own): rows of PSD cones whose
+// raw CSR rows t = A r_x - b r_N - r_y go to StepArgs::tmp for that launch.
+enum UnitType { U_XROWS = 0, U_DIAG = 1, U_SOC = 2, U_EXP = 3, U_PSD = 4, U_PSDROWS = 5 };
 struct Unit {
     int type, begin, end, row0;  // row0: first y row of a cone run (SOC / exp / PSD)
     // cone runs, filled on the device once the CSR copies exist (fill_unit_ranges): the
@@ -281,6 +287,27 @@ void set_loop_kernel_lds(int bytes);
 void launch_loop_F(const Problem &p, const StepArgs &a, const RowGrid &g, int grid, hipStream_t s);
 void launch_loop_FT(const Problem &p, const StepArgs &a, const FusedGrid &g, int lds, int grid,
                     hipStream_t s);
+void launch_loop_FT_psd(const Problem &p, const StepArgs &a, const FusedGrid &g, int lds,
+                        hipStream_t s);
+
+// LSMR (lsmr.hip): its scalars beyond the LSQR state block, and the arguments of its
+// per-iteration launch (after the U and V product launches of the LSQR loop kernels)
+struct LsmrState {
+    double alphabar;                         // first QR: unfinished diagonal
+    double rho_prev, rhobar_prev, cbar, sbar, zetabar;   // second QR
+    double betadd, betadot, rhodot, thetatil, tautil_prev, zeta_prev, fixed_sq;  // estimate
+};
+struct LsmrArgs {
+    const LsqrState *st;   // state the V launch wrote (its partials pending)
+    LsqrState *st_next;    // state the next U launch reads
+    const double *part;    // the V launch's partial sums (kMaxLoopGrid slots of two doubles)
+    LsmrState *ls;         // two buffers, read [iters % 2], write the other
+    const double *v;       // v~_{k+1} (unnormalised)
+    double *x, *h, *hb;    // iterate and directions (N each)
+    int N;
+};
+void launch_lsmr_step(const LsmrArgs &a, hipStream_t s);
+void launch_lsmr_init(const LsmrArgs &a, hipStream_t s);
 
 // learned preconditioner (learned.hip)
 struct FeatMeta {

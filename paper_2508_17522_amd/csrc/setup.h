@@ -7,6 +7,9 @@ namespace qcpd {
 
 struct ConeHost {
     int n_zero;
+    int n_exp;                // exponential cones (the first 3 x 3 blocks)
+    int n_pow;                // power and dual power cones after them
+    const double *pow_par;    // [device] alpha (power cone) or -alpha (dual power cone)
 };
 
 hipError_t csr_transpose(int nrows, int ncols, int nnz, const int *rp, const int *ci,

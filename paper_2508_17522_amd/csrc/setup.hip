@@ -329,6 +329,98 @@ __global__ void k_exp_factors(const double *zy, int row0, const int *rows, int n
     jdiag[r0 + 2] = J[8];
 }
 
+// Power cone K_pow,a = {(x,y,z): x^a y^(1-a) >= |z|, x, y >= 0} (App. A, "Power cone").
+__device__ inline bool pow_member(double x, double y, double z, double a) {
+    return x >= 0.0 && y >= 0.0 && pow(x, a) * pow(y, 1.0 - a) >= fabs(z);
+}
+// K_pow,a* = {(u,v,w): (u/a)^a (v/(1-a))^(1-a) >= |w|, u, v >= 0}
+__device__ inline bool pow_dual_member(double u, double v, double w, double a) {
+    return u >= 0.0 && v >= 0.0 && pow(u / a, a) * pow(v / (1.0 - a), 1.0 - a) >= fabs(w);
+}
+// (x + sqrt(x^2 + t)) / 2, t >= 0, without cancellation for x < 0
+__device__ inline double half_root(double x, double t) {
+    const double s = sqrt(x * x + t);
+    return x >= 0.0 ? 0.5 * (x + s) : 0.5 * t / (s - x);
+}
+
+// DPi_pow,a(x, y, z) into D (row-major), by the appendix's cases in their order: the cone's
+// interior, the polar cone's, the plane z = 0, and otherwise the closed form around the
+// root r in (0, |z|) of r = f_x(r)^a f_y(r)^(1-a), found by bisection until the bracket stops
+// shrinking (the root is unique; the function is positive just above 0 and negative at |z|).
+__device__ void pow_jacobian(double x, double y, double z, double a, double tol, double D[9],
+                             int *nondiff) {
+    for (int i = 0; i < 9; ++i) D[i] = 0.0;
+    const double az = fabs(z);
+    if (pow_member(x, y, z, a)) {
+        D[0] = D[4] = D[8] = 1.0;
+        if (x <= tol || y <= tol || pow(x, a) * pow(y, 1.0 - a) - az <= tol) atomicOr(nondiff, 1);
+        return;
+    }
+    if (pow_dual_member(-x, -y, -z, a)) {
+        if (-x <= tol || -y <= tol ||
+            pow(-x / a, a) * pow(-y / (1.0 - a), 1.0 - a) - az <= tol)
+            atomicOr(nondiff, 1);
+        return;
+    }
+    if (z == 0.0) {
+        double d = 0.0;
+        if (x > 0.0 && y < 0.0) d = a > 0.5 ? 1.0 : a < 0.5 ? 0.0 : x / (2.0 * fabs(y) + x);
+        else if (x < 0.0 && y > 0.0) d = a < 0.5 ? 1.0 : a > 0.5 ? 0.0 : y / (2.0 * fabs(x) + y);
+        D[0] = x > 0.0 ? 1.0 : 0.0;
+        D[4] = y > 0.0 ? 1.0 : 0.0;
+        D[8] = d;
+        if (fabs(x) <= tol || fabs(y) <= tol) atomicOr(nondiff, 1);
+        return;
+    }
+    double lo = 0.0, hi = az;
+    for (int it = 0; it < 2000; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (!(mid > lo && mid < hi)) break;
+        const double t = mid * (az - mid);
+        const double h = pow(half_root(x, 4.0 * a * t), a) *
+                         pow(half_root(y, 4.0 * (1.0 - a) * t), 1.0 - a) - mid;
+        if (h > 0.0) lo = mid; else hi = mid;
+    }
+    const double r = 0.5 * (lo + hi);
+    const double t = r * (az - r);
+    const double fx = half_root(x, 4.0 * a * t), fy = half_root(y, 4.0 * (1.0 - a) * t);
+    const double gx = 2.0 * fx - x, gy = 2.0 * fy - y;
+    const double S = a * x / gx + (1.0 - a) * y / gy;
+    const double L = 2.0 * (az - r) / (az + (az - 2.0 * r) * S);
+    const double sz = z > 0.0 ? 1.0 : -1.0;
+    const double m = (az - 2.0 * r) * r * L;
+    D[0] = 0.5 + x / (2.0 * gx) + a * a * m / (gx * gx);
+    D[1] = D[3] = (a - a * a) * m / (gx * gy);
+    D[2] = D[6] = sz * a * r * L / gx;
+    D[4] = 0.5 + y / (2.0 * gy) + (1.0 - a) * (1.0 - a) * m / (gy * gy);
+    D[5] = D[7] = sz * (1.0 - a) * r * L / gy;
+    D[8] = r / az - (r / az) * S * L;
+    if (r <= tol || az - r <= tol) atomicOr(nondiff, 1);
+}
+
+// J of the power-cone blocks: par[i] > 0 is alpha of a power cone, whose dual cone is
+// projected by Moreau, J = I - DPi_pow(-z); par[i] < 0 is -alpha of a dual power cone, whose
+// dual cone is K_pow itself, J = DPi_pow(z). Cone i occupies rows row0 + 3 i ..; its J is the
+// 3 x 3 row-major matrix at Jout + 9 i.
+__global__ void k_pow_factors(const double *zy, int row0, int count, const double *par,
+                              double *Jout, double *jdiag, int *nondiff) {
+    const int cone = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cone >= count) return;
+    const int r0 = row0 + 3 * cone;
+    const double a = fabs(par[cone]);
+    const bool dual = par[cone] < 0.0;
+    const double sg = dual ? 1.0 : -1.0;
+    const double x0 = sg * zy[r0], y0 = sg * zy[r0 + 1], z0 = sg * zy[r0 + 2];
+    const double scale = fmax(1.0, fmax(fabs(x0), fmax(fabs(y0), fabs(z0))));
+    double D[9];
+    pow_jacobian(x0, y0, z0, a, kKinkTol * scale, D, nondiff);
+    double *J = Jout + 9 * cone;
+    for (int i = 0; i < 9; ++i) J[i] = dual ? D[i] : ((i % 4 == 0) ? 1.0 : 0.0) - D[i];
+    jdiag[r0] = J[0];
+    jdiag[r0 + 1] = J[4];
+    jdiag[r0 + 2] = J[8];
+}
+
 // PSD cone: eigendecomposition of each k x k block by cyclic Jacobi with a round-robin
 // (tournament) ordering, so k/2 disjoint rotations are applied at once; then
 //   B_ij = 1 (both eigenvalues >= 0), 0 (both < 0), (l_i+ - l_j+)/(l_i - l_j) (mixed),
@@ -661,9 +753,13 @@ void launch_cone_factors(const Problem &p, const ConeHost &ch, double *jdiag, do
     if (p.n_soc > 0)
         hipLaunchKernelGGL(k_soc_factors, dim3(div_up(p.n_soc, 128)), dim3(128), 0, s, p.zy,
                            p.soc_row, p.soc_dim, p.n_soc, soc_par, jdiag, nondiff);
-    if (p.n_exp > 0)
-        hipLaunchKernelGGL(k_exp_factors, dim3(div_up(p.n_exp, 64)), dim3(64), 0, s, p.zy,
-                           p.exp_row0, p.exp_rows, p.n_exp, exp_J, jdiag, nondiff, fail);
+    if (ch.n_exp > 0)
+        hipLaunchKernelGGL(k_exp_factors, dim3(div_up(ch.n_exp, 64)), dim3(64), 0, s, p.zy,
+                           p.exp_row0, p.exp_rows, ch.n_exp, exp_J, jdiag, nondiff, fail);
+    if (ch.n_pow > 0)  // power cones follow the exponential cones (one contiguous row range)
+        hipLaunchKernelGGL(k_pow_factors, dim3(div_up(ch.n_pow, 64)), dim3(64), 0, s, p.zy,
+                           p.exp_row0 + 3 * ch.n_exp, ch.n_pow, ch.pow_par, exp_J + 9LL * ch.n_exp,
+                           jdiag, nondiff);
     if (p.n_psd > 0) {
         (void)hipFuncSetAttribute((const void *)k_psd_factors, hipFuncAttributeMaxDynamicSharedMemorySize, psd_lds);
         hipLaunchKernelGGL(k_psd_factors, dim3(p.n_psd), dim3(kBlock), psd_lds, s, p.zy, p.psd_row,

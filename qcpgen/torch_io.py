@@ -21,7 +21,7 @@ def cones_of(qcp):
     from paper_2508_17522_amd import Cones
     c = qcp.cones
     return Cones(n_zero=c.n_zero, n_nonneg=c.n_nonneg, soc=list(c.soc), psd=list(c.psd),
-                 n_exp=c.n_exp)
+                 n_exp=c.n_exp, pow=list(c.pow), dpow=list(c.dpow))
 
 
 def batch_to_device(qcps, device="cuda:0"):

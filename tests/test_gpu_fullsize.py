@@ -1,0 +1,157 @@
+"""Full-size parity with the oracle's dense implicit-function solve, output by output:
+
+* the 5 000 x 11 000 mixed-cone workload (reduced KKT matrix of order 16 000; one LU serves
+  both directions),
+* a held-out problem of the n = 2 000 learned-preconditioner family,
+* a reduced instance shaped like the n = 20 000 PSD/SOC workload (8 PSD cones of order 50,
+  80 SOC(10), 600 nonnegative rows; n = 800, m = 11 600),
+* a batch of 64 members of the uneven 20 <= n <= 400 family, each member against its own
+  dense solve.
+
+Each output is compared three ways: the relative 2-norm error (<= 1e-7); the 2-norm error of
+every cone block (zero rows, nonnegative rows, each SOC, each PSD, each exponential cone)
+against the larger of the block's own norm and the output's largest entry; and every entry
+against the output's largest entry. The least-squares problems are solved to 1e-12 (Sec. 3.1:
+the forward error can reach cond(K_red) x tol). The forward error at the benchmark tolerance
+1e-8 is printed beside it.
+"""
+import numpy as np
+import pytest
+
+import qcpgen
+from oracle import derivative as D
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2508_17522_amd as Q  # noqa: E402
+from qcpgen.torch_io import batch_create_args, batch_to_device, cones_of, to_device  # noqa: E402
+
+BAR = 1e-7
+
+
+def y_blocks(cones):
+    """Row ranges of the cone blocks of a y-space vector."""
+    out, r = [], 0
+    for size in ([cones.n_zero] if cones.n_zero else []) + \
+            ([cones.n_nonneg] if cones.n_nonneg else []) + list(cones.soc) + \
+            [k * (k + 1) // 2 for k in cones.psd] + \
+            [3] * (cones.n_exp + len(cones.pow) + len(cones.dpow)):
+        out.append((r, r + size))
+        r += size
+    return out
+
+
+def errors(a, r, blocks=None):
+    a, r = np.asarray(a, dtype=np.float64), np.asarray(r, dtype=np.float64)
+    inf = float(np.abs(r).max()) if r.size else 0.0
+    inf = inf if inf > 0 else 1.0
+    nr = np.linalg.norm(r)
+    normwise = np.linalg.norm(a - r) / (nr if nr > 0 else 1.0)
+    elem = float(np.abs(a - r).max()) / inf if r.size else 0.0
+    blk = 0.0
+    for lo, hi in blocks or ():
+        e = np.linalg.norm(a[lo:hi] - r[lo:hi]) / max(np.linalg.norm(r[lo:hi]), inf)
+        blk = max(blk, e)
+    return normwise, blk, elem
+
+
+def check(tag, names, outs, refs, blocks, bar=BAR):
+    worst = 0.0
+    for name, a, r, b in zip(names, outs, refs, blocks):
+        e = errors(a, r, b)
+        print(f"[{tag}] {name}: normwise {e[0]:.2e} worst block {e[1]:.2e} "
+              f"worst entry {e[2]:.2e}", flush=True)
+        worst = max(worst, *e)
+    assert worst <= bar, (tag, worst)
+    return worst
+
+
+def normwise_only(outs, refs):
+    return max(errors(a, r)[0] for a, r in zip(outs, refs))
+
+
+def single(q, tol, precond):
+    t = to_device(q)
+    h = Q.qcpd_create(t["P"], t["A"], t["q"], t["b"], cones_of(q), t["x"], t["y"], t["s"],
+                      opts=Q.Opts(tol=tol, precond=precond))
+    dx, dy, ds, i1, s1 = Q.qcpd_jvp(h, t["dP"], t["dA"], t["dq"], t["db"])
+    dP, dA, dq, db, i2, s2 = Q.qcpd_vjp(h, t["gx"], t["gy"], t["gs"])
+    h.close()
+    cpu = lambda v: v.cpu().numpy()
+    print(f"[{q.name} tol {tol:g}] iters {i1.iters} / {i2.iters}, rel. residuals "
+          f"{i1.rel_residual:.2e} / {i2.rel_residual:.2e}, status {s1} / {s2}", flush=True)
+    return (cpu(dx), cpu(dy), cpu(ds)), (cpu(dP), cpu(dA), cpu(dq), cpu(db)), (i1, s1, i2, s2)
+
+
+def check_single(q, precond, floor=1e-10):
+    """`floor`: the recomputed relative residual the solve at tol 1e-12 must reach (the
+    rounding floor of the residual of an ill-conditioned instance can lie above 1e-12; the
+    library then reports NOT_CONVERGED, and the outputs must still meet the bar)."""
+    (rj, rv) = D.jvp_vjp_dense(q, q.dP, q.dA, q.dq, q.db, q.gx, q.gy, q.gs)
+    yb = y_blocks(q.cones)
+    jv, vj, (i1, s1, i2, s2) = single(q, 1e-12, precond)
+    assert i1.rel_residual <= floor and i2.rel_residual <= floor
+    check(q.name, ("dx", "dy", "ds"), jv, rj, (None, yb, yb))
+    check(q.name, ("dP", "dA", "dq", "db"), vj, rv, (None, None, None, yb))
+    jv8, vj8, (j1, t1, j2, t2) = single(q, 1e-8, precond)
+    assert t1 == Q.QCPD_OK and t2 == Q.QCPD_OK
+    print(f"[{q.name}] forward error at tol 1e-8: JVP {normwise_only(jv8, rj):.2e}, "
+          f"VJP {normwise_only(vj8, rv):.2e}", flush=True)
+
+
+def test_mixed_qcp_full_size_elementwise():
+    check_single(qcpgen.mixed_qcp(0), Q.QCPD_PRECOND_EQUIL)
+
+
+def test_precond_family_member_elementwise():
+    # the recomputed JVP residual of this instance stalls near 3e-10
+    check_single(qcpgen.precond_family(20000), Q.QCPD_PRECOND_EQUIL, floor=1e-9)
+
+
+def test_large_psd_soc_shape_reduced_elementwise():
+    check_single(qcpgen.large_psd_soc(0, scale=0.04), Q.QCPD_PRECOND_EQUIL)
+
+
+def split(v, sizes):
+    return np.split(v, np.cumsum(sizes)[:-1])
+
+
+def test_batch_of_64_family_members_elementwise():
+    qs = [qcpgen.batch_member(i) for i in range(64)]
+    bt = batch_to_device(qs)
+    for tol in (1e-12, 1e-8):
+        h = Q.qcpd_batch_create(*batch_create_args(bt),
+                                opts=Q.Opts(tol=tol, precond=Q.QCPD_PRECOND_EQUIL))
+        dx, dy, ds, i1, s1 = Q.qcpd_batch_jvp(h, bt["dP"], bt["dA"], bt["dq"], bt["db"])
+        dP, dA, dq, db, i2, s2 = Q.qcpd_batch_vjp(h, bt["gx"], bt["gy"], bt["gs"])
+        h.close()
+        print(f"[batch tol {tol:g}] median iters {np.median([i.iters for i in i1])} / "
+              f"{np.median([i.iters for i in i2])}, worst rel. residual "
+              f"{max(i.rel_residual for i in i1 + i2):.2e}, status {s1} / {s2}", flush=True)
+        parts = [split(v.cpu().numpy(), s) for v, s in
+                 ((dx, bt["n"]), (dy, bt["m"]), (ds, bt["m"]), (dP, bt["nnz_P"]),
+                  (dA, bt["nnz_A"]), (dq, bt["n"]), (db, bt["m"]))]
+        worst8 = 0.0
+        for k, q in enumerate(qs):
+            rj, rv = D.jvp_vjp_dense(q, q.dP, q.dA, q.dq, q.db, q.gx, q.gy, q.gs)
+            jv = [p[k] for p in parts[:3]]
+            vj = [p[k] for p in parts[3:]]
+            if tol == 1e-12:
+                # some members' recomputed residual stalls near 2e-10 (their rounding floor)
+                assert i1[k].rel_residual <= 1e-9 and i2[k].rel_residual <= 1e-9, k
+                yb = y_blocks(q.cones)
+                for name, a, r, b in zip(("dx", "dy", "ds", "dP", "dA", "dq", "db"),
+                                         jv + vj, list(rj) + list(rv),
+                                         (None, yb, yb, None, None, None, yb)):
+                    e = errors(a, r, b)
+                    assert max(e) <= BAR, (k, name, e)
+            else:
+                assert s1 == Q.QCPD_OK and s2 == Q.QCPD_OK
+                worst8 = max(worst8, normwise_only(jv, rj), normwise_only(vj, rv))
+        if tol == 1e-8:
+            print(f"[batch] worst forward error over 64 members at tol 1e-8: {worst8:.2e}",
+                  flush=True)

@@ -1,0 +1,155 @@
+"""LSMR, the paper's least-squares method (Sec. 3.1-3.2), on the GPU: JVP and VJP against the
+oracle's dense implicit-function solve (relative error <= 1e-7 at tolerance 1e-12) with the
+diagonal preconditioners and several graph sizes (odd ones too: the LSMR scalars alternate
+between two buffers by iteration), the residual estimate of a capped run against
+the oracle's LSMR with the same column scaling, and the benchmark-size workload converging at
+1e-8 next to LSQR."""
+import numpy as np
+import pytest
+
+import qcpgen
+from oracle import derivative as D
+from oracle import embedding as E
+from oracle.lsmr import lsmr
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2508_17522_amd as Q  # noqa: E402
+from qcpgen.torch_io import cones_of, to_device  # noqa: E402
+
+BAR = 1e-7
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / (nb if nb > 0 else 1.0)
+
+
+def handle(q, **kw):
+    t = to_device(q)
+    o = Q.Opts(solver=Q.QCPD_SOLVER_LSMR, **kw)
+    return Q.qcpd_create(t["P"], t["A"], t["q"], t["b"], cones_of(q), t["x"], t["y"], t["s"],
+                         opts=o), t
+
+
+def medium():
+    return qcpgen.small_mixed(1, n=301, n_zero=37, n_nonneg=260, soc=(3, 4, 5, 6, 7, 8) * 5,
+                              psd=(4, 7, 12, 9), n_exp=23, A_density=0.04, P_rank=150,
+                              nonneg_active=100)
+
+
+@pytest.mark.parametrize("case,precond,chunk", [
+    ("small", Q.QCPD_PRECOND_JACOBI, 32),
+    ("small", Q.QCPD_PRECOND_EQUIL, 1),
+    ("medium", Q.QCPD_PRECOND_EQUIL, 32),
+    ("medium", Q.QCPD_PRECOND_JACOBI, 7),
+    ("tiny", Q.QCPD_PRECOND_NONE, 32),
+])
+def test_lsmr_matches_dense_oracle(case, precond, chunk):
+    q = {"small": lambda: qcpgen.small_mixed(0), "medium": medium,
+         "tiny": lambda: qcpgen.tiny_qp(0)}[case]()
+    h, t = handle(q, tol=1e-12, precond=precond, graph_chunk=chunk)
+    dx, dy, ds, info, st = Q.qcpd_jvp(h, t["dP"], t["dA"], t["dq"], t["db"])
+    print(f"[{case}] lsmr jvp iters={info.iters} est={info.est_residual:.2e} "
+          f"rel={info.rel_residual:.2e} st={st}", flush=True)
+    assert st == Q.QCPD_OK and info.rel_residual <= 1e-11
+    ref = D.jvp_dense(q, q.dP, q.dA, q.dq, q.db)
+    errs = [rel(a.cpu().numpy(), b) for a, b in zip((dx, dy, ds), ref)]
+    print(f"[{case}] jvp errors {errs}", flush=True)
+    assert max(errs) <= BAR
+    dP, dA, dq, db, info2, st2 = Q.qcpd_vjp(h, t["gx"], t["gy"], t["gs"])
+    print(f"[{case}] lsmr vjp iters={info2.iters} rel={info2.rel_residual:.2e} st={st2}",
+          flush=True)
+    assert st2 == Q.QCPD_OK and info2.rel_residual <= 1e-11
+    refv = D.vjp_dense(q, q.gx, q.gy, q.gs)
+    errs2 = [rel(a.cpu().numpy(), b) for a, b in zip((dP, dA, dq, db), refv)]
+    print(f"[{case}] vjp errors {errs2}", flush=True)
+    assert max(errs2) <= BAR
+    h.close()
+
+
+@pytest.mark.parametrize("k", [1, 2, 7, 40])
+def test_lsmr_estimate_matches_oracle_recurrence(k):
+    """After exactly k iterations with the Jacobi column scaling, the library's residual
+    estimate equals the oracle LSMR's (same iterates in exact arithmetic) and, because the
+    estimate is exact up to rounding, the explicitly recomputed residual."""
+    q = medium()
+    h, t = handle(q, tol=1e-14, max_iter=k, precond=Q.QCPD_PRECOND_JACOBI, graph_chunk=4)
+    dx, dy, ds, info, st = Q.qcpd_jvp(h, t["dP"], t["dA"], t["dq"], t["db"])
+    h.close()
+    emb = E.Embedding(q)
+    d = emb.dtheta(q.dP, q.dA, q.dq, q.db)
+    dz, oinfo = lsmr(emb.F, emb.FT, -d, tol=1e-14, max_iter=k,
+                     col_scale=D.jacobi_scale_F(emb))
+    print(f"k={k}: gpu est {info.est_residual:.12e} rel {info.rel_residual:.12e}; oracle est "
+          f"{oinfo['est_residual']:.12e} iters {oinfo['iters']}", flush=True)
+    assert st == Q.QCPD_WARN_NOT_CONVERGED and info.iters == k and oinfo["iters"] == k
+    assert abs(info.est_residual - oinfo["est_residual"]) <= 1e-8 * oinfo["est_residual"]
+    assert abs(info.est_residual - info.rel_residual) <= 1e-8 * info.rel_residual
+    # the iterate itself, through the outputs
+    dxo, dyo, dso = emb.dphi(dz)
+    assert rel(dx.cpu().numpy(), dxo) <= 1e-8
+
+
+def test_lsmr_after_lsqr_on_one_handle():
+    """Switching the method on a handle (qcpd_set_opts) recaptures the loop's graphs."""
+    q = qcpgen.small_mixed(0)
+    t = to_device(q)
+    h = Q.qcpd_create(t["P"], t["A"], t["q"], t["b"], cones_of(q), t["x"], t["y"], t["s"],
+                      opts=Q.Opts(tol=1e-12))
+    a = Q.qcpd_jvp(h, t["dP"], t["dA"], t["dq"], t["db"])
+    Q.qcpd_set_opts(h, Q.Opts(tol=1e-12, solver=Q.QCPD_SOLVER_LSMR))
+    b = Q.qcpd_jvp(h, t["dP"], t["dA"], t["dq"], t["db"])
+    Q.qcpd_set_opts(h, Q.Opts(tol=1e-12, solver=Q.QCPD_SOLVER_LSQR))
+    c = Q.qcpd_jvp(h, t["dP"], t["dA"], t["dq"], t["db"])
+    h.close()
+    for u, v, w in zip(a[:3], b[:3], c[:3]):
+        assert rel(v.cpu().numpy(), u.cpu().numpy()) <= 1e-9
+        assert torch.equal(u, w)   # LSQR again: the same graphs, bit for bit
+    print(f"iters lsqr {a[3].iters} lsmr {b[3].iters}", flush=True)
+
+
+def test_lsmr_needs_the_graph_driver():
+    q = qcpgen.small_mixed(0)
+    t = to_device(q)
+    with pytest.raises(Q.QCPDError) as e:
+        Q.qcpd_create(t["P"], t["A"], t["q"], t["b"], cones_of(q), t["x"], t["y"], t["s"],
+                      opts=Q.Opts(solver=Q.QCPD_SOLVER_LSMR, engine=Q.QCPD_ENGINE_PERSISTENT))
+    assert e.value.status == Q.QCPD_ERR_INVALID_ARG
+
+
+def test_lsmr_rejected_by_the_batch():
+    q = qcpgen.small_mixed(0)
+    from qcpgen.torch_io import batch_create_args, batch_to_device
+    bt = batch_to_device([q])
+    with pytest.raises(Q.QCPDError) as e:
+        Q.qcpd_batch_create(*batch_create_args(bt), opts=Q.Opts(solver=Q.QCPD_SOLVER_LSMR))
+    assert e.value.status == Q.QCPD_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("workload", ["mixed_qcp", "large_psd_soc"])
+def test_lsmr_full_size_converges_next_to_lsqr(workload):
+    """The two methods at the benchmark tolerance on the full-size workloads (EQUIL): both
+    reach 1e-8 and give the same outputs to the tolerance's forward error."""
+    q = qcpgen.make(workload, 0)
+    t = to_device(q)
+    out = {}
+    for name, solver in (("lsqr", Q.QCPD_SOLVER_LSQR), ("lsmr", Q.QCPD_SOLVER_LSMR)):
+        h = Q.qcpd_create(t["P"], t["A"], t["q"], t["b"], cones_of(q), t["x"], t["y"], t["s"],
+                          opts=Q.Opts(tol=1e-8, precond=Q.QCPD_PRECOND_EQUIL, solver=solver))
+        j = Q.qcpd_jvp(h, t["dP"], t["dA"], t["dq"], t["db"])
+        v = Q.qcpd_vjp(h, t["gx"], t["gy"], t["gs"])
+        h.close()
+        print(f"[{workload}] {name}: jvp {j[3].iters} it {j[3].ms_total:.0f} ms rel "
+              f"{j[3].rel_residual:.2e}; vjp {v[4].iters} it {v[4].ms_total:.0f} ms rel "
+              f"{v[4].rel_residual:.2e}", flush=True)
+        assert j[4] == Q.QCPD_OK and v[5] == Q.QCPD_OK
+        assert j[3].rel_residual <= 1e-8 and v[4].rel_residual <= 1e-8
+        out[name] = [x.cpu().numpy() for x in j[:3]] + [x.cpu().numpy() for x in v[:4]]
+    diff = max(rel(a, b) for a, b in zip(out["lsmr"], out["lsqr"]))
+    print(f"[{workload}] largest relative difference LSMR vs LSQR outputs {diff:.2e}", flush=True)
+    assert diff <= 1e-4
