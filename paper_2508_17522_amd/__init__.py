@@ -14,7 +14,8 @@ from .api import (Cones, Opts, Info, Handle, QCPDError, qcpd_create, qcpd_jvp, q
                   qcpd_destroy, qcpd_status_str, qcpd_opts_default, qcpd_set_opts,
                   qcpd_set_precond, qcpd_get_diagnostics, qcpd_profile_kernels,
                   qcpd_set_launch, qcpd_get_launch, qcpd_apply)
-from .autograd import QCPStructure, qcp_solution_map
+from .autograd import (QCPStructure, qcp_solution_map, BatchStructure,
+                       batch_solution_map)
 from .learned import (LearnedModel, qcpd_features, qcpd_learned_targets, qcpd_set_learned,
                       qcpd_mlp_init, qcpd_mlp_predict, qcpd_mlp_grad, qcpd_mlp_adam)
 from .batch import (BatchHandle, qcpd_batch_create, qcpd_batch_jvp, qcpd_batch_vjp,

@@ -7,6 +7,10 @@ built at it. The backward pass is the adjoint of the derivative (Sec. 3.2) evalu
 HIP library (qcpd_vjp); forward-mode AD (torch.func.jvp / autograd.forward_ad) uses the
 derivative itself (Sec. 3.1, qcpd_jvp). Gradients for P and A are on their stored patterns;
 the gradient for P is symmetric on the pattern.
+
+batch_solution_map does the same for many problems of uneven sizes at once: the forward pass
+builds one batch handle, the backward pass is one qcpd_batch_vjp call (the per-problem
+adjoints of all problems in the same launches), forward mode one qcpd_batch_jvp call.
 """
 from __future__ import annotations
 
@@ -17,6 +21,7 @@ from typing import Optional, Sequence
 import torch
 
 from . import api
+from . import batch as B
 
 
 @dataclasses.dataclass
@@ -75,3 +80,66 @@ class _SolutionMap(torch.autograd.Function):
 def qcp_solution_map(P_val, A_val, q, b, x, y, s, structure: QCPStructure):
     """(x, y, s) as a differentiable function of (P_val, A_val, q, b) at a given solution."""
     return _SolutionMap.apply(P_val, A_val, q, b, x, y, s, structure)
+
+
+@dataclasses.dataclass
+class BatchStructure:
+    """The fixed part of a batch of problems: per-problem sizes and cones, and the concatenated
+    sparsity patterns (local CSR row pointers and column indices, int32 GPU tensors)."""
+    n: Sequence[int]
+    m: Sequence[int]
+    nnz_P: Sequence[int]
+    nnz_A: Sequence[int]
+    cones: Sequence[api.Cones]
+    P_rowptr: torch.Tensor
+    P_colind: torch.Tensor
+    A_rowptr: torch.Tensor
+    A_colind: torch.Tensor
+    opts: Optional[api.Opts] = None
+
+
+class _BatchSolutionMap(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, P_val, A_val, q, b, x, y, s, structure: BatchStructure):
+        st = structure
+        h = B.qcpd_batch_create(st.n, st.m, st.nnz_P, st.nnz_A, st.cones, st.P_rowptr,
+                                st.P_colind, P_val.detach(), st.A_rowptr, st.A_colind,
+                                A_val.detach(), q.detach(), b.detach(), x.detach(), y.detach(),
+                                s.detach(), opts=st.opts)
+        ctx.handle = h
+        return x.detach().clone(), y.detach().clone(), s.detach().clone()
+
+    @staticmethod
+    def backward(ctx, gx, gy, gs):
+        h = ctx.handle
+        f64 = dict(dtype=torch.float64, device=h.device)
+        sn, sm = sum(h.n), sum(h.m)
+        gx = torch.zeros(sn, **f64) if gx is None else gx.contiguous()
+        gy = torch.zeros(sm, **f64) if gy is None else gy.contiguous()
+        gs = torch.zeros(sm, **f64) if gs is None else gs.contiguous()
+        dP, dA, dq, db, infos, status = B.qcpd_batch_vjp(h, gx, gy, gs)
+        ctx.vjp_infos = infos
+        if status != 0:
+            bad = [i for i, inf in enumerate(infos) if inf.flags & 1]
+            warnings.warn(f"qcpd_batch_vjp: {api.qcpd_status_str(status)} (problems {bad[:8]})")
+        return dP, dA, dq, db, None, None, None, None
+
+    @staticmethod
+    def jvp(ctx, dP, dA, dq, db, dx_in, dy_in, ds_in, _structure):
+        h = ctx.handle
+        f64 = dict(dtype=torch.float64, device=h.device)
+        z = lambda k: torch.zeros(k, **f64)
+        dP = z(sum(h.nnzP)) if dP is None else dP.contiguous()
+        dA = z(sum(h.nnzA)) if dA is None else dA.contiguous()
+        dq = z(sum(h.n)) if dq is None else dq.contiguous()
+        db = z(sum(h.m)) if db is None else db.contiguous()
+        dx, dy, ds, infos, status = B.qcpd_batch_jvp(h, dP, dA, dq, db)
+        if status != 0:
+            warnings.warn(f"qcpd_batch_jvp: {api.qcpd_status_str(status)}")
+        return dx, dy, ds
+
+
+def batch_solution_map(P_val, A_val, q, b, x, y, s, structure: BatchStructure):
+    """The concatenated (x, y, s) of every problem of a batch as a differentiable function of
+    the concatenated data (P values, A values, q, b) at given solutions."""
+    return _BatchSolutionMap.apply(P_val, A_val, q, b, x, y, s, structure)

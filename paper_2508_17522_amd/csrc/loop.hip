@@ -610,13 +610,15 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 // bf(kk, j) (LDS, zero beyond the cone's order): wave w computes the 16 x 16 tiles w, w + 4,
 // ... in row-major tile order with V_MFMA_F64_16X16X4F64. In step s lane l supplies
 // A[i0 + l%16][4s + l/16] and B[4s + l/16][j0 + l%16]; accumulator entry r of lane l is
-// C[i0 + 4r + l/16][j0 + l%16]. The operands of up to eight steps are loaded before the
-// first product, and even and odd steps accumulate separately (two short dependency chains
-// instead of one long one). epi(i, j, acc) receives i = i0 + l/16 (rows i + 4r) and
-// j = j0 + l%16.
+// C[i0 + 4r + l/16][j0 + l%16]. The operands of a chunk of up to eight steps (a divisor of
+// the step count: six for KP = 48) are loaded before its first product, and even and odd
+// steps accumulate separately (two short dependency chains instead of one long one).
+// epi(i, j, acc) receives i = i0 + l/16 (rows i + 4r) and j = j0 + l%16.
 template <int KP, class AF, class BF, class EPI>
 __device__ inline void mfma_product(AF af, BF bf, EPI epi) {
-    constexpr int NT = KP / 16, NS = KP / 4, CH = NS < 8 ? NS : 8;
+    constexpr int NT = KP / 16, NS = KP / 4;
+    constexpr int CH = NS % 8 == 0 ? 8 : NS % 6 == 0 ? 6 : 4;
+    static_assert(NS % CH == 0 && CH % 2 == 0, "a chunk must divide the steps into pairs");
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     const int li = lane & 15, lk = lane >> 4;
 #pragma unroll 1

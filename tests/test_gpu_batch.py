@@ -76,11 +76,14 @@ def test_batch_matches_oracle_uneven(precond):
 
 
 def test_batch_with_larger_psd_orders():
-    """A PSD cone of order 20 in the batch (padded order 32) runs the batch's general F'
-    kernel; the others have small cones only."""
+    """PSD cones of orders 20 and 40 in the batch (padded orders 32 and 48) run the batch's
+    general F' kernel; the others have small cones only."""
     qs = [qcpgen.small_mixed(300, n=70, n_zero=5, n_nonneg=30, soc=(4, 3), psd=(20, 2),
                              n_exp=1, A_density=0.1, P_rank=60, P_eps=0.05, nonneg_active=10,
                              psd_ranks=(4, 1)),
+          qcpgen.small_mixed(302, n=120, n_zero=5, n_nonneg=40, soc=(3,), psd=(40,), n_exp=2,
+                             A_density=0.05, P_rank=100, P_eps=0.05, nonneg_active=15,
+                             psd_ranks=(6,)),
           qcpgen.small_mixed(301, n=30, n_zero=3, n_nonneg=12, soc=(3,), psd=(3,), n_exp=0,
                              A_density=0.15, P_rank=25, P_eps=0.05, nonneg_active=4)]
     bt = batch_to_device(qs)
