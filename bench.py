@@ -272,6 +272,20 @@ def run_copy_calibration(mib: int):
           flush=True)
 
 
+LAYOUT_FIELDS = ("staged", "deep", "nnz_per_lane_F", "nnz_per_lane_FT", "loop_grid")
+
+
+def layout_opts(args) -> dict:
+    """--layout FIELD=VALUE pairs as Opts keyword arguments."""
+    out = {}
+    for item in args.layout:
+        k, _, v = item.partition("=")
+        if k not in LAYOUT_FIELDS:
+            raise SystemExit(f"bench.py: unknown layout field {k!r} (one of {LAYOUT_FIELDS})")
+        out[k] = int(v)
+    return out
+
+
 def run_kernels_only(args):
     """Setup of the workload, then each LSQR-loop kernel launched back to back (for counter
     runs of a profiler: a few hundred dispatches instead of a whole solve)."""
@@ -285,7 +299,8 @@ def run_kernels_only(args):
     prec = {"equil": Q.QCPD_PRECOND_EQUIL, "jacobi": Q.QCPD_PRECOND_JACOBI,
             "none": Q.QCPD_PRECOND_NONE}[args.precond]
     h = Q.qcpd_create(t["P"], t["A"], t["q"], t["b"], cones_of(q), t["x"], t["y"], t["s"],
-                      opts=Q.Opts(tol=args.tol, precond=prec))
+                      opts=Q.Opts(tol=args.tol, precond=prec, **layout_opts(args)))
+    layout = Q.qcpd_get_layout(h)
     ms = Q.qcpd_profile_kernels(h, reps=args.kernels_only)
     h.close()
     torch.cuda.synchronize()
@@ -293,6 +308,7 @@ def run_kernels_only(args):
     nb = {k: kernel_bytes(q, k) for k in us}
     gbs = {k: nb[k] / us[k] / 1e3 for k in us}
     print(json.dumps({"kernels_only": {"workload": q.name, "reps": args.kernels_only,
+                                       "layout": layout,
                                        "avg_launch_us": us, "bytes_per_launch": nb,
                                        "achieved_GBps": gbs,
                                        "frac_of_hbm_peak": {k: gbs[k] / HBM_PEAK_GBS for k in us}}}),
@@ -321,6 +337,9 @@ def main():
                     help="only run a plain copy of MIB MiB (profiler byte-counter reference)")
     ap.add_argument("--kernels-only", type=int, default=0, metavar="REPS",
                     help="only set up the workload and launch each loop kernel REPS times")
+    ap.add_argument("--layout", action="append", default=[], metavar="FIELD=VALUE",
+                    help="a launch-layout option of the library (staged, deep, nnz_per_lane_F, "
+                         "nnz_per_lane_FT, loop_grid), for tuning runs; repeatable")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; the derivative of one QCP is not "
@@ -353,7 +372,7 @@ def main():
     prec = PREC[args.precond]
     eng = {"auto": Q.QCPD_ENGINE_AUTO, "graph": Q.QCPD_ENGINE_GRAPH,
            "persistent": Q.QCPD_ENGINE_PERSISTENT}[args.engine]
-    opts = Q.Opts(tol=args.tol, precond=prec, engine=eng)
+    opts = Q.Opts(tol=args.tol, precond=prec, engine=eng, **layout_opts(args))
     outs = dict(dx=torch.empty(q.n, dtype=torch.float64, device=dev),
                 dy=torch.empty(q.m, dtype=torch.float64, device=dev),
                 ds=torch.empty(q.m, dtype=torch.float64, device=dev),

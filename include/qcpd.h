@@ -107,7 +107,24 @@ typedef struct {
     int32_t check_symmetry; /* verify that P is symmetric at create              (1)           */
     int32_t engine;       /* LSQR driver: QCPD_ENGINE_AUTO, _GRAPH, _PERSISTENT (AUTO)         */
     int32_t solver;       /* Krylov method: QCPD_SOLVER_LSQR or QCPD_SOLVER_LSMR (LSQR)      */
+    /* Launch layout of the LSQR loop kernels, fixed at qcpd_create (qcpd_set_opts returns
+     * QCPD_ERR_INVALID_ARG for a change). 0 in each = the library's choice. None of them
+     * changes results beyond the order of floating-point sums. */
+    int32_t staged;       /* QCPD_CHOICE_*: products that stage the input's x part (n doubles)
+                             in LDS, one workgroup per CU; ON where it fits (n up to about
+                             20 000), AUTO where it fits on large problems                   */
+    int32_t deep;         /* QCPD_CHOICE_*: deep CSR sums in the fused product with F'
+                             (AUTO: problems whose CSR rows outnumber a launch's threads)    */
+    int32_t nnz_per_lane_F;   /* stored entries per lane of a CSR row, product with F (2)    */
+    int32_t nnz_per_lane_FT;  /* the same, fused product with F' (4; deep sums: about 25)    */
+    int32_t loop_grid;    /* most workgroups of a loop launch, <= 1024 (1024)                */
+    int32_t persist_grid; /* workgroups of the PERSISTENT driver (one wave of the device)     */
+    int32_t equil_sweeps; /* EQUIL scaling sweeps, rounded up to even (20)                    */
 } qcpd_opts;
+
+#define QCPD_CHOICE_AUTO 0
+#define QCPD_CHOICE_OFF  1
+#define QCPD_CHOICE_ON   2
 
 /* Krylov methods for the least-squares problems (Sec. 3.1-3.2). Both build the same
  * Golub-Kahan bidiagonalisation from one product with the operator and one with its
@@ -213,6 +230,12 @@ qcpd_status qcpd_set_launch(qcpd_handle *h, int32_t grid_F, int32_t grid_FT);
 /* out [host] 4 entries: the current grid_F, grid_FT, and the largest useful values (the
  * work items of each launch). */
 qcpd_status qcpd_get_launch(qcpd_handle *h, int32_t *out);
+
+/* The launch layout qcpd_create chose (the options' QCPD_CHOICE_AUTO resolved). out [host]
+ * 5 entries: 1 if the loop products stage the input's x part in LDS, 1 if the fused product
+ * with F' uses deep CSR sums, 1 if its PSD cones run in a launch of their own, and the lanes
+ * per CSR row of the x rows and of the y rows in the product with F. */
+qcpd_status qcpd_get_layout(qcpd_handle *h, int32_t *out);
 
 /* ---------------------------------------------------------------------------------------
  * Learned preconditioner (an addition to the method: the iterative solves of Sec. 3.1-3.2

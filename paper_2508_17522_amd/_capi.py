@@ -29,13 +29,19 @@ class qcpd_cones(ctypes.Structure):
 class qcpd_opts(ctypes.Structure):
     _fields_ = [("tol", c_double), ("max_iter", c_int32), ("precond", c_int32),
                 ("graph_chunk", c_int32), ("check_symmetry", c_int32), ("engine", c_int32),
-                ("solver", c_int32)]
+                ("solver", c_int32), ("staged", c_int32), ("deep", c_int32),
+                ("nnz_per_lane_F", c_int32), ("nnz_per_lane_FT", c_int32),
+                ("loop_grid", c_int32), ("persist_grid", c_int32), ("equil_sweeps", c_int32)]
 
 
 class qcpd_info(ctypes.Structure):
     _fields_ = [("iters", c_int32), ("est_residual", c_double), ("rel_residual", c_double),
                 ("flags", ctypes.c_uint32), ("ms_total", ctypes.c_float)]
 
+
+QCPD_CHOICE_AUTO = 0
+QCPD_CHOICE_OFF = 1
+QCPD_CHOICE_ON = 2
 
 QCPD_OK = 0
 QCPD_WARN_NOT_CONVERGED = 1
@@ -84,7 +90,7 @@ EXPORTS = ["qcpd_opts_default", "qcpd_create", "qcpd_jvp", "qcpd_vjp", "qcpd_set
            "qcpd_set_learned", "qcpd_mlp_init", "qcpd_mlp_predict", "qcpd_mlp_workspace_floats",
            "qcpd_mlp_grad", "qcpd_mlp_adam", "qcpd_set_launch", "qcpd_get_launch",
            "qcpd_batch_set_launch", "qcpd_batch_get_launch", "qcpd_apply",
-           "qcpd_mlp_grad_noalloc"]
+           "qcpd_mlp_grad_noalloc", "qcpd_get_layout"]
 
 _lib = None
 
@@ -158,6 +164,8 @@ def load(path: str = LIB_PATH):
     lib.qcpd_set_launch.restype = c_int32
     lib.qcpd_get_launch.argtypes = [c_void_p, P(c_int32)]
     lib.qcpd_get_launch.restype = c_int32
+    lib.qcpd_get_layout.argtypes = [c_void_p, P(c_int32)]
+    lib.qcpd_get_layout.restype = c_int32
     lib.qcpd_batch_set_launch.argtypes = [c_void_p, c_int32]
     lib.qcpd_batch_set_launch.restype = c_int32
     lib.qcpd_batch_get_launch.argtypes = [c_void_p, P(c_int32)]

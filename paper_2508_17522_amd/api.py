@@ -79,10 +79,20 @@ class Opts:
     check_symmetry: int = 1
     engine: int = C.QCPD_ENGINE_AUTO
     solver: int = C.QCPD_SOLVER_LSQR
+    # launch layout, fixed at create (0 = the library's choice)
+    staged: int = C.QCPD_CHOICE_AUTO
+    deep: int = C.QCPD_CHOICE_AUTO
+    nnz_per_lane_F: int = 0
+    nnz_per_lane_FT: int = 0
+    loop_grid: int = 0
+    persist_grid: int = 0
+    equil_sweeps: int = 0
 
     def to_c(self) -> C.qcpd_opts:
         return C.qcpd_opts(self.tol, self.max_iter, self.precond, self.graph_chunk,
-                           self.check_symmetry, self.engine, self.solver)
+                           self.check_symmetry, self.engine, self.solver, self.staged,
+                           self.deep, self.nnz_per_lane_F, self.nnz_per_lane_FT,
+                           self.loop_grid, self.persist_grid, self.equil_sweeps)
 
 
 @dataclasses.dataclass
@@ -276,6 +286,15 @@ def qcpd_get_launch(h: Handle):
     if st < 0:
         raise QCPDError(st, "qcpd_get_launch")
     return tuple(out)
+
+
+def qcpd_get_layout(h: Handle) -> dict:
+    """The launch layout chosen at create: staged, deep, psd_split, lanes_x, lanes_y."""
+    out = (C.c_int32 * 5)()
+    st = _lib().qcpd_get_layout(h.ptr, out)
+    if st < 0:
+        raise QCPDError(st, "qcpd_get_layout")
+    return dict(zip(("staged", "deep", "psd_split", "lanes_x", "lanes_y"), tuple(out)))
 
 
 def qcpd_destroy(h: Handle):

@@ -28,6 +28,12 @@ struct qcpd_handle {
     // launch's units (U_PSDROWS in place of U_PSD) and the PSD launch's units
     bool psd_split = false;
     FusedGrid fg_rows{}, fg_psd{};
+    // loop products with the input's x part staged in LDS: their row grid, and the cone units
+    // (PSD cones, exponential and SOC runs) of the product with F', its second launch
+    bool xs = false;
+    XsGrid xg{};
+    FusedGrid fg_cones{};
+    int ncu = 0;
     int lds_rows = 0, lds_psd = 0;
     int lds = 0;
     int lds_fused = 0;
@@ -78,6 +84,7 @@ namespace {
 constexpr int kMaxSeg = 8;
 constexpr int kEquilSweeps = 20;  // even: the result ends in the destination buffers
 constexpr int kLoopGrid = kMaxLoopGrid;  // default cap on the workgroups of a loop launch
+constexpr int kXsStaticLds = 1024;       // LDS the staged loop kernels declare themselves
 
 #define HIPCHK(expr)                              \
     do {                                          \
@@ -104,14 +111,8 @@ qcpd_status dalloc(qcpd_handle *h, T **ptr, size_t count) {
 
 // Lanes per CSR row: the largest power of two (<= 64) that still gives each lane about
 // `per_lane` stored entries. The product with F runs best with two entries per lane, the
-// fused product with F' with four (fewer, fuller work units); measured on MI355X.
-// QCPD_NNZ_PER_LANE_F / _FT override the two for tuning.
-int nnz_per_lane(const char *env, int dflt) {
-    const char *e = getenv(env);
-    const int x = e ? atoi(e) : 0;
-    return x > 0 ? x : dflt;
-}
-
+// fused product with F' with four (fewer, fuller work units); measured on MI355X. The
+// options' nnz_per_lane_F / _FT override the two.
 int lanes_for(double avg, int per_lane) {
     int L = 1;
     while (L < 64 && 2 * L * per_lane <= avg) L *= 2;
@@ -145,9 +146,20 @@ qcpd_status check_opts(const qcpd_opts *o) {
         o->precond < QCPD_PRECOND_NONE || o->precond > QCPD_PRECOND_LEARNED ||
         o->engine < QCPD_ENGINE_AUTO || o->engine > QCPD_ENGINE_PERSISTENT ||
         (o->solver != QCPD_SOLVER_LSQR && o->solver != QCPD_SOLVER_LSMR) ||
-        (o->solver == QCPD_SOLVER_LSMR && o->engine == QCPD_ENGINE_PERSISTENT))
+        (o->solver == QCPD_SOLVER_LSMR && o->engine == QCPD_ENGINE_PERSISTENT) ||
+        o->staged < QCPD_CHOICE_AUTO || o->staged > QCPD_CHOICE_ON ||
+        o->deep < QCPD_CHOICE_AUTO || o->deep > QCPD_CHOICE_ON || o->nnz_per_lane_F < 0 ||
+        o->nnz_per_lane_FT < 0 || o->loop_grid < 0 || o->loop_grid > kMaxLoopGrid ||
+        o->persist_grid < 0 || o->equil_sweeps < 0 || o->equil_sweeps > 1000)
         return QCPD_ERR_INVALID_ARG;
     return QCPD_OK;
+}
+
+// the launch-layout fields of the options (read at create only)
+bool same_layout(const qcpd_opts &a, const qcpd_opts &b) {
+    return a.staged == b.staged && a.deep == b.deep && a.nnz_per_lane_F == b.nnz_per_lane_F &&
+           a.nnz_per_lane_FT == b.nnz_per_lane_FT && a.loop_grid == b.loop_grid &&
+           a.persist_grid == b.persist_grid && a.equil_sweeps == b.equil_sweeps;
 }
 
 int max_iter_of(const qcpd_handle *h) {
@@ -243,16 +255,42 @@ void set_baked(const qcpd_handle *h, StepArgs &a) {
     }
 }
 
-// Work units of the loop's F' launch and its grid cap (the partial-sum slots of the PSD
-// launch come after those of the rows launch).
-int loop_units_T(const qcpd_handle *h) { return h->psd_split ? h->fg_rows.nunits : h->fg.nunits; }
-int loop_cap_T(const qcpd_handle *h) {
-    return h->psd_split ? kMaxLoopGrid - h->fg_psd.nunits : kMaxLoopGrid;
+// Work items of the loop's launches (workgroups that have work: rows blocks, units, or
+// for the staged kernels workgroups of kXsBlock / kWave row blocks) and the F' grid cap (the
+// partial-sum slots of a second, cone launch come after those of the rows launch).
+int loop_units_F(const qcpd_handle *h) {
+    return h->xs ? div_up(h->xg.total(), kXsBlock / kWave) : h->rg.total();
+}
+int loop_units_T(const qcpd_handle *h) {
+    return h->xs ? loop_units_F(h) : h->psd_split ? h->fg_rows.nunits : h->fg.nunits;
+}
+int loop_extra_T(const qcpd_handle *h) {
+    return h->xs ? h->fg_cones.nunits : h->psd_split ? h->fg_psd.nunits : 0;
+}
+int loop_cap_T(const qcpd_handle *h) { return kMaxLoopGrid - loop_extra_T(h); }
+// default grid: the staged kernels hold one workgroup per CU
+int loop_default_grid(const qcpd_handle *h) { return h->xs ? std::max(h->ncu, 1) : kLoopGrid; }
+
+void launch_loop_F_product(const qcpd_handle *h, const StepArgs &f, hipStream_t s) {
+    if (h->xs) launch_loop_xs(h->p, f, h->xg, false, h->loop_grid_F, s);
+    else launch_loop_F(h->p, f, h->rg, h->loop_grid_F, s);
 }
 
 // The loop's product with F' (role and vectors in t): one launch of the fused units, or the
-// rows launch followed by the PSD launch reading the state the rows launch finalised.
+// rows launch followed by the cone launch reading the state the rows launch finalised.
 void launch_loop_FT_product(const qcpd_handle *h, StepArgs t, hipStream_t s) {
+    if (h->xs) {
+        StepArgs r = t;
+        r.extra_slots = h->fg_cones.nunits;
+        launch_loop_xs(h->p, r, h->xg, true, h->loop_grid_T, s);
+        if (h->fg_cones.nunits > 0) {
+            StepArgs c = t;
+            c.st = t.st_next;
+            c.slot0 = h->loop_grid_T;
+            launch_loop_FT_cones(h->p, c, h->fg_cones, h->lds_loop, s);
+        }
+        return;
+    }
     if (!h->psd_split) {
         launch_loop_FT(h->p, t, h->fg, h->lds_loop, h->loop_grid_T, s);
         return;
@@ -264,7 +302,7 @@ void launch_loop_FT_product(const qcpd_handle *h, StepArgs t, hipStream_t s) {
     StepArgs c = t;
     c.st = t.st_next;
     c.slot0 = g;
-    launch_loop_FT_psd(h->p, c, h->fg_psd, h->lds_psd, s);
+    launch_loop_FT_cones(h->p, c, h->fg_psd, h->lds_psd, s);
 }
 
 LsmrArgs lsmr_args(const qcpd_handle *h, const LsqrState *st, LsqrState *st_next) {
@@ -298,7 +336,7 @@ void enqueue_iteration(const qcpd_handle *h, int dir, const double *sc, const do
         f.in = h->v; f.in_nrm = NRM_ALPHA; f.in_is_v = 1;
         f.out = h->u; f.role = ROLE_U; f.do_update = lsmr ? 0 : 1;
         set_baked(h, f);
-        launch_loop_F(h->p, f, h->rg, h->loop_grid_F, s);
+        launch_loop_F_product(h, f, s);
         StepArgs &t = second;  // v~ <- sc o F'u - beta v~, then J(sc o v~) for the next product
         t.in = h->u; t.in_nrm = NRM_BETA;
         t.out = h->v; t.role = ROLE_V; t.out_is_v = 1; t.do_pre = 1;
@@ -314,7 +352,7 @@ void enqueue_iteration(const qcpd_handle *h, int dir, const double *sc, const do
         f.in = h->u; f.in_nrm = NRM_BETA;
         f.out = h->v; f.role = ROLE_V; f.out_is_v = 1;
         set_baked(h, f);
-        launch_loop_F(h->p, f, h->rg, h->loop_grid_F, s);
+        launch_loop_F_product(h, f, s);
     }
     if (lsmr) launch_lsmr_step(lsmr_args(h, h->st3, h->st), s);
 }
@@ -549,14 +587,14 @@ qcpd_status create_impl(qcpd_handle *h, const qcpd_csr *P, const qcpd_csr *A, co
     // than a loop launch has) switch the F' loop kernel to deep CSR sums: about 25 entries
     // per lane, kDeep of them in flight, so each workgroup streams more per round. The
     // product with F keeps its shallow sums (measured faster at both large sizes).
-    // QCPD_DEEP=0/1 forces the choice (tuning).
-    bool deep = div_up((long long)n * lanes_for(avg_x, 1), kBlock) +
-                    div_up((long long)(m + 1) * lanes_for(avg_y, 1), kBlock) >
-                kLoopGrid;
-    if (const char *e = getenv("QCPD_DEEP")) deep = atoi(e) != 0;
-    const int npl_F = nnz_per_lane("QCPD_NNZ_PER_LANE_F", 2);
-    const int npl_T = nnz_per_lane("QCPD_NNZ_PER_LANE_FT", 4);
-    const bool npl_T_set = getenv("QCPD_NNZ_PER_LANE_FT") != nullptr;
+    const qcpd_opts &o = h->opts;
+    const bool large = div_up((long long)n * lanes_for(avg_x, 1), kBlock) +
+                           div_up((long long)(m + 1) * lanes_for(avg_y, 1), kBlock) >
+                       kLoopGrid;
+    const bool deep = o.deep == QCPD_CHOICE_AUTO ? large : o.deep == QCPD_CHOICE_ON;
+    const int npl_F = o.nnz_per_lane_F > 0 ? o.nnz_per_lane_F : 2;
+    const int npl_T = o.nnz_per_lane_FT > 0 ? o.nnz_per_lane_FT : 4;
+    const bool npl_T_set = o.nnz_per_lane_FT > 0;
     h->fg.deep = deep ? 1 : 0;
     rg.lx = lanes_for(avg_x, npl_F);
     rg.ly = lanes_for(avg_y, npl_F);
@@ -684,20 +722,35 @@ qcpd_status create_impl(qcpd_handle *h, const qcpd_csr *P, const qcpd_csr *A, co
             h->lds_rows = loop_lds_bytes(nullptr, 0);
             h->lds_psd = h->lds_loop;
         }
+        // the x part staged in LDS (k_loop_F_xs, k_loop_FT_xs + k_loop_FT_cones): where n
+        // doubles fit, on large problems unless the options say otherwise; the cone units come
+        // first in the unit table and form the F' product's second launch
+        int lds_max = 0;
+        hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device);
+        hipDeviceGetAttribute(&h->ncu, hipDeviceAttributeMultiprocessorCount, h->device);
+        const int ncone = (int)(units.size() - row_units.size());
+        const bool fits = n > 0 && xs_lds_bytes(n) + kXsStaticLds <= lds_max &&
+                          ncone <= kMaxLoopGrid / 2 && h->ncu > 0;
+        h->xs = fits && (o.staged == QCPD_CHOICE_ON || (o.staged == QCPD_CHOICE_AUTO && large));
+        if (h->xs) {
+            h->psd_split = false;
+            h->xg.lx = lanes_for(avg_x, npl_F);
+            h->xg.ly = lanes_for(avg_y, std::max(1, npl_F / 2));
+            h->xg.bxw = div_up((long long)n * h->xg.lx, kWave);
+            h->xg.byw = div_up((long long)(m + 1) * h->xg.ly, kWave);
+            h->fg_cones = h->fg;
+            h->fg_cones.nunits = ncone;
+            h->fg_cones.units = du;
+        }
     }
     h->nblk_max = std::max({cg.total(), rg.total(), h->fg.nunits, div_up(N, kBlock), 1});
     // the two launches of the deferred LSQR loop: at most `cap` workgroups each, so the next
-    // launch's fixed-order reduction of their partial sums stays short (QCPD_LOOP_GRID
-    // overrides the cap, for tuning)
+    // launch's fixed-order reduction of their partial sums stays short
     {
-        int cap = kLoopGrid;
-        if (const char *env = getenv("QCPD_LOOP_GRID")) {
-            const int e = atoi(env);
-            if (e > 0) cap = e;
-        }
-        cap = std::min(cap, kMaxLoopGrid);
-        h->loop_grid_F = std::max(1, std::min(rg.total(), cap));
-        h->loop_grid_T = std::max(1, std::min(loop_units_T(h), std::min(cap, loop_cap_T(h))));
+        const int cap = o.loop_grid > 0 ? std::min(o.loop_grid, kMaxLoopGrid) : kLoopGrid;
+        const int dflt = o.loop_grid > 0 ? cap : loop_default_grid(h);
+        h->loop_grid_F = std::max(1, std::min(loop_units_F(h), dflt));
+        h->loop_grid_T = std::max(1, std::min(loop_units_T(h), std::min(dflt, loop_cap_T(h))));
         ALLOC(h->lpart[0], 2LL * kMaxLoopGrid);
         ALLOC(h->lpart[1], 2LL * kMaxLoopGrid);
         ALLOC(h->st2, 1);
@@ -754,11 +807,7 @@ qcpd_status create_impl(qcpd_handle *h, const qcpd_csr *P, const qcpd_csr *A, co
     // two-sided equilibration of F (column scale in equil[0], row scale in equil[1])
     launch_fill(h->equil[0], N, 1.0, st);
     launch_fill(h->equil[1], N, 1.0, st);
-    int sweeps = kEquilSweeps;  // QCPD_EQUIL_SWEEPS overrides (tuning; rounded up to even)
-    if (const char *e = getenv("QCPD_EQUIL_SWEEPS")) {
-        const int v = atoi(e);
-        if (v > 0) sweeps = (v + 1) / 2 * 2;
-    }
+    const int sweeps = h->opts.equil_sweeps > 0 ? (h->opts.equil_sweeps + 1) / 2 * 2 : kEquilSweeps;
     launch_equilibrate(p, rg, h->equil[1], h->equil[0], h->tmp, h->scratch, sweeps,
                        h->partials, h->counter, st);
     HIPCHK(hipMemcpyAsync(h->host_flag, h->flag, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -768,6 +817,7 @@ qcpd_status create_impl(qcpd_handle *h, const qcpd_csr *P, const qcpd_csr *A, co
     if (h->lds > 0) set_cone_kernel_lds(h->lds);
     set_fused_kernel_lds(h->lds_fused);
     set_loop_kernel_lds(h->lds_loop);
+    if (h->xs) set_xs_kernel_lds(xs_lds_bytes(h->p.n));
     // persistent LSQR: as many co-resident workgroups as the work needs, at most one wave of
     // the whole device (QCPD_PERSIST_GRID overrides the count, for tuning)
     {
@@ -777,10 +827,7 @@ qcpd_status create_impl(qcpd_handle *h, const qcpd_csr *P, const qcpd_csr *A, co
         const int per_cu = coop ? persistent_blocks_per_cu(h->lds_fused) : 0;
         if (per_cu > 0) {
             int g = std::min(per_cu * ncu, std::max(rg.total(), h->fg.nunits));
-            if (const char *env = getenv("QCPD_PERSIST_GRID")) {
-                const int e = atoi(env);
-                if (e > 0) g = std::min(e, per_cu * ncu);
-            }
+            if (h->opts.persist_grid > 0) g = std::min(h->opts.persist_grid, per_cu * ncu);
             h->persist_grid = std::max(g, 1);
             ALLOC(h->persist_partials, 6LL * h->persist_grid);
         }
@@ -915,7 +962,8 @@ qcpd_status qcpd_create(qcpd_handle **out, const qcpd_csr *P, const qcpd_csr *A,
 }
 
 qcpd_status qcpd_set_opts(qcpd_handle *h, const qcpd_opts *opts) {
-    if (!h || !opts || check_opts(opts) != QCPD_OK) return QCPD_ERR_INVALID_ARG;
+    if (!h || !opts || check_opts(opts) != QCPD_OK || !same_layout(*opts, h->opts))
+        return QCPD_ERR_INVALID_ARG;
     h->opts = *opts;
     return QCPD_OK;
 }
@@ -1040,8 +1088,9 @@ qcpd_status qcpd_apply(qcpd_handle *h, int32_t transpose, const double *in, doub
 
 qcpd_status qcpd_set_launch(qcpd_handle *h, int32_t grid_F, int32_t grid_FT) {
     if (!h || grid_F < 0 || grid_FT < 0) return QCPD_ERR_INVALID_ARG;
-    const int gF = std::max(1, std::min({h->rg.total(), grid_F ? grid_F : kLoopGrid, kMaxLoopGrid}));
-    const int gT = std::max(1, std::min({loop_units_T(h), grid_FT ? grid_FT : kLoopGrid, loop_cap_T(h)}));
+    const int d = loop_default_grid(h);
+    const int gF = std::max(1, std::min({loop_units_F(h), grid_F ? grid_F : d, kMaxLoopGrid}));
+    const int gT = std::max(1, std::min({loop_units_T(h), grid_FT ? grid_FT : d, loop_cap_T(h)}));
     HIPCHK(hipStreamSynchronize(h->stream));
     h->loop_grid_F = gF;
     h->loop_grid_T = gT;
@@ -1057,8 +1106,18 @@ qcpd_status qcpd_get_launch(qcpd_handle *h, int32_t *out) {
     if (!h || !out) return QCPD_ERR_INVALID_ARG;
     out[0] = h->loop_grid_F;
     out[1] = h->loop_grid_T;
-    out[2] = std::min(h->rg.total(), kMaxLoopGrid);
+    out[2] = std::min(loop_units_F(h), kMaxLoopGrid);
     out[3] = std::min(loop_units_T(h), loop_cap_T(h));
+    return QCPD_OK;
+}
+
+qcpd_status qcpd_get_layout(qcpd_handle *h, int32_t *out) {
+    if (!h || !out) return QCPD_ERR_INVALID_ARG;
+    out[0] = h->xs ? 1 : 0;
+    out[1] = h->fg.deep ? 1 : 0;
+    out[2] = h->psd_split ? 1 : 0;
+    out[3] = h->xs ? h->xg.lx : h->rg.lx;
+    out[4] = h->xs ? h->xg.ly : h->rg.ly;
     return QCPD_OK;
 }
 
@@ -1107,8 +1166,7 @@ qcpd_status qcpd_profile_kernels(qcpd_handle *h, int32_t reps, float *ms_out) {
     LsqrState img{};
     img.alpha = 1.0; img.beta = 1.0; img.one = 1.0; img.tol = 0.0; img.max_iter = 1 << 30;
     img.pend_role = ROLE_PLAIN;
-    img.pend_blocks = std::min(kMaxLoopGrid, std::max(h->loop_grid_F, h->loop_grid_T +
-                                                              (h->psd_split ? h->fg_psd.nunits : 0)));
+    img.pend_blocks = std::min(kMaxLoopGrid, std::max(h->loop_grid_F, h->loop_grid_T + loop_extra_T(h)));
     img.pend_fwd = 0;
     *h->host_st = img;
     HIPCHK(hipMemcpyAsync(h->st, h->host_st, sizeof(LsqrState), hipMemcpyHostToDevice, s));
@@ -1126,7 +1184,7 @@ qcpd_status qcpd_profile_kernels(qcpd_handle *h, int32_t reps, float *ms_out) {
     set_baked(h, t);
     for (int kid = 0; kid < 2; ++kid) {
         auto launch = [&]() {
-            if (kid == 0) launch_loop_F(h->p, f, h->rg, h->loop_grid_F, s);
+            if (kid == 0) launch_loop_F_product(h, f, s);
             else launch_loop_FT_product(h, t, s);
         };
         launch();  // warm

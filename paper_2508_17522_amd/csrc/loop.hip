@@ -28,6 +28,7 @@ namespace qcpd {
 
 constexpr int kPartRegs = kMaxLoopGrid / kBlock;  // previous-launch partials per thread
 
+
 // ---------------------------------------------------------------------------------------
 // reductions on DPP lane moves (a __shfl_xor step is an LDS permute on this GPU; a DPP move
 // is a register operand modifier)
@@ -64,9 +65,11 @@ __device__ inline double wave_total_dpp(double v) {
     return v;
 }
 
-// Sums of a and b over the workgroup, valid in thread 0 (fixed order: waves 0..3).
+// Sums of a and b over a workgroup of BS threads, valid in thread 0 (fixed order: wave 0,
+// 1, ...).
+template <int BS = kBlock>
 __device__ inline void block_sum2(double &a, double &b) {
-    __shared__ double sh[2][kBlock / kWave];
+    __shared__ double sh[2][BS / kWave];
     a = wave_total_dpp(a);
     b = wave_total_dpp(b);
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
@@ -78,7 +81,7 @@ __device__ inline void block_sum2(double &a, double &b) {
     if (threadIdx.x == 0) {
         a = sh[0][0];
         b = sh[1][0];
-        for (int i = 1; i < kBlock / kWave; ++i) {
+        for (int i = 1; i < BS / kWave; ++i) {
             a += sh[0][i];
             b += sh[1][i];
         }
@@ -87,8 +90,9 @@ __device__ inline void block_sum2(double &a, double &b) {
 }
 
 // This workgroup's partial sums for the next launch (plain stores).
+template <int BS = kBlock>
 __device__ inline void leave(const StepArgs &a, double s0, double s1, int slot) {
-    block_sum2(s0, s1);
+    block_sum2<BS>(s0, s1);
     if (threadIdx.x == 0) {
         reinterpret_cast<double2 *>(a.part_next)[slot] = make_double2(s0, s1);
     }
@@ -98,20 +102,24 @@ __device__ inline void leave(const StepArgs &a, double s0, double s1, int slot) 
 // entry: state and the previous launch's partial sums
 // ---------------------------------------------------------------------------------------
 
-struct Entry {
+template <int BS>
+struct EntryT {
+    static constexpr int kRegs = kMaxLoopGrid / BS;  // previous-launch partials per thread
     LsqrState st;
-    double pa[kPartRegs], pb[kPartRegs];
+    double pa[kRegs], pb[kRegs];
 };
+using Entry = EntryT<kBlock>;
 
 // Issue the loads (values are consumed in entry_finish). The partial buffers hold
 // kMaxLoopGrid slots, so the loads stay in bounds; slots beyond pend_blocks are ignored.
 // A wait for a load also waits for every load issued before it, so the kernels issue these
 // after the first loads of their own work.
-__device__ inline void entry_issue(const StepArgs &a, Entry &e) {
+template <int BS>
+__device__ inline void entry_issue(const StepArgs &a, EntryT<BS> &e) {
     e.st = *a.st;
 #pragma unroll
-    for (int j = 0; j < kPartRegs; ++j) {
-        const int i = threadIdx.x + j * kBlock;
+    for (int j = 0; j < EntryT<BS>::kRegs; ++j) {
+        const int i = threadIdx.x + j * BS;
         const double2 v = reinterpret_cast<const double2 *>(a.part_prev)[i];  // one 16-byte load
         e.pa[j] = v.x;
         e.pb[j] = v.y;
@@ -120,8 +128,9 @@ __device__ inline void entry_issue(const StepArgs &a, Entry &e) {
 
 // Sums of a and b over the workgroup, valid in every thread (the same fixed order as
 // block_sum2, so every thread holds the same bits).
+template <int BS = kBlock>
 __device__ inline void block_sum2_all(double &a, double &b) {
-    __shared__ double sh[2][kBlock / kWave];
+    __shared__ double sh[2][BS / kWave];
     a = wave_total_dpp(a);
     b = wave_total_dpp(b);
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
@@ -132,7 +141,7 @@ __device__ inline void block_sum2_all(double &a, double &b) {
     __syncthreads();
     a = sh[0][0];
     b = sh[1][0];
-    for (int i = 1; i < kBlock / kWave; ++i) {
+    for (int i = 1; i < BS / kWave; ++i) {
         a += sh[0][i];
         b += sh[1][i];
     }
@@ -141,7 +150,8 @@ __device__ inline void block_sum2_all(double &a, double &b) {
 // Finalise the previous launch's reduction into S (a copy per thread: every thread holds
 // the totals and evaluates the same scalars, so no broadcast or second barrier is needed);
 // false in every thread once LSQR stopped.
-__device__ inline bool entry_finish(const StepArgs &a, const Entry &e, LsqrState *S, int my_fwd) {
+template <int BS>
+__device__ inline bool entry_finish(const StepArgs &a, const EntryT<BS> &e, LsqrState *S, int my_fwd) {
     const int tid = threadIdx.x;
     if (e.st.done) {
         if (blockIdx.x == 0 && tid == 0) *a.st_next = e.st;
@@ -150,12 +160,12 @@ __device__ inline bool entry_finish(const StepArgs &a, const Entry &e, LsqrState
     double t0 = 0.0, t1 = 0.0;
     if (e.st.pend_role >= 0) {
 #pragma unroll
-        for (int j = 0; j < kPartRegs; ++j)
-            if (tid + j * kBlock < e.st.pend_blocks) {
+        for (int j = 0; j < EntryT<BS>::kRegs; ++j)
+            if (tid + j * BS < e.st.pend_blocks) {
                 t0 += e.pa[j];
                 t1 += e.pb[j];
             }
-        block_sum2_all(t0, t1);
+        block_sum2_all<BS>(t0, t1);
     }
     LsqrState s = e.st;
     if (s.pend_role >= 0) finalize(&s, s.pend_role, t0, t1, s.pend_fwd != 0);
@@ -906,7 +916,7 @@ __device__ inline void unit_pre(const Problem &p, const StepArgs &a, const Ptrs 
         double upre[kSocPref];
 #pragma unroll
         for (int j = 0; j < kSocPref; ++j) upre[j] = j < cdim - 1 ? p.zy[cr0 + 1 + j] : 0.0;
-        yrows();
+        if (TROWS) trows(); else yrows();
 #pragma unroll
         for (int j = 0; j < kSocPref; ++j)
             if (j < cdim - 1) ub[cr0 - r0 + 1 + j] = upre[j] * P.cp[1];
@@ -919,7 +929,7 @@ __device__ inline void unit_pre(const Problem &p, const StepArgs &a, const Ptrs 
         const bool own = cone < u.end;
 #pragma unroll
         for (int j = 0; j < 9; ++j) J[j] = own ? p.exp_J[9 * cone + j] : 0.0;
-        yrows();
+        if (TROWS) trows(); else yrows();
         if (own) {
 #pragma unroll
             for (int j = 0; j < 9; ++j) ub[9 * tid + j] = J[j];
@@ -1070,11 +1080,13 @@ __global__ __launch_bounds__(kBlock) void k_loop_FT_multi_deep(Problem p, StepAr
     loop_FT_body<true, true>(p, a, g, sm, S);
 }
 
-// The PSD cones of a product with F' whose rows launch (k_loop_FT*, U_PSDROWS units) left
-// their raw rows in a.tmp: one workgroup per cone, the scalars of the state that launch
-// finalised (a.st), partial sums from slot a.slot0 on. Large cones stage up to 130 KB of LDS;
-// in their own launch they no longer hold every other unit to one workgroup per CU.
-__global__ __launch_bounds__(kBlock) void k_loop_FT_psd(Problem p, StepArgs a, FusedGrid g) {
+// The cone units of a product with F' whose rows launch (k_loop_FT* with U_PSDROWS units,
+// or k_loop_FT_xs) left their raw rows t = A r_x - b r_N - r_y in a.tmp: one workgroup per
+// unit (a PSD cone, or a run of SOC or exponential cones), the scalars of the state that
+// launch finalised (a.st), partial sums from slot a.slot0 on. Large PSD cones stage up to
+// 130 KB of LDS; in their own launch they no longer hold every other unit to one workgroup
+// per CU.
+__global__ __launch_bounds__(kBlock) void k_loop_FT_cones(Problem p, StepArgs a, FusedGrid g) {
     extern __shared__ double sm[];
     const Ptrs q = ptrs_of(p, a);
     const double in_N_raw = in_raw(a, q, p.N - 1);
@@ -1087,6 +1099,153 @@ __global__ __launch_bounds__(kBlock) void k_loop_FT_psd(Problem p, StepArgs a, F
     double s0 = 0.0, s1 = 0.0;
     unit_post(p, a, q, c, u, sm, P, s0, s1);
     leave(a, s0, s1, a.slot0 + blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------------------
+// products with the input's x part staged in LDS
+//
+// When n doubles fit in LDS, (isc o in)_x is staged there by every workgroup (kXsBlock
+// threads, one workgroup per CU), and the CSR sums with P and A gather from LDS instead of
+// through the L1 and L2 caches (one 8-byte entry per 128-byte line on random columns).
+// The workgroup's waves then take 64-thread blocks of rows round robin over the launch.
+// The sums with A' gather the y part (m long) from global memory. Product with F: x rows,
+// y rows and the tau row, as k_loop_F. Product with F': x rows and the diagonal y rows are
+// finished here, the raw rows of the cones go to a.tmp for k_loop_FT_cones (their blocks
+// of J are not diagonal), and the tau entry is finished by the first thread.
+// ---------------------------------------------------------------------------------------
+
+struct XsPre {
+    int idx;  // output entry of this thread (lane 0 of its row group), or -1
+    double acc, accT;
+    double coef;  // F: q (x rows) or b (y rows); F': c (x rows) or b (diagonal rows)
+    double self;  // y rows: (isc o in) at the row
+    double aux;   // F y rows: J applied to the previous input at the row; F': diag of J
+    Fin f;
+};
+
+template <bool FT>
+__device__ inline void xs_pre(const Problem &p, const StepArgs &a, const Ptrs &q,
+                              const double *xs, const XsGrid &g, int wb, int lane64,
+                              double in_N_raw, XsPre &r) {
+    const int n = p.n, m = p.m, N = p.N;
+    const bool xr = wb < g.bxw;
+    const int L = xr ? g.lx : g.ly;
+    const long long gt = (long long)(xr ? wb : wb - g.bxw) * kWave + lane64;
+    const int row = (int)(gt / L), lane = (int)(gt & (L - 1));
+    double acc = 0.0, accT = 0.0;
+    int idx = -1;
+    if (xr) {
+        if (row < n) {
+            acc = csr_dot4<false>(p.Pci, p.Pv, p.Prp[row], p.Prp[row + 1], lane, L, xs, nullptr, 0);
+            const int t0 = p.Trp[row], t1 = p.Trp[row + 1];
+            if (FT) accT = csr_dot(p.Tci, q.Tv, t0, t1, lane, L, a.in, q.gsc, n);
+            else accT = csr_dot4<false>(p.Tci, p.Tv, t0, t1, lane, L, a.wy, nullptr, 0);
+            idx = row;
+        }
+    } else if (row < m) {
+        acc = csr_dot4<false>(p.Aci, p.Av, p.Arp[row], p.Arp[row + 1], lane, L, xs, nullptr, 0);
+        idx = n + row;
+    } else if (!FT && row == m) {
+        idx = N - 1;
+    }
+    r.acc = group_sum_dpp(acc, L);
+    r.accT = group_sum_dpp(accT, L);
+    idx = lane == 0 ? idx : -1;
+    // operands in locals, stored once (a field chosen per branch would go through memory)
+    double coef = 0.0, self = 0.0, aux = 0.0;
+    if (idx >= 0 && idx < n) {
+        coef = FT ? p.c[idx] : p.q[idx];
+    } else if (idx >= n && idx < N - 1) {
+        const int y = idx - n;
+        self = in_raw(a, q, idx);
+        coef = p.b[y];
+        if (FT && y >= p.n_diag) {  // a cone row: its raw row for the cone launch
+            a.tmp[idx] = r.acc - coef * in_N_raw - self;
+            idx = -1;
+        } else {
+            aux = FT ? p.jdiag[y] : a.wy[y];
+        }
+    }
+    r.idx = idx;
+    r.coef = coef;
+    r.self = self;
+    r.aux = aux;
+    if (idx >= 0) fin_load(a, q, idx, r.f);
+}
+
+template <bool FT>
+__device__ inline void xs_post(const Problem &p, const StepArgs &a, const Ctx &c,
+                               const LsqrState &S, const XsPre &r, double &s0, double &s1) {
+    const int n = p.n, N = p.N;
+    if (r.idx < 0) return;
+    if (FT) {
+        if (r.idx < n) {
+            const double o = fin_store(a, c, r.idx, r.f, (r.acc - r.accT) * c.inv + r.coef * c.in_N, s0);
+            if (a.do_pre) s1 += r.coef * r.f.nxs * o;
+        } else {
+            const double t = (r.acc - r.self) * c.inv - r.coef * c.in_N;
+            const double o = fin_store(a, c, r.idx, r.f, r.aux * t + r.self * c.inv, s0);
+            if (a.do_pre) {
+                const double w = r.aux * r.f.nxs * o;
+                a.wy[r.idx - n] = w;
+                s1 -= r.coef * w;
+            }
+        }
+        return;
+    }
+    double val;
+    if (r.idx < n)
+        val = (r.acc + r.accT) * c.inv + r.coef * c.in_N;
+    else if (r.idx < N - 1)
+        val = (r.self - r.acc - r.aux) * c.inv + r.coef * c.in_N;
+    else
+        val = S.dot_fwd * c.inv + p.xPx * c.in_N;
+    const double o = fin_store(a, c, r.idx, r.f, val, s0);
+    if (r.idx < N - 1) s1 += r.coef * r.f.nxs * o;
+}
+
+template <bool FT>
+__device__ inline void loop_xs_body(const Problem &p, const StepArgs &a, const XsGrid &g,
+                                    double *xs) {
+    constexpr int kW = kXsBlock / kWave;
+    const int tid = threadIdx.x;
+    const Ptrs q = ptrs_of(p, a);
+    for (int j = tid; j < p.n; j += kXsBlock) xs[j] = in_raw(a, q, j);
+    const double in_N_raw = in_raw(a, q, p.N - 1);
+    __syncthreads();
+    const int lane64 = tid & (kWave - 1), total = g.total(), W = gridDim.x * kW;
+    int wb = blockIdx.x * kW + tid / kWave;
+    XsPre r;
+    r.idx = -1;
+    if (wb < total) xs_pre<FT>(p, a, q, xs, g, wb, lane64, in_N_raw, r);
+    EntryT<kXsBlock> e;
+    entry_issue(a, e);  // after the first rows' loads: the memory counter is in order
+    LsqrState S;
+    if (!entry_finish(a, e, &S, FT ? 1 : 0)) return;
+    const Ctx c = scalars(a, S, q, in_N_raw);
+    double s0 = 0.0, s1 = 0.0;
+    xs_post<FT>(p, a, c, S, r, s0, s1);
+    for (wb += W; wb < total; wb += W) {
+        xs_pre<FT>(p, a, q, xs, g, wb, lane64, in_N_raw, r);
+        xs_post<FT>(p, a, c, S, r, s0, s1);
+    }
+    if (FT && blockIdx.x == 0 && tid == 0) {  // the tau entry
+        const int N = p.N;
+        Fin f;
+        fin_load(a, q, N - 1, f);
+        fin_store(a, c, N - 1, f, S.dot_adj * c.inv + p.xPx * c.in_N, s0);
+    }
+    leave<kXsBlock>(a, s0, s1, blockIdx.x);
+}
+
+__global__ __launch_bounds__(kXsBlock) void k_loop_F_xs(Problem p, StepArgs a, XsGrid g) {
+    extern __shared__ double xs[];
+    loop_xs_body<false>(p, a, g, xs);
+}
+
+__global__ __launch_bounds__(kXsBlock) void k_loop_FT_xs(Problem p, StepArgs a, XsGrid g) {
+    extern __shared__ double xs[];
+    loop_xs_body<true>(p, a, g, xs);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1306,7 +1465,7 @@ int loop_lds_bytes(const int *psd_orders, int n_psd) {
 }
 
 void set_loop_kernel_lds(int bytes) {
-    (void)hipFuncSetAttribute((const void *)k_loop_FT_psd, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    (void)hipFuncSetAttribute((const void *)k_loop_FT_cones, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     (void)hipFuncSetAttribute((const void *)k_loop_FT, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     (void)hipFuncSetAttribute((const void *)k_loop_FT_multi, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     (void)hipFuncSetAttribute((const void *)k_loop_FT_deep, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
@@ -1327,9 +1486,22 @@ void launch_loop_FT(const Problem &p, const StepArgs &a, const FusedGrid &g, int
         hipLaunchKernelGGL(one ? k_loop_FT : k_loop_FT_multi, dim3(grid), dim3(kBlock), lds, s, p, a, g);
 }
 
-void launch_loop_FT_psd(const Problem &p, const StepArgs &a, const FusedGrid &g, int lds,
-                        hipStream_t s) {
-    hipLaunchKernelGGL(k_loop_FT_psd, dim3(g.nunits), dim3(kBlock), lds, s, p, a, g);
+void launch_loop_FT_cones(const Problem &p, const StepArgs &a, const FusedGrid &g, int lds,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(k_loop_FT_cones, dim3(g.nunits), dim3(kBlock), lds, s, p, a, g);
+}
+
+int xs_lds_bytes(int n) { return (int)sizeof(double) * n; }
+
+void set_xs_kernel_lds(int bytes) {
+    (void)hipFuncSetAttribute((const void *)k_loop_F_xs, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    (void)hipFuncSetAttribute((const void *)k_loop_FT_xs, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+void launch_loop_xs(const Problem &p, const StepArgs &a, const XsGrid &g, bool ft, int grid,
+                    hipStream_t s) {
+    hipLaunchKernelGGL(ft ? k_loop_FT_xs : k_loop_F_xs, dim3(grid), dim3(kXsBlock),
+                       xs_lds_bytes(p.n), s, p, a, g);
 }
 
 void set_seg_kernel_lds(int bytes) {

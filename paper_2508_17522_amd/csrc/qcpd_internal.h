@@ -84,6 +84,16 @@ struct RowGrid {
     int total() const { return bx + by; }
 };
 
+// LSQR loop kernels with the input's x part staged in LDS (loop.hip): one workgroup of
+// kXsBlock threads per CU; x rows with lx lanes each in bxw blocks of 64 threads, then y rows
+// (+ tau) with ly lanes each in byw blocks, taken by the waves round robin.
+constexpr int kXsBlock = 1024;
+struct XsGrid {
+    int lx, ly;
+    int bxw, byw;
+    __host__ __device__ int total() const { return bxw + byw; }
+};
+
 // ---------------------------------------------------------------------------------------
 // reductions
 // ---------------------------------------------------------------------------------------
@@ -197,8 +207,8 @@ struct StepArgs {
     // (val * isc[col], isc = sc or scl as in_is_v says), or null: the loop kernels then
     // gather isc per entry
     const double *Pvs, *Avs, *Tvs;
-    // a product with F' in two launches (rows, then the PSD cones): the rows launch counts
-    // extra_slots more partial sums for the next launch to reduce; the PSD launch writes its
+    // a product with F' in two launches (rows, then the cones): the rows launch counts
+    // extra_slots more partial sums for the next launch to reduce; the cone launch writes its
     // partials from slot slot0 on
     int extra_slots, slot0;
 };
@@ -287,8 +297,12 @@ void set_loop_kernel_lds(int bytes);
 void launch_loop_F(const Problem &p, const StepArgs &a, const RowGrid &g, int grid, hipStream_t s);
 void launch_loop_FT(const Problem &p, const StepArgs &a, const FusedGrid &g, int lds, int grid,
                     hipStream_t s);
-void launch_loop_FT_psd(const Problem &p, const StepArgs &a, const FusedGrid &g, int lds,
-                        hipStream_t s);
+void launch_loop_FT_cones(const Problem &p, const StepArgs &a, const FusedGrid &g, int lds,
+                          hipStream_t s);
+int xs_lds_bytes(int n);
+void set_xs_kernel_lds(int bytes);
+void launch_loop_xs(const Problem &p, const StepArgs &a, const XsGrid &g, bool ft, int grid,
+                    hipStream_t s);
 
 // LSMR (lsmr.hip): its scalars beyond the LSQR state block, and the arguments of its
 // per-iteration launch (after the U and V product launches of the LSQR loop kernels)

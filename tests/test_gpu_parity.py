@@ -34,9 +34,10 @@ def rel(a, b):
 
 
 def make_handle(qcp, tol=1e-12, precond=Q.QCPD_PRECOND_JACOBI, max_iter=0, chunk=32,
-                engine=Q.QCPD_ENGINE_AUTO):
+                engine=Q.QCPD_ENGINE_AUTO, **layout):
     t = to_device(qcp)
-    o = Q.Opts(tol=tol, max_iter=max_iter, precond=precond, graph_chunk=chunk, engine=engine)
+    o = Q.Opts(tol=tol, max_iter=max_iter, precond=precond, graph_chunk=chunk, engine=engine,
+               **layout)
     h = Q.qcpd_create(t["P"], t["A"], t["q"], t["b"], cones_of(qcp), t["x"], t["y"], t["s"], opts=o)
     return h, t
 
@@ -123,14 +124,13 @@ def test_psd_max_order():
 
 
 @pytest.mark.parametrize("precond", [Q.QCPD_PRECOND_JACOBI, Q.QCPD_PRECOND_EQUIL])
-def test_deep_csr_form_matches_oracle(precond, monkeypatch):
+def test_deep_csr_form_matches_oracle(precond):
     """The F' loop kernel's deep-CSR form (chosen by the library for large problems) forced
     on a small one with every cone type, in its single-unit and looping launch shapes."""
     q = qcpgen.small_mixed(1)
-    monkeypatch.setenv("QCPD_DEEP", "1")
-    check_jvp_vjp_dense(q, precond=precond)
-    h, t = make_handle(q, precond=precond)
-    monkeypatch.delenv("QCPD_DEEP")
+    layout = dict(deep=Q.QCPD_CHOICE_ON, staged=Q.QCPD_CHOICE_OFF)
+    check_jvp_vjp_dense(q, precond=precond, **layout)
+    h, t = make_handle(q, precond=precond, **layout)
     gF, gT, mF, mT = Q.qcpd_get_launch(h)
     Q.qcpd_set_launch(h, gF, max(1, mT // 3))  # fewer workgroups than units: looping form
     dx, dy, ds, info, st = gpu_jvp(h, t)
@@ -142,18 +142,17 @@ def test_deep_csr_form_matches_oracle(precond, monkeypatch):
     h.close()
 
 
-@pytest.mark.parametrize("deep", ["0", "1"])
-def test_psd_cones_in_their_own_launch(deep, monkeypatch):
+@pytest.mark.parametrize("deep", [Q.QCPD_CHOICE_OFF, Q.QCPD_CHOICE_ON])
+def test_psd_cones_in_their_own_launch(deep):
     """PSD cones of order above 32 run in a launch of their own after the rows launch of the
     product with F' (their raw rows pass through a buffer): plain and deep CSR sums, the
     single-unit and the looping launch shapes, every other cone type beside them."""
     q = qcpgen.small_mixed(4, n=150, n_zero=10, n_nonneg=60, soc=(3, 4, 5) * 3, psd=(40, 6, 33),
                            n_exp=5, A_density=0.03, P_rank=120, P_eps=1e-2, nonneg_active=20,
                            psd_ranks=(8, 2, 5))
-    monkeypatch.setenv("QCPD_DEEP", deep)
-    check_jvp_vjp_dense(q, precond=Q.QCPD_PRECOND_EQUIL)
-    h, t = make_handle(q, precond=Q.QCPD_PRECOND_EQUIL)
-    monkeypatch.delenv("QCPD_DEEP")
+    layout = dict(deep=deep, staged=Q.QCPD_CHOICE_OFF)
+    check_jvp_vjp_dense(q, precond=Q.QCPD_PRECOND_EQUIL, **layout)
+    h, t = make_handle(q, precond=Q.QCPD_PRECOND_EQUIL, **layout)
     gF, gT, mF, mT = Q.qcpd_get_launch(h)
     Q.qcpd_set_launch(h, gF, max(1, mT // 3))  # fewer workgroups than units: looping form
     dx, dy, ds, info, st = gpu_jvp(h, t)
