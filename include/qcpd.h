@@ -335,9 +335,11 @@ typedef struct {
  * pointers, starting at 0), P_colind / P_val sum(nnz_P) entries with local column indices;
  * A likewise with sum(m_i + 1) row pointers; q, x: sum(n_i); b, y, s: sum(m_i).
  * opts->precond may be NONE, JACOBI or EQUIL (each problem's two-sided equilibration is
- * computed here, 20 sweeps); graph_chunk is the number of LSQR iterations (of all problems)
+ * computed here, 20 sweeps); opts->solver must be QCPD_SOLVER_LSQR (else
+ * QCPD_ERR_INVALID_ARG); graph_chunk is the number of LSQR iterations (of all problems)
  * per captured HIP graph launch, at most 32 here (the host shrinks the launch lists to the
- * running problems between graph launches). */
+ * running problems between graph launches). The launch-layout fields of opts are not read:
+ * the batch has its own schedule (qcpd_batch_set_launch). */
 qcpd_status qcpd_batch_create(qcpd_batch **hb, const qcpd_batch_layout *layout,
                               const int32_t *P_rowptr, const int32_t *P_colind, const double *P_val,
                               const int32_t *A_rowptr, const int32_t *A_colind, const double *A_val,

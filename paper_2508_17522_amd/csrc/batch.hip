@@ -42,6 +42,7 @@ struct BatchDev {
     const double *scl; // row (u-side) scale of the current direction, or null
     int *resume;       // per problem: LSQR resumed after its explicit residual check
     int *nresumed;
+    double *prev_rel;  // per problem: explicit relative residual before its last resume, or 0
     LsqrState *st_out;
     double tol;
     int max_iter;
@@ -476,9 +477,11 @@ __global__ __launch_bounds__(kBlock) void k_batch_begin(BatchDev d, int dir, con
     }
 }
 
-// With a row scaling the LSQR stopping test sees the scaled residual: a problem whose
-// explicit (unscaled) relative residual is above tol resumes its LSQR from its loop state with
-// a tighter internal tolerance (at most a few times, as the single-problem path does).
+// The LSQR stopping test sees its own estimate (of the scaled residual, with a row scaling):
+// a problem whose explicit (unscaled) relative residual is above tol resumes its LSQR from its
+// loop state with a tighter internal tolerance, at most a few times and, as in the
+// single-problem path, not again after a resume that lowered that residual by less than a
+// tenth while the estimate went far below tol (its rounding floor).
 __global__ __launch_bounds__(kBlock) void k_batch_end(BatchDev d, int dir, double *o0, double *o1,
                                                       double *o2, double *o3, LsqrState *st0,
                                                       LsqrState *st1, int only_resumed,
@@ -493,10 +496,15 @@ __global__ __launch_bounds__(kBlock) void k_batch_end(BatchDev d, int dir, doubl
         solve_end(d, dir, b, &S, sm, o0, o1, o2, o3);
         if (threadIdx.x == 0) {
             const double rel = S.tau_rhs > 0.0 ? S.resid / S.tau_rhs : 0.0;
-            const bool again = allow_resume && d.scl && !(rel <= d.tol) && loop_state.conv &&
-                               loop_state.iters < loop_state.max_iter && loop_state.tol > 0.0;
+            const double prev = d.prev_rel[b];
+            const double est = loop_state.beta1 > 0.0 ? loop_state.phibar / loop_state.beta1 : 0.0;
+            const bool floor = prev > 0.0 && rel > 0.9 * prev && est <= 0.05 * d.tol;
+            const bool again = allow_resume && !(rel <= d.tol) && loop_state.conv &&
+                               loop_state.iters < loop_state.max_iter && loop_state.tol > 0.0 &&
+                               !floor;
             d.resume[b] = again ? 1 : 0;
             if (again) {
+                d.prev_rel[b] = rel;
                 LsqrState r = loop_state;
                 r.tol *= fmax(0.02, 0.5 * d.tol / rel);
                 r.done = 0;
@@ -965,6 +973,7 @@ qcpd_status batch_create_impl(qcpd_batch *h, const qcpd_batch_layout *L, const i
     p.n_exp = (int)exp_rows.size(); p.exp_row0 = 0; p.exp_rows = d_exp_rows; p.exp_J = exp_J;
     p.n_psd = (int)psd_row.size(); p.psd_row = d_psd_row; p.psd_k = d_psd_k; p.psd_off = d_psd_off;
     p.psd_pool = pool;
+    p.psd_lr = nullptr;  // the batch kernels apply the full form
     // Px, c, x'Px per problem, z_y, cone factors, scales
     double *partials;
     int *counter;
@@ -1001,7 +1010,7 @@ qcpd_status batch_create_impl(qcpd_batch *h, const qcpd_batch_layout *L, const i
     BALLOC(d.queue, 2);
     BALLOC(d.u, NT); BALLOC(d.v, NT); BALLOC(d.xk, NT); BALLOC(d.wk, NT); BALLOC(d.rhs, NT);
     BALLOC(d.sol, NT); BALLOC(d.scratch, NT); BALLOC(d.wy, m); BALLOC(d.wy_res, m);
-    BALLOC(d.resume, B); BALLOC(d.nresumed, 1);
+    BALLOC(d.resume, B); BALLOC(d.nresumed, 1); BALLOC(d.prev_rel, B);
     BCHK(hipMemsetAsync(d.resume, 0, sizeof(int) * B, st));
     // two-sided equilibration of every problem (even number of sweeps: ends in equil[])
     {
@@ -1222,6 +1231,7 @@ qcpd_status batch_run(qcpd_batch *h, int dir, const double *i0, const double *i1
     if (rc != QCPD_OK) return rc;
     BCHK(hipMemsetAsync(h->d.queue, 0, 2 * sizeof(int), s));
     BCHK(hipMemsetAsync(h->seg.ndone, 0, sizeof(int), s));
+    BCHK(hipMemsetAsync(h->d.prev_rel, 0, sizeof(double) * h->d.B, s));
     hipLaunchKernelGGL(k_batch_begin, dim3(h->grid), dim3(kBlock), h->lds, s, h->d, dir, i0, i1, i2,
                        i3, h->stl[0], h->seg.ndone);
     BCHK(hipGetLastError());
@@ -1324,7 +1334,8 @@ qcpd_status qcpd_batch_create(qcpd_batch **out, const qcpd_batch_layout *L, cons
     if (opts) o = *opts;
     if (!(o.tol >= 0.0) || o.max_iter < 0 ||
         (o.precond != QCPD_PRECOND_NONE && o.precond != QCPD_PRECOND_JACOBI &&
-         o.precond != QCPD_PRECOND_EQUIL) || o.graph_chunk < 1 || o.graph_chunk > 4096)
+         o.precond != QCPD_PRECOND_EQUIL) || o.graph_chunk < 1 || o.graph_chunk > 4096 ||
+        o.solver != QCPD_SOLVER_LSQR)
         return QCPD_ERR_INVALID_ARG;
     qcpd_batch *h = new (std::nothrow) qcpd_batch();
     if (!h) return QCPD_ERR_OOM;
@@ -1363,7 +1374,8 @@ qcpd_status qcpd_batch_vjp(qcpd_batch *h, const double *gx, const double *gy, co
 qcpd_status qcpd_batch_set_opts(qcpd_batch *h, const qcpd_opts *opts) {
     if (!h || !opts || !(opts->tol >= 0.0) || opts->max_iter < 0 ||
         (opts->precond != QCPD_PRECOND_NONE && opts->precond != QCPD_PRECOND_JACOBI &&
-         opts->precond != QCPD_PRECOND_EQUIL) || opts->graph_chunk < 1 || opts->graph_chunk > 4096)
+         opts->precond != QCPD_PRECOND_EQUIL) || opts->graph_chunk < 1 || opts->graph_chunk > 4096 ||
+        opts->solver != QCPD_SOLVER_LSQR)
         return QCPD_ERR_INVALID_ARG;
     h->opts = *opts;
     return QCPD_OK;

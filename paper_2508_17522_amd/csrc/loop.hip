@@ -690,6 +690,100 @@ __device__ inline void psd_apply_kp(int k, const PsdLds &L, double *sm, const do
     __syncthreads();
 }
 
+// As mfma_product for a (16 MT) x (4 KS) times (4 KS) x (16 NT) product.
+template <int MT, int NT, int KS, class AF, class BF, class EPI>
+__device__ inline void mfma_mnk(AF af, BF bf, EPI epi) {
+    constexpr int CH = KS % 8 == 0 ? 8 : KS % 6 == 0 ? 6 : 4;
+    static_assert(KS % CH == 0 && CH % 2 == 0, "a chunk must divide the steps into pairs");
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int li = lane & 15, lk = lane >> 4;
+#pragma unroll 1
+    for (int t = wave; t < MT * NT; t += kBlock / kWave) {
+        const int i0 = (t / NT) * 16, j0 = (t % NT) * 16;
+        dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+        for (int s0 = 0; s0 < KS; s0 += CH) {
+            double av[CH], bv[CH];
+#pragma unroll
+            for (int s = 0; s < CH; ++s) {
+                const int kk = 4 * (s0 + s) + lk;
+                av[s] = af(i0 + li, kk);
+                bv[s] = bf(kk, j0 + li);
+            }
+#pragma unroll
+            for (int s = 0; s < CH; s += 2) {
+                acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], bv[s], acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s + 1], bv[s + 1], acc1, 0, 0, 0);
+            }
+        }
+        epi(i0 + lk, j0 + li, acc0 + acc1);
+    }
+}
+
+// Low-rank form of the same Jacobian, for a cone whose eigenvalues leave c <= 16 on one side
+// of zero: setup stores those eigenpairs first in V and B (S, the first c columns). With
+// M = V'XV and Bs = B (S: eigenvalues >= 0) or 1 - B (S: eigenvalues < 0), both equal to one
+// on S x S and
+//   V (Bs o M) V' = E + E' - V_S M_SS V_S',   E = V (Bs o M)[:, S] V_S'
+// (Bs o M is nonzero on the rows or columns of S only), and J[X] = V (B o M) V' equals that
+// sum (S >= 0) or X minus it (V orthogonal). With H = (V'(X V_S)) times Bs[:, S] elementwise,
+// its S x S block halved, and U = V H: J[X] = Z + Z' with Z = U V_S' or X/2 - U V_S'. Four
+// products with one dimension 16: 4 KP^2 16 multiply-adds instead of 4 KP^3. X (symmetric,
+// zero beyond the order) is replaced by Y as in psd_apply_kp; W and H are KP x 16 panels in
+// the T region.
+template <int KP>
+__device__ inline void psd_apply_lr(int k, int c, bool neg, const PsdLds &L, double *sm,
+                                    const double *Bg) {
+    constexpr int ld = KP + 1, mat = KP * ld, lc = 17;
+    static_assert(2 * KP * lc <= mat, "two KP x 16 panels fit in the T region");
+    double *X = sm, *W = sm + mat, *H = sm + mat + KP * lc;
+    const double *V = sm + 2 * mat, *B = L.b >= 0 ? sm + L.b : nullptr;
+    auto vf = [&](int i, int j) { return V[i * ld + j]; };
+    auto vt = [&](int i, int j) { return V[j * ld + i]; };
+    auto wf = [&](int i, int j) { return W[i * lc + j]; };
+    auto to_w = [&](int i, int j, const dbl4 &a) {
+        for (int r = 0; r < 4; ++r) W[(i + 4 * r) * lc + j] = a[r];
+    };
+    mfma_mnk<KP / 16, 1, KP / 4>([&](int i, int j) { return X[i * ld + j]; }, vf, to_w);  // W = X V_S
+    __syncthreads();
+    mfma_mnk<KP / 16, 1, KP / 4>(vt, wf, [&](int i, int j, const dbl4 &a) {  // H = Bs' o (V'W)
+        for (int r = 0; r < 4; ++r) {
+            const int ii = i + 4 * r;
+            double f = 0.0;
+            if (ii < k && j < c) {
+                if (ii < c) {
+                    f = 0.5;
+                } else {
+                    const double b = B ? B[ii * ld + j] : Bg[ii * k + j];
+                    f = neg ? 1.0 - b : b;
+                }
+            }
+            H[ii * lc + j] = f * a[r];
+        }
+    });
+    __syncthreads();
+    mfma_mnk<KP / 16, 1, KP / 4>(vf, [&](int i, int j) { return H[i * lc + j]; }, to_w);  // W = V H
+    __syncthreads();
+    mfma_mnk<KP / 16, KP / 16, 4>(wf, vt, [&](int i, int j, const dbl4 &a) {  // Z in X
+        for (int r = 0; r < 4; ++r) {
+            double &x = X[(i + 4 * r) * ld + j];
+            x = neg ? 0.5 * x - a[r] : a[r];
+        }
+    });
+    __syncthreads();
+    for (int e = threadIdx.x; e < KP * KP; e += kBlock) {  // Y = Z + Z'
+        const int i = e / KP, j = e - (e / KP) * KP;
+        if (i > j) {
+            const double y = X[i * ld + j] + X[j * ld + i];
+            X[i * ld + j] = y;
+            X[j * ld + i] = y;
+        } else if (i == j) {
+            X[i * ld + i] *= 2.0;
+        }
+    }
+    __syncthreads();
+}
+
 // MAXKP: the largest padded order the caller can meet (fewer instances, fewer registers)
 template <int MAXKP = 64>
 __device__ inline void psd_apply(int k, const PsdLds &L, double *sm, const double *Bg) {
@@ -703,6 +797,22 @@ __device__ inline void psd_apply(int k, const PsdLds &L, double *sm, const doubl
     case 48: psd_apply_kp<48>(k, L, sm, Bg); break;
     default: psd_apply_kp<64>(k, L, sm, Bg); break;
     }
+}
+
+// The Jacobian of PSD cone `cone`: the low-rank form where LR is set, the factors record a
+// side of at most 16 eigenvalues and the padded order is 48 or 64; else the full form.
+template <int MAXKP = 64, bool LR = false>
+__device__ __forceinline__ void psd_apply_sel(const int *psd_lr, int cone, int k, const PsdLds &L,
+                                     double *sm, const double *Bg) {
+    if (LR && MAXKP >= 48 && L.kp >= 48 && psd_lr) {
+        const int lr = psd_lr[cone], c = lr & 255;
+        if (c <= 16) {
+            if (L.kp == 48) psd_apply_lr<48>(k, c, lr >= 256, L, sm, Bg);
+            else psd_apply_lr<64>(k, c, lr >= 256, L, sm, Bg);
+            return;
+        }
+    }
+    psd_apply<MAXKP>(k, L, sm, Bg);
 }
 
 // svec row i of an order-k cone is the matrix entry (ii, jj), ii >= jj (column jj holds the
@@ -738,7 +848,7 @@ __device__ inline double smat_get(const double *Y, int ld, int ii, int jj) {
 // DEEP: the row units' CSR sums keep kDeep entries per lane in flight (batched loop).
 // TROWS: the raw rows of a PSD unit come from a.tmp (written by the rows launch of the same
 // product) instead of the unit's own CSR gather.
-template <bool DEEP = false, int MAXKP = 64, bool TROWS = false>
+template <bool DEEP = false, int MAXKP = 64, bool TROWS = false, bool LR = false>
 __device__ inline void unit_pre(const Problem &p, const StepArgs &a, const Ptrs &q, int lx,
                                 int ly, const Unit &u, double *sm, double in_N_raw,
                                 UnitPre &P) {
@@ -846,12 +956,26 @@ __device__ inline void unit_pre(const Problem &p, const StepArgs &a, const Ptrs 
             tb[i] = (e1 > e0 ? tb[i] : 0.0) - bb * in_N_raw - y;
         }
     };
-    // the same rows from a.tmp (raw t of the rows launch) and the input
+    // the same rows from a.tmp (raw t of the rows launch) and the input, the loads of four
+    // rows per thread in flight at once
     auto trows = [&]() {
-        for (int i = tid; i < nr; i += kBlock) {
-            const double y = i == tid ? ry : in_raw(a, q, n + r0 + i);
-            rb[i] = y;
-            tb[i] = a.tmp[n + r0 + i];
+        constexpr int R = 4;
+        for (int i0 = tid; i0 < nr; i0 += R * kBlock) {
+            double y[R], t[R];
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                const int i = i0 + j * kBlock;
+                y[j] = i >= nr ? 0.0 : i == tid ? ry : in_raw(a, q, n + r0 + i);
+                t[j] = i < nr ? a.tmp[n + r0 + i] : 0.0;
+            }
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                const int i = i0 + j * kBlock;
+                if (i < nr) {
+                    rb[i] = y[j];
+                    tb[i] = t[j];
+                }
+            }
         }
         __syncthreads();
     };
@@ -884,9 +1008,32 @@ __device__ inline void unit_pre(const Problem &p, const StepArgs &a, const Ptrs 
                     if (i >= k || jj >= k) sm[i * Ld.ld + jj] = 0.0;  // X beyond order k
                 }
             }
+        } else if (TROWS) {  // the cone launch: eight entries of V (and B) per load batch
+            if (tid < nr) svec_rc(tid, k, P.ii, P.jj);
+            trows();
+            constexpr int R = 8;
+            for (int e0 = tid; e0 < kp * kp; e0 += R * kBlock) {
+                double vv[R], bb[R];
+#pragma unroll
+                for (int j = 0; j < R; ++j) {
+                    const int e = e0 + j * kBlock, i = e / kp, jj = e - (e / kp) * kp;
+                    const bool in_k = e < kp * kp && i < k && jj < k;
+                    vv[j] = in_k ? Vg[i * k + jj] : 0.0;
+                    bb[j] = (in_k && B) ? Bg[i * k + jj] : 0.0;
+                }
+#pragma unroll
+                for (int j = 0; j < R; ++j) {
+                    const int e = e0 + j * kBlock, i = e / kp, jj = e - (e / kp) * kp;
+                    if (e < kp * kp) {
+                        V[i * Ld.ld + jj] = vv[j];
+                        if (B) B[i * Ld.ld + jj] = bb[j];
+                        if (i >= k || jj >= k) sm[i * Ld.ld + jj] = 0.0;
+                    }
+                }
+            }
         } else {
             if (tid < nr) svec_rc(tid, k, P.ii, P.jj);
-            if (TROWS) trows(); else yrows();
+            yrows();
             for (int e = tid; e < kp * kp; e += kBlock) {
                 const int i = e / kp, jj = e - (e / kp) * kp;
                 const bool in_k = i < k && jj < k;
@@ -902,7 +1049,7 @@ __device__ inline void unit_pre(const Problem &p, const StepArgs &a, const Ptrs 
             smat_put(sm, Ld.ld, ii, jj, tb[i]);
         }
         __syncthreads();
-        psd_apply<MAXKP>(k, Ld, sm, Bg);  // ends with a barrier; J t in the X region
+        psd_apply_sel<MAXKP, LR>(p.psd_lr, u.begin, k, Ld, sm, Bg);  // ends with a barrier
     } else if (u.type == U_SOC) {
         int cr0 = 0, cdim = 0;
         if (cone < u.end) {
@@ -940,7 +1087,9 @@ __device__ inline void unit_pre(const Problem &p, const StepArgs &a, const Ptrs 
     }
 }
 
-template <int MAXKP = 64>
+// CL: the cone launch (k_loop_FT_cones): low-rank PSD Jacobians, and the loads of four rows
+// per thread in flight in the row loops
+template <int MAXKP = 64, bool CL = false>
 __device__ inline void unit_post(const Problem &p, const StepArgs &a, const Ptrs &q,
                                  const Ctx &c, const Unit &u, double *sm, const UnitPre &P,
                                  double &s0, double &s1) {
@@ -973,18 +1122,42 @@ __device__ inline void unit_post(const Problem &p, const StepArgs &a, const Ptrs
     (void)gb;
     const bool psd = u.type == U_PSD;
     const int k = u.k, ld = psd ? psd_lds(k).ld : 0;
-    for (int i = tid; i < nr; i += kBlock) {
-        Fin f;
-        if (i == tid) f = P.f;
-        else fin_load(a, q, n + r0 + i, f);
-        int ii = P.ii, jj = P.jj;
-        if (psd && i != tid) svec_rc(i, k, ii, jj);
-        // PSD: J t is the matrix Y in the X region; each thread reads its own lower-triangle
-        // entries before it writes them, and no thread reads the upper triangle
-        const double jv = psd ? smat_get(sm, ld, ii, jj) : jt[i];
-        const double o = fin_store(a, c, n + r0 + i, f, (jv + rb[i]) * c.inv, s0);
-        rb[i] = f.nxs * o;  // the next product's input, in place of r_y
-        if (psd && a.do_pre) smat_put(sm, ld, ii, jj, rb[i]);
+    if constexpr (CL) {  // as below, the operands of four rows per thread loaded first
+        constexpr int R = 4;
+        for (int i0 = tid; i0 < nr; i0 += R * kBlock) {
+            Fin f[R];
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                const int i = i0 + j * kBlock;
+                if (i == tid) f[j] = P.f;
+                else if (i < nr) fin_load(a, q, n + r0 + i, f[j]);
+            }
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                const int i = i0 + j * kBlock;
+                if (i >= nr) break;
+                int ii = P.ii, jj = P.jj;
+                if (psd && i != tid) svec_rc(i, k, ii, jj);
+                const double jv = psd ? smat_get(sm, ld, ii, jj) : jt[i];
+                const double o = fin_store(a, c, n + r0 + i, f[j], (jv + rb[i]) * c.inv, s0);
+                rb[i] = f[j].nxs * o;
+                if (psd && a.do_pre) smat_put(sm, ld, ii, jj, rb[i]);
+            }
+        }
+    } else {
+        for (int i = tid; i < nr; i += kBlock) {
+            Fin f;
+            if (i == tid) f = P.f;
+            else fin_load(a, q, n + r0 + i, f);
+            int ii = P.ii, jj = P.jj;
+            if (psd && i != tid) svec_rc(i, k, ii, jj);
+            // PSD: J t is the matrix Y in the X region; each thread reads its own lower-triangle
+            // entries before it writes them, and no thread reads the upper triangle
+            const double jv = psd ? smat_get(sm, ld, ii, jj) : jt[i];
+            const double o = fin_store(a, c, n + r0 + i, f, (jv + rb[i]) * c.inv, s0);
+            rb[i] = f.nxs * o;  // the next product's input, in place of r_y
+            if (psd && a.do_pre) smat_put(sm, ld, ii, jj, rb[i]);
+        }
     }
     if (!a.do_pre) return;
     __syncthreads();
@@ -993,7 +1166,7 @@ __device__ inline void unit_post(const Problem &p, const StepArgs &a, const Ptrs
     auto jout = [&](int i, double v) { jt[i] = v; };
     if (psd) {
         const double *Bg = p.psd_pool + p.psd_off[u.begin] + k * k;
-        psd_apply<MAXKP>(k, psd_lds(k), sm, Bg);  // Y in the X region
+        psd_apply_sel<MAXKP, CL>(p.psd_lr, u.begin, k, psd_lds(k), sm, Bg);  // Y in X
         for (int i = tid; i < nr; i += kBlock) {
             int ii = P.ii, jj = P.jj;
             if (i != tid) svec_rc(i, k, ii, jj);
@@ -1007,10 +1180,31 @@ __device__ inline void unit_post(const Problem &p, const StepArgs &a, const Ptrs
         }
         __syncthreads();
     }
-    for (int i = tid; i < nr; i += kBlock) {
-        const double w = jt[i];
-        a.wy[r0 + i] = w;
-        s1 -= (i == tid ? P.bv : p.b[r0 + i]) * w;
+    if constexpr (CL) {
+        constexpr int R = 4;
+        for (int i0 = tid; i0 < nr; i0 += R * kBlock) {
+            double bb[R];
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                const int i = i0 + j * kBlock;
+                bb[j] = i >= nr ? 0.0 : i == tid ? P.bv : p.b[r0 + i];
+            }
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                const int i = i0 + j * kBlock;
+                if (i < nr) {
+                    const double w = jt[i];
+                    a.wy[r0 + i] = w;
+                    s1 -= bb[j] * w;
+                }
+            }
+        }
+    } else {
+        for (int i = tid; i < nr; i += kBlock) {
+            const double w = jt[i];
+            a.wy[r0 + i] = w;
+            s1 -= (i == tid ? P.bv : p.b[r0 + i]) * w;
+        }
     }
 }
 
@@ -1092,12 +1286,12 @@ __global__ __launch_bounds__(kBlock) void k_loop_FT_cones(Problem p, StepArgs a,
     const double in_N_raw = in_raw(a, q, p.N - 1);
     const Unit u = g.units[blockIdx.x];
     UnitPre P;
-    unit_pre<false, 64, true>(p, a, q, g.lx, g.ly, u, sm, in_N_raw, P);
+    unit_pre<false, 64, true, true>(p, a, q, g.lx, g.ly, u, sm, in_N_raw, P);
     const LsqrState S = *a.st;
     if (S.done) return;
     const Ctx c = scalars(a, S, q, in_N_raw);
     double s0 = 0.0, s1 = 0.0;
-    unit_post(p, a, q, c, u, sm, P, s0, s1);
+    unit_post<64, true>(p, a, q, c, u, sm, P, s0, s1);
     leave(a, s0, s1, a.slot0 + blockIdx.x);
 }
 

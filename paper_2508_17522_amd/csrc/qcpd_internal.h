@@ -68,6 +68,8 @@ struct Problem {
     const int *psd_row, *psd_k;
     const long long *psd_off;       // offset of (V, B) in psd_pool, 2 k^2 doubles per cone
     const double *psd_pool;
+    const int *psd_lr;              // per cone: the low-rank side of its Jacobian (c, + 256 when
+                                    // it is the negative side), or null
 };
 
 // Cone-kernel grid: [elementwise | SOC | exp | PSD] block ranges.

@@ -10,6 +10,7 @@ struct ConeHost {
     int n_exp;                // exponential cones (the first 3 x 3 blocks)
     int n_pow;                // power and dual power cones after them
     const double *pow_par;    // [device] alpha (power cone) or -alpha (dual power cone)
+    int *psd_lr = nullptr;    // [device] per PSD cone: low-rank side (k_psd_factors), or null
 };
 
 hipError_t csr_transpose(int nrows, int ncols, int nnz, const int *rp, const int *ci,

@@ -425,11 +425,14 @@ __global__ void k_pow_factors(const double *zy, int row0, int count, const doubl
 // (tournament) ordering, so k/2 disjoint rotations are applied at once; then
 //   B_ij = 1 (both eigenvalues >= 0), 0 (both < 0), (l_i+ - l_j+)/(l_i - l_j) (mixed),
 // which equals the appendix's B for any eigenvalue order. V (row-major, columns are
-// eigenvectors) and B are stored side by side in the pool.
+// eigenvectors) and B are stored side by side in the pool, with the eigenpairs of the
+// smaller side of the split first: those with eigenvalue >= 0 when they are at most half,
+// else those < 0. psd_lr (when given) records c, the size of that side, plus 256 when it is
+// the negative side (the low-rank form of the Jacobian in the loop kernels reads it).
 __global__ __launch_bounds__(kBlock) void k_psd_factors(const double *zy, const int *psd_row,
                                                         const int *psd_k, const long long *psd_off,
                                                         double *pool, double *jdiag,
-                                                        int *nondiff, int *fail) {
+                                                        int *nondiff, int *fail, int *psd_lr) {
     extern __shared__ double sm[];
     const int cone = blockIdx.x;
     const int k = psd_k[cone], r0 = psd_row[cone];
@@ -536,6 +539,20 @@ __global__ __launch_bounds__(kBlock) void k_psd_factors(const double *zy, const 
     if (tid == 0 && !(off_last <= 1e-20 * all_last)) atomicOr(fail, 2);
     for (int i = tid; i < k; i += kBlock) lam_s[i] = A[i * ld + i];
     __syncthreads();
+    __shared__ int perm_s[kMaxPsd];  // stored position -> eigenpair
+    if (tid == 0) {
+        int r = 0;
+        for (int i = 0; i < k; ++i) r += lam_s[i] >= 0.0;
+        const bool neg = r > k - r;
+        const int c = neg ? k - r : r;
+        int a = 0, b = c;
+        for (int i = 0; i < k; ++i) {
+            const bool side = neg ? lam_s[i] < 0.0 : lam_s[i] >= 0.0;
+            perm_s[side ? a++ : b++] = i;
+        }
+        if (psd_lr) psd_lr[cone] = c | (neg ? 256 : 0);
+    }
+    __syncthreads();
     double *Vg = pool + psd_off[cone];
     double *Bg = Vg + k * k;
     double lmax = 0.0;
@@ -544,16 +561,16 @@ __global__ __launch_bounds__(kBlock) void k_psd_factors(const double *zy, const 
         for (int i = 0; i < k; ++i)
             if (fabs(lam_s[i]) <= kKinkTol * fmax(1.0, lmax)) atomicOr(nondiff, 1);
     }
+    auto bfun = [](double li, double lj) {
+        if (li >= 0.0 && lj >= 0.0) return 1.0;
+        if (li < 0.0 && lj < 0.0) return 0.0;
+        return (fmax(li, 0.0) - fmax(lj, 0.0)) / (li - lj);
+    };
     for (int e = tid; e < k * k; e += kBlock) {
         const int i = e / k, j = e % k;
-        Vg[e] = V[i * ld + j];
-        const double li = lam_s[i], lj = lam_s[j];
-        double bij;
-        if (li >= 0.0 && lj >= 0.0) bij = 1.0;
-        else if (li < 0.0 && lj < 0.0) bij = 0.0;
-        else bij = (fmax(li, 0.0) - fmax(lj, 0.0)) / (li - lj);
-        Bg[e] = bij;
-        A[i * ld + j] = bij;  // keep B in LDS for the diagonal below
+        Vg[e] = V[i * ld + perm_s[j]];
+        Bg[e] = bfun(lam_s[perm_s[i]], lam_s[perm_s[j]]);
+        A[i * ld + j] = bfun(lam_s[i], lam_s[j]);  // B in eigenpair order, for the diagonal below
     }
     __syncthreads();
     // diag of J on svec coordinates: entry (i,i): sum_ab B_ab V_ia^2 V_ib^2;
@@ -763,7 +780,7 @@ void launch_cone_factors(const Problem &p, const ConeHost &ch, double *jdiag, do
     if (p.n_psd > 0) {
         (void)hipFuncSetAttribute((const void *)k_psd_factors, hipFuncAttributeMaxDynamicSharedMemorySize, psd_lds);
         hipLaunchKernelGGL(k_psd_factors, dim3(p.n_psd), dim3(kBlock), psd_lds, s, p.zy, p.psd_row,
-                           p.psd_k, p.psd_off, pool, jdiag, nondiff, fail);
+                           p.psd_k, p.psd_off, pool, jdiag, nondiff, fail, ch.psd_lr);
     }
 }
 void launch_scales(const Problem &p, const RowGrid &g, double *dj, double *dv, double *partials,

@@ -1,10 +1,12 @@
 """The LSQR loop with the input's x part staged in LDS (one workgroup per CU; the CSR sums
 with P and A gather from LDS; the cones of the product with F' in a second launch that reads
-their raw rows from a buffer), forced on problems small enough for the dense oracle: JVP and
-VJP against its implicit-function solve (relative error <= 1e-7 at tolerance 1e-12) with
-every cone type, LSQR and LSMR, the default launch shape and one with far fewer workgroups
-than row blocks, a problem without cone units, and a reduced instance of the n = 20 000
-workload's shape. The full-size workload runs this layout by default (its own tests)."""
+their raw rows from a buffer, PSD cones of order 33-64 with at most 16 eigenvalues on one
+side of zero through the low-rank form of their Jacobian), forced on problems small enough
+for the dense oracle: JVP and VJP against its implicit-function solve (relative error <= 1e-7
+at tolerance 1e-12) with every cone type, both sides of the low-rank form, LSQR and LSMR,
+the default launch shape and one with far fewer workgroups than row blocks, a problem
+without cone units, and a reduced instance of the n = 20 000 workload's shape. The
+full-size workload runs this layout by default (its own tests)."""
 import numpy as np
 import pytest
 
@@ -37,9 +39,21 @@ def medium():
                               dpow_alphas=tuple(rng.uniform(0.1, 0.9, 4)))
 
 
+def psd_negative_side():
+    """An order-34 PSD cone with 22 positive eigenvalues at the solution: the low-rank
+    Jacobian works on the 12 negative ones (J = X minus the low-rank sum)."""
+    rng = np.random.default_rng(11)
+    return qcpgen.small_mixed(2, n=600, n_zero=37, n_nonneg=260, soc=(3, 4, 5, 6, 7, 8) * 5,
+                              psd=(4, 34), n_exp=23, A_density=0.04, P_rank=150, P_eps=1e-2,
+                              nonneg_active=10, psd_ranks=(2, 22),
+                              pow_alphas=tuple(rng.uniform(0.1, 0.9, 6)),
+                              dpow_alphas=tuple(rng.uniform(0.1, 0.9, 4)))
+
+
 CASES = {
     "small": lambda: qcpgen.small_mixed(0),
     "medium": medium,
+    "psd_negative_side": psd_negative_side,
     "tiny_qp": lambda: qcpgen.tiny_qp(1),   # zero and nonnegative rows only: no cone launch
     "reduced_large": lambda: qcpgen.large_psd_soc(0, scale=0.04),
 }
@@ -71,6 +85,7 @@ def check(h, t, q, tag):
     ("small", Q.QCPD_PRECOND_JACOBI, Q.QCPD_SOLVER_LSQR),
     ("medium", Q.QCPD_PRECOND_EQUIL, Q.QCPD_SOLVER_LSQR),
     ("medium", Q.QCPD_PRECOND_EQUIL, Q.QCPD_SOLVER_LSMR),
+    ("psd_negative_side", Q.QCPD_PRECOND_EQUIL, Q.QCPD_SOLVER_LSQR),
     ("tiny_qp", Q.QCPD_PRECOND_JACOBI, Q.QCPD_SOLVER_LSQR),
     ("reduced_large", Q.QCPD_PRECOND_EQUIL, Q.QCPD_SOLVER_LSQR),
 ])
