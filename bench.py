@@ -43,11 +43,22 @@ def kernel_bytes(q, which: str) -> float:
         # in, scale, J-input wy, q, b, out read+write, LSQR x and w read+write
         vec = 8.0 * (N + N + m + n + m + 2 * N + 4 * N)
         return csr + vec
+    c = q.cones
+    fac = 8.0 * (4 * len(c.soc) + sum(c.soc) + 9 * c.n_exp + sum(2 * k * k for k in c.psd))
+    n_diag = c.n_zero + c.n_nonneg
+    m_c = m - n_diag  # rows of non-diagonal cone blocks
     if which == "k_loop_FT":
-        c = q.cones
-        fac = 8.0 * (4 * len(c.soc) + sum(c.soc) + 9 * c.n_exp + sum(2 * k * k for k in c.psd))
         # in, c, b, out read+write, scale, jdiag of diagonal rows, wy write
-        return csr + fac + 8.0 * (N + n + m + 2 * N + N + c.n_zero + c.n_nonneg + m)
+        return csr + fac + 8.0 * (N + n + m + 2 * N + N + n_diag + m)
+    if which == "k_loop_FT_rows":
+        # the first of two launches: in, scale, c, b of the diagonal rows, out read+write of
+        # the x rows, diagonal rows and tau, jdiag and wy of the diagonal rows, and the raw
+        # cone rows written for the second launch
+        return csr + 8.0 * (2 * N + n + n_diag + 2 * (n + n_diag + 1) + 2 * n_diag + m_c)
+    if which == "k_loop_FT_cones":
+        # the second launch: the cone factors, and per cone row its raw row, in, scale, b,
+        # out read+write, wy write
+        return fac + 8.0 * 7 * m_c
     raise ValueError(which)
 
 
@@ -272,7 +283,8 @@ def run_copy_calibration(mib: int):
           flush=True)
 
 
-LAYOUT_FIELDS = ("staged", "deep", "nnz_per_lane_F", "nnz_per_lane_FT", "loop_grid")
+LAYOUT_FIELDS = ("staged", "deep", "nnz_per_lane_F", "nnz_per_lane_FT", "lanes_x", "lanes_y",
+                 "loop_grid")
 
 
 def layout_opts(args) -> dict:
@@ -283,6 +295,24 @@ def layout_opts(args) -> dict:
         if k not in LAYOUT_FIELDS:
             raise SystemExit(f"bench.py: unknown layout field {k!r} (one of {LAYOUT_FIELDS})")
         out[k] = int(v)
+    return out
+
+
+# single kernels of an LSQR iteration (the symbols a profiler shows) -> their byte model
+BYTES_OF = {"k_loop_F": "k_loop_F", "k_loop_F_xs": "k_loop_F", "k_loop_FT": "k_loop_FT",
+            "k_loop_FT_xs": "k_loop_FT_rows", "k_loop_FT rows form": "k_loop_FT_rows",
+            "k_loop_FT_cones": "k_loop_FT_cones"}
+
+
+def launch_times(ms, layout) -> dict:
+    """The launches of one iteration by kernel, from qcpd_profile_kernels' four durations."""
+    staged = layout["staged"] == 1
+    out = {"k_loop_F_xs" if staged else "k_loop_F": ms[0]}
+    if ms[3] > 0.0:
+        out["k_loop_FT_xs" if staged else "k_loop_FT rows form"] = ms[2]
+        out["k_loop_FT_cones"] = ms[3]
+    else:
+        out["k_loop_FT"] = ms[1]
     return out
 
 
@@ -304,8 +334,8 @@ def run_kernels_only(args):
     ms = Q.qcpd_profile_kernels(h, reps=args.kernels_only)
     h.close()
     torch.cuda.synchronize()
-    us = {"k_loop_F": ms[0] * 1e3, "k_loop_FT": ms[1] * 1e3}
-    nb = {k: kernel_bytes(q, k) for k in us}
+    us = {k: v * 1e3 for k, v in launch_times(ms, layout).items()}
+    nb = {k: kernel_bytes(q, BYTES_OF[k]) for k in us}
     gbs = {k: nb[k] / us[k] / 1e3 for k in us}
     print(json.dumps({"kernels_only": {"workload": q.name, "reps": args.kernels_only,
                                        "layout": layout,
@@ -339,7 +369,8 @@ def main():
                     help="only set up the workload and launch each loop kernel REPS times")
     ap.add_argument("--layout", action="append", default=[], metavar="FIELD=VALUE",
                     help="a launch-layout option of the library (staged, deep, nnz_per_lane_F, "
-                         "nnz_per_lane_FT, loop_grid), for tuning runs; repeatable")
+                         "nnz_per_lane_FT, lanes_x, lanes_y, loop_grid), for tuning runs; "
+                         "repeatable")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; the derivative of one QCP is not "
@@ -423,20 +454,23 @@ def main():
 
     # roofline of the dominant kernel: average launch duration measured with HIP events
     h = step(None)
+    layout = Q.qcpd_get_layout(h)
     ms = Q.qcpd_profile_kernels(h, reps=200)
     h.close()
-    names = ["k_loop_F", "k_loop_FT"]
     iters_total = rec[-1]["ij"].iters + rec[-1]["iv"].iters
-    dom = int(np.argmax(ms))
-    dom_name = names[dom]
-    nbytes = kernel_bytes(q, dom_name)
-    achieved = nbytes / (ms[dom] * 1e-3) / 1e9
+    times = launch_times(ms, layout)
+    dom_name = max(times, key=times.get)
+    nbytes = kernel_bytes(q, BYTES_OF[dom_name])
+    achieved = nbytes / (times[dom_name] * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
                 "traffic": profiled_traffic(q.name, dom_name),
-                "kernel": dom_name, "avg_launch_us": round(ms[dom] * 1e3, 3),
+                "kernel": dom_name, "avg_launch_us": round(times[dom_name] * 1e3, 3),
                 "bytes_per_launch": int(nbytes),
-                "all_kernels_us": {k: round(v * 1e3, 3) for k, v in zip(names, ms)}}
+                "all_kernels_us": {k: round(v * 1e3, 3) for k, v in times.items()},
+                "frac_by_kernel": {k: round(kernel_bytes(q, BYTES_OF[k]) / (v * 1e-3) / 1e9
+                                            / HBM_PEAK_GBS, 4) for k, v in times.items()},
+                "us_per_iteration": round((ms[0] + ms[1]) * 1e3, 3)}
 
     line = {
         "metric": METRIC,

@@ -113,10 +113,14 @@ typedef struct {
     int32_t staged;       /* QCPD_CHOICE_*: products that stage the input's x part (n doubles)
                              in LDS, one workgroup per CU; ON where it fits (n up to about
                              20 000), AUTO where it fits on large problems                   */
-    int32_t deep;         /* QCPD_CHOICE_*: deep CSR sums in the fused product with F'
-                             (AUTO: problems whose CSR rows outnumber a launch's threads)    */
+    int32_t deep;         /* QCPD_CHOICE_*: deep CSR sums (16 entries per lane in flight) in
+                             the fused product with F' (AUTO: problems whose CSR rows
+                             outnumber a launch's threads) and, ON only, in the staged kernels */
     int32_t nnz_per_lane_F;   /* stored entries per lane of a CSR row, product with F (2)    */
     int32_t nnz_per_lane_FT;  /* the same, fused product with F' (4; deep sums: about 25)    */
+    int32_t lanes_x;      /* lanes per x row (P and A' rows) in the product with F and the
+                             staged kernels, a power of two <= 64 (from nnz_per_lane_F)      */
+    int32_t lanes_y;      /* the same for the y rows (A rows)                               */
     int32_t loop_grid;    /* most workgroups of a loop launch, <= 1024 (1024)                */
     int32_t persist_grid; /* workgroups of the PERSISTENT driver (one wave of the device)     */
     int32_t equil_sweeps; /* EQUIL scaling sweeps, rounded up to even (20)                    */
@@ -206,12 +210,14 @@ qcpd_status qcpd_set_precond(qcpd_handle *h, const double *d_col, const double *
 qcpd_status qcpd_get_diagnostics(qcpd_handle *h, double *d_jvp, double *d_vjp, double *eq_col,
                                  double *eq_row, double *jdiag);
 
-/* Measurement support: time the two kernels of one LSQR iteration of the JVP (the product
- * with F over CSR rows; the fused product with F': CSR rows of each cone block followed by
- * its Jacobian block) by launching each `reps` times back to back on the handle's stream
- * between HIP events, on the handle's current vectors. Writes the average duration of one
- * launch in milliseconds to ms_out[0..1] [host]. Leaves the LSQR state undefined: call it
- * between, not during, derivative evaluations. */
+/* Measurement support: time the launches of one LSQR iteration of the JVP (the product
+ * with F over CSR rows; the product with F': CSR rows of each cone block and its Jacobian
+ * block, in one fused launch or in a rows launch followed by a cone launch) by launching each
+ * `reps` times back to back on the handle's stream between HIP events, on the handle's
+ * current vectors. ms_out [host] 4 entries, the average duration in milliseconds of: the
+ * product with F, the product with F' (all its launches), the first launch of that product
+ * alone, its second launch alone (0 when it has one launch). Leaves the LSQR state
+ * undefined: call it between, not during, derivative evaluations. */
 qcpd_status qcpd_profile_kernels(qcpd_handle *h, int32_t reps, float *ms_out);
 
 /* One product with the operator of the least-squares problems, F = D_z N at z (Sec. 2.4):

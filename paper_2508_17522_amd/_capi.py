@@ -31,6 +31,7 @@ class qcpd_opts(ctypes.Structure):
                 ("graph_chunk", c_int32), ("check_symmetry", c_int32), ("engine", c_int32),
                 ("solver", c_int32), ("staged", c_int32), ("deep", c_int32),
                 ("nnz_per_lane_F", c_int32), ("nnz_per_lane_FT", c_int32),
+                ("lanes_x", c_int32), ("lanes_y", c_int32),
                 ("loop_grid", c_int32), ("persist_grid", c_int32), ("equil_sweeps", c_int32)]
 
 

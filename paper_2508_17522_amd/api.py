@@ -84,6 +84,8 @@ class Opts:
     deep: int = C.QCPD_CHOICE_AUTO
     nnz_per_lane_F: int = 0
     nnz_per_lane_FT: int = 0
+    lanes_x: int = 0
+    lanes_y: int = 0
     loop_grid: int = 0
     persist_grid: int = 0
     equil_sweeps: int = 0
@@ -92,6 +94,7 @@ class Opts:
         return C.qcpd_opts(self.tol, self.max_iter, self.precond, self.graph_chunk,
                            self.check_symmetry, self.engine, self.solver, self.staged,
                            self.deep, self.nnz_per_lane_F, self.nnz_per_lane_FT,
+                           self.lanes_x, self.lanes_y,
                            self.loop_grid, self.persist_grid, self.equil_sweeps)
 
 
@@ -250,9 +253,10 @@ def qcpd_get_diagnostics(h: Handle):
 
 
 def qcpd_profile_kernels(h: Handle, reps: int = 50):
-    """Average launch duration (ms) of the two LSQR-iteration kernels of the JVP:
-    (k_loop_F: the product with F over CSR rows, k_loop_FT: the fused product with F')."""
-    out = (ctypes.c_float * 2)()
+    """Average durations (ms) of the LSQR-iteration launches of the JVP: [the product with F,
+    the product with F' (all its launches), its first launch alone, its second launch alone
+    (0 when it has one)]."""
+    out = (ctypes.c_float * 4)()
     with torch.cuda.device(h.device):
         st = _lib().qcpd_profile_kernels(h.ptr, int(reps), out)
     if st < 0:

@@ -150,6 +150,8 @@ qcpd_status check_opts(const qcpd_opts *o) {
         o->staged < QCPD_CHOICE_AUTO || o->staged > QCPD_CHOICE_ON ||
         o->deep < QCPD_CHOICE_AUTO || o->deep > QCPD_CHOICE_ON || o->nnz_per_lane_F < 0 ||
         o->nnz_per_lane_FT < 0 || o->loop_grid < 0 || o->loop_grid > kMaxLoopGrid ||
+        o->lanes_x < 0 || o->lanes_x > 64 || (o->lanes_x & (o->lanes_x - 1)) != 0 ||
+        o->lanes_y < 0 || o->lanes_y > 64 || (o->lanes_y & (o->lanes_y - 1)) != 0 ||
         o->persist_grid < 0 || o->equil_sweeps < 0 || o->equil_sweeps > 1000)
         return QCPD_ERR_INVALID_ARG;
     return QCPD_OK;
@@ -158,7 +160,8 @@ qcpd_status check_opts(const qcpd_opts *o) {
 // the launch-layout fields of the options (read at create only)
 bool same_layout(const qcpd_opts &a, const qcpd_opts &b) {
     return a.staged == b.staged && a.deep == b.deep && a.nnz_per_lane_F == b.nnz_per_lane_F &&
-           a.nnz_per_lane_FT == b.nnz_per_lane_FT && a.loop_grid == b.loop_grid &&
+           a.nnz_per_lane_FT == b.nnz_per_lane_FT && a.lanes_x == b.lanes_x &&
+           a.lanes_y == b.lanes_y && a.loop_grid == b.loop_grid &&
            a.persist_grid == b.persist_grid && a.equil_sweeps == b.equil_sweeps;
 }
 
@@ -276,33 +279,43 @@ void launch_loop_F_product(const qcpd_handle *h, const StepArgs &f, hipStream_t 
     else launch_loop_F(h->p, f, h->rg, h->loop_grid_F, s);
 }
 
-// The loop's product with F' (role and vectors in t): one launch of the fused units, or the
-// rows launch followed by the cone launch reading the state the rows launch finalised.
-void launch_loop_FT_product(const qcpd_handle *h, StepArgs t, hipStream_t s) {
+// The loop's product with F' (role and vectors in t): one launch of the fused units, or a
+// rows launch followed by a cone launch reading the state the rows launch finalised. part 0
+// is the first launch, part 1 the second (none for the fused form).
+bool loop_FT_has_second(const qcpd_handle *h) {
+    return h->xs ? h->fg_cones.nunits > 0 : h->psd_split;
+}
+
+void launch_loop_FT_part(const qcpd_handle *h, StepArgs t, int part, hipStream_t s) {
     if (h->xs) {
-        StepArgs r = t;
-        r.extra_slots = h->fg_cones.nunits;
-        launch_loop_xs(h->p, r, h->xg, true, h->loop_grid_T, s);
-        if (h->fg_cones.nunits > 0) {
-            StepArgs c = t;
-            c.st = t.st_next;
-            c.slot0 = h->loop_grid_T;
-            launch_loop_FT_cones(h->p, c, h->fg_cones, h->lds_loop, s);
+        if (part == 0) {
+            t.extra_slots = h->fg_cones.nunits;
+            launch_loop_xs(h->p, t, h->xg, true, h->loop_grid_T, s);
+        } else if (h->fg_cones.nunits > 0) {
+            t.st = t.st_next;
+            t.slot0 = h->loop_grid_T;
+            launch_loop_FT_cones(h->p, t, h->fg_cones, h->lds_loop, s);
         }
         return;
     }
     if (!h->psd_split) {
-        launch_loop_FT(h->p, t, h->fg, h->lds_loop, h->loop_grid_T, s);
+        if (part == 0) launch_loop_FT(h->p, t, h->fg, h->lds_loop, h->loop_grid_T, s);
         return;
     }
     const int g = std::min(h->loop_grid_T, h->fg_rows.nunits);  // the grid the launch uses
-    StepArgs r = t;
-    r.extra_slots = h->fg_psd.nunits;
-    launch_loop_FT(h->p, r, h->fg_rows, h->lds_rows, g, s);
-    StepArgs c = t;
-    c.st = t.st_next;
-    c.slot0 = g;
-    launch_loop_FT_cones(h->p, c, h->fg_psd, h->lds_psd, s);
+    if (part == 0) {
+        t.extra_slots = h->fg_psd.nunits;
+        launch_loop_FT(h->p, t, h->fg_rows, h->lds_rows, g, s);
+    } else {
+        t.st = t.st_next;
+        t.slot0 = g;
+        launch_loop_FT_cones(h->p, t, h->fg_psd, h->lds_psd, s);
+    }
+}
+
+void launch_loop_FT_product(const qcpd_handle *h, const StepArgs &t, hipStream_t s) {
+    launch_loop_FT_part(h, t, 0, s);
+    launch_loop_FT_part(h, t, 1, s);
 }
 
 LsmrArgs lsmr_args(const qcpd_handle *h, const LsqrState *st, LsqrState *st_next) {
@@ -600,8 +613,8 @@ qcpd_status create_impl(qcpd_handle *h, const qcpd_csr *P, const qcpd_csr *A, co
     const int npl_T = o.nnz_per_lane_FT > 0 ? o.nnz_per_lane_FT : 4;
     const bool npl_T_set = o.nnz_per_lane_FT > 0;
     h->fg.deep = deep ? 1 : 0;
-    rg.lx = lanes_for(avg_x, npl_F);
-    rg.ly = lanes_for(avg_y, npl_F);
+    rg.lx = o.lanes_x > 0 ? o.lanes_x : lanes_for(avg_x, npl_F);
+    rg.ly = o.lanes_y > 0 ? o.lanes_y : lanes_for(avg_y, npl_F);
     rg.bx = div_up((long long)n * rg.lx, kBlock);
     rg.by = div_up((long long)(m + 1) * rg.ly, kBlock);
     // cone tables
@@ -740,8 +753,9 @@ qcpd_status create_impl(qcpd_handle *h, const qcpd_csr *P, const qcpd_csr *A, co
             h->psd_split = false;
             // short y rows: few lanes each, several entries per lane (the gathers are cheap
             // from LDS; measured on the n = 20 000 workload: 2 lanes of ~5 entries beat 8 of ~1)
-            h->xg.lx = lanes_for(avg_x, npl_F);
-            h->xg.ly = lanes_for(avg_y, 2 * npl_F);
+            h->xg.lx = o.lanes_x > 0 ? o.lanes_x : lanes_for(avg_x, npl_F);
+            h->xg.ly = o.lanes_y > 0 ? o.lanes_y : lanes_for(avg_y, 2 * npl_F);
+            h->xg.deep = o.deep == QCPD_CHOICE_ON ? 1 : 0;
             h->xg.bxw = div_up((long long)n * h->xg.lx, kWave);
             h->xg.byw = div_up((long long)(m + 1) * h->xg.ly, kWave);
             h->fg_cones = h->fg;
@@ -1192,10 +1206,13 @@ qcpd_status qcpd_profile_kernels(qcpd_handle *h, int32_t reps, float *ms_out) {
     StepArgs t = a;
     t.in = h->u; t.out = h->scratch; t.do_pre = 1; t.out_is_v = 1;
     set_baked(h, t);
-    for (int kid = 0; kid < 2; ++kid) {
+    ms_out[3] = 0.f;
+    for (int kid = 0; kid < 4; ++kid) {
+        if (kid == 3 && !loop_FT_has_second(h)) break;
         auto launch = [&]() {
             if (kid == 0) launch_loop_F_product(h, f, s);
-            else launch_loop_FT_product(h, t, s);
+            else if (kid == 1) launch_loop_FT_product(h, t, s);
+            else launch_loop_FT_part(h, t, kid - 2, s);
         };
         launch();  // warm
         HIPCHK(hipEventRecord(h->ev0, s));

@@ -93,6 +93,7 @@ constexpr int kXsBlock = 1024;
 struct XsGrid {
     int lx, ly;
     int bxw, byw;
+    int deep;  // CSR sums with kDeep entries per lane in flight
     __host__ __device__ int total() const { return bxw + byw; }
 };
 

@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts():
     from paper_2508_17522_amd import _capi as C
     assert ctypes.sizeof(C.qcpd_csr) == 4 * 3 + 4 + 8 * 3  # 3 int32 + padding + 3 pointers
-    assert ctypes.sizeof(C.qcpd_opts) == 8 + 4 * 13 + 4  # 13 int32 fields, tail padding
+    assert ctypes.sizeof(C.qcpd_opts) == 8 + 4 * 15 + 4  # 15 int32 fields, tail padding
     assert ctypes.sizeof(C.qcpd_info) == 4 + 4 + 8 + 8 + 4 + 4
 
 
