@@ -165,6 +165,16 @@ def run_batch(args):
     prec = {"equil": Q.QCPD_PRECOND_EQUIL, "jacobi": Q.QCPD_PRECOND_JACOBI,
             "none": Q.QCPD_PRECOND_NONE}[args.precond]
     opts = Q.Opts(tol=args.tol, precond=prec)
+    tuned = None
+    if not args.no_tune:
+        # the autotuner's lane schedule for this batch (entries per lane of a CSR row), chosen
+        # before the timed region on 100 LSQR iterations per candidate
+        from paper_2508_17522_amd import tune as T
+        hb0, opts, tuned = T.tune_batch_lanes(
+            lambda o: Q.qcpd_batch_create(*batch_create_args(bt), opts=o),
+            (bt["dP"], bt["dA"], bt["dq"], bt["db"]), opts, cache=T.TuneCache())
+        hb0.close()
+        print(f"[bench] tuned batch lanes: {tuned}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
 
     def step(record):
@@ -216,7 +226,8 @@ def run_batch(args):
                    "sum_N": int(sum(q.n + q.m + 1 for q in qs)),
                    "sum_nnz_P": int(sum(q.P.nnz for q in qs)),
                    "sum_nnz_A": int(sum(q.A.nnz for q in qs)), "tol": args.tol,
-                   "precond": args.precond},
+                   "precond": args.precond,
+                   "nnz_per_lane": opts.nnz_per_lane_F or 32, "tuned": tuned},
         "lsqr_iters": {"jvp_median": float(np.median(it_j)), "jvp_max": int(max(it_j)),
                        "vjp_median": float(np.median(it_v)), "vjp_max": int(max(it_v))},
         "max_rel_residual": {"jvp": max(i.rel_residual for i in last["ij"]),
@@ -312,7 +323,7 @@ def launch_times(ms, layout) -> dict:
         out["k_loop_FT_xs" if staged else "k_loop_FT rows form"] = ms[2]
         out["k_loop_FT_cones"] = ms[3]
     else:
-        out["k_loop_FT"] = ms[1]
+        out["k_loop_FT_xs" if staged else "k_loop_FT"] = ms[1]
     return out
 
 
@@ -367,6 +378,8 @@ def main():
                     help="only run a plain copy of MIB MiB (profiler byte-counter reference)")
     ap.add_argument("--kernels-only", type=int, default=0, metavar="REPS",
                     help="only set up the workload and launch each loop kernel REPS times")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="batch workload: keep the library's default lane schedule")
     ap.add_argument("--layout", action="append", default=[], metavar="FIELD=VALUE",
                     help="a launch-layout option of the library (staged, deep, nnz_per_lane_F, "
                          "nnz_per_lane_FT, lanes_x, lanes_y, loop_grid), for tuning runs; "

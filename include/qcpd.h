@@ -344,8 +344,9 @@ typedef struct {
  * computed here, 20 sweeps); opts->solver must be QCPD_SOLVER_LSQR (else
  * QCPD_ERR_INVALID_ARG); graph_chunk is the number of LSQR iterations (of all problems)
  * per captured HIP graph launch, at most 32 here (the host shrinks the launch lists to the
- * running problems between graph launches). The launch-layout fields of opts are not read:
- * the batch has its own schedule (qcpd_batch_set_launch). */
+ * running problems between graph launches). Of the launch-layout fields of opts the batch
+ * reads nnz_per_lane_F only: the stored entries per lane of a CSR row in its loop kernels
+ * (0: 32; the autotuner's choice), fixed at create. */
 qcpd_status qcpd_batch_create(qcpd_batch **hb, const qcpd_batch_layout *layout,
                               const int32_t *P_rowptr, const int32_t *P_colind, const double *P_val,
                               const int32_t *A_rowptr, const int32_t *A_colind, const double *A_val,

@@ -144,8 +144,7 @@ def qcpd_status_str(status: int) -> str:
 def qcpd_opts_default() -> Opts:
     o = C.qcpd_opts()
     _lib().qcpd_opts_default(ctypes.byref(o))
-    return Opts(o.tol, o.max_iter, o.precond, o.graph_chunk, o.check_symmetry, o.engine,
-                o.solver)
+    return Opts(**{name: getattr(o, name) for name, _ in C.qcpd_opts._fields_})
 
 
 def _csr(rowptr, colind, val, nrows, ncols, name):

@@ -96,16 +96,40 @@ class BatchStructure:
     A_rowptr: torch.Tensor
     A_colind: torch.Tensor
     opts: Optional[api.Opts] = None
+    # the lane schedule of the batch's loop kernels is chosen by the autotuner on the first
+    # forward (unless opts fix nnz_per_lane_F or tune is False) and kept for later ones
+    tune: bool = True
+    tuned: Optional[dict] = None
+
+
+def _batch_opts(st: BatchStructure, make, device) -> api.Opts:
+    opts = st.opts or api.qcpd_opts_default()
+    if not st.tune or opts.nnz_per_lane_F > 0:
+        return opts
+    if st.tuned is None:
+        from . import tune as T
+        f64 = dict(dtype=torch.float64, device=device)
+        g = torch.Generator(device=device).manual_seed(0)
+        inputs = (torch.zeros(sum(st.nnz_P), **f64), torch.zeros(sum(st.nnz_A), **f64),
+                  torch.randn(sum(st.n), generator=g, **f64), torch.zeros(sum(st.m), **f64))
+        h, _, report = T.tune_batch_lanes(make, inputs, opts, cache=T.TuneCache())
+        h.close()
+        st.tuned = report
+    return api.Opts(**{**opts.__dict__, "nnz_per_lane_F": st.tuned["nnz_per_lane"]})
 
 
 class _BatchSolutionMap(torch.autograd.Function):
     @staticmethod
     def forward(ctx, P_val, A_val, q, b, x, y, s, structure: BatchStructure):
         st = structure
-        h = B.qcpd_batch_create(st.n, st.m, st.nnz_P, st.nnz_A, st.cones, st.P_rowptr,
-                                st.P_colind, P_val.detach(), st.A_rowptr, st.A_colind,
-                                A_val.detach(), q.detach(), b.detach(), x.detach(), y.detach(),
-                                s.detach(), opts=st.opts)
+
+        def make(o):
+            return B.qcpd_batch_create(st.n, st.m, st.nnz_P, st.nnz_A, st.cones, st.P_rowptr,
+                                       st.P_colind, P_val.detach(), st.A_rowptr, st.A_colind,
+                                       A_val.detach(), q.detach(), b.detach(), x.detach(),
+                                       y.detach(), s.detach(), opts=o)
+
+        h = make(_batch_opts(st, make, P_val.device))
         ctx.handle = h
         return x.detach().clone(), y.detach().clone(), s.detach().clone()
 

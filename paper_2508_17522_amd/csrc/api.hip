@@ -897,6 +897,7 @@ extern "C" {
 
 void qcpd_opts_default(qcpd_opts *o) {
     if (!o) return;
+    *o = qcpd_opts{};  // every launch-layout field 0: the library's choice
     o->tol = 1e-8;
     o->max_iter = 0;
     o->precond = QCPD_PRECOND_JACOBI;

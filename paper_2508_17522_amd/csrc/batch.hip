@@ -773,11 +773,11 @@ qcpd_status upload(qcpd_batch *h, T **dst, const std::vector<T> &src) {
     } while (0)
 
 // Lanes per CSR row of the batched loop: a power of two (<= 64) that gives each lane about
-// kSegPerLane entries (the loop kernels keep that many in flight per lane).
+// `per_lane` stored entries (opts.nnz_per_lane_F, else kSegPerLane; the autotuner picks it).
 constexpr double kSegPerLane = 32.0;
-int lanes_of(double avg) {
+int lanes_of(double avg, double per_lane) {
     int L = 1;
-    while (L < 64 && 2 * L * kSegPerLane <= avg) L *= 2;
+    while (L < 64 && 2 * L * per_lane <= avg) L *= 2;
     return L;
 }
 
@@ -874,6 +874,7 @@ qcpd_status batch_create_impl(qcpd_batch *h, const qcpd_batch_layout *L, const i
     p.Trp = Trp; p.Tci = Tci; p.Tv = Tv; p.Tperm = Tperm;
     p.q = dq_; p.b = db_; p.x = dx_; p.y = dy_; p.s = ds_; p.c = c; p.zy = zy; p.jdiag = jdiag;
     // per-problem lanes, cone tables (global y rows), work units
+    const double spl = h->opts.nnz_per_lane_F > 0 ? (double)h->opts.nnz_per_lane_F : kSegPerLane;
     std::vector<int> lx(B), ly(B), soc_row, soc_dim, psd_row, psd_k, exp_rows, nzv(B), nnv(B);
     std::vector<long long> psd_off;
     std::vector<Unit> units;
@@ -884,8 +885,8 @@ qcpd_status batch_create_impl(qcpd_batch *h, const qcpd_batch_layout *L, const i
     for (int b = 0; b < B; ++b) {
         const qcpd_cones &K = L->cones[b];
         const int nb = L->n[b], mb = L->m[b];
-        lx[b] = lanes_of(nb ? (double)(L->nnz_P[b] + L->nnz_A[b]) / nb : 1.0);
-        ly[b] = lanes_of(mb ? (double)L->nnz_A[b] / mb : 1.0);
+        lx[b] = lanes_of(nb ? (double)(L->nnz_P[b] + L->nnz_A[b]) / nb : 1.0, spl);
+        ly[b] = lanes_of(mb ? (double)L->nnz_A[b] / mb : 1.0, spl);
         nzv[b] = K.n_zero;
         nnv[b] = K.n_nonneg;
         units.push_back({U_XROWS, n_off[b], n_off[b + 1], 0});
@@ -978,8 +979,8 @@ qcpd_status batch_create_impl(qcpd_batch *h, const qcpd_batch_layout *L, const i
     double *partials;
     int *counter;
     RowGrid rg;
-    rg.lx = lanes_of(n ? (double)(pz[B] + az[B]) / n : 1.0);
-    rg.ly = lanes_of(m ? (double)az[B] / m : 1.0);
+    rg.lx = lanes_of(n ? (double)(pz[B] + az[B]) / n : 1.0, spl);
+    rg.ly = lanes_of(m ? (double)az[B] / m : 1.0, spl);
     rg.bx = div_up((long long)n * rg.lx, kBlock);
     rg.by = div_up((long long)(m + 1) * rg.ly, kBlock);
     BALLOC(partials, 3LL * (rg.total() + 1)); BALLOC(counter, 1);

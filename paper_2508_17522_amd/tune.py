@@ -1,8 +1,9 @@
 """Autotuner for the launch shapes of the LSQR loops.
 
 Single problem: the workgroup caps of the two loop launches (qcpd_set_launch) and the number
-of LSQR iterations per captured graph (opts.graph_chunk). Batch: the number of persistent
-workgroups of the batch kernel (qcpd_batch_set_launch).
+of LSQR iterations per captured graph (opts.graph_chunk). Batch: the lane schedule of its loop
+kernels (entries per lane of a CSR row, opts.nnz_per_lane_F, fixed at create: each candidate
+is a new handle) and the number of persistent workgroups (qcpd_batch_set_launch).
 
 Each candidate is timed on the caller's own handle over a fixed number of LSQR iterations
 (tolerance 0, so every candidate does the same work), best of `reps`. Results are cached in a
@@ -154,3 +155,45 @@ def tune_batch(hb: BatchHandle, inputs, opts: Opts, *, iters: int = 100, reps: i
     if cache is not None:
         cache.put(key, out)
     return dict(out, cached=False)
+
+
+def tune_batch_lanes(make, inputs, opts: Opts, *, candidates: Iterable[int] = (8, 16, 32, 64),
+                     iters: int = 100, reps: int = 2, cache: Optional[TuneCache] = None,
+                     force: bool = False):
+    """Pick the batch's entries per lane of a CSR row (opts.nnz_per_lane_F). `make(opts)`
+    creates the batch handle for given options (the candidates differ at create); `inputs` =
+    (dP, dA, dq, db) of a JVP. Every candidate runs `iters` LSQR iterations per problem
+    (tolerance 0). Returns (handle created with the chosen options, those options, report);
+    the other candidates' handles are closed."""
+    best_h, report = None, None
+    probe = make(opts)
+    sN = sum(probe.n) + sum(probe.m) + probe.nprob
+    key = shape_key("batch_lanes", probe.device, sN, sum(probe.nnzP) + 2 * sum(probe.nnzA),
+                    f"|B2^{_bucket(probe.nprob)}|prec{opts.precond}")
+    hit = cache.get(key) if (cache is not None and not force) else None
+    if hit:
+        chosen = Opts(**{**opts.__dict__, "nnz_per_lane_F": hit["nnz_per_lane"]})
+        if hit["nnz_per_lane"] == opts.nnz_per_lane_F:
+            return probe, chosen, dict(hit, cached=True)
+        probe.close()
+        return make(chosen), chosen, dict(hit, cached=True)
+    probe.close()
+    timing = Opts(**{**opts.__dict__, "tol": 0.0, "max_iter": iters})
+    results = []
+    for spl in candidates:
+        o = Opts(**{**timing.__dict__, "nnz_per_lane_F": int(spl)})
+        hb = make(o)
+        best = math.inf
+        for _ in range(reps):
+            *_, infos, _ = qcpd_batch_jvp(hb, *inputs)
+            best = min(best, infos[0].ms_total)
+        hb.close()
+        results.append((best, int(spl)))
+    results.sort()
+    ms, spl = results[0]
+    chosen = Opts(**{**opts.__dict__, "nnz_per_lane_F": spl})
+    report = dict(nnz_per_lane=spl, ms=ms, tried={str(s_): t for t, s_ in results})
+    if cache is not None:
+        cache.put(key, report)
+    best_h = make(chosen)
+    return best_h, chosen, dict(report, cached=False)

@@ -120,6 +120,10 @@ def transpose_slots(M: sp.csr_matrix) -> np.ndarray:
     rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(M.indptr))
     cols = M.indices.astype(np.int64)
     key = rows * n + cols
+    if key.size and bool(np.all(key[1:] > key[:-1])):  # canonical CSR: keys ascending
+        if key.size == n * n:  # every entry stored: slot of (i, j) is i n + j
+            return cols * n + rows
+        return np.searchsorted(key, cols * n + rows)
     tkey = cols * n + rows
     order = np.argsort(key)
     pos = np.searchsorted(key[order], tkey)

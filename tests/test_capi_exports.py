@@ -42,3 +42,21 @@ def test_status_strings_without_gpu():
     lib = _capi.load()
     assert lib.qcpd_status_str(0) == b"ok"
     assert b"NaN" in lib.qcpd_status_str(-5)
+
+
+def test_default_options_without_gpu():
+    """qcpd_opts_default fills every field: the documented defaults, and 0 (the library's
+    choice) in each launch-layout field, whatever the caller's struct held before."""
+    from paper_2508_17522_amd import _capi as C
+    if not os.path.exists(C.LIB_PATH):
+        pytest.skip("library not built")
+    lib = C.load()
+    o = C.qcpd_opts()
+    ctypes.memset(ctypes.byref(o), 0x5A, ctypes.sizeof(o))
+    lib.qcpd_opts_default(ctypes.byref(o))
+    assert (o.tol, o.max_iter, o.precond, o.graph_chunk, o.check_symmetry, o.engine,
+            o.solver) == (1e-8, 0, C.QCPD_PRECOND_JACOBI, 128, 1, C.QCPD_ENGINE_AUTO,
+                          C.QCPD_SOLVER_LSQR)
+    for name in ("staged", "deep", "nnz_per_lane_F", "nnz_per_lane_FT", "lanes_x", "lanes_y",
+                 "loop_grid", "persist_grid", "equil_sweeps"):
+        assert getattr(o, name) == 0, name

@@ -74,10 +74,12 @@ def normwise_only(outs, refs):
     return max(errors(a, r)[0] for a, r in zip(outs, refs))
 
 
-def single(q, tol, precond):
+def single(q, tol, precond, model=None):
     t = to_device(q)
     h = Q.qcpd_create(t["P"], t["A"], t["q"], t["b"], cones_of(q), t["x"], t["y"], t["s"],
                       opts=Q.Opts(tol=tol, precond=precond))
+    if model is not None:
+        model.install(h)
     dx, dy, ds, i1, s1 = Q.qcpd_jvp(h, t["dP"], t["dA"], t["dq"], t["db"])
     dP, dA, dq, db, i2, s2 = Q.qcpd_vjp(h, t["gx"], t["gy"], t["gs"])
     h.close()
@@ -101,6 +103,7 @@ def check_single(q, precond, floor=1e-10):
     assert t1 == Q.QCPD_OK and t2 == Q.QCPD_OK
     print(f"[{q.name}] forward error at tol 1e-8: JVP {normwise_only(jv8, rj):.2e}, "
           f"VJP {normwise_only(vj8, rv):.2e}", flush=True)
+    return rj, rv
 
 
 def test_mixed_qcp_full_size_elementwise():
@@ -108,8 +111,22 @@ def test_mixed_qcp_full_size_elementwise():
 
 
 def test_precond_family_member_elementwise():
+    """A held-out member of the n = 2 000 family with EQUIL, then with the committed learned
+    model (trained on members 0..999) at the benchmark tolerance: its final error against
+    the dense solve."""
+    q = qcpgen.precond_family(20000)
     # the recomputed JVP residual of this instance stalls near 3e-10
-    check_single(qcpgen.precond_family(20000), Q.QCPD_PRECOND_EQUIL, floor=1e-9)
+    (rj, rv) = check_single(q, Q.QCPD_PRECOND_EQUIL, floor=1e-9)
+    import os
+    model = Q.LearnedModel.load(os.path.join(os.path.dirname(Q.__file__), "weights",
+                                             "precond_family_mlp"))
+    jv, vj, (i1, s1, i2, s2) = single(q, 1e-8, Q.QCPD_PRECOND_LEARNED, model)
+    assert s1 == Q.QCPD_OK and s2 == Q.QCPD_OK
+    assert not (i1.flags & Q.QCPD_FLAG_FALLBACK) and not (i2.flags & Q.QCPD_FLAG_FALLBACK)
+    ej, ev = normwise_only(jv, rj), normwise_only(vj, rv)
+    print(f"[{q.name}] learned model, tol 1e-8: iters {i1.iters} / {i2.iters}, final error "
+          f"JVP {ej:.2e}, VJP {ev:.2e}", flush=True)
+    assert max(ej, ev) <= 1e-5  # EQUIL at the same tolerance: 1.8e-9 / 1.7e-7
 
 
 def test_large_psd_soc_shape_reduced_elementwise():

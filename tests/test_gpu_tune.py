@@ -116,3 +116,38 @@ def test_batch_grid_agrees_and_tunes(tmp_path):
     for a, b in zip(out[:3], ref[:3]):
         assert torch.equal(a, b)
     hb.close()
+
+
+def test_batch_lane_schedule_tunes_and_agrees(tmp_path):
+    """The batch's entries per lane (a create-time choice): every candidate gives the same
+    derivative up to the order of sums; the tuner returns a handle built with its choice,
+    and the cache hands the same choice back."""
+    qs = small_batch()
+    bt = batch_to_device(qs)
+    args = batch_create_args(bt)
+    inputs = (bt["dP"], bt["dA"], bt["dq"], bt["db"])
+    refs = {}
+    for spl in (4, 32, 128):
+        hb = Q.qcpd_batch_create(*args, opts=Q.Opts(tol=1e-12, nnz_per_lane_F=spl))
+        out = Q.qcpd_batch_jvp(hb, *inputs)
+        hb.close()
+        assert out[4] == Q.QCPD_OK
+        refs[spl] = out[:3]
+    for spl in (4, 128):
+        d = max(rel(a, b) for a, b in zip(refs[spl], refs[32]))
+        print(f"entries per lane {spl} vs 32: {d:.2e}", flush=True)
+        assert d <= 1e-9
+    cache = T.TuneCache(str(tmp_path / "lanes.json"))
+    make = lambda o: Q.qcpd_batch_create(*args, opts=o)
+    hb, o, r = T.tune_batch_lanes(make, inputs, Q.Opts(tol=1e-12), candidates=(4, 32, 128),
+                                  iters=30, reps=1, cache=cache)
+    print("lanes tuned", r, flush=True)
+    assert not r["cached"] and r["nnz_per_lane"] in (4, 32, 128)
+    assert o.nnz_per_lane_F == r["nnz_per_lane"] and o.tol == 1e-12
+    out = Q.qcpd_batch_jvp(hb, *inputs)
+    assert out[4] == Q.QCPD_OK
+    assert max(rel(a, b) for a, b in zip(out[:3], refs[32])) <= 1e-9
+    hb.close()
+    hb2, o2, r2 = T.tune_batch_lanes(make, inputs, Q.Opts(tol=1e-12), cache=cache)
+    assert r2["cached"] and o2.nnz_per_lane_F == r["nnz_per_lane"]
+    hb2.close()
