@@ -31,14 +31,16 @@ METRIC = "JVP+VJP solves/sec at 1e-8 rel. residual; LSQR iters & HBM GB/s vs pla
 HBM_PEAK_GBS = 8000.0
 
 
-def kernel_bytes(q, which: str) -> float:
+def kernel_bytes(q, which: str, index16: bool = False) -> float:
     """Algorithmic bytes of one launch of an LSQR-iteration kernel (JVP configuration):
-    every CSR stream once (8 B value + 4 B column per entry, 4 B per row pointer) and every
-    vector it must read or write once."""
+    every CSR stream once (8 B value + 4 B column per entry, 2 B columns for P and A where the
+    staged kernels read 16-bit copies, 4 B per row pointer) and every vector it must read or
+    write once."""
     n, m = q.n, q.m
     N = n + m + 1
     nnzP, nnzA = q.P.nnz, q.A.nnz
-    csr = 12.0 * (nnzP + 2 * nnzA) + 4.0 * (2 * n + m + 3)
+    col = 2.0 if index16 else 4.0
+    csr = (8.0 + col) * (nnzP + nnzA) + 12.0 * nnzA + 4.0 * (2 * n + m + 3)
     if which == "k_loop_F":
         # in, scale, J-input wy, q, b, out read+write, LSQR x and w read+write
         vec = 8.0 * (N + N + m + n + m + 2 * N + 4 * N)
@@ -315,6 +317,11 @@ BYTES_OF = {"k_loop_F": "k_loop_F", "k_loop_F_xs": "k_loop_F", "k_loop_FT": "k_l
             "k_loop_FT_cones": "k_loop_FT_cones"}
 
 
+def launch_bytes(q, name, layout) -> float:
+    """The byte model of a launch; the staged kernels read 16-bit column indices of P, A."""
+    return kernel_bytes(q, BYTES_OF[name], index16=name.endswith("_xs"))
+
+
 def launch_times(ms, layout) -> dict:
     """The launches of one iteration by kernel, from qcpd_profile_kernels' four durations."""
     staged = layout["staged"] == 1
@@ -346,7 +353,7 @@ def run_kernels_only(args):
     h.close()
     torch.cuda.synchronize()
     us = {k: v * 1e3 for k, v in launch_times(ms, layout).items()}
-    nb = {k: kernel_bytes(q, BYTES_OF[k]) for k in us}
+    nb = {k: launch_bytes(q, k, layout) for k in us}
     gbs = {k: nb[k] / us[k] / 1e3 for k in us}
     print(json.dumps({"kernels_only": {"workload": q.name, "reps": args.kernels_only,
                                        "layout": layout,
@@ -473,7 +480,7 @@ def main():
     iters_total = rec[-1]["ij"].iters + rec[-1]["iv"].iters
     times = launch_times(ms, layout)
     dom_name = max(times, key=times.get)
-    nbytes = kernel_bytes(q, BYTES_OF[dom_name])
+    nbytes = launch_bytes(q, dom_name, layout)
     achieved = nbytes / (times[dom_name] * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
@@ -481,7 +488,7 @@ def main():
                 "kernel": dom_name, "avg_launch_us": round(times[dom_name] * 1e3, 3),
                 "bytes_per_launch": int(nbytes),
                 "all_kernels_us": {k: round(v * 1e3, 3) for k, v in times.items()},
-                "frac_by_kernel": {k: round(kernel_bytes(q, BYTES_OF[k]) / (v * 1e-3) / 1e9
+                "frac_by_kernel": {k: round(launch_bytes(q, k, layout) / (v * 1e-3) / 1e9
                                             / HBM_PEAK_GBS, 4) for k, v in times.items()},
                 "us_per_iteration": round((ms[0] + ms[1]) * 1e3, 3)}
 

@@ -115,7 +115,7 @@ typedef struct {
                              20 000), AUTO where it fits on large problems                   */
     int32_t deep;         /* QCPD_CHOICE_*: deep CSR sums (16 entries per lane in flight) in
                              the fused product with F' (AUTO: problems whose CSR rows
-                             outnumber a launch's threads) and, ON only, in the staged kernels */
+                             outnumber a launch's threads)                                   */
     int32_t nnz_per_lane_F;   /* stored entries per lane of a CSR row, product with F (2)    */
     int32_t nnz_per_lane_FT;  /* the same, fused product with F' (4; deep sums: about 25)    */
     int32_t lanes_x;      /* lanes per x row (P and A' rows) in the product with F and the
@@ -238,9 +238,11 @@ qcpd_status qcpd_set_launch(qcpd_handle *h, int32_t grid_F, int32_t grid_FT);
 qcpd_status qcpd_get_launch(qcpd_handle *h, int32_t *out);
 
 /* The launch layout qcpd_create chose (the options' QCPD_CHOICE_AUTO resolved). out [host]
- * 5 entries: 1 if the loop products stage the input's x part in LDS, 1 if the fused product
- * with F' uses deep CSR sums, 1 if its PSD cones run in a launch of their own, and the lanes
- * per CSR row of the x rows and of the y rows in the product with F. */
+ * 6 entries: 1 if the loop products stage the input's x part in LDS, 1 if the fused product
+ * with F' uses deep CSR sums, 1 if its PSD cones run in a launch of their own, the lanes
+ * per CSR row of the x rows and of the y rows in the product with F, and 1 if the staged
+ * products read 16-bit copies of P's and A's column indices (n <= 65 536; 2 bytes per stored
+ * entry instead of 4, the copies held by the handle). */
 qcpd_status qcpd_get_layout(qcpd_handle *h, int32_t *out);
 
 /* ---------------------------------------------------------------------------------------

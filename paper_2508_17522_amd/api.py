@@ -292,12 +292,13 @@ def qcpd_get_launch(h: Handle):
 
 
 def qcpd_get_layout(h: Handle) -> dict:
-    """The launch layout chosen at create: staged, deep, psd_split, lanes_x, lanes_y."""
-    out = (C.c_int32 * 5)()
+    """The launch layout chosen at create: staged, deep, psd_split, lanes_x, lanes_y,
+    index16."""
+    out = (C.c_int32 * 6)()
     st = _lib().qcpd_get_layout(h.ptr, out)
     if st < 0:
         raise QCPDError(st, "qcpd_get_layout")
-    return dict(zip(("staged", "deep", "psd_split", "lanes_x", "lanes_y"), tuple(out)))
+    return dict(zip(("staged", "deep", "psd_split", "lanes_x", "lanes_y", "index16"), tuple(out)))
 
 
 def qcpd_destroy(h: Handle):

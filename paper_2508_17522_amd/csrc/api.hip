@@ -746,7 +746,7 @@ qcpd_status create_impl(qcpd_handle *h, const qcpd_csr *P, const qcpd_csr *A, co
         hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device);
         hipDeviceGetAttribute(&h->ncu, hipDeviceAttributeMultiprocessorCount, h->device);
         const int ncone = (int)(units.size() - row_units.size());
-        const bool fits = n > 0 && xs_lds_bytes(n) + kXsStaticLds <= lds_max &&
+        const bool fits = n > 0 && n < 65536 && xs_lds_bytes(n) + kXsStaticLds <= lds_max &&
                           ncone <= kMaxLoopGrid / 2 && h->ncu > 0;
         h->xs = fits && (o.staged == QCPD_CHOICE_ON || (o.staged == QCPD_CHOICE_AUTO && large));
         if (h->xs) {
@@ -755,7 +755,15 @@ qcpd_status create_impl(qcpd_handle *h, const qcpd_csr *P, const qcpd_csr *A, co
             // from LDS; measured on the n = 20 000 workload: 2 lanes of ~5 entries beat 8 of ~1)
             h->xg.lx = o.lanes_x > 0 ? o.lanes_x : lanes_for(avg_x, npl_F);
             h->xg.ly = o.lanes_y > 0 ? o.lanes_y : lanes_for(avg_y, 2 * npl_F);
-            h->xg.deep = o.deep == QCPD_CHOICE_ON ? 1 : 0;
+            // 16-bit column indices for P and A (their columns index x, n < 65 536 here):
+            // 2 bytes less per stored entry
+            unsigned short *pc, *ac;
+            ALLOC(pc, P->nnz);
+            ALLOC(ac, A->nnz);
+            launch_to_u16(p.Pci, pc, P->nnz, st);
+            launch_to_u16(p.Aci, ac, A->nnz, st);
+            p.Pc16 = pc;
+            p.Ac16 = ac;
             h->xg.bxw = div_up((long long)n * h->xg.lx, kWave);
             h->xg.byw = div_up((long long)(m + 1) * h->xg.ly, kWave);
             h->fg_cones = h->fg;
@@ -1143,6 +1151,7 @@ qcpd_status qcpd_get_layout(qcpd_handle *h, int32_t *out) {
     out[2] = h->psd_split ? 1 : 0;
     out[3] = h->xs ? h->xg.lx : h->rg.lx;
     out[4] = h->xs ? h->xg.ly : h->rg.ly;
+    out[5] = h->xs ? 1 : 0;
     return QCPD_OK;
 }
 

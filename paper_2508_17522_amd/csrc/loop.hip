@@ -309,16 +309,31 @@ __device__ inline double csr_dot_deep(const int *col, const double *val, int k0,
     return acc;
 }
 
-// the staged kernels' sums: four entries per lane in flight, or eight (DEEP; sixteen would
-// exceed the registers of a 1024-thread workgroup). Measured on the n = 20 000 workload:
-// eight in flight, masked instead of clamped loads past a row's end, and non-temporal loads
-// of the CSR streams (to keep the gathered vectors in L2) gain nothing or lose (40 %).
-template <bool DEEP>
-__device__ inline double csr_dot_x(const int *col, const double *val, int k0, int k1, int lane,
-                                   int L, const double *x, const double *sc, int off) {
-    if (!DEEP) return csr_dot(col, val, k0, k1, lane, L, x, sc, off);
-    return sc ? csr_dot_deep<true, 8>(col, val, k0, k1, lane, L, x, sc, off)
-              : csr_dot_deep<false, 8>(col, val, k0, k1, lane, L, x, sc, off);
+// The staged kernels' sums with the input in LDS: as csr_dot4 (no scale), with 16-bit column
+// indices (two bytes less per stored entry than the 32-bit CSR). Measured on the
+// n = 20 000 workload: eight entries per lane in flight instead of four, masked instead of
+// clamped loads past a row's end, and non-temporal loads of the CSR streams (to keep the
+// gathered vectors in L2) gain nothing or lose (up to 40 %).
+template <class IT>
+__device__ inline double csr_dot_lds(const IT *col, const double *val, int k0, int k1, int lane,
+                                     int L, const double *xs) {
+    double acc = 0.0;
+    for (int k = k0 + lane; k < k1; k += 4 * L) {
+        int j[4];
+        double v[4], xv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int kk = min(k + u * L, k1 - 1);
+            j[u] = (int)col[kk];
+            v[u] = val[kk];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) xv[u] = xs[j[u]];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (k + u * L < k1) acc += v[u] * xv[u];
+    }
+    return acc;
 }
 
 template <bool DEEP>
@@ -1329,7 +1344,7 @@ struct XsPre {
     Fin f;
 };
 
-template <bool FT, bool DEEP>
+template <bool FT>
 __device__ inline void xs_pre(const Problem &p, const StepArgs &a, const Ptrs &q,
                               const double *xs, const XsGrid &g, int wb, int lane64,
                               double in_N_raw, XsPre &r) {
@@ -1342,14 +1357,16 @@ __device__ inline void xs_pre(const Problem &p, const StepArgs &a, const Ptrs &q
     int idx = -1;
     if (xr) {
         if (row < n) {
-            acc = csr_dot_x<DEEP>(p.Pci, p.Pv, p.Prp[row], p.Prp[row + 1], lane, L, xs, nullptr, 0);
+            const int k0 = p.Prp[row], k1 = p.Prp[row + 1];
+            acc = csr_dot_lds(p.Pc16, p.Pv, k0, k1, lane, L, xs);
             const int t0 = p.Trp[row], t1 = p.Trp[row + 1];
-            if (FT) accT = csr_dot_x<DEEP>(p.Tci, q.Tv, t0, t1, lane, L, a.in, q.gsc, n);
-            else accT = csr_dot_x<DEEP>(p.Tci, p.Tv, t0, t1, lane, L, a.wy, nullptr, 0);
+            if (FT) accT = csr_dot(p.Tci, q.Tv, t0, t1, lane, L, a.in, q.gsc, n);
+            else accT = csr_dot4<false>(p.Tci, p.Tv, t0, t1, lane, L, a.wy, nullptr, 0);
             idx = row;
         }
     } else if (row < m) {
-        acc = csr_dot_x<DEEP>(p.Aci, p.Av, p.Arp[row], p.Arp[row + 1], lane, L, xs, nullptr, 0);
+        const int k0 = p.Arp[row], k1 = p.Arp[row + 1];
+        acc = csr_dot_lds(p.Ac16, p.Av, k0, k1, lane, L, xs);
         idx = n + row;
     } else if (!FT && row == m) {
         idx = N - 1;
@@ -1410,7 +1427,7 @@ __device__ inline void xs_post(const Problem &p, const StepArgs &a, const Ctx &c
     if (r.idx < N - 1) s1 += r.coef * r.f.nxs * o;
 }
 
-template <bool FT, bool DEEP>
+template <bool FT>
 __device__ inline void loop_xs_body(const Problem &p, const StepArgs &a, const XsGrid &g,
                                     double *xs) {
     constexpr int kW = kXsBlock / kWave;
@@ -1423,7 +1440,7 @@ __device__ inline void loop_xs_body(const Problem &p, const StepArgs &a, const X
     int wb = blockIdx.x * kW + tid / kWave;
     XsPre r;
     r.idx = -1;
-    if (wb < total) xs_pre<FT, DEEP>(p, a, q, xs, g, wb, lane64, in_N_raw, r);
+    if (wb < total) xs_pre<FT>(p, a, q, xs, g, wb, lane64, in_N_raw, r);
     EntryT<kXsBlock> e;
     entry_issue(a, e);  // after the first rows' loads: the memory counter is in order
     LsqrState S;
@@ -1432,7 +1449,7 @@ __device__ inline void loop_xs_body(const Problem &p, const StepArgs &a, const X
     double s0 = 0.0, s1 = 0.0;
     xs_post<FT>(p, a, c, S, r, s0, s1);
     for (wb += W; wb < total; wb += W) {
-        xs_pre<FT, DEEP>(p, a, q, xs, g, wb, lane64, in_N_raw, r);
+        xs_pre<FT>(p, a, q, xs, g, wb, lane64, in_N_raw, r);
         xs_post<FT>(p, a, c, S, r, s0, s1);
     }
     if (FT && blockIdx.x == 0 && tid == 0) {  // the tau entry
@@ -1446,22 +1463,19 @@ __device__ inline void loop_xs_body(const Problem &p, const StepArgs &a, const X
 
 __global__ __launch_bounds__(kXsBlock) void k_loop_F_xs(Problem p, StepArgs a, XsGrid g) {
     extern __shared__ double xs[];
-    loop_xs_body<false, false>(p, a, g, xs);
+    loop_xs_body<false>(p, a, g, xs);
 }
 
 __global__ __launch_bounds__(kXsBlock) void k_loop_FT_xs(Problem p, StepArgs a, XsGrid g) {
     extern __shared__ double xs[];
-    loop_xs_body<true, false>(p, a, g, xs);
+    loop_xs_body<true>(p, a, g, xs);
 }
 
-__global__ __launch_bounds__(kXsBlock) void k_loop_F_xs_deep(Problem p, StepArgs a, XsGrid g) {
-    extern __shared__ double xs[];
-    loop_xs_body<false, true>(p, a, g, xs);
-}
-
-__global__ __launch_bounds__(kXsBlock) void k_loop_FT_xs_deep(Problem p, StepArgs a, XsGrid g) {
-    extern __shared__ double xs[];
-    loop_xs_body<true, true>(p, a, g, xs);
+// 16-bit copies of column indices below 65 536: P's and A's columns index x, whose n doubles
+// the staged kernels hold in LDS, so n is far below that
+__global__ void k_to_u16(const int *col, unsigned short *out, long long nnz) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nnz) out[i] = (unsigned short)col[i];
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1709,17 +1723,20 @@ void launch_loop_FT_cones(const Problem &p, const StepArgs &a, const FusedGrid &
 
 int xs_lds_bytes(int n) { return (int)sizeof(double) * n; }
 
+void launch_to_u16(const int *col, unsigned short *out, long long nnz, hipStream_t s) {
+    if (nnz > 0)
+        hipLaunchKernelGGL(k_to_u16, dim3((unsigned)((nnz + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                           col, out, nnz);
+}
+
 void set_xs_kernel_lds(int bytes) {
     (void)hipFuncSetAttribute((const void *)k_loop_F_xs, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     (void)hipFuncSetAttribute((const void *)k_loop_FT_xs, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    (void)hipFuncSetAttribute((const void *)k_loop_F_xs_deep, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    (void)hipFuncSetAttribute((const void *)k_loop_FT_xs_deep, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 void launch_loop_xs(const Problem &p, const StepArgs &a, const XsGrid &g, bool ft, int grid,
                     hipStream_t s) {
-    auto k = g.deep ? (ft ? k_loop_FT_xs_deep : k_loop_F_xs_deep) : (ft ? k_loop_FT_xs : k_loop_F_xs);
-    hipLaunchKernelGGL(k, dim3(grid), dim3(kXsBlock), xs_lds_bytes(p.n), s, p, a, g);
+    hipLaunchKernelGGL(ft ? k_loop_FT_xs : k_loop_F_xs, dim3(grid), dim3(kXsBlock), xs_lds_bytes(p.n), s, p, a, g);
 }
 
 void set_seg_kernel_lds(int bytes) {

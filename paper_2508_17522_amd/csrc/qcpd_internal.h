@@ -70,6 +70,7 @@ struct Problem {
     const double *psd_pool;
     const int *psd_lr;              // per cone: the low-rank side of its Jacobian (c, + 256 when
                                     // it is the negative side), or null
+    const unsigned short *Pc16, *Ac16;  // 16-bit copies of Pci and Aci (staged kernels), or null
 };
 
 // Cone-kernel grid: [elementwise | SOC | exp | PSD] block ranges.
@@ -93,7 +94,6 @@ constexpr int kXsBlock = 1024;
 struct XsGrid {
     int lx, ly;
     int bxw, byw;
-    int deep;  // CSR sums with kDeep entries per lane in flight
     __host__ __device__ int total() const { return bxw + byw; }
 };
 
@@ -306,6 +306,7 @@ int xs_lds_bytes(int n);
 void set_xs_kernel_lds(int bytes);
 void launch_loop_xs(const Problem &p, const StepArgs &a, const XsGrid &g, bool ft, int grid,
                     hipStream_t s);
+void launch_to_u16(const int *col, unsigned short *out, long long nnz, hipStream_t s);
 
 // LSMR (lsmr.hip): its scalars beyond the LSQR state block, and the arguments of its
 // per-iteration launch (after the U and V product launches of the LSQR loop kernels)
