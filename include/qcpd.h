@@ -112,7 +112,7 @@ typedef struct {
      * changes results beyond the order of floating-point sums. */
     int32_t staged;       /* QCPD_CHOICE_*: products that stage the input's x part (n doubles)
                              in LDS, one workgroup per CU; ON where it fits (n up to about
-                             20 000), AUTO where it fits on large problems                   */
+                             20 000), AUTO where it fits on large problems with n > 8 192    */
     int32_t deep;         /* QCPD_CHOICE_*: deep CSR sums (16 entries per lane in flight) in
                              the fused product with F' (AUTO: problems whose CSR rows
                              outnumber a launch's threads)                                   */

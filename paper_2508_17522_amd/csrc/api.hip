@@ -740,15 +740,19 @@ qcpd_status create_impl(qcpd_handle *h, const qcpd_csr *P, const qcpd_csr *A, co
             h->lds_psd = h->lds_loop;
         }
         // the x part staged in LDS (k_loop_F_xs, k_loop_FT_xs + k_loop_FT_cones): where n
-        // doubles fit, on large problems unless the options say otherwise; the cone units come
-        // first in the unit table and form the F' product's second launch
+        // doubles fit, on large problems whose x part is too large for the L1 cache to serve
+        // its gathers (above 64 KB; at n = 2 000, 16 KB, the unstaged kernels measured 15 %
+        // faster), unless the options say otherwise; the cone units come first in the unit
+        // table and form the F' product's second launch
         int lds_max = 0;
         hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device);
         hipDeviceGetAttribute(&h->ncu, hipDeviceAttributeMultiprocessorCount, h->device);
         const int ncone = (int)(units.size() - row_units.size());
         const bool fits = n > 0 && n < 65536 && xs_lds_bytes(n) + kXsStaticLds <= lds_max &&
                           ncone <= kMaxLoopGrid / 2 && h->ncu > 0;
-        h->xs = fits && (o.staged == QCPD_CHOICE_ON || (o.staged == QCPD_CHOICE_AUTO && large));
+        const bool beyond_l1 = 8LL * n > 65536;
+        h->xs = fits && (o.staged == QCPD_CHOICE_ON ||
+                         (o.staged == QCPD_CHOICE_AUTO && large && beyond_l1));
         if (h->xs) {
             h->psd_split = false;
             // short y rows: few lanes each, several entries per lane (the gathers are cheap
