@@ -31,16 +31,24 @@ METRIC = "JVP+VJP solves/sec at 1e-8 rel. residual; LSQR iters & HBM GB/s vs pla
 HBM_PEAK_GBS = 8000.0
 
 
-def kernel_bytes(q, which: str, index16: bool = False) -> float:
+def _quads(indptr) -> int:
+    import numpy as np
+    return int((((np.diff(indptr) + 3) // 4) * 4).sum())
+
+
+def kernel_bytes(q, which: str, packed: bool = False) -> float:
     """Algorithmic bytes of one launch of an LSQR-iteration kernel (JVP configuration):
-    every CSR stream once (8 B value + 4 B column per entry, 2 B columns for P and A where the
-    staged kernels read 16-bit copies, 4 B per row pointer) and every vector it must read or
-    write once."""
+    every CSR stream once (8 B value + 4 B column per entry, 4 B per row pointer; where the
+    staged kernels read the packed copies of P and A, 8 B value + 2 B column per entry of rows
+    padded to whole quads) and every vector it must read or write once."""
     n, m = q.n, q.m
     N = n + m + 1
     nnzP, nnzA = q.P.nnz, q.A.nnz
-    col = 2.0 if index16 else 4.0
-    csr = (8.0 + col) * (nnzP + nnzA) + 12.0 * nnzA + 4.0 * (2 * n + m + 3)
+    if packed:
+        pa = 10.0 * (_quads(q.P.indptr) + _quads(q.A.indptr))
+    else:
+        pa = 12.0 * (nnzP + nnzA)
+    csr = pa + 12.0 * nnzA + 4.0 * (2 * n + m + 3)
     if which == "k_loop_F":
         # in, scale, J-input wy, q, b, out read+write, LSQR x and w read+write
         vec = 8.0 * (N + N + m + n + m + 2 * N + 4 * N)
@@ -318,8 +326,8 @@ BYTES_OF = {"k_loop_F": "k_loop_F", "k_loop_F_xs": "k_loop_F", "k_loop_FT": "k_l
 
 
 def launch_bytes(q, name, layout) -> float:
-    """The byte model of a launch; the staged kernels read 16-bit column indices of P, A."""
-    return kernel_bytes(q, BYTES_OF[name], index16=name.endswith("_xs"))
+    """The byte model of a launch; the staged kernels read the packed copies of P and A."""
+    return kernel_bytes(q, BYTES_OF[name], packed=name.endswith("_xs"))
 
 
 def launch_times(ms, layout) -> dict:

@@ -241,8 +241,8 @@ qcpd_status qcpd_get_launch(qcpd_handle *h, int32_t *out);
  * 6 entries: 1 if the loop products stage the input's x part in LDS, 1 if the fused product
  * with F' uses deep CSR sums, 1 if its PSD cones run in a launch of their own, the lanes
  * per CSR row of the x rows and of the y rows in the product with F, and 1 if the staged
- * products read 16-bit copies of P's and A's column indices (n <= 65 536; 2 bytes per stored
- * entry instead of 4, the copies held by the handle). */
+ * products read packed copies of P and A (held by the handle: rows padded to whole quads of
+ * entries, 16-bit column indices, 10 bytes per entry instead of 12). */
 qcpd_status qcpd_get_layout(qcpd_handle *h, int32_t *out);
 
 /* ---------------------------------------------------------------------------------------

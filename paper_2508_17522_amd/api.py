@@ -293,12 +293,12 @@ def qcpd_get_launch(h: Handle):
 
 def qcpd_get_layout(h: Handle) -> dict:
     """The launch layout chosen at create: staged, deep, psd_split, lanes_x, lanes_y,
-    index16."""
+    packed (the staged kernels' packed copies of P and A)."""
     out = (C.c_int32 * 6)()
     st = _lib().qcpd_get_layout(h.ptr, out)
     if st < 0:
         raise QCPDError(st, "qcpd_get_layout")
-    return dict(zip(("staged", "deep", "psd_split", "lanes_x", "lanes_y", "index16"), tuple(out)))
+    return dict(zip(("staged", "deep", "psd_split", "lanes_x", "lanes_y", "packed"), tuple(out)))
 
 
 def qcpd_destroy(h: Handle):

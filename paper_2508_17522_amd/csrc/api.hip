@@ -32,6 +32,7 @@ struct qcpd_handle {
     // (PSD cones, exponential and SOC runs) of the product with F', its second launch
     bool xs = false;
     XsGrid xg{};
+    long long packed_nnz[2] = {0, 0};        // entries of the packed copies of P and A
     FusedGrid fg_cones{};
     int ncu = 0;
     int lds_rows = 0, lds_psd = 0;
@@ -759,15 +760,57 @@ qcpd_status create_impl(qcpd_handle *h, const qcpd_csr *P, const qcpd_csr *A, co
             // from LDS; measured on the n = 20 000 workload: 2 lanes of ~5 entries beat 8 of ~1)
             h->xg.lx = o.lanes_x > 0 ? o.lanes_x : lanes_for(avg_x, npl_F);
             h->xg.ly = o.lanes_y > 0 ? o.lanes_y : lanes_for(avg_y, 2 * npl_F);
-            // 16-bit column indices for P and A (their columns index x, n < 65 536 here):
-            // 2 bytes less per stored entry
-            unsigned short *pc, *ac;
-            ALLOC(pc, P->nnz);
-            ALLOC(ac, A->nnz);
-            launch_to_u16(p.Pci, pc, P->nnz, st);
-            launch_to_u16(p.Aci, ac, A->nnz, st);
-            p.Pc16 = pc;
-            p.Ac16 = ac;
+            // packed copies of P and A (their columns index x, n < 65 536 here): rows padded to
+            // whole quads, 16-bit columns, so a lane reads four entries with three loads. The
+            // row pointers are checked first (from 0 to nnz, non-decreasing); if they are not,
+            // the validation below rejects the matrix and nothing is packed.
+            const int *rps[2] = {p.Prp, p.Arp};
+            const int *cis[2] = {p.Pci, p.Aci};
+            const double *vs[2] = {p.Pv, p.Av};
+            const int rows[2] = {n, m};
+            const long long nnzs[2] = {P->nnz, A->nnz};
+            std::vector<int> hrp[2], hrp4[2];
+            for (int w = 0; w < 2; ++w) {
+                hrp[w].resize(rows[w] + 1);
+                HIPCHK(hipMemcpyAsync(hrp[w].data(), rps[w], sizeof(int) * (rows[w] + 1),
+                                      hipMemcpyDeviceToHost, st));
+            }
+            HIPCHK(hipStreamSynchronize(st));
+            bool ok = true;
+            for (int w = 0; w < 2 && ok; ++w) {
+                const std::vector<int> &r = hrp[w];
+                ok = r[0] == 0 && r[rows[w]] == nnzs[w];
+                long long tot = 0;
+                for (int i = 0; i < rows[w] && ok; ++i) {
+                    ok = r[i + 1] >= r[i];
+                    tot += (r[i + 1] - r[i] + 3) / 4 * 4;
+                }
+                ok = ok && tot < (1LL << 31);
+                if (ok) {
+                    hrp4[w].assign(rows[w] + 1, 0);
+                    for (int i = 0; i < rows[w]; ++i)
+                        hrp4[w][i + 1] = hrp4[w][i] + (r[i + 1] - r[i] + 3) / 4 * 4;
+                }
+            }
+            h->xs = ok;
+            for (int w = 0; w < 2 && ok; ++w) {
+                int *rp4;
+                unsigned short *c4;
+                double *v4;
+                ALLOC(rp4, rows[w] + 1);
+                ALLOC(c4, std::max(hrp4[w][rows[w]], 4));
+                ALLOC(v4, std::max(hrp4[w][rows[w]], 4));
+                HIPCHK(hipMemcpyAsync(rp4, hrp4[w].data(), sizeof(int) * (rows[w] + 1),
+                                      hipMemcpyHostToDevice, st));
+                launch_pack_rows(rps[w], cis[w], vs[w], rp4, c4, v4, rows[w], st);
+                HIPCHK(hipStreamSynchronize(st));  // before the host vector of the copy goes
+                (w == 0 ? p.Prp4 : p.Arp4) = rp4;
+                (w == 0 ? p.Pc4 : p.Ac4) = c4;
+                (w == 0 ? p.Pv4 : p.Av4) = v4;
+                h->packed_nnz[w] = hrp4[w][rows[w]];
+            }
+        }
+        if (h->xs) {
             h->xg.bxw = div_up((long long)n * h->xg.lx, kWave);
             h->xg.byw = div_up((long long)(m + 1) * h->xg.ly, kWave);
             h->fg_cones = h->fg;

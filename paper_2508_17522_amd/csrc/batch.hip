@@ -975,7 +975,9 @@ qcpd_status batch_create_impl(qcpd_batch *h, const qcpd_batch_layout *L, const i
     p.n_psd = (int)psd_row.size(); p.psd_row = d_psd_row; p.psd_k = d_psd_k; p.psd_off = d_psd_off;
     p.psd_pool = pool;
     p.psd_lr = nullptr;  // the batch kernels apply the full form
-    p.Pc16 = p.Ac16 = nullptr;
+    p.Prp4 = p.Arp4 = nullptr;
+    p.Pc4 = p.Ac4 = nullptr;
+    p.Pv4 = p.Av4 = nullptr;
     // Px, c, x'Px per problem, z_y, cone factors, scales
     double *partials;
     int *counter;

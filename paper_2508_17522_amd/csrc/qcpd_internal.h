@@ -70,7 +70,11 @@ struct Problem {
     const double *psd_pool;
     const int *psd_lr;              // per cone: the low-rank side of its Jacobian (c, + 256 when
                                     // it is the negative side), or null
-    const unsigned short *Pc16, *Ac16;  // 16-bit copies of Pci and Aci (staged kernels), or null
+    // packed copies of P and A for the staged kernels (or null): rows padded to whole quads of
+    // entries (row starts Prp4 / Arp4, multiples of 4), 16-bit columns, padding 0 and 0.0
+    const int *Prp4, *Arp4;
+    const unsigned short *Pc4, *Ac4;
+    const double *Pv4, *Av4;
 };
 
 // Cone-kernel grid: [elementwise | SOC | exp | PSD] block ranges.
@@ -306,7 +310,8 @@ int xs_lds_bytes(int n);
 void set_xs_kernel_lds(int bytes);
 void launch_loop_xs(const Problem &p, const StepArgs &a, const XsGrid &g, bool ft, int grid,
                     hipStream_t s);
-void launch_to_u16(const int *col, unsigned short *out, long long nnz, hipStream_t s);
+void launch_pack_rows(const int *rp, const int *ci, const double *v, const int *rp4,
+                      unsigned short *c4, double *v4, int rows, hipStream_t s);
 
 // LSMR (lsmr.hip): its scalars beyond the LSQR state block, and the arguments of its
 // per-iteration launch (after the U and V product launches of the LSQR loop kernels)

@@ -74,6 +74,15 @@ def normwise_only(outs, refs):
     return max(errors(a, r)[0] for a, r in zip(outs, refs))
 
 
+def status_matches_residual(tol, *calls):
+    """A call reports OK (flags bit 0 clear) exactly when its recomputed relative residual
+    meets tol, whether the method stopped on its own test (refinement resumes used up, the
+    residual at its rounding floor) or at its iteration cap."""
+    for info, st in calls:
+        ok = info.rel_residual <= tol
+        assert (st == Q.QCPD_OK) == ok and bool(info.flags & 1) == (not ok), (tol, info, st)
+
+
 def single(q, tol, precond, model=None):
     t = to_device(q)
     h = Q.qcpd_create(t["P"], t["A"], t["q"], t["b"], cones_of(q), t["x"], t["y"], t["s"],
@@ -86,13 +95,15 @@ def single(q, tol, precond, model=None):
     cpu = lambda v: v.cpu().numpy()
     print(f"[{q.name} tol {tol:g}] iters {i1.iters} / {i2.iters}, rel. residuals "
           f"{i1.rel_residual:.2e} / {i2.rel_residual:.2e}, status {s1} / {s2}", flush=True)
+    status_matches_residual(tol, (i1, s1), (i2, s2))
     return (cpu(dx), cpu(dy), cpu(ds)), (cpu(dP), cpu(dA), cpu(dq), cpu(db)), (i1, s1, i2, s2)
 
 
 def check_single(q, precond, floor=1e-10):
     """`floor`: the recomputed relative residual the solve at tol 1e-12 must reach (the
     rounding floor of the residual of an ill-conditioned instance can lie above 1e-12; the
-    library then reports NOT_CONVERGED, and the outputs must still meet the bar)."""
+    library then reports NOT_CONVERGED, checked by `single`, and the outputs must still meet
+    the bar)."""
     (rj, rv) = D.jvp_vjp_dense(q, q.dP, q.dA, q.dq, q.db, q.gx, q.gy, q.gs)
     yb = y_blocks(q.cones)
     jv, vj, (i1, s1, i2, s2) = single(q, 1e-12, precond)
@@ -149,6 +160,10 @@ def test_batch_of_64_family_members_elementwise():
         print(f"[batch tol {tol:g}] median iters {np.median([i.iters for i in i1])} / "
               f"{np.median([i.iters for i in i2])}, worst rel. residual "
               f"{max(i.rel_residual for i in i1 + i2):.2e}, status {s1} / {s2}", flush=True)
+        for infos, st in ((i1, s1), (i2, s2)):
+            status_matches_residual(tol, *[(i, Q.QCPD_OK if not (i.flags & 1) else
+                                            Q.QCPD_WARN_NOT_CONVERGED) for i in infos])
+            assert (st == Q.QCPD_OK) == all(i.rel_residual <= tol for i in infos)
         parts = [split(v.cpu().numpy(), s) for v, s in
                  ((dx, bt["n"]), (dy, bt["m"]), (ds, bt["m"]), (dP, bt["nnz_P"]),
                   (dA, bt["nnz_A"]), (dq, bt["n"]), (db, bt["m"]))]
