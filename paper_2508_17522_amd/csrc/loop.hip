@@ -723,34 +723,27 @@ __device__ inline void psd_apply_kp(int k, const PsdLds &L, double *sm, const do
     __syncthreads();
 }
 
-// As mfma_product for a (16 MT) x (4 KS) times (4 KS) x (16 NT) product.
-template <int MT, int NT, int KS, class AF, class BF, class EPI>
-__device__ inline void mfma_mnk(AF af, BF bf, EPI epi) {
-    constexpr int CH = KS % 8 == 0 ? 8 : KS % 6 == 0 ? 6 : 4;
-    static_assert(KS % CH == 0 && CH % 2 == 0, "a chunk must divide the steps into pairs");
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    const int li = lane & 15, lk = lane >> 4;
-#pragma unroll 1
-    for (int t = wave; t < MT * NT; t += kBlock / kWave) {
-        const int i0 = (t / NT) * 16, j0 = (t % NT) * 16;
-        dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 1
-        for (int s0 = 0; s0 < KS; s0 += CH) {
-            double av[CH], bv[CH];
+// The K = 4 KS sum of one 16 x 16 tile, lanes and accumulator entries as in mfma_product:
+// all 2 KS operands are loaded before the first product (one wave per SIMD: nothing else
+// would hide the LDS latency), even and odd steps in two accumulators.
+template <int KS, class AF, class BF>
+__device__ inline dbl4 mfma_tile(int i0, int j0, AF af, BF bf) {
+    const int lane = threadIdx.x & (kWave - 1), li = lane & 15, lk = lane >> 4;
+    double av[KS], bv[KS];
 #pragma unroll
-            for (int s = 0; s < CH; ++s) {
-                const int kk = 4 * (s0 + s) + lk;
-                av[s] = af(i0 + li, kk);
-                bv[s] = bf(kk, j0 + li);
-            }
-#pragma unroll
-            for (int s = 0; s < CH; s += 2) {
-                acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], bv[s], acc0, 0, 0, 0);
-                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s + 1], bv[s + 1], acc1, 0, 0, 0);
-            }
-        }
-        epi(i0 + lk, j0 + li, acc0 + acc1);
+    for (int s = 0; s < KS; ++s) {
+        av[s] = af(i0 + li, 4 * s + lk);
+        bv[s] = bf(4 * s + lk, j0 + li);
     }
+    dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s + 1 < KS; s += 2) {
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], bv[s], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s + 1], bv[s + 1], acc1, 0, 0, 0);
+    }
+    if constexpr (KS % 2 == 1)
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[KS - 1], bv[KS - 1], acc0, 0, 0, 0);
+    return acc0 + acc1;
 }
 
 // Low-rank form of the same Jacobian, for a cone whose eigenvalues leave c <= 16 on one side
@@ -760,58 +753,74 @@ __device__ inline void mfma_mnk(AF af, BF bf, EPI epi) {
 //   V (Bs o M) V' = E + E' - V_S M_SS V_S',   E = V (Bs o M)[:, S] V_S'
 // (Bs o M is nonzero on the rows or columns of S only), and J[X] = V (B o M) V' equals that
 // sum (S >= 0) or X minus it (V orthogonal). With H = (V'(X V_S)) times Bs[:, S] elementwise,
-// its S x S block halved, and U = V H: J[X] = Z + Z' with Z = U V_S' or X/2 - U V_S'. Four
-// products with one dimension 16: 4 KP^2 16 multiply-adds instead of 4 KP^3. X (symmetric,
-// zero beyond the order) is replaced by Y as in psd_apply_kp; W and H are KP x 16 panels in
-// the T region.
+// its S x S block halved, and U = V H: the sum is U V_S' + V_S U', one product of the
+// KP x 32 panel [U V_S] with [V_S U]'. Three KP x KP x 16 products and that one, on the
+// lower triangle of 16 x 16 tiles only: about 4 KP^2 16 multiply-adds instead of 4 KP^3.
+// X (symmetric, zero beyond the order) is replaced by Y on and below the diagonal (the
+// callers read the lower triangle only; above it X is left as it was, zero beyond the
+// order); W and H are KP x 16 panels in the T region. Waves own whole tiles: the first
+// three products have KP / 16 <= 4 of them, one per wave.
 template <int KP>
 __device__ inline void psd_apply_lr(int k, int c, bool neg, const PsdLds &L, double *sm,
                                     const double *Bg) {
-    constexpr int ld = KP + 1, mat = KP * ld, lc = 17;
+    constexpr int ld = KP + 1, mat = KP * ld, lc = 17, MT = KP / 16, KS = KP / 4;
     static_assert(2 * KP * lc <= mat, "two KP x 16 panels fit in the T region");
+    static_assert(MT <= kBlock / kWave, "one row tile per wave");
     double *X = sm, *W = sm + mat, *H = sm + mat + KP * lc;
     const double *V = sm + 2 * mat, *B = L.b >= 0 ? sm + L.b : nullptr;
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int li = lane & 15, lk = lane >> 4;
     auto vf = [&](int i, int j) { return V[i * ld + j]; };
     auto vt = [&](int i, int j) { return V[j * ld + i]; };
-    auto wf = [&](int i, int j) { return W[i * lc + j]; };
-    auto to_w = [&](int i, int j, const dbl4 &a) {
-        for (int r = 0; r < 4; ++r) W[(i + 4 * r) * lc + j] = a[r];
-    };
-    mfma_mnk<KP / 16, 1, KP / 4>([&](int i, int j) { return X[i * ld + j]; }, vf, to_w);  // W = X V_S
+    if (wave < MT) {  // W = X V_S
+        const dbl4 a = mfma_tile<KS>(16 * wave, 0, [&](int i, int j) { return X[i * ld + j]; }, vf);
+        for (int r = 0; r < 4; ++r) W[(16 * wave + lk + 4 * r) * lc + li] = a[r];
+    }
     __syncthreads();
-    mfma_mnk<KP / 16, 1, KP / 4>(vt, wf, [&](int i, int j, const dbl4 &a) {  // H = Bs' o (V'W)
+    if (wave < MT) {  // H = Bs' o (V'W), the factors read before the products
+        double f[4];
         for (int r = 0; r < 4; ++r) {
-            const int ii = i + 4 * r;
-            double f = 0.0;
-            if (ii < k && j < c) {
+            const int ii = 16 * wave + lk + 4 * r;
+            f[r] = 0.0;
+            if (ii < k && li < c) {
                 if (ii < c) {
-                    f = 0.5;
+                    f[r] = 0.5;
                 } else {
-                    const double b = B ? B[ii * ld + j] : Bg[ii * k + j];
-                    f = neg ? 1.0 - b : b;
+                    const double b = B ? B[ii * ld + li] : Bg[ii * k + li];
+                    f[r] = neg ? 1.0 - b : b;
                 }
             }
-            H[ii * lc + j] = f * a[r];
         }
-    });
+        const dbl4 a = mfma_tile<KS>(16 * wave, 0, vt, [&](int i, int j) { return W[i * lc + j]; });
+        for (int r = 0; r < 4; ++r) H[(16 * wave + lk + 4 * r) * lc + li] = f[r] * a[r];
+    }
     __syncthreads();
-    mfma_mnk<KP / 16, 1, KP / 4>(vf, [&](int i, int j) { return H[i * lc + j]; }, to_w);  // W = V H
+    if (wave < MT) {  // U = V H, into the W panel
+        const dbl4 a = mfma_tile<KS>(16 * wave, 0, vf, [&](int i, int j) { return H[i * lc + j]; });
+        for (int r = 0; r < 4; ++r) W[(16 * wave + lk + 4 * r) * lc + li] = a[r];
+    }
     __syncthreads();
-    mfma_mnk<KP / 16, KP / 16, 4>(wf, vt, [&](int i, int j, const dbl4 &a) {  // Z in X
+    // Y = U V_S' + V_S U' (or X minus it) on tile (ti, tj), ti >= tj: tiles t = wave,
+    // wave + 4, ... of the lower triangle in row order. A wave short of its last tile
+    // recomputes tile 0 and drops the result.
+    constexpr int NLT = MT * (MT + 1) / 2, NJ = (NLT + kBlock / kWave - 1) / (kBlock / kWave);
+    auto af = [&](int i, int kk) { return kk < 16 ? W[i * lc + kk] : V[i * ld + kk - 16]; };
+    auto bf = [&](int kk, int j) { return kk < 16 ? V[j * ld + kk] : W[j * lc + kk - 16]; };
+    dbl4 acc[NJ];
+    int ti[NJ], tj[NJ];
+#pragma unroll
+    for (int jn = 0; jn < NJ; ++jn) {
+        const int t = wave + jn * (kBlock / kWave), tt = t < NLT ? t : 0;
+        ti[jn] = tt >= 6 ? 3 : tt >= 3 ? 2 : tt >= 1 ? 1 : 0;
+        tj[jn] = tt - ti[jn] * (ti[jn] + 1) / 2;
+        acc[jn] = mfma_tile<8>(16 * ti[jn], 16 * tj[jn], af, bf);
+    }
+#pragma unroll
+    for (int jn = 0; jn < NJ; ++jn) {
+        if (wave + jn * (kBlock / kWave) >= NLT) break;
         for (int r = 0; r < 4; ++r) {
-            double &x = X[(i + 4 * r) * ld + j];
-            x = neg ? 0.5 * x - a[r] : a[r];
-        }
-    });
-    __syncthreads();
-    for (int e = threadIdx.x; e < KP * KP; e += kBlock) {  // Y = Z + Z'
-        const int i = e / KP, j = e - (e / KP) * KP;
-        if (i > j) {
-            const double y = X[i * ld + j] + X[j * ld + i];
-            X[i * ld + j] = y;
-            X[j * ld + i] = y;
-        } else if (i == j) {
-            X[i * ld + i] *= 2.0;
+            double &x = X[(16 * ti[jn] + lk + 4 * r) * ld + 16 * tj[jn] + li];
+            x = neg ? x - acc[jn][r] : acc[jn][r];
         }
     }
     __syncthreads();
