@@ -512,6 +512,8 @@ __global__ __launch_bounds__(kBlock) void k_loop_F(Problem p, StepArgs a, RowGri
 // product with F', fused with the cone Jacobians (work units as in k_fused_FT)
 // ---------------------------------------------------------------------------------------
 
+constexpr int kPostPref = 4;  // PSD units of the cone launch: later rows prefetched per thread
+
 struct UnitPre {
     int idx;                   // entry of this thread (x / diagonal rows: lane 0), or -1
     double acc, accT, self, coef, jd;
@@ -519,6 +521,11 @@ struct UnitPre {
     double cp[4];              // SOC factors of this thread's cone: mode, 1/|u|, c1, c2
     int ii, jj;                // PSD units: the matrix entry of this thread's first row
     Fin f;
+    // PSD units of the cone launch: finish operands and b of rows tid + j kBlock,
+    // j = 1 .. kPostPref (clamped to the last row), loaded before the first Jacobian so
+    // that they arrive while it runs
+    Fin fq[kPostPref];
+    double bq[kPostPref];
 };
 
 // LDS of a cone unit. Runs of SOC / exponential cones: tb (raw rows), rb (raw r_y, then the
@@ -758,8 +765,10 @@ __device__ inline dbl4 mfma_tile(int i0, int j0, AF af, BF bf) {
 // lower triangle of 16 x 16 tiles only: about 4 KP^2 16 multiply-adds instead of 4 KP^3.
 // X (symmetric, zero beyond the order) is replaced by Y on and below the diagonal (the
 // callers read the lower triangle only; above it X is left as it was, zero beyond the
-// order); W and H are KP x 16 panels in the T region. Waves own whole tiles: the first
-// three products have KP / 16 <= 4 of them, one per wave.
+// order); W and H are KP x 16 panels in the T region. Bs[:, S] comes from B in LDS, else
+// from the KP x 16 panel of B's first columns staged after W and H (KP = 64: the cone
+// launch stages it with V). Waves own whole tiles: the first three products have
+// KP / 16 <= 4 of them, one per wave.
 template <int KP>
 __device__ inline void psd_apply_lr(int k, int c, bool neg, const PsdLds &L, double *sm,
                                     const double *Bg) {
@@ -768,6 +777,8 @@ __device__ inline void psd_apply_lr(int k, int c, bool neg, const PsdLds &L, dou
     static_assert(MT <= kBlock / kWave, "one row tile per wave");
     double *X = sm, *W = sm + mat, *H = sm + mat + KP * lc;
     const double *V = sm + 2 * mat, *B = L.b >= 0 ? sm + L.b : nullptr;
+    const double *Bp = nullptr;
+    if constexpr (3 * KP * lc <= mat) Bp = sm + mat + 2 * KP * lc;
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     const int li = lane & 15, lk = lane >> 4;
     auto vf = [&](int i, int j) { return V[i * ld + j]; };
@@ -786,7 +797,7 @@ __device__ inline void psd_apply_lr(int k, int c, bool neg, const PsdLds &L, dou
                 if (ii < c) {
                     f[r] = 0.5;
                 } else {
-                    const double b = B ? B[ii * ld + li] : Bg[ii * k + li];
+                    const double b = B ? B[ii * ld + li] : Bp ? Bp[ii * lc + li] : Bg[ii * k + li];
                     f[r] = neg ? 1.0 - b : b;
                 }
             }
@@ -887,6 +898,15 @@ __device__ inline double smat_get(const double *Y, int ld, int ii, int jj) {
     return ii == jj ? Y[ii * ld + ii] : Y[ii * ld + jj] * kSqrt2;
 }
 
+// e / kp for 0 <= e < 8192 and kp a multiple of 16 up to 64, rkp = 1 / kp in FP32: the
+// quotient (e + 1/2) / kp is at least 1 / (2 kp) >= 2^-7 from an integer and the FP32
+// product is within 2^-22 (e + 1/2) / kp <= 2^-13 of it, so truncation gives the integer
+// quotient (an integer division by a value known only at run time costs tens of
+// instructions per use)
+__device__ inline int quot_kp(int e, float rkp) {
+    return (int)(((float)e + 0.5f) * rkp);
+}
+
 // DEEP: the row units' CSR sums keep kDeep entries per lane in flight (batched loop).
 // TROWS: the raw rows of a PSD unit come from a.tmp (written by the rows launch of the same
 // product) instead of the unit's own CSR gather.
@@ -960,16 +980,24 @@ __device__ inline void unit_pre(const Problem &p, const StepArgs &a, const Ptrs 
     const int nr = unit_rows(u, r0);
     double *tb, *rb, *jt, *ub, *gb;
     unit_bufs(p, u, sm, nr, tb, rb, jt, ub, gb);
+    // this thread's row operands; a PSD unit of the cone launch issues them after the loads
+    // of its factors (whose addresses would otherwise wait for these loads to return)
     int rs = 0, re = 0;
     double ry = 0.0;
-    if (tid < nr) {
-        P.idx = n + r0 + tid;
-        P.bv = p.b[r0 + tid];
-        rs = p.Arp[r0 + tid];
-        re = p.Arp[r0 + tid + 1];
-        ry = in_raw(a, q, n + r0 + tid);
-        fin_load(a, q, n + r0 + tid, P.f);
-    }
+    auto row_ops = [&]() {
+        if (tid < nr) {
+            P.idx = n + r0 + tid;
+            P.bv = p.b[r0 + tid];
+            if (!TROWS) {
+                rs = p.Arp[r0 + tid];
+                re = p.Arp[r0 + tid + 1];
+                ry = in_raw(a, q, n + r0 + tid);
+            }
+            fin_load(a, q, n + r0 + tid, P.f);
+        }
+    };
+    const bool late_ops = TROWS && u.type == U_PSD;
+    if (!late_ops) row_ops();
     // raw rows t = A r_x - b r_N - r_y of the unit (unnormalised). The unit's rows are
     // consecutive CSR rows, so their entries are one range [e0, e1): the workgroup gathers
     // the products of kGather entries at a time into gb, then each row adds its own entries
@@ -998,17 +1026,19 @@ __device__ inline void unit_pre(const Problem &p, const StepArgs &a, const Ptrs 
             tb[i] = (e1 > e0 ? tb[i] : 0.0) - bb * in_N_raw - y;
         }
     };
-    // the same rows from a.tmp (raw t of the rows launch) and the input, the loads of four
-    // rows per thread in flight at once
-    auto trows = [&]() {
-        constexpr int R = 4;
+    // the same rows from a.tmp (raw t of the rows launch) and the input, the loads of eight
+    // rows per thread in flight at once (past the last row they read the last row, kept
+    // unconditional); xld > 0: a PSD unit, whose rows also go into the symmetric matrix X
+    // (leading dimension xld) while the loads are in flight
+    auto trows = [&](int xld) {
+        constexpr int R = 8;
         for (int i0 = tid; i0 < nr; i0 += R * kBlock) {
             double y[R], t[R];
 #pragma unroll
             for (int j = 0; j < R; ++j) {
-                const int i = i0 + j * kBlock;
-                y[j] = i >= nr ? 0.0 : i == tid ? ry : in_raw(a, q, n + r0 + i);
-                t[j] = i < nr ? a.tmp[n + r0 + i] : 0.0;
+                const int i = min(i0 + j * kBlock, nr - 1);
+                y[j] = in_raw(a, q, n + r0 + i);
+                t[j] = a.tmp[n + r0 + i];
             }
 #pragma unroll
             for (int j = 0; j < R; ++j) {
@@ -1016,6 +1046,11 @@ __device__ inline void unit_pre(const Problem &p, const StepArgs &a, const Ptrs 
                 if (i < nr) {
                     rb[i] = y[j];
                     tb[i] = t[j];
+                    if (xld > 0) {
+                        int ii, jj;
+                        svec_rc(i, u.k, ii, jj);
+                        smat_put(sm, xld, ii, jj, t[j]);
+                    }
                 }
             }
         }
@@ -1028,69 +1063,115 @@ __device__ inline void unit_pre(const Problem &p, const StepArgs &a, const Ptrs 
         const int k = u.k;
         const PsdLds Ld = psd_lds(k);
         const int kp = Ld.kp;
-        const double *Vg = p.psd_pool + p.psd_off[u.begin], *Bg = Vg + k * k;
+        const double *Vg = p.psd_pool + u.voff, *Bg = Vg + k * k;
         double *V = sm + 2 * kp * Ld.ld, *B = Ld.b >= 0 ? sm + Ld.b : nullptr;
+        const float rkp = 1.0f / (float)kp;
         if (kp * kp <= kPsdPref * kBlock) {
             double vpre[kPsdPref], bpre[kPsdPref];
 #pragma unroll
             for (int j = 0; j < kPsdPref; ++j) {
-                const int e = tid + j * kBlock, i = e / kp, jj = e - (e / kp) * kp;
+                const int e = tid + j * kBlock, i = quot_kp(e, rkp), jj = e - i * kp;
                 const bool in_k = e < kp * kp && i < k && jj < k;
                 vpre[j] = in_k ? Vg[i * k + jj] : 0.0;
                 bpre[j] = (in_k && B) ? Bg[i * k + jj] : 0.0;
             }
+            if (late_ops) row_ops();
             if (tid < nr) svec_rc(tid, k, P.ii, P.jj);  // while the loads are in flight
-            if (TROWS) trows(); else yrows();
+            if (TROWS) trows(Ld.ld); else yrows();
 #pragma unroll
             for (int j = 0; j < kPsdPref; ++j) {
-                const int e = tid + j * kBlock, i = e / kp, jj = e - (e / kp) * kp;
+                const int e = tid + j * kBlock, i = quot_kp(e, rkp), jj = e - i * kp;
                 if (e < kp * kp) {
                     V[i * Ld.ld + jj] = vpre[j];
                     if (B) B[i * Ld.ld + jj] = bpre[j];
                     if (i >= k || jj >= k) sm[i * Ld.ld + jj] = 0.0;  // X beyond order k
                 }
             }
-        } else if (TROWS) {  // the cone launch: eight entries of V (and B) per load batch
-            if (tid < nr) svec_rc(tid, k, P.ii, P.jj);
-            trows();
-            constexpr int R = 8;
-            for (int e0 = tid; e0 < kp * kp; e0 += R * kBlock) {
-                double vv[R], bb[R];
+        } else if (TROWS) {
+            // the cone launch: all of V (and B) in flight with the rows' loads, and with
+            // kp = 64 (B not in LDS) the panel of B's first 16 columns for the low-rank form
+            // after the W and H panels of the T region (also staged when it goes unused).
+            // Thread tid takes column c = tid % 64 of rows tid / 64 + 4 j (of the panel:
+            // column tid % 16 of rows tid / 16 + 16 j); every load is issued, from a valid
+            // address, and its value kept or replaced by zero.
+            constexpr int RJ = 16, RB = 4;
+            static_assert(RJ * (kBlock / 64) >= 64 && RB * (kBlock / 16) >= 64, "one batch");
+            const int c = tid & 63, rq = tid / 64, cb = tid & 15, rqb = tid / 16;
+            const bool cin = c < k, panel = LR && kp == 64 && !B;
+            const double *vp = Vg + (cin ? c : 0) + rq * k, *bq = Bg + (cin ? c : 0) + rq * k;
+            const double *pp = Bg + cb + rqb * k;
+            double vv[RJ], bb[RJ], bp[RB];
 #pragma unroll
-                for (int j = 0; j < R; ++j) {
-                    const int e = e0 + j * kBlock, i = e / kp, jj = e - (e / kp) * kp;
-                    const bool in_k = e < kp * kp && i < k && jj < k;
-                    vv[j] = in_k ? Vg[i * k + jj] : 0.0;
-                    bb[j] = (in_k && B) ? Bg[i * k + jj] : 0.0;
+            for (int j = 0; j < RJ; ++j) {
+                const bool ok = cin && rq + 4 * j < k;
+                const double v = vp[ok ? 4 * j * k : 0];
+                vv[j] = ok ? v : 0.0;
+            }
+            if (B) {
+#pragma unroll
+                for (int j = 0; j < RJ; ++j) {
+                    const bool ok = cin && rq + 4 * j < k;
+                    const double v = bq[ok ? 4 * j * k : 0];
+                    bb[j] = ok ? v : 0.0;
                 }
+            }
+            if (panel) {
 #pragma unroll
-                for (int j = 0; j < R; ++j) {
-                    const int e = e0 + j * kBlock, i = e / kp, jj = e - (e / kp) * kp;
-                    if (e < kp * kp) {
-                        V[i * Ld.ld + jj] = vv[j];
-                        if (B) B[i * Ld.ld + jj] = bb[j];
-                        if (i >= k || jj >= k) sm[i * Ld.ld + jj] = 0.0;
+                for (int j = 0; j < RB; ++j) {
+                    const bool ok = cb < k && rqb + 16 * j < k;
+                    const double v = pp[ok ? 16 * j * k : 0];
+                    bp[j] = ok ? v : 0.0;
+                }
+            }
+            asm volatile("" ::: "memory");  // keeps the row operands' loads after these
+            row_ops();
+            if (tid < nr) svec_rc(tid, k, P.ii, P.jj);
+            trows(Ld.ld);
+            if (c < kp) {
+#pragma unroll
+                for (int j = 0; j < RJ; ++j) {
+                    const int r = rq + 4 * j;
+                    if (r < kp) {
+                        V[r * Ld.ld + c] = vv[j];
+                        if (B) B[r * Ld.ld + c] = bb[j];
+                        if (r >= k || c >= k) sm[r * Ld.ld + c] = 0.0;  // X beyond order k
                     }
                 }
+            }
+            if (panel) {
+                double *Bp = sm + kp * Ld.ld + 2 * kp * 17;
+#pragma unroll
+                for (int j = 0; j < RB; ++j) Bp[(rqb + 16 * j) * 17 + cb] = bp[j];
             }
         } else {
             if (tid < nr) svec_rc(tid, k, P.ii, P.jj);
             yrows();
             for (int e = tid; e < kp * kp; e += kBlock) {
-                const int i = e / kp, jj = e - (e / kp) * kp;
+                const int i = quot_kp(e, rkp), jj = e - i * kp;
                 const bool in_k = i < k && jj < k;
                 V[i * Ld.ld + jj] = in_k ? Vg[i * k + jj] : 0.0;
                 if (B) B[i * Ld.ld + jj] = in_k ? Bg[i * k + jj] : 0.0;
                 if (!in_k) sm[i * Ld.ld + jj] = 0.0;
             }
         }
-        // the raw rows as the symmetric matrix X (the gather buffer may have used the region)
-        for (int i = tid; i < nr; i += kBlock) {
-            int ii = P.ii, jj = P.jj;
-            if (i != tid) svec_rc(i, k, ii, jj);
-            smat_put(sm, Ld.ld, ii, jj, tb[i]);
+        // the raw rows as the symmetric matrix X (the gather buffer may have used the region;
+        // trows wrote it already)
+        if (!TROWS) {
+            for (int i = tid; i < nr; i += kBlock) {
+                int ii = P.ii, jj = P.jj;
+                if (i != tid) svec_rc(i, k, ii, jj);
+                smat_put(sm, Ld.ld, ii, jj, tb[i]);
+            }
         }
         __syncthreads();
+        if constexpr (TROWS && LR) {
+#pragma unroll
+            for (int j = 0; j < kPostPref; ++j) {
+                const int i = min(tid + (j + 1) * kBlock, nr - 1);
+                fin_load(a, q, n + r0 + i, P.fq[j]);
+                P.bq[j] = p.b[r0 + i];
+            }
+        }
         psd_apply_sel<MAXKP, LR>(p.psd_lr, u.begin, k, Ld, sm, Bg);  // ends with a barrier
     } else if (u.type == U_SOC) {
         int cr0 = 0, cdim = 0;
@@ -1105,7 +1186,7 @@ __device__ inline void unit_pre(const Problem &p, const StepArgs &a, const Ptrs 
         double upre[kSocPref];
 #pragma unroll
         for (int j = 0; j < kSocPref; ++j) upre[j] = j < cdim - 1 ? p.zy[cr0 + 1 + j] : 0.0;
-        if (TROWS) trows(); else yrows();
+        if (TROWS) trows(0); else yrows();
 #pragma unroll
         for (int j = 0; j < kSocPref; ++j)
             if (j < cdim - 1) ub[cr0 - r0 + 1 + j] = upre[j] * P.cp[1];
@@ -1118,7 +1199,7 @@ __device__ inline void unit_pre(const Problem &p, const StepArgs &a, const Ptrs 
         const bool own = cone < u.end;
 #pragma unroll
         for (int j = 0; j < 9; ++j) J[j] = own ? p.exp_J[9 * cone + j] : 0.0;
-        if (TROWS) trows(); else yrows();
+        if (TROWS) trows(0); else yrows();
         if (own) {
 #pragma unroll
             for (int j = 0; j < 9; ++j) ub[9 * tid + j] = J[j];
@@ -1165,8 +1246,25 @@ __device__ inline void unit_post(const Problem &p, const StepArgs &a, const Ptrs
     const bool psd = u.type == U_PSD;
     const int k = u.k, ld = psd ? psd_lds(k).ld : 0;
     if constexpr (CL) {  // as below, the operands of four rows per thread loaded first
+        auto fin_row = [&](int i, const Fin &f) {
+            int ii = P.ii, jj = P.jj;
+            if (psd && i != tid) svec_rc(i, k, ii, jj);
+            const double jv = psd ? smat_get(sm, ld, ii, jj) : jt[i];
+            const double o = fin_store(a, c, n + r0 + i, f, (jv + rb[i]) * c.inv, s0);
+            rb[i] = f.nxs * o;
+            if (psd && a.do_pre) smat_put(sm, ld, ii, jj, rb[i]);
+        };
+        int from = tid;
+        if (psd) {  // the first rows from the operands unit_pre loaded
+#pragma unroll
+            for (int j = 0; j <= kPostPref; ++j) {
+                const int i = tid + j * kBlock;
+                if (i < nr) fin_row(i, j == 0 ? P.f : P.fq[j - 1]);
+            }
+            from = tid + (kPostPref + 1) * kBlock;
+        }
         constexpr int R = 4;
-        for (int i0 = tid; i0 < nr; i0 += R * kBlock) {
+        for (int i0 = from; i0 < nr; i0 += R * kBlock) {
             Fin f[R];
 #pragma unroll
             for (int j = 0; j < R; ++j) {
@@ -1178,12 +1276,7 @@ __device__ inline void unit_post(const Problem &p, const StepArgs &a, const Ptrs
             for (int j = 0; j < R; ++j) {
                 const int i = i0 + j * kBlock;
                 if (i >= nr) break;
-                int ii = P.ii, jj = P.jj;
-                if (psd && i != tid) svec_rc(i, k, ii, jj);
-                const double jv = psd ? smat_get(sm, ld, ii, jj) : jt[i];
-                const double o = fin_store(a, c, n + r0 + i, f[j], (jv + rb[i]) * c.inv, s0);
-                rb[i] = f[j].nxs * o;
-                if (psd && a.do_pre) smat_put(sm, ld, ii, jj, rb[i]);
+                fin_row(i, f[j]);
             }
         }
     } else {
@@ -1207,7 +1300,7 @@ __device__ inline void unit_post(const Problem &p, const StepArgs &a, const Ptrs
     auto oin = [&](int i) { return rb[i]; };
     auto jout = [&](int i, double v) { jt[i] = v; };
     if (psd) {
-        const double *Bg = p.psd_pool + p.psd_off[u.begin] + k * k;
+        const double *Bg = p.psd_pool + u.voff + k * k;
         psd_apply_sel<MAXKP, CL>(p.psd_lr, u.begin, k, psd_lds(k), sm, Bg);  // Y in X
         for (int i = tid; i < nr; i += kBlock) {
             int ii = P.ii, jj = P.jj;
@@ -1223,8 +1316,21 @@ __device__ inline void unit_post(const Problem &p, const StepArgs &a, const Ptrs
         __syncthreads();
     }
     if constexpr (CL) {
+        int from = tid;
+        if (psd) {
+#pragma unroll
+            for (int j = 0; j <= kPostPref; ++j) {
+                const int i = tid + j * kBlock;
+                if (i < nr) {
+                    const double w = jt[i];
+                    a.wy[r0 + i] = w;
+                    s1 -= (j == 0 ? P.bv : P.bq[j - 1]) * w;
+                }
+            }
+            from = tid + (kPostPref + 1) * kBlock;
+        }
         constexpr int R = 4;
-        for (int i0 = tid; i0 < nr; i0 += R * kBlock) {
+        for (int i0 = from; i0 < nr; i0 += R * kBlock) {
             double bb[R];
 #pragma unroll
             for (int j = 0; j < R; ++j) {
@@ -1316,6 +1422,21 @@ __global__ __launch_bounds__(kBlock) void k_loop_FT_multi_deep(Problem p, StepAr
     loop_FT_body<true, true>(p, a, g, sm, S);
 }
 
+// g.units[i] by scalar loads (the table is constant during a launch): its words read
+// through a pointer into the constant address space
+__device__ inline Unit unit_at(const Unit *units, int i) {
+    using CWord = const __attribute__((address_space(4))) int;
+    constexpr int NW = sizeof(Unit) / sizeof(int);
+    static_assert(NW * sizeof(int) == sizeof(Unit), "whole words");
+    CWord *w = (CWord *)(units + i);
+    int v[NW];
+#pragma unroll
+    for (int j = 0; j < NW; ++j) v[j] = w[j];
+    Unit u;
+    __builtin_memcpy(&u, v, sizeof(Unit));
+    return u;
+}
+
 // The cone units of a product with F' whose rows launch (k_loop_FT* with U_PSDROWS units,
 // or k_loop_FT_xs) left their raw rows t = A r_x - b r_N - r_y in a.tmp: one workgroup per
 // unit (a PSD cone, or a run of SOC or exponential cones), the scalars of the state that
@@ -1324,11 +1445,15 @@ __global__ __launch_bounds__(kBlock) void k_loop_FT_multi_deep(Problem p, StepAr
 // per CU.
 __global__ __launch_bounds__(kBlock) void k_loop_FT_cones(Problem p, StepArgs a, FusedGrid g) {
     extern __shared__ double sm[];
+    // the unit first, through the scalar cache (read only here): the loads of its factors
+    // and rows depend on it, and in vector registers its fields would wait for every vector
+    // load issued before their first use (the raw rows come from a.tmp, so unit_pre does
+    // not read in_N_raw)
+    const Unit u = unit_at(g.units, blockIdx.x);
     const Ptrs q = ptrs_of(p, a);
-    const double in_N_raw = in_raw(a, q, p.N - 1);
-    const Unit u = g.units[blockIdx.x];
     UnitPre P;
-    unit_pre<false, 64, true, true>(p, a, q, g.lx, g.ly, u, sm, in_N_raw, P);
+    unit_pre<false, 64, true, true>(p, a, q, g.lx, g.ly, u, sm, 0.0, P);
+    const double in_N_raw = in_raw(a, q, p.N - 1);
     const LsqrState S = *a.st;
     if (S.done) return;
     const Ctx c = scalars(a, S, q, in_N_raw);
@@ -1687,7 +1812,10 @@ __global__ void k_unit_ranges(Problem p, Unit *units, int n) {
         u.nrows = unit_rows_of(p, u, r0);
         u.e0 = p.Arp[r0];
         u.e1 = p.Arp[r0 + u.nrows];
-        if (u.type == U_PSD) u.k = p.psd_k[u.begin];
+        if (u.type == U_PSD) {
+            u.k = p.psd_k[u.begin];
+            u.voff = p.psd_off[u.begin];
+        }
     }
     units[i] = u;
 }

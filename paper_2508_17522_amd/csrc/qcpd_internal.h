@@ -230,7 +230,10 @@ struct Unit {
     int type, begin, end, row0;  // row0: first y row of a cone run (SOC / exp / PSD)
     // cone runs, filled on the device once the CSR copies exist (fill_unit_ranges): the
     // number of y rows, the range [e0, e1) of their CSR entries in A, and a PSD cone's order
+    // and the offset of its (V, B) in the factor pool (one dependent load less at the start
+    // of a PSD unit)
     int nrows, e0, e1, k;
+    long long voff;
 };
 constexpr int kUnitRows = 1024;   // most y rows staged by one SOC / exp unit
 
