@@ -299,8 +299,18 @@ def run_copy_calibration(mib: int):
     for _ in range(20):
         dst.copy_(src)
     torch.cuda.synchronize()
+    # the same copies timed with HIP events: the bandwidth a plain stream reaches
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(20):
+        dst.copy_(src)
+    t1.record()
+    t1.synchronize()
+    us = t0.elapsed_time(t1) * 1e3 / 20
     print(json.dumps({"copy_calibration": {"bytes_read_per_launch": n * 8,
-                                           "bytes_written_per_launch": n * 8, "launches": 20}}),
+                                           "bytes_written_per_launch": n * 8, "launches": 20,
+                                           "us_per_launch": round(us, 2),
+                                           "GBps_read_plus_write": round(2 * n * 8 / us / 1e3, 1)}}),
           flush=True)
 
 
