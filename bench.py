@@ -288,6 +288,25 @@ def run_batch(args):
     print(json.dumps(line), flush=True)
 
 
+def copy_bandwidth(mib: int = 1024, launches: int = 20) -> float:
+    """GB/s (bytes read + written) of a plain device-to-device copy of `mib` MiB, timed with
+    HIP events after one untimed copy: the bandwidth a plain stream reaches on this GPU."""
+    import torch
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(launches):
+        dst.copy_(src)
+    t1.record()
+    t1.synchronize()
+    us = t0.elapsed_time(t1) * 1e3 / launches
+    del src, dst
+    return 2 * n * 8 / us / 1e3
+
+
 def run_copy_calibration(mib: int):
     """A plain device-to-device copy of known size (the reference for scaling the HBM byte
     counters of a profiler run): reads and writes `mib` MiB per launch, 20 launches."""
@@ -299,18 +318,11 @@ def run_copy_calibration(mib: int):
     for _ in range(20):
         dst.copy_(src)
     torch.cuda.synchronize()
-    # the same copies timed with HIP events: the bandwidth a plain stream reaches
-    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0.record()
-    for _ in range(20):
-        dst.copy_(src)
-    t1.record()
-    t1.synchronize()
-    us = t0.elapsed_time(t1) * 1e3 / 20
+    del src, dst
+    gbs = copy_bandwidth(mib)  # 21 more copies of the same size, timed
     print(json.dumps({"copy_calibration": {"bytes_read_per_launch": n * 8,
                                            "bytes_written_per_launch": n * 8, "launches": 20,
-                                           "us_per_launch": round(us, 2),
-                                           "GBps_read_plus_write": round(2 * n * 8 / us / 1e3, 1)}}),
+                                           "GBps_read_plus_write": round(gbs, 1)}}),
           flush=True)
 
 
@@ -509,6 +521,9 @@ def main():
                 "frac_by_kernel": {k: round(launch_bytes(q, k, layout) / (v * 1e-3) / 1e9
                                             / HBM_PEAK_GBS, 4) for k, v in times.items()},
                 "us_per_iteration": round((ms[0] + ms[1]) * 1e3, 3)}
+    copy_gbs = copy_bandwidth()
+    roofline["measured_copy_GBps"] = round(copy_gbs, 1)
+    roofline["frac_of_measured_copy"] = round(achieved / copy_gbs, 4)
 
     line = {
         "metric": METRIC,
