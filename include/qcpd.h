@@ -226,6 +226,37 @@ qcpd_status qcpd_profile_kernels(qcpd_handle *h, int32_t reps, float *ms_out);
  * itself and for checking it against a reference. */
 qcpd_status qcpd_apply(qcpd_handle *h, int32_t transpose, const double *in, double *out);
 
+/* Pi_{K*}(zy): the projection onto the dual cone of the handle's cone spec, block by block
+ * (Appendix A: nonnegative, SOC, PSD by eigendecomposition, exponential and power cones by
+ * their root-finds, dual cones by Moreau). zy, out [device], m entries each, distinct.
+ * The handle's own factors are left as they are. Returns QCPD_ERR_CONE when a root-find or
+ * an eigendecomposition fails. */
+qcpd_status qcpd_proj_dual(qcpd_handle *h, const double *zy, double *out);
+
+typedef struct {
+    int32_t newton_iters;    /* Newton steps taken                                           */
+    int32_t lsqr_iters;      /* LSQR iterations over all steps                               */
+    double  residual;        /* ||G(x, y - s)|| / (1 + ||q|| + ||b||) at the returned point  */
+    int32_t converged;       /* 1 when residual <= tol                                       */
+} qcpd_resolve_info;
+
+/* Forward solve by refinement from a nearby point (the solution a numerical solver supplies,
+ * Sec. 2.2; the previous solution when theta moves in a learning loop, Sec. 3.4): Newton's
+ * method on the optimality conditions (Sec. 2.1) in the variables (x, eta = y - s),
+ *   G(x, eta) = (P x + A'y + q, -A x + b - y + eta),  y = Pi_{K*}(eta),  s = y - eta,
+ * each step K_red step = -G solved as one JVP of this library at the current point along
+ * (dP, dA, dq, db) = (0, 0, G_x, G_y), then x += dx, eta += dy - ds. Stops when
+ * ||G|| <= tol (1 + ||q|| + ||b||) or after max_newton steps. P, A, q, b, K as in
+ * qcpd_create; x (n), y, s (m) [device]: the starting point on entry, the refined solution
+ * on return (y and s are always the projections of the final eta, so y is in K*, s in K
+ * and y's = 0). opts: the LSQR options of the steps (NULL: defaults). info [host] may be
+ * NULL. Returns QCPD_OK, QCPD_WARN_NOT_CONVERGED (the point after the last step is
+ * returned), or an error of qcpd_create. Allocates a handle per step. */
+qcpd_status qcpd_resolve(const qcpd_csr *P, const qcpd_csr *A, const double *q, const double *b,
+                         const qcpd_cones *K, double *x, double *y, double *s,
+                         const qcpd_opts *opts, double tol, int32_t max_newton,
+                         qcpd_resolve_info *info, void *stream);
+
 /* Launch shape of the LSQR loop, for tuning (an autotuner's choice): the product with F
  * over CSR rows runs on at most grid_F workgroups and the fused product with F' on at most
  * grid_FT (each loops over its work with a grid stride; 0 = the default cap, 512). Results

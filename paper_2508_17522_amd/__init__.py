@@ -13,7 +13,8 @@ from ._capi import (QCPD_OK, QCPD_WARN_NOT_CONVERGED, QCPD_WARN_NONDIFF, QCPD_ER
 from .api import (Cones, Opts, Info, Handle, QCPDError, qcpd_create, qcpd_jvp, qcpd_vjp,
                   qcpd_destroy, qcpd_status_str, qcpd_opts_default, qcpd_set_opts,
                   qcpd_set_precond, qcpd_get_diagnostics, qcpd_profile_kernels,
-                  qcpd_set_launch, qcpd_get_launch, qcpd_get_layout, qcpd_apply)
+                  qcpd_set_launch, qcpd_get_launch, qcpd_get_layout, qcpd_apply,
+                  qcpd_proj_dual, qcpd_resolve, ResolveInfo)
 from .autograd import (QCPStructure, qcp_solution_map, BatchStructure,
                        batch_solution_map)
 from .learned import (LearnedModel, qcpd_features, qcpd_learned_targets, qcpd_set_learned,
@@ -25,7 +26,8 @@ from .batch import (BatchHandle, qcpd_batch_create, qcpd_batch_jvp, qcpd_batch_v
 __all__ = [
     "BatchHandle", "qcpd_batch_create", "qcpd_batch_jvp", "qcpd_batch_vjp", "qcpd_batch_set_opts",
     "qcpd_batch_destroy", "qcpd_batch_set_launch", "qcpd_batch_get_launch", "qcpd_set_launch",
-    "qcpd_get_launch", "qcpd_get_layout", "qcpd_apply",
+    "qcpd_get_launch", "qcpd_get_layout", "qcpd_apply", "qcpd_proj_dual", "qcpd_resolve",
+    "ResolveInfo",
     "QCPStructure", "qcp_solution_map",
     "LearnedModel", "qcpd_features", "qcpd_learned_targets", "qcpd_set_learned", "qcpd_mlp_init",
     "qcpd_mlp_predict", "qcpd_mlp_grad", "qcpd_mlp_adam",

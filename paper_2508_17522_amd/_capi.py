@@ -40,6 +40,11 @@ class qcpd_info(ctypes.Structure):
                 ("flags", ctypes.c_uint32), ("ms_total", ctypes.c_float)]
 
 
+class qcpd_resolve_info(ctypes.Structure):
+    _fields_ = [("newton_iters", c_int32), ("lsqr_iters", c_int32), ("residual", c_double),
+                ("converged", c_int32)]
+
+
 QCPD_CHOICE_AUTO = 0
 QCPD_CHOICE_OFF = 1
 QCPD_CHOICE_ON = 2
@@ -91,7 +96,7 @@ EXPORTS = ["qcpd_opts_default", "qcpd_create", "qcpd_jvp", "qcpd_vjp", "qcpd_set
            "qcpd_set_learned", "qcpd_mlp_init", "qcpd_mlp_predict", "qcpd_mlp_workspace_floats",
            "qcpd_mlp_grad", "qcpd_mlp_adam", "qcpd_set_launch", "qcpd_get_launch",
            "qcpd_batch_set_launch", "qcpd_batch_get_launch", "qcpd_apply",
-           "qcpd_mlp_grad_noalloc", "qcpd_get_layout"]
+           "qcpd_mlp_grad_noalloc", "qcpd_get_layout", "qcpd_proj_dual", "qcpd_resolve"]
 
 _lib = None
 
@@ -161,6 +166,12 @@ def load(path: str = LIB_PATH):
     lib.qcpd_mlp_adam.restype = c_int32
     lib.qcpd_apply.argtypes = [c_void_p, c_int32, c_void_p, c_void_p]
     lib.qcpd_apply.restype = c_int32
+    lib.qcpd_proj_dual.argtypes = [c_void_p, c_void_p, c_void_p]
+    lib.qcpd_proj_dual.restype = c_int32
+    lib.qcpd_resolve.argtypes = [P(qcpd_csr), P(qcpd_csr), c_void_p, c_void_p, P(qcpd_cones),
+                                 c_void_p, c_void_p, c_void_p, P(qcpd_opts), c_double, c_int32,
+                                 P(qcpd_resolve_info), c_void_p]
+    lib.qcpd_resolve.restype = c_int32
     lib.qcpd_set_launch.argtypes = [c_void_p, c_int32, c_int32]
     lib.qcpd_set_launch.restype = c_int32
     lib.qcpd_get_launch.argtypes = [c_void_p, P(c_int32)]

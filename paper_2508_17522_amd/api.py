@@ -263,6 +263,54 @@ def qcpd_profile_kernels(h: Handle, reps: int = 50):
     return list(out)
 
 
+@dataclasses.dataclass
+class ResolveInfo:
+    newton_iters: int
+    lsqr_iters: int
+    residual: float
+    converged: bool
+
+
+def qcpd_proj_dual(h: Handle, zy, out=None):
+    """out = Pi_{K*}(zy) with the handle's cone spec (m entries)."""
+    out = torch.empty(h.m, dtype=torch.float64, device=h.device) if out is None else out
+    with torch.cuda.device(h.device):
+        st = _lib().qcpd_proj_dual(h.ptr, _ptr(zy, torch.float64, "zy", h.m),
+                                   _ptr(out, torch.float64, "out", h.m))
+    if st < 0:
+        raise QCPDError(st, "qcpd_proj_dual")
+    return out
+
+
+def qcpd_resolve(P: tuple, A: tuple, q, b, cones: Cones, x, y, s, tol: float = 1e-12,
+                 max_newton: int = 20, opts: Optional[Opts] = None,
+                 stream: Optional[torch.cuda.Stream] = None):
+    """Newton refinement of (x, y, s) to a solution of the QCP (P, A, q, b, cones): the
+    inputs are the starting point and are left as they are; returns (x, y, s, ResolveInfo,
+    status) with new tensors."""
+    n = int(q.numel())
+    m = int(b.numel())
+    Pc = _csr(*P, n, n, "P")
+    Ac = _csr(*A, m, n, "A")
+    K, keep = cones.to_c()
+    o = (opts or qcpd_opts_default()).to_c()
+    dev = q.device
+    strm = stream if stream is not None else torch.cuda.current_stream(dev)
+    xo, yo, so = x.detach().clone(), y.detach().clone(), s.detach().clone()
+    info = C.qcpd_resolve_info()
+    with torch.cuda.device(dev):
+        st = _lib().qcpd_resolve(ctypes.byref(Pc), ctypes.byref(Ac),
+                                 _ptr(q, torch.float64, "q", n), _ptr(b, torch.float64, "b", m),
+                                 ctypes.byref(K), _ptr(xo, torch.float64, "x", n),
+                                 _ptr(yo, torch.float64, "y", m), _ptr(so, torch.float64, "s", m),
+                                 ctypes.byref(o), float(tol), int(max_newton), ctypes.byref(info),
+                                 ctypes.c_void_p(strm.cuda_stream))
+    if st < 0:
+        raise QCPDError(st, "qcpd_resolve")
+    return xo, yo, so, ResolveInfo(info.newton_iters, info.lsqr_iters, info.residual,
+                                   bool(info.converged)), st
+
+
 def qcpd_apply(h: Handle, v, transpose: bool = False, out=None):
     """out = F v (or F' v): the operator of the least-squares problems, unscaled."""
     out = torch.empty(h.N, dtype=torch.float64, device=h.device) if out is None else out

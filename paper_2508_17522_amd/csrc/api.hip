@@ -7,6 +7,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
+#include <cstdint>
 #include <new>
 #include <vector>
 
@@ -78,6 +80,13 @@ struct qcpd_handle {
     int graph_solver[2] = {-1, -1};
     uint32_t create_flags = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // projections onto K* of arbitrary points (qcpd_proj_dual, the refinement): the cone spec
+    // of create and factor buffers of their own, so the handle's factors stay as they are
+    ConeHost ch{};
+    int psd_fact_lds = 0;
+    long long pool_len = 0;
+    double *pj_jdiag = nullptr, *pj_soc = nullptr, *pj_exp = nullptr, *pj_pool = nullptr;
+    int *pj_flag = nullptr;
 };
 
 namespace {
@@ -880,6 +889,10 @@ qcpd_status create_impl(qcpd_handle *h, const qcpd_csr *P, const qcpd_csr *A, co
     ALLOC(psd_lr, K->n_psd);
     ch.psd_lr = psd_lr;
     h->p.psd_lr = psd_lr;
+    h->ch = ch;
+    h->ch.psd_lr = nullptr;
+    h->psd_fact_lds = psd_factor_lds_bytes(kmax);
+    h->pool_len = off;
     launch_cone_factors(p, ch, h->jdiag, soc_par, exp_J, pool, h->flag + 1, h->flag + 2,
                         psd_factor_lds_bytes(kmax), st);
     launch_scales(p, rg, h->scale[0], h->scale[1], h->partials, h->counter, st);
@@ -944,6 +957,88 @@ qcpd_status vjp_solve(qcpd_handle *h, const double *gx, const double *gy, const 
     r.out = h->u;
     launch_vjp_rhs(p, r, h->cg, h->lds, gx, gy, gs, s);
     return solve(h, 1, sc, scl, rel);
+}
+
+// Pi_{K*}(zy) into out (m entries, device) with the handle's cone spec, through the setup's
+// factor kernels on scratch buffers of the handle's own
+qcpd_status project_dual(qcpd_handle *h, const double *zy, double *out) {
+    const Problem &p = h->p;
+    if (p.m == 0) return QCPD_OK;
+    if (!h->pj_flag) {
+        ALLOC(h->pj_jdiag, p.m);
+        ALLOC(h->pj_soc, 4LL * p.n_soc);
+        ALLOC(h->pj_exp, 9LL * p.n_exp);
+        ALLOC(h->pj_pool, h->pool_len);
+        ALLOC(h->pj_flag, 2);
+    }
+    hipStream_t st = h->stream;
+    Problem pp = p;
+    pp.zy = zy;
+    HIPCHK(hipMemsetAsync(h->pj_flag, 0, 2 * sizeof(int), st));
+    launch_cone_factors(pp, h->ch, h->pj_jdiag, h->pj_soc, h->pj_exp, h->pj_pool, h->pj_flag,
+                        h->pj_flag + 1, h->psd_fact_lds, st, out);
+    HIPCHK(hipMemcpyAsync(h->host_flag, h->pj_flag, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipGetLastError());
+    return h->host_flag[1] ? QCPD_ERR_CONE : QCPD_OK;
+}
+
+// One Newton step of the refinement at the handle's point: K_red step = -G. K_red is the
+// embedding's operator F without its tau row and column (Sec. 3.1, F restricted to
+// w_N = 0), so LSQR runs on F with the active preconditioner's scales and both tau entries
+// of the scales set to zero, on the right-hand side of a derivative along (0, 0, G_x, G_y)
+// (whose first n + m entries are G); the step is that derivative's (dx, dy - ds). The
+// explicit-residual resumes of a derivative are skipped: its residual includes the tau row
+// the step leaves out. sc, scl: scratch, N entries each. G: n + m entries.
+qcpd_status newton_step(qcpd_handle *h, const double *zP, const double *zA, const double *g,
+                        double *sc, double *scl, double *dx, double *dy, double *ds,
+                        int *iters) {
+    const Problem &p = h->p;
+    const int N = p.N;
+    hipStream_t st = h->stream;
+    const double *sc0, *scl0;
+    active_scales(h, 0, &sc0, &scl0);
+    if (sc0) HIPCHK(hipMemcpyAsync(sc, sc0, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+    else launch_fill(sc, N, 1.0, st);
+    if (scl0) HIPCHK(hipMemcpyAsync(scl, scl0, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+    else launch_fill(scl, N, 1.0, st);
+    launch_fill(sc + N - 1, 1, 0.0, st);
+    launch_fill(scl + N - 1, 1, 0.0, st);
+    launch_state_init(h->st, h->opts.tol, max_iter_of(h), st);
+    launch_fill(h->xk, N, 0.0, st);
+    launch_fill(h->wk, N, 0.0, st);
+    StepArgs r = base_args(h, sc, scl);
+    r.out = h->u;
+    launch_jvp_rhs(p, r, h->rg, zP, zA, g, g + p.n, st);
+    qcpd_status rc = bake_scales(h, sc, scl);
+    if (rc != QCPD_OK) return rc;
+    lsqr_start(h, 0, sc, scl);
+    rc = lsqr_iterate(h, 0, sc, scl);
+    if (rc != QCPD_OK) return rc;
+    double rel = 0.0;
+    rc = explicit_residual(h, 0, &rel);  // also leaves J sol_y in wy_res for the read-out
+    if (rc != QCPD_OK) return rc;
+    launch_jvp_out(p, h->sol, h->wy_res, dx, dy, ds, st);
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipGetLastError());
+    *iters = h->host_st[0].iters;
+    return QCPD_OK;
+}
+
+// Sum of squares of n device entries, returned on the host (two small launches, then a copy)
+qcpd_status sumsq_host(qcpd_handle *h, const double *v, long long n, double *part, double *dout,
+                       double *out) {
+    hipStream_t st = h->stream;
+    if (n <= 0) {
+        *out = 0.0;
+        return QCPD_OK;
+    }
+    launch_sumsq(v, n, part, dout, st);
+    HIPCHK(hipMemcpyAsync(&h->host_st->tau_rhs, dout, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipGetLastError());
+    *out = h->host_st->tau_rhs;
+    return QCPD_OK;
 }
 
 }  // namespace
@@ -1288,6 +1383,81 @@ void qcpd_destroy(qcpd_handle *h) {
     if (!h) return;
     hipStreamSynchronize(h->stream);
     free_handle(h);
+}
+
+qcpd_status qcpd_proj_dual(qcpd_handle *h, const double *zy, double *out) {
+    if (!h || (h->p.m > 0 && (!zy || !out))) return QCPD_ERR_INVALID_ARG;
+    return project_dual(h, zy, out);
+}
+
+qcpd_status qcpd_resolve(const qcpd_csr *P, const qcpd_csr *A, const double *q, const double *b,
+                         const qcpd_cones *K, double *x, double *y, double *s,
+                         const qcpd_opts *opts, double tol, int32_t max_newton,
+                         qcpd_resolve_info *info, void *stream) {
+    if (info) memset(info, 0, sizeof(*info));
+    if (!(tol > 0.0) || max_newton < 0) return QCPD_ERR_INVALID_ARG;
+    qcpd_handle *h = nullptr;  // the handle at the warm start: tables, CSR copies, scratch
+    qcpd_status rc = qcpd_create(&h, P, A, q, b, K, x, y, s, opts, stream);
+    if (rc < 0) return rc;
+    struct Guard {
+        qcpd_handle *h;
+        ~Guard() { qcpd_destroy(h); }
+    } guard{h};
+    const Problem &p = h->p;
+    const int n = p.n, m = p.m;
+    hipStream_t st = h->stream;
+    double *eta, *g, *dx, *dy, *ds, *zP, *zA, *part, *dout, *sc, *scl;
+    ALLOC(eta, m); ALLOC(g, (long long)n + m); ALLOC(dx, n); ALLOC(dy, m); ALLOC(ds, m);
+    ALLOC(zP, p.nnzP); ALLOC(zA, p.nnzA); ALLOC(part, kSumsqParts); ALLOC(dout, 1);
+    ALLOC(sc, p.N); ALLOC(scl, p.N);
+    launch_fill(zP, p.nnzP, 0.0, st);
+    launch_fill(zA, p.nnzA, 0.0, st);
+    if (m) launch_sub(y, s, eta, m, st);
+    double qq = 0.0, bb = 0.0, gg = 0.0;
+    rc = sumsq_host(h, p.q, n, part, dout, &qq);
+    if (rc != QCPD_OK) return rc;
+    rc = sumsq_host(h, p.b, m, part, dout, &bb);
+    if (rc != QCPD_OK) return rc;
+    const double scale = 1.0 + std::sqrt(qq) + std::sqrt(bb);
+    int steps = 0;
+    long long lsqr = 0;
+    double res = 0.0;
+    bool conv = false;
+    for (;;) {
+        if (m) {  // y = Pi_{K*}(eta), s = y - eta
+            rc = project_dual(h, eta, y);
+            if (rc != QCPD_OK) return rc;
+            launch_sub(y, eta, s, m, st);
+        }
+        launch_kkt_map(p, x, y, eta, g, st);
+        rc = sumsq_host(h, g, (long long)n + m, part, dout, &gg);
+        if (rc != QCPD_OK) return rc;
+        res = std::sqrt(gg) / scale;
+        if (!(res > tol) || steps == max_newton) {
+            conv = res <= tol;
+            break;
+        }
+        // Newton step K_red step = -G with the factors of a handle at the current point
+        qcpd_handle *h1 = nullptr;
+        rc = qcpd_create(&h1, P, A, q, b, K, x, y, s, opts, stream);
+        if (rc < 0) return rc;
+        int it = 0;
+        rc = newton_step(h1, zP, zA, g, sc, scl, dx, dy, ds, &it);
+        qcpd_destroy(h1);
+        if (rc != QCPD_OK) return rc;
+        lsqr += it;
+        launch_newton_update(x, eta, dx, dy, ds, n, m, st);
+        ++steps;
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipGetLastError());
+    if (info) {
+        info->newton_iters = steps;
+        info->lsqr_iters = (int32_t)std::min<long long>(lsqr, INT32_MAX);
+        info->residual = res;
+        info->converged = conv ? 1 : 0;
+    }
+    return conv ? QCPD_OK : QCPD_WARN_NOT_CONVERGED;
 }
 
 }  // extern "C"

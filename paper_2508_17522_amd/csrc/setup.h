@@ -25,9 +25,20 @@ void launch_check_symmetric(const int *rp, const int *ci, const double *v, const
 void launch_px(const Problem &p, const RowGrid &g, double *c, double *xpx, double *partials,
                int *counter, hipStream_t s);
 void launch_sub(const double *a, const double *b, double *out, int n, hipStream_t s);
+// solution refinement: G(x, eta) of the QCP's KKT conditions at y = Pi_{K*}(eta) (n + m
+// entries), the Newton update x += dx, eta += dy - ds, and the sum of squares of n entries into
+// out[0] (part: kSumsqParts doubles of scratch)
+constexpr int kSumsqParts = 256;
+void launch_kkt_map(const Problem &p, const double *x, const double *y, const double *eta,
+                    double *g, hipStream_t s);
+void launch_newton_update(double *x, double *eta, const double *dx, const double *dy,
+                          const double *ds, int n, int m, hipStream_t s);
+void launch_sumsq(const double *v, long long n, double *part, double *out, hipStream_t s);
+
+// proj (optional): Pi_{K*}(z_y) of every cone row (zero and nonnegative rows included)
 void launch_cone_factors(const Problem &p, const ConeHost &ch, double *jdiag, double *soc_par,
                          double *exp_J, double *pool, int *nondiff, int *fail, int psd_lds,
-                         hipStream_t s);
+                         hipStream_t s, double *proj = nullptr);
 void launch_scales(const Problem &p, const RowGrid &g, double *dj, double *dv, double *partials,
                    int *counter, hipStream_t s, int do_tau = 1);
 int psd_factor_lds_bytes(int kmax);

@@ -162,16 +162,19 @@ __global__ void k_sub(const double *a, const double *b, double *out, int n) {
 
 constexpr double kKinkTol = 1e-10;
 
-// zero cone rows: the dual cone is R, J = 1. nonnegative rows: J = 1{z > 0}.
+// zero cone rows: the dual cone is R, J = 1. nonnegative rows: J = 1{z > 0}. Every factor
+// kernel also writes Pi_{K*}(z_y) of its rows to proj when that is given.
 __global__ void k_diag_factors(const double *zy, int n_zero, int n_diag, double *jdiag,
-                               int *nondiff) {
+                               int *nondiff, double *proj) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r < n_diag) {
+        const double z = zy[r];
         if (r < n_zero) {
             jdiag[r] = 1.0;
+            if (proj) proj[r] = z;
         } else {
-            const double z = zy[r];
             jdiag[r] = z > 0.0 ? 1.0 : 0.0;
+            if (proj) proj[r] = fmax(z, 0.0);
             if (fabs(z) <= kKinkTol) atomicOr(nondiff, 1);
         }
     }
@@ -179,7 +182,7 @@ __global__ void k_diag_factors(const double *zy, int n_zero, int n_diag, double 
 
 // second-order cone {(t, u) : ||u|| <= t}; cases tested in the order of the appendix.
 __global__ void k_soc_factors(const double *zy, const int *soc_row, const int *soc_dim, int n_soc,
-                              double *par, double *jdiag, int *nondiff) {
+                              double *par, double *jdiag, int *nondiff, double *proj) {
     const int cone = blockIdx.x * blockDim.x + threadIdx.x;
     if (cone >= n_soc) return;
     const int r0 = soc_row[cone], k = soc_dim[cone];
@@ -196,9 +199,13 @@ __global__ void k_soc_factors(const double *zy, const int *soc_row, const int *s
     if (nu <= -t) {
         pp[0] = 0.0; pp[1] = 0.0; pp[2] = 0.0; pp[3] = 0.0;
         for (int i = 0; i < k; ++i) jdiag[r0 + i] = 0.0;
+        if (proj)
+            for (int i = 0; i < k; ++i) proj[r0 + i] = 0.0;
     } else if (nu <= t) {
         pp[0] = 1.0; pp[1] = 0.0; pp[2] = 0.0; pp[3] = 0.0;
         for (int i = 0; i < k; ++i) jdiag[r0 + i] = 1.0;
+        if (proj)
+            for (int i = 0; i < k; ++i) proj[r0 + i] = zy[r0 + i];
     } else {
         const double inv = 1.0 / nu;
         const double c1 = 0.5 * (t + nu) * inv, c2 = 0.5 * t * inv;
@@ -207,6 +214,11 @@ __global__ void k_soc_factors(const double *zy, const int *soc_row, const int *s
         for (int i = 1; i < k; ++i) {
             const double uh = zy[r0 + i] * inv;
             jdiag[r0 + i] = c1 - c2 * uh * uh;
+        }
+        if (proj) {  // (t + |u|)/2 (1, u/|u|)
+            const double h = 0.5 * (t + nu);
+            proj[r0] = h;
+            for (int i = 1; i < k; ++i) proj[r0 + i] = h * zy[r0 + i] * inv;
         }
     }
 }
@@ -281,7 +293,7 @@ __device__ bool exp_root(double x0, double y0, double z0, double &r_out) {
 // matrix [[H, g], [g', 0]] with H = I + mu Hess(y e^{x/y}) and g = grad(y e^{x/y} - z),
 // evaluated as H^-1 - (H^-1 g)(H^-1 g)'/(g' H^-1 g).
 __global__ void k_exp_factors(const double *zy, int row0, const int *rows, int n_exp, double *Jout,
-                              double *jdiag, int *nondiff, int *fail) {
+                              double *jdiag, int *nondiff, int *fail, double *proj) {
     const int cone = blockIdx.x * blockDim.x + threadIdx.x;
     if (cone >= n_exp) return;
     const int r0 = rows ? rows[cone] : row0 + 3 * cone;
@@ -289,8 +301,10 @@ __global__ void k_exp_factors(const double *zy, int row0, const int *rows, int n
     const double scale = fmax(1.0, fmax(fabs(x0), fmax(fabs(y0), fabs(z0))));
     const double tol = kKinkTol * scale;
     double D[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // DPi_exp(p)
+    double ph[3] = {0.0, 0.0, 0.0};              // Pi_exp(p)
     if (exp_member(x0, y0, z0)) {
         D[0] = D[4] = D[8] = 1.0;
+        ph[0] = x0; ph[1] = y0; ph[2] = z0;
         if (y0 <= tol || z0 - y0 * exp(x0 / y0) <= tol) atomicOr(nondiff, 1);
     } else if (exp_dual_member(-x0, -y0, -z0)) {
         const double u = -x0, v = -y0, w = -z0;
@@ -298,6 +312,7 @@ __global__ void k_exp_factors(const double *zy, int row0, const int *rows, int n
     } else if (x0 < 0.0 && y0 < 0.0) {
         D[0] = 1.0;
         D[8] = z0 > 0.0 ? 1.0 : 0.0;
+        ph[0] = x0; ph[2] = fmax(z0, 0.0);
         if (fabs(z0) <= tol || x0 >= -tol || y0 >= -tol) atomicOr(nondiff, 1);
     } else {
         double r;
@@ -307,6 +322,7 @@ __global__ void k_exp_factors(const double *zy, int row0, const int *rows, int n
         }
         const double E = exp(r);
         const double yh = (x0 * r + y0 + z0 * E) / (r * r + 1.0 + E * E);
+        ph[0] = yh * r; ph[1] = yh; ph[2] = yh * E;
         const double g0 = E, g1 = (1.0 - r) * E, g2 = -1.0;
         const double mu = (x0 * g0 + y0 * g1 + z0 * g2) / (g0 * g0 + g1 * g1 + g2 * g2);
         if (yh <= tol || mu <= tol) atomicOr(nondiff, 1);
@@ -324,6 +340,8 @@ __global__ void k_exp_factors(const double *zy, int row0, const int *rows, int n
     double *J = Jout + 9 * cone;
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) J[3 * i + j] = (i == j ? 1.0 : 0.0) - D[3 * i + j];
+    if (proj)  // Moreau: Pi_{exp*}(z) = z + Pi_exp(-z)
+        for (int i = 0; i < 3; ++i) proj[r0 + i] = zy[r0 + i] + ph[i];
     jdiag[r0] = J[0];
     jdiag[r0 + 1] = J[4];
     jdiag[r0 + 2] = J[8];
@@ -348,11 +366,13 @@ __device__ inline double half_root(double x, double t) {
 // root r in (0, |z|) of r = f_x(r)^a f_y(r)^(1-a), found by bisection until the bracket stops
 // shrinking (the root is unique; the function is positive just above 0 and negative at |z|).
 __device__ void pow_jacobian(double x, double y, double z, double a, double tol, double D[9],
-                             int *nondiff) {
+                             int *nondiff, double ph[3]) {
     for (int i = 0; i < 9; ++i) D[i] = 0.0;
+    ph[0] = ph[1] = ph[2] = 0.0;  // Pi_pow,a(x, y, z)
     const double az = fabs(z);
     if (pow_member(x, y, z, a)) {
         D[0] = D[4] = D[8] = 1.0;
+        ph[0] = x; ph[1] = y; ph[2] = z;
         if (x <= tol || y <= tol || pow(x, a) * pow(y, 1.0 - a) - az <= tol) atomicOr(nondiff, 1);
         return;
     }
@@ -369,6 +389,7 @@ __device__ void pow_jacobian(double x, double y, double z, double a, double tol,
         D[0] = x > 0.0 ? 1.0 : 0.0;
         D[4] = y > 0.0 ? 1.0 : 0.0;
         D[8] = d;
+        ph[0] = fmax(x, 0.0); ph[1] = fmax(y, 0.0);
         if (fabs(x) <= tol || fabs(y) <= tol) atomicOr(nondiff, 1);
         return;
     }
@@ -388,6 +409,7 @@ __device__ void pow_jacobian(double x, double y, double z, double a, double tol,
     const double S = a * x / gx + (1.0 - a) * y / gy;
     const double L = 2.0 * (az - r) / (az + (az - 2.0 * r) * S);
     const double sz = z > 0.0 ? 1.0 : -1.0;
+    ph[0] = fx; ph[1] = fy; ph[2] = sz * r;
     const double m = (az - 2.0 * r) * r * L;
     D[0] = 0.5 + x / (2.0 * gx) + a * a * m / (gx * gx);
     D[1] = D[3] = (a - a * a) * m / (gx * gy);
@@ -403,7 +425,7 @@ __device__ void pow_jacobian(double x, double y, double z, double a, double tol,
 // dual cone is K_pow itself, J = DPi_pow(z). Cone i occupies rows row0 + 3 i ..; its J is the
 // 3 x 3 row-major matrix at Jout + 9 i.
 __global__ void k_pow_factors(const double *zy, int row0, int count, const double *par,
-                              double *Jout, double *jdiag, int *nondiff) {
+                              double *Jout, double *jdiag, int *nondiff, double *proj) {
     const int cone = blockIdx.x * blockDim.x + threadIdx.x;
     if (cone >= count) return;
     const int r0 = row0 + 3 * cone;
@@ -412,10 +434,12 @@ __global__ void k_pow_factors(const double *zy, int row0, int count, const doubl
     const double sg = dual ? 1.0 : -1.0;
     const double x0 = sg * zy[r0], y0 = sg * zy[r0 + 1], z0 = sg * zy[r0 + 2];
     const double scale = fmax(1.0, fmax(fabs(x0), fmax(fabs(y0), fabs(z0))));
-    double D[9];
-    pow_jacobian(x0, y0, z0, a, kKinkTol * scale, D, nondiff);
+    double D[9], ph[3];
+    pow_jacobian(x0, y0, z0, a, kKinkTol * scale, D, nondiff, ph);
     double *J = Jout + 9 * cone;
     for (int i = 0; i < 9; ++i) J[i] = dual ? D[i] : ((i % 4 == 0) ? 1.0 : 0.0) - D[i];
+    if (proj)  // dual power cone: Pi_pow(z); power cone: z + Pi_pow(-z) (Moreau)
+        for (int i = 0; i < 3; ++i) proj[r0 + i] = dual ? ph[i] : zy[r0 + i] + ph[i];
     jdiag[r0] = J[0];
     jdiag[r0 + 1] = J[4];
     jdiag[r0 + 2] = J[8];
@@ -432,7 +456,8 @@ __global__ void k_pow_factors(const double *zy, int row0, int count, const doubl
 __global__ __launch_bounds__(kBlock) void k_psd_factors(const double *zy, const int *psd_row,
                                                         const int *psd_k, const long long *psd_off,
                                                         double *pool, double *jdiag,
-                                                        int *nondiff, int *fail, int *psd_lr) {
+                                                        int *nondiff, int *fail, int *psd_lr,
+                                                        double *proj) {
     extern __shared__ double sm[];
     const int cone = blockIdx.x;
     const int k = psd_k[cone], r0 = psd_row[cone];
@@ -593,6 +618,16 @@ __global__ __launch_bounds__(kBlock) void k_psd_factors(const double *zy, const 
         jdiag[r0 + t] = acc;
     }
     (void)nr;
+    if (proj) {  // Pi = V diag(max(lambda, 0)) V' in svec (off-diagonals times sqrt 2)
+        for (int e = tid; e < k * k; e += kBlock) {
+            const int i = e / k, j = e % k;
+            if (i < j) continue;
+            double acc = 0.0;
+            for (int a = 0; a < k; ++a) acc += V[i * ld + a] * fmax(lam_s[a], 0.0) * V[j * ld + a];
+            const int t = j * k - (j * (j - 1)) / 2 + (i - j);
+            proj[r0 + t] = i == j ? acc : acc * 1.41421356237309504880;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -758,29 +793,97 @@ void launch_px(const Problem &p, const RowGrid &g, double *c, double *xpx, doubl
                int *counter, hipStream_t s) {
     hipLaunchKernelGGL(k_px, dim3(std::max(g.bx, 1)), dim3(kBlock), 0, s, p, g, c, xpx, partials, counter);
 }
+// ---------------------------------------------------------------------------------------
+// Solution refinement (the forward re-solve): the KKT map of the QCP at a point (x, eta),
+// with y = Pi_{K*}(eta) and s = y - eta (Moreau: y and s in K* and K, orthogonal),
+//   G(x, eta) = (P x + A' y + q, -A x + b - y + eta),
+// zero exactly at a primal-dual solution (Sec. 2.1 optimality conditions). One thread per
+// row of the n + m rows, the stored CSR copies of P, A and A'.
+// ---------------------------------------------------------------------------------------
+
+__global__ void k_kkt_map(Problem p, const double *x, const double *y, const double *eta,
+                          double *g) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = p.n, m = p.m;
+    if (i < n) {
+        double acc = p.q[i];
+        for (int k = p.Prp[i]; k < p.Prp[i + 1]; ++k) acc += p.Pv[k] * x[p.Pci[k]];
+        for (int k = p.Trp[i]; k < p.Trp[i + 1]; ++k) acc += p.Tv[k] * y[p.Tci[k]];
+        g[i] = acc;
+    } else if (i < (long long)n + m) {
+        const int r = (int)(i - n);
+        double acc = 0.0;
+        for (int k = p.Arp[r]; k < p.Arp[r + 1]; ++k) acc += p.Av[k] * x[p.Aci[k]];
+        g[i] = -acc + p.b[r] - y[r] + eta[r];
+    }
+}
+
+// x += dx, eta += dy - ds: the Newton step of the refinement from a derivative's outputs
+__global__ void k_newton_update(double *x, double *eta, const double *dx, const double *dy,
+                                const double *ds, int n, int m) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] += dx[i];
+    else if (i < (long long)n + m) eta[i - n] += dy[i - n] - ds[i - n];
+}
+
+// sum of squares: per-workgroup partial sums, then one workgroup adds them in a fixed order
+__global__ __launch_bounds__(kBlock) void k_sumsq_part(const double *v, long long n, double *part) {
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (long long)gridDim.x * kBlock)
+        a += v[i] * v[i];
+    block_sum3(a, b, c);
+    if (threadIdx.x == 0) part[blockIdx.x] = a;
+}
+__global__ __launch_bounds__(kBlock) void k_sum_final(const double *part, int np, double *out) {
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int i = threadIdx.x; i < np; i += kBlock) a += part[i];
+    block_sum3(a, b, c);
+    if (threadIdx.x == 0) out[0] = a;
+}
+
+void launch_kkt_map(const Problem &p, const double *x, const double *y, const double *eta,
+                    double *g, hipStream_t s) {
+    const long long rows = (long long)p.n + p.m;
+    if (rows > 0)
+        hipLaunchKernelGGL(k_kkt_map, dim3(div_up(rows, kBlock)), dim3(kBlock), 0, s, p, x, y, eta, g);
+}
+void launch_newton_update(double *x, double *eta, const double *dx, const double *dy,
+                          const double *ds, int n, int m, hipStream_t s) {
+    const long long rows = (long long)n + m;
+    if (rows > 0)
+        hipLaunchKernelGGL(k_newton_update, dim3(div_up(rows, kBlock)), dim3(kBlock), 0, s, x, eta,
+                           dx, dy, ds, n, m);
+}
+void launch_sumsq(const double *v, long long n, double *part, double *out, hipStream_t s) {
+    const int g = std::max(1, std::min(kSumsqParts, div_up(n, kBlock)));
+    hipLaunchKernelGGL(k_sumsq_part, dim3(g), dim3(kBlock), 0, s, v, n, part);
+    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kBlock), 0, s, part, g, out);
+}
+
 void launch_sub(const double *a, const double *b, double *out, int n, hipStream_t s) {
     if (n > 0) hipLaunchKernelGGL(k_sub, dim3(div_up(n, 256)), dim3(256), 0, s, a, b, out, n);
 }
 void launch_cone_factors(const Problem &p, const ConeHost &ch, double *jdiag, double *soc_par,
                          double *exp_J, double *pool, int *nondiff, int *fail, int psd_lds,
-                         hipStream_t s) {
+                         hipStream_t s, double *proj) {
     if (p.n_diag > 0)
         hipLaunchKernelGGL(k_diag_factors, dim3(div_up(p.n_diag, 256)), dim3(256), 0, s, p.zy,
-                           ch.n_zero, p.n_diag, jdiag, nondiff);
+                           ch.n_zero, p.n_diag, jdiag, nondiff, proj);
     if (p.n_soc > 0)
         hipLaunchKernelGGL(k_soc_factors, dim3(div_up(p.n_soc, 128)), dim3(128), 0, s, p.zy,
-                           p.soc_row, p.soc_dim, p.n_soc, soc_par, jdiag, nondiff);
+                           p.soc_row, p.soc_dim, p.n_soc, soc_par, jdiag, nondiff, proj);
     if (ch.n_exp > 0)
         hipLaunchKernelGGL(k_exp_factors, dim3(div_up(ch.n_exp, 64)), dim3(64), 0, s, p.zy,
-                           p.exp_row0, p.exp_rows, ch.n_exp, exp_J, jdiag, nondiff, fail);
+                           p.exp_row0, p.exp_rows, ch.n_exp, exp_J, jdiag, nondiff, fail, proj);
     if (ch.n_pow > 0)  // power cones follow the exponential cones (one contiguous row range)
         hipLaunchKernelGGL(k_pow_factors, dim3(div_up(ch.n_pow, 64)), dim3(64), 0, s, p.zy,
                            p.exp_row0 + 3 * ch.n_exp, ch.n_pow, ch.pow_par, exp_J + 9LL * ch.n_exp,
-                           jdiag, nondiff);
+                           jdiag, nondiff, proj);
     if (p.n_psd > 0) {
         (void)hipFuncSetAttribute((const void *)k_psd_factors, hipFuncAttributeMaxDynamicSharedMemorySize, psd_lds);
         hipLaunchKernelGGL(k_psd_factors, dim3(p.n_psd), dim3(kBlock), psd_lds, s, p.zy, p.psd_row,
-                           p.psd_k, p.psd_off, pool, jdiag, nondiff, fail, ch.psd_lr);
+                           p.psd_k, p.psd_off, pool, jdiag, nondiff, fail, ch.psd_lr, proj);
     }
 }
 void launch_scales(const Problem &p, const RowGrid &g, double *dj, double *dv, double *partials,
