@@ -1,9 +1,12 @@
 """torch.autograd integration: the solution map S(theta) = (x, y, s) of a QCP as a
 differentiable function of the data theta = (P values, A values, q, b).
 
-The forward pass does not solve the QCP: as in the paper (Sec. 2.2), the solution comes from
-an upstream solver and is passed in. It returns that solution and keeps a library handle
-built at it. The backward pass is the adjoint of the derivative (Sec. 3.2) evaluated by the
+The forward pass does not solve the QCP from scratch: as in the paper (Sec. 2.2), the
+solution comes from an upstream solver and is passed in. With refine_tol set in the
+structure, the point passed in is a warm start (a nearby solution, such as the previous one
+when theta moves in a learning loop, Sec. 3.4) that the library refines to a solution of the
+current data by Newton steps (qcpd_resolve) before building its handle there. The forward
+pass returns the solution and keeps a library handle built at it. The backward pass is the adjoint of the derivative (Sec. 3.2) evaluated by the
 HIP library (qcpd_vjp); forward-mode AD (torch.func.jvp / autograd.forward_ad) uses the
 derivative itself (Sec. 3.1, qcpd_jvp). Gradients for P and A are on their stored patterns;
 the gradient for P is symmetric on the pattern.
@@ -34,12 +37,25 @@ class QCPStructure:
     A_colind: torch.Tensor
     cones: api.Cones
     opts: Optional[api.Opts] = None
+    # refine the passed point to a solution of the current data first (None: take it as is)
+    refine_tol: Optional[float] = None
+    refine_max_newton: int = 20
 
 
 class _SolutionMap(torch.autograd.Function):
     @staticmethod
     def forward(ctx, P_val, A_val, q, b, x, y, s, structure: QCPStructure):
         st = structure
+        ctx.resolve_info = None
+        if st.refine_tol is not None:
+            x, y, s, info, status = api.qcpd_resolve(
+                (st.P_rowptr, st.P_colind, P_val.detach()), (st.A_rowptr, st.A_colind, A_val.detach()),
+                q.detach(), b.detach(), st.cones, x.detach(), y.detach(), s.detach(),
+                tol=st.refine_tol, max_newton=st.refine_max_newton, opts=st.opts)
+            ctx.resolve_info = info
+            if status != 0:
+                warnings.warn(f"qcpd_resolve: {api.qcpd_status_str(status)} "
+                              f"(steps {info.newton_iters}, residual {info.residual:.2e})")
         h = api.qcpd_create((st.P_rowptr, st.P_colind, P_val.detach()),
                             (st.A_rowptr, st.A_colind, A_val.detach()),
                             q.detach(), b.detach(), st.cones, x.detach(), y.detach(), s.detach(),
@@ -78,7 +94,8 @@ class _SolutionMap(torch.autograd.Function):
 
 
 def qcp_solution_map(P_val, A_val, q, b, x, y, s, structure: QCPStructure):
-    """(x, y, s) as a differentiable function of (P_val, A_val, q, b) at a given solution."""
+    """(x, y, s) as a differentiable function of (P_val, A_val, q, b) at a given solution, or
+    at the solution refined from the given point when structure.refine_tol is set."""
     return _SolutionMap.apply(P_val, A_val, q, b, x, y, s, structure)
 
 

@@ -112,3 +112,46 @@ def test_resolve_at_a_solution_takes_no_step_and_rejects_bad_arguments():
         Q.qcpd_resolve(t["P"], t["A"], t["q"], t["b"], cones_of(q), t["x"], t["y"], t["s"],
                        tol=0.0)
     assert e.value.status == Q.QCPD_ERR_INVALID_ARG
+
+
+def test_learning_loop_refines_and_differentiates():
+    """A small synthetic learning loop (Sec. 3.4 without its comparison systems): theta =
+    (q, b) moves by gradient steps on ||x*(theta) - x_target||^2; each forward refines the
+    previous solution to the current data (QCPStructure.refine_tol) and each backward is the
+    library's adjoint. Per step: the refined solution against the oracle's re-solve of the
+    same data from the same start (1e-9), the gradients against the oracle's dense adjoint at
+    that solution (1e-7); the loss decreases."""
+    q0 = instance(3)
+    t0 = to_device(q0)
+    st = Q.QCPStructure(t0["P"][0], t0["P"][1], t0["A"][0], t0["A"][1], cones_of(q0),
+                        Q.Opts(tol=1e-12, precond=Q.QCPD_PRECOND_EQUIL), refine_tol=1e-12)
+    rng = np.random.default_rng(12)
+    xt = q0.x + 0.1 * rng.standard_normal(q0.n)
+    xt_d = torch.tensor(xt, device="cuda:0")
+    qv, bv = t0["q"].clone(), t0["b"].clone()
+    x, y, s = t0["x"], t0["y"], t0["s"]
+    losses = []
+    for k in range(4):
+        qp = qv.clone().requires_grad_()
+        bp = bv.clone().requires_grad_()
+        xs, ys, ss = Q.qcp_solution_map(t0["P"][2], t0["A"][2], qp, bp, x, y, s, st)
+        loss = ((xs - xt_d) ** 2).sum()
+        loss.backward()
+        qk = E.with_data(q0, dq=qv.cpu().numpy() - q0.q, db=bv.cpu().numpy() - q0.b)
+        xr, yr, sr, res = D.newton_resolve(qk, x.cpu().numpy(), (y - s).cpu().numpy())
+        assert res < 1e-12
+        errs = [rel(a.detach().cpu().numpy(), b) for a, b in zip((xs, ys, ss), (xr, yr, sr))]
+        qk.x, qk.y, qk.s = xr, yr, sr
+        ref = D.vjp_dense(qk, 2.0 * (xr - xt), np.zeros(q0.m), np.zeros(q0.m))
+        gerr = max(rel(qp.grad.cpu().numpy(), ref[2]), rel(bp.grad.cpu().numpy(), ref[3]))
+        print(f"step {k}: loss {loss.item():.6e} solution {['%.1e' % e for e in errs]} "
+              f"gradient {gerr:.1e}", flush=True)
+        assert max(errs) <= 1e-9 and gerr <= 1e-7
+        losses.append(loss.item())
+        with torch.no_grad():  # steps of 1e-3 relative in theta keep each refinement local
+            g = torch.cat([qp.grad, bp.grad])
+            lr = 1e-3 * torch.cat([qv, bv]).norm() / g.norm()
+            qv -= lr * qp.grad
+            bv -= lr * bp.grad
+        x, y, s = xs.detach(), ys.detach(), ss.detach()
+    assert losses[-1] < losses[0]
