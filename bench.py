@@ -393,6 +393,70 @@ def run_kernels_only(args):
           flush=True)
 
 
+def run_resolve(args):
+    """The forward solve by refinement on the workload: theta moved by a seeded step of
+    relative size --resolve-step along random directions on the patterns, the old solution as
+    the starting point, Newton steps to --resolve-tol (qcpd_resolve). Timed with the GPU
+    synchronised on both sides; the oracle's dense re-solve of the same data is timed beside
+    it when n + m <= 4 000 (it factors the dense reduced KKT matrix at every step)."""
+    import numpy as np
+    import torch
+
+    import paper_2508_17522_amd as Q
+    import qcpgen
+    from qcpgen.torch_io import cones_of, to_device
+    q = qcpgen.make(args.workload, 0)
+    rng = np.random.default_rng([7, q.n, q.m])
+    h = args.resolve_step
+    dP = qcpgen.symmetric_on_pattern(rng, q.P, 1.0)
+    dA, dq, db = (rng.standard_normal(k) for k in (q.A.nnz, q.n, q.m))
+    P1 = q.P.copy()
+    P1.data = q.P.data + h * np.abs(q.P.data).mean() * dP
+    A1 = q.A.copy()
+    A1.data = q.A.data + h * np.abs(q.A.data).mean() * dA
+    q1 = q.q + h * np.abs(q.q).mean() * dq
+    b1 = q.b + h * np.abs(q.b).mean() * db
+    f = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda:0")
+    t = to_device(q)
+    Pd = (t["P"][0], t["P"][1], f(P1.data))
+    Ad = (t["A"][0], t["A"][1], f(A1.data))
+    prec = {"equil": Q.QCPD_PRECOND_EQUIL, "jacobi": Q.QCPD_PRECOND_JACOBI,
+            "none": Q.QCPD_PRECOND_NONE}[args.precond]
+    opts = Q.Opts(tol=args.tol, precond=prec, **layout_opts(args))
+    runs = []
+    for rep in range(args.steps + args.warmup):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, y, s, info, st = Q.qcpd_resolve(Pd, Ad, f(q1), f(b1), cones_of(q), t["x"], t["y"],
+                                           t["s"], tol=args.resolve_tol, opts=opts)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        print(f"[bench] resolve {rep + 1}: {dt:.3f} s, {info.newton_iters} steps, "
+              f"{info.lsqr_iters} LSQR iterations, residual {info.residual:.2e}",
+              file=sys.stderr, flush=True)
+        if rep >= args.warmup:
+            runs.append(dt)
+    moved = float(np.linalg.norm(x.cpu().numpy() - q.x) / max(np.linalg.norm(q.x), 1e-300))
+    out = {"resolve": {"workload": q.name, "theta_step": h, "tol": args.resolve_tol,
+                       "lsqr_tol": args.tol, "precond": args.precond,
+                       "seconds_median": float(np.median(runs)), "runs": len(runs),
+                       "newton_iters": info.newton_iters, "lsqr_iters": info.lsqr_iters,
+                       "residual": info.residual, "status": st,
+                       "relative_change_of_x": moved}}
+    if q.n + q.m <= 4000 and not args.no_cpu_baseline:
+        from oracle import derivative as D
+        from oracle import embedding as E
+        qp = E.with_data(q, h * np.abs(q.P.data).mean() * dP, h * np.abs(q.A.data).mean() * dA,
+                         h * np.abs(q.q).mean() * dq, h * np.abs(q.b).mean() * db)
+        t0 = time.perf_counter()
+        xr, yr, sr, res = D.newton_resolve(qp, q.x, q.y - q.s)
+        out["resolve"]["cpu_baseline"] = {
+            "seconds": time.perf_counter() - t0, "kind": "oracle", "residual": res,
+            "sample": "the oracle's dense semismooth Newton re-solve of the same data",
+            "max_rel_diff_x": float(np.linalg.norm(x.cpu().numpy() - xr) / np.linalg.norm(xr))}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -413,6 +477,12 @@ def main():
                     help="problems timed on the single-problem path for --workload batch")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain copy of MIB MiB (profiler byte-counter reference)")
+    ap.add_argument("--resolve", action="store_true",
+                    help="time the forward solve by refinement after a step in theta")
+    ap.add_argument("--resolve-step", type=float, default=1e-3,
+                    help="relative size of the step in theta for --resolve")
+    ap.add_argument("--resolve-tol", type=float, default=1e-10,
+                    help="stopping tolerance of the refinement for --resolve")
     ap.add_argument("--kernels-only", type=int, default=0, metavar="REPS",
                     help="only set up the workload and launch each loop kernel REPS times")
     ap.add_argument("--no-tune", action="store_true",
@@ -432,6 +502,9 @@ def main():
         return
     if args.kernels_only:
         run_kernels_only(args)
+        return
+    if args.resolve:
+        run_resolve(args)
         return
     if args.workload == "batch":
         run_batch(args)
