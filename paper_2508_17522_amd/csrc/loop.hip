@@ -241,6 +241,54 @@ __device__ inline double csr_dot4(const int *col, const double *val, int k0, int
     return acc;
 }
 
+// csr_dot4's first pass (entries k, k + L, k + 2L, k + 3L of a lane, clamped to the row's
+// last entry and, for an empty row, to entry 0) loaded ahead of other work, and the sum that
+// starts from it: the same terms in the same order as csr_dot4.
+struct Pass4 {
+    int j[4];
+    double v[4];
+};
+__device__ inline void pass4_load(const int *col, const double *val, int k, int k1, int L,
+                                  int off, Pass4 &ps) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int kk = max(min(k + u * L, k1 - 1), 0);
+        ps.j[u] = col[kk] + off;
+        ps.v[u] = val[kk];
+    }
+}
+template <bool SC>
+__device__ inline double csr_dot4_from(const Pass4 &ps, const int *col, const double *val,
+                                       int k0, int k1, int lane, int L, const double *x,
+                                       const double *sc, int off) {
+    double acc = 0.0;
+    int k = k0 + lane;
+    if (k < k1) {
+        double xv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) xv[u] = SC ? x[ps.j[u]] * sc[ps.j[u]] : x[ps.j[u]];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (k + u * L < k1) acc += ps.v[u] * xv[u];
+    }
+    for (k += 4 * L; k < k1; k += 4 * L) {
+        int j[4];
+        double v[4], xv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int kk = min(k + u * L, k1 - 1);
+            j[u] = col[kk] + off;
+            v[u] = val[kk];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) xv[u] = SC ? x[j[u]] * sc[j[u]] : x[j[u]];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (k + u * L < k1) acc += v[u] * xv[u];
+    }
+    return acc;
+}
+
 __device__ inline double csr_dot(const int *col, const double *val, int k0, int k1, int lane,
                                  int L, const double *x, const double *sc, int off) {
     return sc ? csr_dot4<true>(col, val, k0, k1, lane, L, x, sc, off)
@@ -1497,10 +1545,16 @@ __device__ inline void xs_pre(const Problem &p, const StepArgs &a, const Ptrs &q
     int idx = -1;
     if (xr) {
         if (row < n) {
-            acc = csr_dot_quads(p.Prp4, p.Pc4, p.Pv4, row, lane, L, xs);
+            // the first pass of the A' sums loaded before P's quads: its column and value
+            // loads are in flight while P's sums run, its gathers follow them
             const int t0 = p.Trp[row], t1 = p.Trp[row + 1];
-            if (FT) accT = csr_dot(p.Tci, q.Tv, t0, t1, lane, L, a.in, q.gsc, n);
-            else accT = csr_dot4<false>(p.Tci, p.Tv, t0, t1, lane, L, a.wy, nullptr, 0);
+            const double *Tv = FT ? q.Tv : p.Tv;
+            Pass4 tp;
+            pass4_load(p.Tci, Tv, t0 + lane, t1, L, FT ? n : 0, tp);
+            acc = csr_dot_quads(p.Prp4, p.Pc4, p.Pv4, row, lane, L, xs);
+            if (!FT) accT = csr_dot4_from<false>(tp, p.Tci, Tv, t0, t1, lane, L, a.wy, nullptr, 0);
+            else if (q.gsc) accT = csr_dot4_from<true>(tp, p.Tci, Tv, t0, t1, lane, L, a.in, q.gsc, n);
+            else accT = csr_dot4_from<false>(tp, p.Tci, Tv, t0, t1, lane, L, a.in, nullptr, n);
             idx = row;
         }
     } else if (row < m) {
