@@ -1541,8 +1541,29 @@ __device__ inline void xs_pre(const Problem &p, const StepArgs &a, const Ptrs &q
     const int L = xr ? g.lx : g.ly;
     const long long gt = (long long)(xr ? wb : wb - g.bxw) * kWave + lane64;
     const int row = (int)(gt / L), lane = (int)(gt & (L - 1));
-    double acc = 0.0, accT = 0.0;
+    // this thread's output entry (lane 0 of its row group) and its operands, loaded before
+    // the sums so that they arrive with them (no arithmetic on them until the sums are done:
+    // a product here would wait for the loads before the sums' own loads are issued)
     int idx = -1;
+    if (lane == 0) {
+        if (xr) idx = row < n ? row : -1;
+        else if (row < m) idx = n + row;
+        else if (!FT && row == m) idx = N - 1;
+    }
+    double coef = 0.0, self = 0.0, self_sc = 1.0, aux = 0.0;
+    bool cone_row = false;
+    if (idx >= 0 && idx < n) {
+        coef = FT ? p.c[idx] : p.q[idx];
+    } else if (idx >= n && idx < N - 1) {
+        const int y = idx - n;
+        self = a.in[idx];
+        if (q.isc) self_sc = q.isc[idx];
+        coef = p.b[y];
+        cone_row = FT && y >= p.n_diag;  // its raw row goes to the cone launch
+        if (!cone_row) aux = FT ? p.jdiag[y] : a.wy[y];
+    }
+    if (idx >= 0 && !cone_row) fin_load(a, q, idx, r.f);
+    double acc = 0.0, accT = 0.0;
     if (xr) {
         if (row < n) {
             // the first pass of the A' sums loaded before P's quads: its column and value
@@ -1555,37 +1576,21 @@ __device__ inline void xs_pre(const Problem &p, const StepArgs &a, const Ptrs &q
             if (!FT) accT = csr_dot4_from<false>(tp, p.Tci, Tv, t0, t1, lane, L, a.wy, nullptr, 0);
             else if (q.gsc) accT = csr_dot4_from<true>(tp, p.Tci, Tv, t0, t1, lane, L, a.in, q.gsc, n);
             else accT = csr_dot4_from<false>(tp, p.Tci, Tv, t0, t1, lane, L, a.in, nullptr, n);
-            idx = row;
         }
     } else if (row < m) {
         acc = csr_dot_quads(p.Arp4, p.Ac4, p.Av4, row, lane, L, xs);
-        idx = n + row;
-    } else if (!FT && row == m) {
-        idx = N - 1;
     }
     r.acc = group_sum_dpp(acc, L);
     r.accT = group_sum_dpp(accT, L);
-    idx = lane == 0 ? idx : -1;
-    // operands in locals, stored once (a field chosen per branch would go through memory)
-    double coef = 0.0, self = 0.0, aux = 0.0;
-    if (idx >= 0 && idx < n) {
-        coef = FT ? p.c[idx] : p.q[idx];
-    } else if (idx >= n && idx < N - 1) {
-        const int y = idx - n;
-        self = in_raw(a, q, idx);
-        coef = p.b[y];
-        if (FT && y >= p.n_diag) {  // a cone row: its raw row for the cone launch
-            a.tmp[idx] = r.acc - coef * in_N_raw - self;
-            idx = -1;
-        } else {
-            aux = FT ? p.jdiag[y] : a.wy[y];
-        }
+    if (q.isc) self *= self_sc;  // in_raw of the row's own entry
+    if (cone_row) {
+        a.tmp[idx] = r.acc - coef * in_N_raw - self;
+        idx = -1;
     }
     r.idx = idx;
     r.coef = coef;
     r.self = self;
     r.aux = aux;
-    if (idx >= 0) fin_load(a, q, idx, r.f);
 }
 
 template <bool FT>
