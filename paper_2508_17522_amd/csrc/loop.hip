@@ -476,8 +476,28 @@ __device__ inline void rows_pre(const Problem &p, const StepArgs &a, const Ptrs 
     const int L = xr ? g.lx : g.ly;
     const long long gt = (long long)(xr ? vb : vb - g.bx) * kBlock + tid;
     const int row = (int)(gt / L), lane = (int)(gt & (L - 1));
-    double acc = 0.0, accT = 0.0;
+    // the output entry of lane 0 of each row group and its operands, loaded before the sums
+    // (no arithmetic on them until the sums are done)
     int idx = -1;
+    if (lane == 0) {
+        if (xr) idx = row < n ? row : -1;
+        else if (row < m) idx = n + row;
+        else if (row == m) idx = N - 1;
+    }
+    double qb = 0.0, self = 0.0, self_sc = 1.0, wyr = 0.0;
+    if (idx >= 0) {
+        fin_load(a, q, idx, r.f);
+        if (idx < n) {
+            qb = p.q[idx];
+        } else if (idx < N - 1) {
+            const int y = idx - n;
+            qb = p.b[y];
+            self = a.in[idx];
+            if (q.isc) self_sc = q.isc[idx];
+            wyr = a.wy[y];
+        }
+    }
+    double acc = 0.0, accT = 0.0;
     if (xr) {
         if (row < n) {
             const int k0 = p.Prp[row], k1 = p.Prp[row + 1];
@@ -485,34 +505,16 @@ __device__ inline void rows_pre(const Problem &p, const StepArgs &a, const Ptrs 
             // two separate passes measure faster here than csr_dot_pair (fewer registers)
             acc = csr_dot_d<DEEP>(p.Pci, q.Pv, k0, k1, lane, L, a.in, q.gsc, 0);
             accT = csr_dot_d<DEEP>(p.Tci, p.Tv, t0, t1, lane, L, a.wy, nullptr, 0);
-            idx = row;
         }
-    } else {
-        if (row < m) {
-            const int k0 = p.Arp[row], k1 = p.Arp[row + 1];
-            acc = csr_dot_d<DEEP>(p.Aci, q.Av, k0, k1, lane, L, a.in, q.gsc, 0);
-            idx = n + row;
-        } else if (row == m) {
-            idx = N - 1;
-        }
+    } else if (row < m) {
+        const int k0 = p.Arp[row], k1 = p.Arp[row + 1];
+        acc = csr_dot_d<DEEP>(p.Aci, q.Av, k0, k1, lane, L, a.in, q.gsc, 0);
     }
     r.acc = group_sum_dpp(acc, L);
     r.accT = group_sum_dpp(accT, L);
-    r.idx = (lane == 0) ? idx : -1;
-    double qb = 0.0, self = 0.0, wyr = 0.0;
-    if (r.idx >= 0) {
-        fin_load(a, q, r.idx, r.f);
-        if (r.idx < n) {
-            qb = p.q[r.idx];
-        } else if (r.idx < N - 1) {
-            const int y = r.idx - n;
-            qb = p.b[y];
-            self = in_raw(a, q, r.idx);
-            wyr = a.wy[y];
-        }
-    }
+    r.idx = idx;
     r.qb = qb;
-    r.self = self;
+    r.self = q.isc ? self * self_sc : self;  // in_raw of the row's own entry
     r.wyr = wyr;
 }
 
