@@ -466,6 +466,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precond", default="equil", choices=["equil", "jacobi", "none"])
+    ap.add_argument("--solver", default="lsqr", choices=["lsqr", "lsmr"],
+                    help="the Krylov method of the derivative solves (LSMR: the paper's)")
     ap.add_argument("--no-plain", action="store_true",
                     help="skip the plain Jacobi-preconditioned LSQR comparison")
     ap.add_argument("--plain-max-iter", type=int, default=100000,
@@ -526,7 +528,8 @@ def main():
     prec = PREC[args.precond]
     eng = {"auto": Q.QCPD_ENGINE_AUTO, "graph": Q.QCPD_ENGINE_GRAPH,
            "persistent": Q.QCPD_ENGINE_PERSISTENT}[args.engine]
-    opts = Q.Opts(tol=args.tol, precond=prec, engine=eng, **layout_opts(args))
+    solver = {"lsqr": Q.QCPD_SOLVER_LSQR, "lsmr": Q.QCPD_SOLVER_LSMR}[args.solver]
+    opts = Q.Opts(tol=args.tol, precond=prec, engine=eng, solver=solver, **layout_opts(args))
     outs = dict(dx=torch.empty(q.n, dtype=torch.float64, device=dev),
                 dy=torch.empty(q.m, dtype=torch.float64, device=dev),
                 ds=torch.empty(q.m, dtype=torch.float64, device=dev),
@@ -613,7 +616,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": q.name, "n": q.n, "m": q.m, "nnz_P": int(q.P.nnz),
                    "nnz_A": int(q.A.nnz), "tol": args.tol, "precond": args.precond,
-                   "engine": args.engine,
+                   "engine": args.engine, "solver": args.solver,
                    "cones": {"zero": q.cones.n_zero, "nonneg": q.cones.n_nonneg,
                              "soc": len(q.cones.soc), "psd": len(q.cones.psd),
                              "exp": q.cones.n_exp}},
