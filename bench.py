@@ -495,8 +495,8 @@ def main():
                          "repeatable")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only; the derivative of one QCP is not "
-              "split across GPUs (see DESIGN.md for how it would shard).", file=sys.stderr)
+        print("bench.py: measures one GPU only (--gpus 1); the derivative of one QCP is not "
+              "split across GPUs.", file=sys.stderr)
         sys.exit(2)
 
     if args.copy_calibration:
