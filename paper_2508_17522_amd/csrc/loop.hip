@@ -818,11 +818,13 @@ __device__ inline dbl4 mfma_tile(int i0, int j0, AF af, BF bf) {
 // order); W and H are KP x 16 panels in the T region. Bs[:, S] comes from B in LDS, else
 // from the KP x 16 panel of B's first columns staged after W and H (KP = 64: the cone
 // launch stages it with V). Waves own whole tiles: the first three products have
-// KP / 16 <= 4 of them, one per wave.
-template <int KP>
+// KP / 16 <= 4 of them, one per wave. KS: the k-steps of 4 of the first three products' sums
+// (KP / 4, or fewer when the order leaves the last rows and columns of X and V zero).
+template <int KP, int KS = KP / 4>
 __device__ inline void psd_apply_lr(int k, int c, bool neg, const PsdLds &L, double *sm,
                                     const double *Bg) {
-    constexpr int ld = KP + 1, mat = KP * ld, lc = 17, MT = KP / 16, KS = KP / 4;
+    constexpr int ld = KP + 1, mat = KP * ld, lc = 17, MT = KP / 16;
+    static_assert(KS >= 1 && KS <= KP / 4, "steps within the padded order");
     static_assert(2 * KP * lc <= mat, "two KP x 16 panels fit in the T region");
     static_assert(MT <= kBlock / kWave, "one row tile per wave");
     double *X = sm, *W = sm + mat, *H = sm + mat + KP * lc;
@@ -911,6 +913,7 @@ __device__ __forceinline__ void psd_apply_sel(const int *psd_lr, int cone, int k
         const int lr = psd_lr[cone], c = lr & 255;
         if (c <= 16) {
             if (L.kp == 48) psd_apply_lr<48>(k, c, lr >= 256, L, sm, Bg);
+            else if (k <= 52) psd_apply_lr<64, 13>(k, c, lr >= 256, L, sm, Bg);  // 13 k-steps
             else psd_apply_lr<64>(k, c, lr >= 256, L, sm, Bg);
             return;
         }
