@@ -803,6 +803,38 @@ __device__ inline dbl4 mfma_tile(int i0, int j0, AF af, BF bf) {
     return acc0 + acc1;
 }
 
+// The last product of the low-rank Jacobian: Y = U V_S' + V_S U' (neg: X minus it) on the
+// lower triangle of 16 x 16 tiles, as the product of the KP x 8 CS panel [U_:, <4CS | V_:, <4CS]
+// with [V_:, <4CS | U_:, <4CS]' (U's columns from c <= 4 CS on are zero, so the columns
+// dropped add nothing). Tiles t = wave, wave + 4, ... of the lower triangle in row order; a
+// wave short of its last tile recomputes tile 0 and drops the result. W holds U (KP x 17).
+template <int KP, int CS>
+__device__ inline void lr_sym_product(double *X, const double *W, const double *V, bool neg) {
+    constexpr int ld = KP + 1, lc = 17, MT = KP / 16;
+    constexpr int NLT = MT * (MT + 1) / 2, NJ = (NLT + kBlock / kWave - 1) / (kBlock / kWave);
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int li = lane & 15, lk = lane >> 4;
+    auto af = [&](int i, int kk) { return kk < 4 * CS ? W[i * lc + kk] : V[i * ld + kk - 4 * CS]; };
+    auto bf = [&](int kk, int j) { return kk < 4 * CS ? V[j * ld + kk] : W[j * lc + kk - 4 * CS]; };
+    dbl4 acc[NJ];
+    int ti[NJ], tj[NJ];
+#pragma unroll
+    for (int jn = 0; jn < NJ; ++jn) {
+        const int t = wave + jn * (kBlock / kWave), tt = t < NLT ? t : 0;
+        ti[jn] = tt >= 6 ? 3 : tt >= 3 ? 2 : tt >= 1 ? 1 : 0;
+        tj[jn] = tt - ti[jn] * (ti[jn] + 1) / 2;
+        acc[jn] = mfma_tile<2 * CS>(16 * ti[jn], 16 * tj[jn], af, bf);
+    }
+#pragma unroll
+    for (int jn = 0; jn < NJ; ++jn) {
+        if (wave + jn * (kBlock / kWave) >= NLT) break;
+        for (int r = 0; r < 4; ++r) {
+            double &x = X[(16 * ti[jn] + lk + 4 * r) * ld + 16 * tj[jn] + li];
+            x = neg ? x - acc[jn][r] : acc[jn][r];
+        }
+    }
+}
+
 // Low-rank form of the same Jacobian, for a cone whose eigenvalues leave c <= 16 on one side
 // of zero: setup stores those eigenpairs first in V and B (S, the first c columns). With
 // M = V'XV and Bs = B (S: eigenvalues >= 0) or 1 - B (S: eigenvalues < 0), both equal to one
@@ -863,28 +895,14 @@ __device__ inline void psd_apply_lr(int k, int c, bool neg, const PsdLds &L, dou
         for (int r = 0; r < 4; ++r) W[(16 * wave + lk + 4 * r) * lc + li] = a[r];
     }
     __syncthreads();
-    // Y = U V_S' + V_S U' (or X minus it) on tile (ti, tj), ti >= tj: tiles t = wave,
-    // wave + 4, ... of the lower triangle in row order. A wave short of its last tile
-    // recomputes tile 0 and drops the result.
-    constexpr int NLT = MT * (MT + 1) / 2, NJ = (NLT + kBlock / kWave - 1) / (kBlock / kWave);
-    auto af = [&](int i, int kk) { return kk < 16 ? W[i * lc + kk] : V[i * ld + kk - 16]; };
-    auto bf = [&](int kk, int j) { return kk < 16 ? V[j * ld + kk] : W[j * lc + kk - 16]; };
-    dbl4 acc[NJ];
-    int ti[NJ], tj[NJ];
-#pragma unroll
-    for (int jn = 0; jn < NJ; ++jn) {
-        const int t = wave + jn * (kBlock / kWave), tt = t < NLT ? t : 0;
-        ti[jn] = tt >= 6 ? 3 : tt >= 3 ? 2 : tt >= 1 ? 1 : 0;
-        tj[jn] = tt - ti[jn] * (ti[jn] + 1) / 2;
-        acc[jn] = mfma_tile<8>(16 * ti[jn], 16 * tj[jn], af, bf);
-    }
-#pragma unroll
-    for (int jn = 0; jn < NJ; ++jn) {
-        if (wave + jn * (kBlock / kWave) >= NLT) break;
-        for (int r = 0; r < 4; ++r) {
-            double &x = X[(16 * ti[jn] + lk + 4 * r) * ld + 16 * tj[jn] + li];
-            x = neg ? x - acc[jn][r] : acc[jn][r];
-        }
+    // Y = U V_S' + V_S U' (or X minus it) on the lower tiles, over the 4 CS columns of each
+    // panel that can be nonzero (U's columns from c on are zero)
+    switch ((c + 3) >> 2) {
+    case 0:
+    case 1: lr_sym_product<KP, 1>(X, W, V, neg); break;
+    case 2: lr_sym_product<KP, 2>(X, W, V, neg); break;
+    case 3: lr_sym_product<KP, 3>(X, W, V, neg); break;
+    default: lr_sym_product<KP, 4>(X, W, V, neg); break;
     }
     __syncthreads();
 }
