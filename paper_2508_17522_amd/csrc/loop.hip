@@ -706,6 +706,29 @@ __device__ inline void exp_apply(const double *J, int i0, IN in, OUT out) {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
+// The K = 4 KS sum of one 16 x 16 tile, lanes and accumulator entries as in mfma_product below:
+// all 2 KS operands are loaded before the first product (one wave per SIMD: nothing else
+// would hide the LDS latency), even and odd steps in two accumulators.
+template <int KS, class AF, class BF>
+__device__ inline dbl4 mfma_tile(int i0, int j0, AF af, BF bf) {
+    const int lane = threadIdx.x & (kWave - 1), li = lane & 15, lk = lane >> 4;
+    double av[KS], bv[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+        av[s] = af(i0 + li, 4 * s + lk);
+        bv[s] = bf(4 * s + lk, j0 + li);
+    }
+    dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s + 1 < KS; s += 2) {
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], bv[s], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s + 1], bv[s + 1], acc1, 0, 0, 0);
+    }
+    if constexpr (KS % 2 == 1)
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[KS - 1], bv[KS - 1], acc0, 0, 0, 0);
+    return acc0 + acc1;
+}
+
 // One KP x KP product C = A B on the FP64 matrix cores, operands read through af(i, kk) and
 // bf(kk, j) (LDS, zero beyond the cone's order): wave w computes the 16 x 16 tiles w, w + 4,
 // ... in row-major tile order with V_MFMA_F64_16X16X4F64. In step s lane l supplies
@@ -713,17 +736,24 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 // C[i0 + 4r + l/16][j0 + l%16]. The operands of a chunk of up to eight steps (a divisor of
 // the step count: six for KP = 48) are loaded before its first product, and even and odd
 // steps accumulate separately (two short dependency chains instead of one long one).
-// epi(i, j, acc) receives i = i0 + l/16 (rows i + 4r) and j = j0 + l%16.
-template <int KP, class AF, class BF, class EPI>
+// epi(i, j, acc) receives i = i0 + l/16 (rows i + 4r) and j = j0 + l%16. KS < KP / 4: the
+// sum over the first 4 KS entries of K only (the rest of A's columns or B's rows are zero),
+// its operands all loaded ahead.
+template <int KP, int KS = KP / 4, class AF, class BF, class EPI>
 __device__ inline void mfma_product(AF af, BF bf, EPI epi) {
     constexpr int NT = KP / 16, NS = KP / 4;
     constexpr int CH = NS % 8 == 0 ? 8 : NS % 6 == 0 ? 6 : 4;
     static_assert(NS % CH == 0 && CH % 2 == 0, "a chunk must divide the steps into pairs");
+    static_assert(KS == NS || KS <= 8, "a cut sum is loaded whole");
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     const int li = lane & 15, lk = lane >> 4;
 #pragma unroll 1
     for (int t = wave; t < NT * NT; t += kBlock / kWave) {
         const int i0 = (t / NT) * 16, j0 = (t % NT) * 16;
+        if constexpr (KS < NS) {
+            epi(i0 + lk, j0 + li, mfma_tile<KS>(i0, j0, af, bf));
+            continue;
+        }
         dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 1
         for (int s0 = 0; s0 < NS; s0 += CH) {
@@ -748,8 +778,9 @@ __device__ inline void mfma_product(AF af, BF bf, EPI epi) {
 // in the X region (zero beyond the order), with V (and B) staged in LDS as KP x (KP + 1)
 // matrices; the four products on the matrix cores. Y replaces X (zero beyond the order, as
 // V is). The callers write X from the svec rows and read Y back into them (svec_rc), so the
-// products themselves do no index arithmetic.
-template <int KP>
+// products themselves do no index arithmetic. KS < KP / 4 (orders up to 4 KS): each product's
+// sum over the first 4 KS entries only, those beyond the order being zero in X, V and T.
+template <int KP, int KS = KP / 4>
 __device__ inline void psd_apply_kp(int k, const PsdLds &L, double *sm, const double *Bg) {
     constexpr int ld = KP + 1, mat = KP * ld;
     double *X = sm, *T = sm + mat;
@@ -761,9 +792,9 @@ __device__ inline void psd_apply_kp(int k, const PsdLds &L, double *sm, const do
     auto to_t = [&](int i, int j, const dbl4 &c) {
         for (int r = 0; r < 4; ++r) T[(i + 4 * r) * ld + j] = c[r];
     };
-    mfma_product<KP>(xm, vf, to_t);  // T = X V
+    mfma_product<KP, KS>(xm, vf, to_t);  // T = X V
     __syncthreads();
-    mfma_product<KP>(vt, tf, [&](int i, int j, const dbl4 &c) {  // X = B o (V'T)
+    mfma_product<KP, KS>(vt, tf, [&](int i, int j, const dbl4 &c) {  // X = B o (V'T)
         for (int r = 0; r < 4; ++r) {
             const int ii = i + 4 * r;
             double bij = 0.0;
@@ -772,35 +803,12 @@ __device__ inline void psd_apply_kp(int k, const PsdLds &L, double *sm, const do
         }
     });
     __syncthreads();
-    mfma_product<KP>(vf, xm, to_t);  // T = V X
+    mfma_product<KP, KS>(vf, xm, to_t);  // T = V X
     __syncthreads();
-    mfma_product<KP>(tf, vt, [&](int i, int j, const dbl4 &c) {  // X = Y = T V'
+    mfma_product<KP, KS>(tf, vt, [&](int i, int j, const dbl4 &c) {  // X = Y = T V'
         for (int r = 0; r < 4; ++r) X[(i + 4 * r) * ld + j] = c[r];
     });
     __syncthreads();
-}
-
-// The K = 4 KS sum of one 16 x 16 tile, lanes and accumulator entries as in mfma_product:
-// all 2 KS operands are loaded before the first product (one wave per SIMD: nothing else
-// would hide the LDS latency), even and odd steps in two accumulators.
-template <int KS, class AF, class BF>
-__device__ inline dbl4 mfma_tile(int i0, int j0, AF af, BF bf) {
-    const int lane = threadIdx.x & (kWave - 1), li = lane & 15, lk = lane >> 4;
-    double av[KS], bv[KS];
-#pragma unroll
-    for (int s = 0; s < KS; ++s) {
-        av[s] = af(i0 + li, 4 * s + lk);
-        bv[s] = bf(4 * s + lk, j0 + li);
-    }
-    dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int s = 0; s + 1 < KS; s += 2) {
-        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], bv[s], acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s + 1], bv[s + 1], acc1, 0, 0, 0);
-    }
-    if constexpr (KS % 2 == 1)
-        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[KS - 1], bv[KS - 1], acc0, 0, 0, 0);
-    return acc0 + acc1;
 }
 
 // The last product of the low-rank Jacobian: Y = U V_S' + V_S U' (neg: X minus it) on the
@@ -916,7 +924,10 @@ __device__ inline void psd_apply(int k, const PsdLds &L, double *sm, const doubl
     }
     switch (L.kp) {
     case 16: psd_apply_kp<16>(k, L, sm, Bg); break;
-    case 32: psd_apply_kp<32>(k, L, sm, Bg); break;
+    case 32:  // orders 17-20: sums over the order only (5 k-steps)
+        if (k <= 20) psd_apply_kp<32, 5>(k, L, sm, Bg);
+        else psd_apply_kp<32>(k, L, sm, Bg);
+        break;
     case 48: psd_apply_kp<48>(k, L, sm, Bg); break;
     default: psd_apply_kp<64>(k, L, sm, Bg); break;
     }
