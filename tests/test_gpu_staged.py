@@ -3,7 +3,8 @@ with P and A gather from LDS; the cones of the product with F' in a second launc
 their raw rows from a buffer, PSD cones of order 33-64 with at most 16 eigenvalues on one
 side of zero through the low-rank form of their Jacobian), forced on problems small enough
 for the dense oracle: JVP and VJP against its implicit-function solve (relative error <= 1e-7
-at tolerance 1e-12) with every cone type, both sides of the low-rank form, LSQR and LSMR,
+at tolerance 1e-12) with every cone type, both sides of the low-rank form (smaller sides of
+2 to 15 eigenvalues, orders 34 to 60), LSQR and LSMR,
 the default launch shape and one with far fewer workgroups than row blocks, a problem
 without cone units, and a reduced instance of the n = 20 000 workload's shape. The
 full-size workload runs this layout by default (its own tests)."""
@@ -50,12 +51,26 @@ def psd_negative_side():
                               dpow_alphas=tuple(rng.uniform(0.1, 0.9, 4)))
 
 
+def psd_wide_side(order, ranks, n):
+    """One PSD cone of order 53-64 (padded order 64, sums over all 16 k-steps) whose smaller
+    side holds 13-16 eigenvalues: the low-rank Jacobian's symmetric product over its whole
+    32-column panel."""
+    rng = np.random.default_rng(11)
+    return qcpgen.small_mixed(3, n=n, n_zero=37, n_nonneg=260, soc=(3, 4, 5, 6, 7, 8) * 5,
+                              psd=(4, order), n_exp=23, A_density=0.04, P_rank=150,
+                              P_eps=1e-2, nonneg_active=10, psd_ranks=ranks,
+                              pow_alphas=tuple(rng.uniform(0.1, 0.9, 6)),
+                              dpow_alphas=tuple(rng.uniform(0.1, 0.9, 4)))
+
+
 CASES = {
     "small": lambda: qcpgen.small_mixed(0),
     "medium": medium,
     "psd_negative_side": psd_negative_side,
     "tiny_qp": lambda: qcpgen.tiny_qp(1),   # zero and nonnegative rows only: no cone launch
     "reduced_large": lambda: qcpgen.large_psd_soc(0, scale=0.04),
+    "psd60_positive_15": lambda: psd_wide_side(60, (2, 15), 900),
+    "psd53_negative_13": lambda: psd_wide_side(53, (2, 40), 1500),
 }
 
 
@@ -88,6 +103,8 @@ def check(h, t, q, tag):
     ("psd_negative_side", Q.QCPD_PRECOND_EQUIL, Q.QCPD_SOLVER_LSQR),
     ("tiny_qp", Q.QCPD_PRECOND_JACOBI, Q.QCPD_SOLVER_LSQR),
     ("reduced_large", Q.QCPD_PRECOND_EQUIL, Q.QCPD_SOLVER_LSQR),
+    ("psd60_positive_15", Q.QCPD_PRECOND_EQUIL, Q.QCPD_SOLVER_LSQR),
+    ("psd53_negative_13", Q.QCPD_PRECOND_EQUIL, Q.QCPD_SOLVER_LSQR),
 ])
 def test_staged_loop_matches_dense_oracle(case, precond, solver):
     q = CASES[case]()
