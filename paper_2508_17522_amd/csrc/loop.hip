@@ -1173,15 +1173,15 @@ __device__ inline void unit_pre(const Problem &p, const StepArgs &a, const Ptrs 
             // the cone launch: all of V (and B) in flight with the rows' loads, and with
             // kp = 64 (B not in LDS) the panel of B's first 16 columns for the low-rank form
             // after the W and H panels of the T region (also staged when it goes unused).
-            // Thread tid takes column c = tid % 64 of rows tid / 64 + 4 j (of the panel:
-            // column tid % 16 of rows tid / 16 + 16 j); every load is issued, from a valid
+            // Thread tid takes column c = tid % 64 of rows tid / 64 + 4 j, of V and of the
+            // panel's transpose (B is symmetric: column j of the panel is row j of B, whole
+            // lines instead of 16 entries of every row); every load is issued, from a valid
             // address, and its value kept or replaced by zero.
             constexpr int RJ = 16, RB = 4;
-            static_assert(RJ * (kBlock / 64) >= 64 && RB * (kBlock / 16) >= 64, "one batch");
-            const int c = tid & 63, rq = tid / 64, cb = tid & 15, rqb = tid / 16;
+            static_assert(RJ * (kBlock / 64) >= 64 && RB * (kBlock / 64) >= 16, "one batch");
+            const int c = tid & 63, rq = tid / 64;
             const bool cin = c < k, panel = LR && kp == 64 && !B;
             const double *vp = Vg + (cin ? c : 0) + rq * k, *bq = Bg + (cin ? c : 0) + rq * k;
-            const double *pp = Bg + cb + rqb * k;
             double vv[RJ], bb[RJ], bp[RB];
 #pragma unroll
             for (int j = 0; j < RJ; ++j) {
@@ -1200,8 +1200,8 @@ __device__ inline void unit_pre(const Problem &p, const StepArgs &a, const Ptrs 
             if (panel) {
 #pragma unroll
                 for (int j = 0; j < RB; ++j) {
-                    const bool ok = cb < k && rqb + 16 * j < k;
-                    const double v = pp[ok ? 16 * j * k : 0];
+                    const bool ok = cin && rq + 4 * j < k;
+                    const double v = bq[ok ? 4 * j * k : 0];
                     bp[j] = ok ? v : 0.0;
                 }
             }
@@ -1223,7 +1223,7 @@ __device__ inline void unit_pre(const Problem &p, const StepArgs &a, const Ptrs 
             if (panel) {
                 double *Bp = sm + kp * Ld.ld + 2 * kp * 17;
 #pragma unroll
-                for (int j = 0; j < RB; ++j) Bp[(rqb + 16 * j) * 17 + cb] = bp[j];
+                for (int j = 0; j < RB; ++j) Bp[c * 17 + rq + 4 * j] = bp[j];  // c < kp = 64
             }
         } else {
             if (tid < nr) svec_rc(tid, k, P.ii, P.jj);
